@@ -1,0 +1,517 @@
+/*
+ * coralai_oracle.c -- plain, slow FP64 CPU oracle of the Coralai per-step
+ * ecosystem update.  TEST INFRASTRUCTURE ONLY: it is called by the tests,
+ * by the bench's CPU-baseline leg and by the smoke check, never by the
+ * product path, and it shares no code with the HIP library.
+ *
+ * What it follows (the paper, "Coralai: Intrinsic Evolution of Embodied
+ * Neural Cellular Automata Ecosystems"):
+ *   - System Design: substrate with named channels; GenomeIndex selects the
+ *     cell's network; each step sends the Kernel neighbourhood of Sensor
+ *     channels to that network, whose Actuator outputs Physics turns into
+ *     substrate change.
+ *   - System Design, second paragraph: HyperNEAT -- a small CPPN generates
+ *     the weights and biases of each genome's larger dense network.
+ *   - Experiment: Infrastructure / Energy / Communication channels; Invest and
+ *     Liquidate convert Energy <-> Infrastructure; communication passes
+ *     through a sigmoid; the kernel is the Moore neighbourhood ordered by
+ *     angular distance to the cell's Rotation; Explore actuators, one per
+ *     offset, spread infrastructure; takeover rule with maximal investment.
+ *   - Fig. 1 (C): radiation mutates CPPN genomes and regenerates weights.
+ * Every constant the paper leaves open is a recorded reading (directions,
+ * kernel order, ledger quanta, rates, flow budget, CPPN geometry, Philox
+ * layout); each function names the reading it uses.
+ *
+ * Arithmetic: FP64 throughout; mass is an exact int64 ledger of 2^-24 units.
+ * Arrays are row-major, linear cell index i = y*W + x, y pointing down.
+ *
+ * Parity pins: every function here is pinned by CPU tests against closed
+ * forms, invariants, library routines (numpy Philox, bincount, argsort, a
+ * numpy MLP) or a brute-force pull-from-definition implementation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_QUANTUM (1.0 / 16777216.0) /* 2^-24 mass units per quantum */
+#define ORC_NPARAM 56                   /* CPPN: A (8x5) then B (2x8) */
+#define ORC_NIN 54                      /* 9 kernel positions x 6 channels */
+#define ORC_NOUT 14                     /* invest, liquidate, 4 comm, 8 flow */
+
+typedef struct {
+    int32_t width, height;
+    int32_t n_weight_layers; /* 2: 54-h-14, 3: 54-h-h-14 */
+    int32_t hidden;
+    double rho_invest, rho_liquidate, kappa_flow;
+} orc_desc;
+
+/* Per-cell result of sense -> act -> local conversion (the "record" that the
+ * physics pass reads from a cell's neighbours). */
+typedef struct {
+    int64_t e1, i1;        /* ledger after invest / liquidate */
+    int64_t flow[8];       /* outflow toward absolute direction d */
+    int32_t explore_dir;   /* absolute direction of the argmax explore */
+    int32_t explore_pos;   /* kernel position p* in 1..8 */
+    double logit_gap;      /* top-1 minus top-2 flow logit (FP64) */
+} orc_record;
+
+/* Directions: d at 45*d degrees counter-clockwise from +x, y pointing down. */
+static const int DX[8] = {1, 1, 0, -1, -1, -1, 0, 1};
+static const int DY[8] = {0, -1, -1, -1, 0, 1, 1, 1};
+/* Kernel order for rotation r: centre, then r, r+1, r-1, r+2, r-2, r+3, r-3,
+ * r+4 (increasing angular distance; the counter-clockwise member of each
+ * equal-distance pair first). */
+static const int KOFF[9] = {0, 0, 1, -1, 2, -2, 3, -3, 4};
+
+int orc_kernel_dir(int r, int p) { return (r + KOFF[p] + 8) & 7; } /* p in 1..8 */
+
+static int64_t nbr(const orc_desc* d, int64_t i, int dir) {
+    int64_t W = d->width, H = d->height;
+    int64_t x = i % W, y = i / W;
+    x = ((x + DX[dir]) % W + W) % W;
+    y = ((y + DY[dir]) % H + H) % H;
+    return y * W + x;
+}
+
+int orc_layer_widths(const orc_desc* d, int32_t* widths) {
+    int n = d->n_weight_layers;
+    widths[0] = ORC_NIN;
+    for (int l = 1; l < n; ++l) widths[l] = d->hidden;
+    widths[n] = ORC_NOUT;
+    return n + 1;
+}
+
+/* Number of doubles in one genome's flat network: for each layer l,
+ * W_l (L_{l+1} x L_l, row-major) followed by b_l (L_{l+1}). */
+int64_t orc_net_size(const orc_desc* d) {
+    int32_t L[8];
+    orc_layer_widths(d, L);
+    int64_t n = 0;
+    for (int l = 0; l < d->n_weight_layers; ++l) n += (int64_t)L[l + 1] * L[l] + L[l + 1];
+    return n;
+}
+
+/* CPPN (HyperNEAT, System Design): inputs z = (x1, y1, x2, y2, 1); 8 hidden
+ * nodes h_k = phi_k(sum_m A[k][m] z_m) with phi = sin, gauss, tanh, identity
+ * for k mod 4 = 0, 1, 2, 3 and gauss(s) = exp(-s^2); two linear outputs
+ * (weight, bias) = B h. */
+void orc_cppn(const double* p, double x1, double y1, double x2, double y2, double out[2]) {
+    const double z[5] = {x1, y1, x2, y2, 1.0};
+    double h[8];
+    for (int k = 0; k < 8; ++k) {
+        double s = 0.0;
+        for (int m = 0; m < 5; ++m) s += p[k * 5 + m] * z[m];
+        switch (k & 3) {
+            case 0: h[k] = sin(s); break;
+            case 1: h[k] = exp(-s * s); break;
+            case 2: h[k] = tanh(s); break;
+            default: h[k] = s; break;
+        }
+    }
+    for (int o = 0; o < 2; ++o) {
+        double s = 0.0;
+        for (int k = 0; k < 8; ++k) s += p[40 + o * 8 + k] * h[k];
+        out[o] = s;
+    }
+}
+
+/* HyperNEAT substrate: neuron j of layer l sits at (x_{l,j}, y_l) with
+ * y_l = -1 + 2l/n and x_{l,j} = -1 + 2j/(L_l - 1).  Weight W_l[o][j] is the
+ * CPPN weight output at (x_{l,j}, y_l, x_{l+1,o}, y_{l+1}) divided by
+ * sqrt(L_l); bias b_l[o] is the CPPN bias output at (0, y_l, x_{l+1,o},
+ * y_{l+1}).  No expression threshold. */
+void orc_cppn_to_net(const orc_desc* d, const double* p, double* net) {
+    int32_t L[8];
+    orc_layer_widths(d, L);
+    int n = d->n_weight_layers;
+    double* w = net;
+    for (int l = 0; l < n; ++l) {
+        double yi = -1.0 + 2.0 * l / n, yo = -1.0 + 2.0 * (l + 1) / n;
+        double scale = 1.0 / sqrt((double)L[l]);
+        for (int o = 0; o < L[l + 1]; ++o) {
+            double xo = -1.0 + 2.0 * o / (L[l + 1] - 1);
+            for (int j = 0; j < L[l]; ++j) {
+                double xi = -1.0 + 2.0 * j / (L[l] - 1);
+                double r[2];
+                orc_cppn(p, xi, yi, xo, yo, r);
+                w[(int64_t)o * L[l] + j] = r[0] * scale;
+            }
+        }
+        w += (int64_t)L[l + 1] * L[l];
+        for (int o = 0; o < L[l + 1]; ++o) {
+            double xo = -1.0 + 2.0 * o / (L[l + 1] - 1);
+            double r[2];
+            orc_cppn(p, 0.0, yi, xo, yo, r);
+            w[o] = r[1];
+        }
+        w += L[l + 1];
+    }
+}
+
+/* Sensors over the Kernel (Experiment): u[p*6 + ch] is channel ch of the
+ * cell at kernel position p, channels (E, I, C0, C1, C2, C3), E and I as
+ * mass values (quanta * 2^-24). */
+void orc_sense(const orc_desc* d, const int64_t* E, const int64_t* I, const double* C,
+               const uint8_t* R, int64_t i, double* u) {
+    int64_t N = (int64_t)d->width * d->height;
+    int r = R[i] & 7;
+    for (int p = 0; p < 9; ++p) {
+        int64_t n = p == 0 ? i : nbr(d, i, orc_kernel_dir(r, p));
+        u[p * 6 + 0] = (double)E[n] * ORC_QUANTUM;
+        u[p * 6 + 1] = (double)I[n] * ORC_QUANTUM;
+        for (int c = 0; c < 4; ++c) u[p * 6 + 2 + c] = C[c * N + n];
+    }
+}
+
+/* The genome's dense network: tanh hidden layers, linear output layer. */
+void orc_forward(const orc_desc* d, const double* net, const double* u, double* a) {
+    int32_t L[8];
+    orc_layer_widths(d, L);
+    double buf0[128], buf1[128];
+    const double* x = u;
+    double* y = buf0;
+    const double* w = net;
+    for (int l = 0; l < d->n_weight_layers; ++l) {
+        const double* b = w + (int64_t)L[l + 1] * L[l];
+        int last = l == d->n_weight_layers - 1;
+        double* dst = last ? a : y;
+        for (int o = 0; o < L[l + 1]; ++o) {
+            double s = 0.0;
+            for (int j = 0; j < L[l]; ++j) s += w[(int64_t)o * L[l] + j] * x[j];
+            s += b[o];
+            dst[o] = last ? s : tanh(s);
+        }
+        w = b + L[l + 1];
+        x = dst;
+        y = (y == buf0) ? buf1 : buf0;
+    }
+}
+
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* Actuators -> local part of the physics (Experiment):
+ *   invest / liquidate: x_inv = min(E, floor(rho_inv * sig(a0) * E)),
+ *                       x_liq = min(I, floor(rho_liq * sig(a1) * I)),
+ *                       E1 = E - x_inv + x_liq, I1 = I + x_inv - x_liq;
+ *   communication:      C'_j = sig(a_{2+j});
+ *   explore / flow:     budget F = floor(kappa * I1) split by the softmax of
+ *                       the 8 flow logits a_6..a_13 (kernel positions 1..8),
+ *                       f_p = min(floor(w_p F), F - sum_{q<p} f_q);
+ *                       the explored neighbour is the argmax position (lowest
+ *                       on ties) and its investment is that position's flow.
+ * All in FP64, quanta as integers. */
+void orc_actuate(const orc_desc* d, int64_t e, int64_t i, int r, const double* a,
+                 orc_record* rec, double* comm_out) {
+    double se = sigmoid(a[0]), sl = sigmoid(a[1]);
+    int64_t xi = (int64_t)floor(d->rho_invest * se * (double)e);
+    int64_t xl = (int64_t)floor(d->rho_liquidate * sl * (double)i);
+    if (xi > e) xi = e;
+    if (xl > i) xl = i;
+    if (xi < 0) xi = 0;
+    if (xl < 0) xl = 0;
+    rec->e1 = e - xi + xl;
+    rec->i1 = i + xi - xl;
+    for (int j = 0; j < 4; ++j) comm_out[j] = sigmoid(a[2 + j]);
+
+    const double* lg = a + 6; /* lg[p-1] is the logit of position p */
+    double m = lg[0];
+    int best = 0;
+    for (int k = 1; k < 8; ++k)
+        if (lg[k] > m) { m = lg[k]; best = k; }
+    double second = -INFINITY;
+    for (int k = 0; k < 8; ++k)
+        if (k != best && lg[k] > second) second = lg[k];
+    rec->logit_gap = m - second;
+    double ex[8], s = 0.0;
+    for (int k = 0; k < 8; ++k) { ex[k] = exp(lg[k] - m); s += ex[k]; }
+    int64_t F = (int64_t)floor(d->kappa_flow * (double)rec->i1);
+    if (F < 0) F = 0;
+    int64_t used = 0;
+    for (int k = 0; k < 8; ++k) {
+        int64_t f = (int64_t)floor((ex[k] / s) * (double)F);
+        if (f > F - used) f = F - used;
+        if (f < 0) f = 0;
+        used += f;
+        rec->flow[orc_kernel_dir(r, k + 1)] = f;
+    }
+    rec->explore_pos = best + 1;
+    rec->explore_dir = orc_kernel_dir(r, best + 1);
+}
+
+/* Whole per-cell act: sense, network of the cell's genome, actuate. */
+static void cell_record(const orc_desc* d, const int64_t* E, const int64_t* I, const double* C,
+                        const int32_t* G, const uint8_t* R, const double* nets, int64_t nsz,
+                        int64_t i, orc_record* rec, double* comm, double* act) {
+    double u[ORC_NIN], a[ORC_NOUT];
+    orc_sense(d, E, I, C, R, i, u);
+    orc_forward(d, nets + (int64_t)G[i] * nsz, u, a);
+    if (act)
+        for (int k = 0; k < ORC_NOUT; ++k) act[k] = a[k];
+    orc_actuate(d, E[i], I[i], R[i] & 7, a, rec, comm);
+}
+
+/* Physics (Experiment, exploration and takeover), pulled at target t: every
+ * neighbour n = nbr(t, d) sends t its flow toward direction (d+4) mod 8;
+ * neighbours whose explore direction is (d+4) mod 8 are candidates; the
+ * maximal investment wins (lowest d on ties) and takes the cell over when it
+ * strictly exceeds I1(t), t adopting n's genome and the exploration
+ * direction as its rotation.  E2 = E1.  Returns the takeover flag and the
+ * decision margins (FP64 quanta) used by the near-tie protocol. */
+static int cell_physics(const orc_desc* d, const orc_record* rec_t, const orc_record* const nrec[8],
+                        const int32_t* G, const uint8_t* R, const int64_t nidx[8], int64_t t,
+                        int64_t* i2, int32_t* g2, uint8_t* r2, double* margin_take,
+                        double* margin_rank) {
+    int64_t out = 0, in = 0;
+    for (int k = 0; k < 8; ++k) out += rec_t->flow[k];
+    int win = -1;
+    int64_t vbest = 0, vsecond = -1;
+    for (int dd = 0; dd < 8; ++dd) {
+        int back = (dd + 4) & 7;
+        const orc_record* rn = nrec[dd];
+        in += rn->flow[back];
+        if (rn->explore_dir == back) {
+            int64_t v = rn->flow[back];
+            if (win < 0 || v > vbest) {
+                if (win >= 0) vsecond = vbest;
+                vbest = v;
+                win = dd;
+            } else if (v > vsecond) {
+                vsecond = v;
+            }
+        }
+    }
+    *i2 = rec_t->i1 - out + in;
+    *g2 = G[t];
+    *r2 = R[t];
+    *margin_take = INFINITY;
+    *margin_rank = INFINITY;
+    int took = 0;
+    if (win >= 0) {
+        *margin_take = fabs((double)vbest - (double)rec_t->i1);
+        if (vsecond >= 0) *margin_rank = (double)(vbest - vsecond);
+        if (vbest > rec_t->i1) {
+            *g2 = G[nidx[win]];
+            *r2 = (uint8_t)((win + 4) & 7);
+            took = 1;
+        }
+    }
+    return took;
+}
+
+/* One step for output rows [y0, y1) of the torus.  Records are computed for
+ * rows y0-1 .. y1 (wrapping); a full step is y0 = 0, y1 = H.
+ * Outputs (full-size arrays; only the requested rows are written):
+ *   E2, I2 (int64), C2 (4 planes, double), G2, R2;
+ *   act (N x 14, nullable): raw network outputs of the rows;
+ *   rec_out (N, nullable): per-cell records of the rows;
+ *   margins (N x 3, nullable): per target (min neighbour logit gap,
+ *   |v_win - I1|, v_win - v_second).
+ * Returns the number of takeovers in the rows, or -1 on a bad genome id. */
+int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, const double* C,
+                      const int32_t* G, const uint8_t* R, const double* nets, int32_t n_genomes,
+                      int32_t y0, int32_t y1, int64_t* E2, int64_t* I2, double* C2, int32_t* G2,
+                      uint8_t* R2, double* act, orc_record* rec_out, double* margins) {
+    const int64_t W = d->width, H = d->height, N = W * H;
+    const int64_t nsz = orc_net_size(d);
+    for (int64_t i = 0; i < N; ++i)
+        if (G[i] < 0 || G[i] >= n_genomes) return -1;
+    int32_t rows = y1 - y0;
+    int32_t rrows = rows + 2 > H ? (int32_t)H : rows + 2;
+    int32_t rstart = rows + 2 > H ? 0 : y0 - 1;
+    orc_record* rec = (orc_record*)malloc(sizeof(orc_record) * (size_t)N);
+    double* cn = (double*)malloc(sizeof(double) * 4 * (size_t)N);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)rrows * W; ++k) {
+        int64_t y = ((rstart + k / W) % H + H) % H, x = k % W, i = y * W + x;
+        double comm[4];
+        int in_rows = (y - y0 + H) % H < rows;
+        cell_record(d, E, I, C, G, R, nets, nsz, i, &rec[i], comm,
+                    (act && in_rows) ? act + i * ORC_NOUT : NULL);
+        for (int c = 0; c < 4; ++c) cn[c * N + i] = comm[c];
+    }
+    int64_t takeovers = 0;
+#pragma omp parallel for schedule(static) reduction(+ : takeovers)
+    for (int64_t k = 0; k < (int64_t)rows * W; ++k) {
+        int64_t y = (y0 + k / W) % H, x = k % W, t = y * W + x;
+        int64_t nidx[8];
+        const orc_record* nrec[8];
+        double gap = INFINITY; /* t's own argmax does not decide t's genome */
+        for (int dd = 0; dd < 8; ++dd) {
+            nidx[dd] = nbr(d, t, dd);
+            nrec[dd] = &rec[nidx[dd]];
+            if (nrec[dd]->logit_gap < gap) gap = nrec[dd]->logit_gap;
+        }
+        double mt, mr;
+        takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt, &mr);
+        E2[t] = rec[t].e1;
+        for (int c = 0; c < 4; ++c) C2[c * N + t] = cn[c * N + t];
+        if (rec_out) rec_out[t] = rec[t];
+        if (margins) {
+            margins[t * 3 + 0] = gap;
+            margins[t * 3 + 1] = mt;
+            margins[t * 3 + 2] = mr;
+        }
+    }
+    free(rec);
+    free(cn);
+    return takeovers;
+}
+
+/* Physics alone, from given records (I1, flows in absolute-direction order,
+ * explore direction).  Pure integer work. */
+int64_t orc_physics_from_records(const orc_desc* d, const int64_t* i1, const int64_t* flow8,
+                                 const int32_t* explore_dir, const int32_t* G, const uint8_t* R,
+                                 int64_t* I2, int32_t* G2, uint8_t* R2) {
+    const int64_t N = (int64_t)d->width * d->height;
+    orc_record* rec = (orc_record*)malloc(sizeof(orc_record) * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        rec[i].i1 = i1[i];
+        rec[i].e1 = 0;
+        for (int k = 0; k < 8; ++k) rec[i].flow[k] = flow8[i * 8 + k];
+        rec[i].explore_dir = explore_dir[i];
+        rec[i].explore_pos = 0;
+        rec[i].logit_gap = 0;
+    }
+    int64_t takeovers = 0;
+    for (int64_t t = 0; t < N; ++t) {
+        int64_t nidx[8];
+        const orc_record* nrec[8];
+        for (int dd = 0; dd < 8; ++dd) {
+            nidx[dd] = nbr(d, t, dd);
+            nrec[dd] = &rec[nidx[dd]];
+        }
+        double mt, mr;
+        takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt, &mr);
+    }
+    free(rec);
+    return takeovers;
+}
+
+/* Buckets: counts = histogram of G over [0, cap), offsets = exclusive prefix
+ * sum, perm = cells ordered by genome, ascending cell index within a genome
+ * (a stable counting sort).  Returns -1 on an id outside [0, cap). */
+int orc_buckets(int64_t n, const int32_t* G, int32_t cap, int32_t* counts, int32_t* offsets,
+                int32_t* perm) {
+    for (int32_t g = 0; g < cap; ++g) counts[g] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (G[i] < 0 || G[i] >= cap) return -1;
+        counts[G[i]]++;
+    }
+    int32_t run = 0;
+    for (int32_t g = 0; g < cap; ++g) { offsets[g] = run; run += counts[g]; }
+    offsets[cap] = run;
+    int32_t* cur = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+    memcpy(cur, offsets, sizeof(int32_t) * (size_t)cap);
+    for (int64_t i = 0; i < n; ++i) perm[cur[G[i]]++] = (int32_t)i;
+    free(cur);
+    return 0;
+}
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11 "Parallel random numbers:
+ * as easy as 1, 2, 3"): ten rounds of two 64x64->128 multiplies with the
+ * published multipliers and Weyl key increments. */
+static void mul128(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+    unsigned __int128 p = (unsigned __int128)a * b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t h0, l0, h1, l1;
+        mul128(0xD2E7470EE14C6C93ULL, x0, &h0, &l0);
+        mul128(0xCA5A826395121157ULL, x2, &h1, &l1);
+        uint64_t n0 = h1 ^ x1 ^ k0, n1 = l1, n2 = h0 ^ x3 ^ k1, n3 = l0;
+        x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+        k0 += 0x9E3779B97F4A7C15ULL;
+        k1 += 0xBB67AE8584CAA73BULL;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform in (0,1) from a 64-bit draw: the top 23 bits as an odd multiple of
+ * 2^-24, u = (2 (o >> 41) + 1) 2^-24, exactly representable in FP32. */
+double orc_uniform(uint64_t o) { return (double)(2 * (o >> 41) + 1) * (1.0 / 16777216.0); }
+
+/* The 56 standard normals of a mutation at cell i, step s: Philox blocks at
+ * counter (i, s, 1+b, 0), b = 0..13; Box-Muller on (o0,o1) -> z[4b], z[4b+1]
+ * and (o2,o3) -> z[4b+2], z[4b+3]: z = sqrt(-2 ln u1) (cos, sin)(2 pi u2). */
+void orc_mutation_normals(uint64_t seed, uint64_t i, uint64_t s, double* z) {
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t key[2] = {seed, 0};
+    for (int b = 0; b < 14; ++b) {
+        uint64_t ctr[4] = {i, s, (uint64_t)(1 + b), 0}, o[4];
+        orc_philox4x64_10(ctr, key, o);
+        for (int h = 0; h < 2; ++h) {
+            double u1 = orc_uniform(o[2 * h]), u2 = orc_uniform(o[2 * h + 1]);
+            double rr = sqrt(-2.0 * log(u1));
+            z[4 * b + 2 * h] = rr * cos(two_pi * u2);
+            z[4 * b + 2 * h + 1] = rr * sin(two_pi * u2);
+        }
+    }
+}
+
+/* Hit threshold: a cell is hit when its first draw is below floor(rate 2^64). */
+uint64_t orc_hit_threshold(double rate) {
+    if (!(rate > 0.0)) return 0;
+    if (rate >= 1.0) return UINT64_MAX;
+    return (uint64_t)floor(rate * 18446744073709551616.0);
+}
+
+/* Radiation (Fig. 1 C) applied after step s: each cell i draws Philox at
+ * counter (i, s, 0, 0), key (seed, 0), and is hit when o0 < T.  Free slots
+ * are the slot ids with zero count in G (ascending); the k-th hit in
+ * ascending i takes free slot k, gets its parent's CPPN parameters plus
+ * sigma * z, and G[i] becomes that slot; hits beyond the free slots are
+ * dropped.  params is cap x 56 (FP64), in/out.  hit_cells / hit_slots
+ * (nullable, capacity max_hits) list the hits in order (slot -1 = dropped).
+ * Returns the number of hits; *dropped counts the dropped ones. */
+int64_t orc_radiate(int64_t n, int32_t* G, int32_t cap, double* params, uint64_t seed, uint64_t s,
+                    uint64_t T, double sigma, int64_t* hit_cells, int32_t* hit_slots,
+                    int64_t max_hits, int64_t* dropped) {
+    int32_t* counts = (int32_t*)calloc((size_t)cap, sizeof(int32_t));
+    int32_t* freel = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+    for (int64_t i = 0; i < n; ++i) counts[G[i]]++;
+    int32_t nfree = 0;
+    for (int32_t g = 0; g < cap; ++g)
+        if (counts[g] == 0) freel[nfree++] = g;
+    uint64_t key[2] = {seed, 0};
+    int64_t hits = 0;
+    *dropped = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t ctr[4] = {(uint64_t)i, s, 0, 0}, o[4];
+        orc_philox4x64_10(ctr, key, o);
+        if (!(o[0] < T)) continue;
+        int32_t slot = -1;
+        if (hits < nfree) {
+            slot = freel[hits];
+            int32_t parent = G[i];
+            double z[ORC_NPARAM];
+            orc_mutation_normals(seed, (uint64_t)i, s, z);
+            for (int m = 0; m < ORC_NPARAM; ++m)
+                params[(int64_t)slot * ORC_NPARAM + m] =
+                    params[(int64_t)parent * ORC_NPARAM + m] + sigma * z[m];
+            G[i] = slot;
+        } else {
+            (*dropped)++;
+        }
+        if (hit_cells && hits < max_hits) {
+            hit_cells[hits] = i;
+            hit_slots[hits] = slot;
+        }
+        hits++;
+    }
+    free(counts);
+    free(freel);
+    return hits;
+}
+
+/* Exact and FP64 total mass sum(E + I). */
+int64_t orc_mass(int64_t n, const int64_t* E, const int64_t* I) {
+    int64_t s = 0;
+    for (int64_t i = 0; i < n; ++i) s += E[i] + I[i];
+    return s;
+}

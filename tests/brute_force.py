@@ -1,0 +1,153 @@
+"""Pure-Python brute force of one update step, written pull-from-definition.
+
+A test pin for the C oracle on tiny grids.  It shares nothing with the
+oracle: the direction vectors come from the 45-degree angles, the kernel order
+from sorting directions by angular distance to the cell's rotation, and each
+target cell recomputes the actions of every neighbour it pulls from.  Every
+number is a Python float (IEEE double) or int.
+"""
+from __future__ import annotations
+
+import math
+
+Q = 2.0 ** -24
+
+
+def direction_vector(d: int) -> tuple[int, int]:
+    """Direction d points 45*d degrees counter-clockwise from +x on a screen
+    whose y axis points down."""
+    th = math.radians(45.0 * d)
+    c, s = math.cos(th), math.sin(th)
+    dx = 0 if abs(c) < 1e-9 else (1 if c > 0 else -1)
+    dy = 0 if abs(s) < 1e-9 else (-1 if s > 0 else 1)
+    return dx, dy
+
+
+def kernel_order(r: int) -> list[int]:
+    """The 8 neighbour directions by increasing angular distance to rotation r;
+    within an equal-distance pair the counter-clockwise one comes first."""
+    def key(d):
+        ccw = (d - r) % 8
+        dist = min(ccw, 8 - ccw)
+        return (dist, 0 if ccw == dist else 1)
+    return sorted(range(8), key=key)
+
+
+def cppn_eval(p, z):
+    zz = list(z) + [1.0]
+    acts = [math.sin, lambda s: math.exp(-s * s), math.tanh, lambda s: s]
+    h = []
+    for k in range(8):
+        s = 0.0
+        for m in range(5):
+            s += p[k * 5 + m] * zz[m]
+        h.append(acts[k % 4](s))
+    out = []
+    for o in range(2):
+        s = 0.0
+        for k in range(8):
+            s += p[40 + o * 8 + k] * h[k]
+        out.append(s)
+    return out
+
+
+def build_net(p, widths):
+    """HyperNEAT: layer l neurons at x = -1 + 2j/(L-1), y = -1 + 2l/n."""
+    n = len(widths) - 1
+    layers = []
+    for l in range(n):
+        lin, lout = widths[l], widths[l + 1]
+        yi, yo = -1.0 + 2.0 * l / n, -1.0 + 2.0 * (l + 1) / n
+        W = [[cppn_eval(p, (-1.0 + 2.0 * j / (lin - 1), yi, -1.0 + 2.0 * o / (lout - 1), yo))[0]
+              * (1.0 / math.sqrt(lin)) for j in range(lin)] for o in range(lout)]
+        b = [cppn_eval(p, (0.0, yi, -1.0 + 2.0 * o / (lout - 1), yo))[1] for o in range(lout)]
+        layers.append((W, b))
+    return layers
+
+
+def run_net(layers, u):
+    x = list(u)
+    for li, (W, b) in enumerate(layers):
+        y = []
+        for o in range(len(W)):
+            s = 0.0
+            for j in range(len(x)):
+                s += W[o][j] * x[j]
+            s += b[o]
+            y.append(s if li == len(layers) - 1 else math.tanh(s))
+        x = y
+    return x
+
+
+def sig(x):
+    return 1.0 / (1.0 + math.exp(-x))
+
+
+class World:
+    def __init__(self, W, H, E, I, C, G, R, nets, rho_i, rho_l, kappa):
+        self.W, self.H = W, H
+        self.E, self.I, self.C, self.G, self.R = E, I, C, G, R   # flat lists; C = 4 lists
+        self.nets = nets
+        self.rho_i, self.rho_l, self.kappa = rho_i, rho_l, kappa
+
+    def at(self, x, y):
+        return (y % self.H) * self.W + (x % self.W)
+
+    def neighbour(self, i, d):
+        dx, dy = direction_vector(d)
+        return self.at(i % self.W + dx, i // self.W + dy)
+
+    def plan(self, i):
+        """Everything cell i decides this step, from the pre-step state."""
+        order = kernel_order(self.R[i] % 8)
+        cells = [i] + [self.neighbour(i, d) for d in order]
+        u = []
+        for c in cells:
+            u += [self.E[c] * Q, self.I[c] * Q] + [self.C[k][c] for k in range(4)]
+        a = run_net(self.nets[self.G[i]], u)
+        e, inf = self.E[i], self.I[i]
+        x_inv = min(e, math.floor(self.rho_i * sig(a[0]) * e))
+        x_liq = min(inf, math.floor(self.rho_l * sig(a[1]) * inf))
+        e1, i1 = e - x_inv + x_liq, inf + x_inv - x_liq
+        comm = [sig(a[2 + k]) for k in range(4)]
+        logits = a[6:14]
+        m = max(logits)
+        ex = [math.exp(v - m) for v in logits]
+        tot = 0.0
+        for v in ex:
+            tot += v
+        F = math.floor(self.kappa * i1)
+        flows, used = {}, 0
+        for p in range(8):
+            f = min(math.floor((ex[p] / tot) * F), F - used)
+            used += f
+            flows[order[p]] = f
+        best = logits.index(m)
+        return dict(e1=e1, i1=i1, comm=comm, flows=flows, explore=order[best], act=a)
+
+    def step(self):
+        N = self.W * self.H
+        plans = [self.plan(i) for i in range(N)]
+        E2, I2, G2, R2 = [0] * N, [0] * N, [0] * N, [0] * N
+        C2 = [[0.0] * N for _ in range(4)]
+        takeovers = 0
+        for t in range(N):
+            pt = plans[t]
+            inflow = 0
+            best = None
+            for d in range(8):
+                n = self.neighbour(t, d)
+                back = (d + 4) % 8
+                amount = plans[n]["flows"][back]
+                inflow += amount
+                if plans[n]["explore"] == back and (best is None or amount > best[0]):
+                    best = (amount, d, n)
+            I2[t] = pt["i1"] - sum(pt["flows"].values()) + inflow
+            E2[t] = pt["e1"]
+            for k in range(4):
+                C2[k][t] = pt["comm"][k]
+            G2[t], R2[t] = self.G[t], self.R[t]
+            if best is not None and best[0] > pt["i1"]:
+                G2[t], R2[t] = self.G[best[2]], (best[1] + 4) % 8
+                takeovers += 1
+        return E2, I2, C2, G2, R2, takeovers, plans

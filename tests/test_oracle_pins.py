@@ -1,0 +1,481 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test fixes the oracle to brute force, a closed form, an invariant or a
+library routine, so that a dropped term, a wrong sign or index, or a
+transposed operand anywhere in it fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from tests import brute_force as bf
+
+
+def tiny_world(oracle, W, H, n_genomes=3, hidden=8, layers=2, seed=1, scale=1.0,
+               sparse_infra=True):
+    rng = np.random.default_rng(seed)
+    E = wl.to_ledger(rng.random((H, W)))
+    inf = rng.random((H, W)) ** 3
+    if sparse_infra:
+        inf *= rng.random((H, W)) < 0.6
+    I = wl.to_ledger(inf * 2.0)
+    C = rng.random((4, H, W))
+    G = rng.integers(0, n_genomes, size=(H, W)).astype(np.int32)
+    R = rng.integers(0, 8, size=(H, W)).astype(np.uint8)
+    params = rng.standard_normal((n_genomes, 56)) * scale
+    d = oracle.Desc(W, H, layers, hidden)
+    return d, oracle.State(E, I, C, G, R), params
+
+
+def bf_world(d, s, params, oracle):
+    widths = d.widths()
+    nets = [bf.build_net(list(map(float, p)), widths) for p in params]
+    return bf.World(d.width, d.height, [int(v) for v in s.E.ravel()], [int(v) for v in s.I.ravel()],
+                    [list(map(float, s.C[k].ravel())) for k in range(4)],
+                    [int(v) for v in s.G.ravel()], [int(v) for v in s.R.ravel()], nets,
+                    d.rho_invest, d.rho_liquidate, d.kappa_flow)
+
+
+# ---------------------------------------------------------------- geometry
+
+def test_direction_and_kernel_order_tables(oracle_lib):
+    """The oracle's kernel order equals sorting directions by angular distance."""
+    for r in range(8):
+        order = bf.kernel_order(r)
+        assert [oracle_lib.kernel_dir(r, p) for p in range(1, 9)] == order
+        assert order[0] == r and order[-1] == (r + 4) % 8
+    assert [bf.direction_vector(d) for d in range(8)] == [
+        (1, 0), (1, -1), (0, -1), (-1, -1), (-1, 0), (-1, 1), (0, 1), (1, 1)]
+
+
+def test_sense_vector_by_hand(oracle_lib):
+    """u[p*6+ch] enumerated by hand for one cell of a 5x4 grid."""
+    d, s, _ = tiny_world(oracle_lib, 5, 4, seed=3)
+    i = 0                      # corner cell: every neighbour wraps
+    s.R[0, 0] = 3
+    u = oracle_lib.sense(d, s, i)
+    order = [3, 4, 2, 5, 1, 6, 0, 7]      # r, r+1, r-1, r+2, r-2, r+3, r-3, r+4
+    vec = {0: (1, 0), 1: (1, -1), 2: (0, -1), 3: (-1, -1), 4: (-1, 0), 5: (-1, 1), 6: (0, 1),
+           7: (1, 1)}
+    cells = [(0, 0)] + [((vec[k][0]) % 5, (vec[k][1]) % 4) for k in order]
+    for p, (x, y) in enumerate(cells):
+        assert u[p * 6 + 0] == s.E[y, x] * 2.0 ** -24
+        assert u[p * 6 + 1] == s.I[y, x] * 2.0 ** -24
+        for c in range(4):
+            assert u[p * 6 + 2 + c] == s.C[c, y, x]
+
+
+# ---------------------------------------------------------------- CPPN
+
+def test_cppn_identity_node_gives_coordinate_weights(oracle_lib):
+    """Only the identity node (k=3) passes x_in: W_l[o, j] = x_{l,j} / sqrt(L_l), b = 0."""
+    d = oracle_lib.Desc(4, 4, 3, 16)
+    p = np.zeros(56)
+    p[3 * 5 + 0] = 1.0          # h_3 = x1
+    p[40 + 3] = 1.0             # weight output = h_3
+    net = oracle_lib.cppn_to_net(d, p)
+    for l, (w, b) in enumerate(oracle_lib.unflatten(d, net)):
+        lin = d.widths()[l]
+        x = -1.0 + 2.0 * np.arange(lin) / (lin - 1)
+        np.testing.assert_allclose(w, np.broadcast_to(x / math.sqrt(lin), w.shape),
+                                   rtol=4e-16, atol=0)
+        np.testing.assert_array_equal(b, 0.0)
+
+
+@pytest.mark.parametrize("node,fn", [(0, np.sin), (1, lambda s: np.exp(-s * s)), (2, np.tanh),
+                                     (4, np.sin), (6, np.tanh), (7, lambda s: s)])
+def test_cppn_single_node_against_numpy(oracle_lib, node, fn):
+    """One hidden node wired from y_out and x_out; bias output from the same node."""
+    d = oracle_lib.Desc(4, 4, 2, 32)
+    p = np.zeros(56)
+    p[node * 5 + 2] = 0.7       # x2 (x_out)
+    p[node * 5 + 3] = -1.3      # y2 (y_out)
+    p[node * 5 + 4] = 0.25      # constant input
+    p[40 + node] = 2.0
+    p[48 + node] = -0.5
+    (w0, b0), (w1, b1) = oracle_lib.unflatten(d, oracle_lib.cppn_to_net(d, p))
+    for l, (w, b) in enumerate([(w0, b0), (w1, b1)]):
+        lin, lout = d.widths()[l], d.widths()[l + 1]
+        yo = -1.0 + 2.0 * (l + 1) / 2
+        xo = -1.0 + 2.0 * np.arange(lout) / (lout - 1)
+        s = 0.7 * xo - 1.3 * yo + 0.25
+        np.testing.assert_allclose(w, np.repeat((2.0 * fn(s) / math.sqrt(lin))[:, None], lin, 1),
+                                   rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(b, -0.5 * fn(s), rtol=1e-15, atol=1e-15)
+
+
+def test_cppn_matches_bruteforce_random(oracle_lib):
+    rng = np.random.default_rng(5)
+    d = oracle_lib.Desc(4, 4, 3, 16)
+    p = rng.standard_normal(56)
+    net = oracle_lib.cppn_to_net(d, p)
+    layers = bf.build_net(list(p), d.widths())
+    flat = []
+    for W, b in layers:
+        flat += [v for row in W for v in row] + b
+    np.testing.assert_array_equal(net, np.array(flat))
+
+
+# ---------------------------------------------------------------- network
+
+@pytest.mark.parametrize("layers,hidden", [(2, 32), (3, 64)])
+def test_forward_against_numpy_mlp(oracle_lib, layers, hidden):
+    rng = np.random.default_rng(11)
+    d = oracle_lib.Desc(4, 4, layers, hidden)
+    net = oracle_lib.cppn_to_net(d, rng.standard_normal(56))
+    u = rng.random(54)
+    x = u
+    lays = oracle_lib.unflatten(d, net)
+    for k, (w, b) in enumerate(lays):
+        x = w @ x + b
+        if k < len(lays) - 1:
+            x = np.tanh(x)
+    np.testing.assert_allclose(oracle_lib.forward(d, net, u), x, rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------------------- whole step vs brute force
+
+@pytest.mark.parametrize("W,H,layers,hidden", [(1, 1, 2, 8), (2, 2, 2, 8), (1, 5, 2, 8),
+                                               (3, 3, 3, 8), (5, 7, 2, 8), (8, 8, 2, 16),
+                                               (6, 4, 3, 8)])
+def test_step_matches_bruteforce(oracle_lib, W, H, layers, hidden):
+    for seed in range(3):
+        d, s, params = tiny_world(oracle_lib, W, H, hidden=hidden, layers=layers, seed=seed,
+                                  scale=2.0)
+        nets = oracle_lib.nets_for(d, params)
+        s2, info = oracle_lib.step(d, s, nets, want_act=True)
+        bw = bf_world(d, s, params, oracle_lib)
+        E2, I2, C2, G2, R2, tk, plans = bw.step()
+        assert s2.E.ravel().tolist() == E2
+        assert s2.I.ravel().tolist() == I2
+        assert s2.G.ravel().tolist() == G2
+        assert s2.R.ravel().tolist() == R2
+        assert info["takeovers"] == tk
+        np.testing.assert_allclose(s2.C.reshape(4, -1), np.array(C2), rtol=0, atol=1e-14)
+        act = np.array([p["act"] for p in plans])
+        np.testing.assert_allclose(info["act"].reshape(-1, 14), act, rtol=0, atol=1e-13)
+
+
+def test_bruteforce_exercises_takeovers(oracle_lib):
+    """The brute-force cases above include takeovers (else they would not pin the rule)."""
+    total = 0
+    for seed in range(3):
+        d, s, params = tiny_world(oracle_lib, 8, 8, hidden=16, seed=seed, scale=2.0)
+        _, info = oracle_lib.step(d, s, oracle_lib.nets_for(d, params))
+        total += info["takeovers"]
+    assert total > 0
+
+
+def test_step_rows_equal_full_step(oracle_lib):
+    d, s, params = tiny_world(oracle_lib, 9, 11, hidden=8, seed=4, scale=2.0)
+    nets = oracle_lib.nets_for(d, params)
+    full, _ = oracle_lib.step(d, s, nets)
+    for y0, y1 in [(0, 3), (3, 4), (8, 11), (10, 11), (0, 11)]:
+        part, _ = oracle_lib.step(d, s, nets, rows=(y0, y1))
+        for a, b in [(part.E, full.E), (part.I, full.I), (part.G, full.G), (part.R, full.R)]:
+            np.testing.assert_array_equal(a[y0:y1], b[y0:y1])
+        np.testing.assert_array_equal(part.C[:, y0:y1], full.C[:, y0:y1])
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_mass_conserved_exactly_over_many_steps(oracle_lib):
+    init = wl.config_plain_64()
+    d = oracle_lib.Desc.from_spec(init.spec)
+    nets = oracle_lib.nets_for(d, init.params)
+    s = oracle_lib.State.from_init(init)
+    m0 = oracle_lib.mass(s.E, s.I)
+    assert m0 == int(s.E.sum() + s.I.sum())
+    for _ in range(25):
+        s, _ = oracle_lib.step(d, s, nets)
+        assert oracle_lib.mass(s.E, s.I) == m0
+        assert (s.E >= 0).all() and (s.I >= 0).all()
+
+
+def test_translation_invariance(oracle_lib):
+    d, s, params = tiny_world(oracle_lib, 12, 10, hidden=8, seed=7, scale=2.0)
+    nets = oracle_lib.nets_for(d, params)
+    out, _ = oracle_lib.step(d, s, nets)
+    for dx, dy in [(1, 0), (0, 1), (5, 3), (11, 9)]:
+        roll = lambda a: np.roll(a, (dy, dx), axis=(-2, -1))
+        rs = oracle_lib.State(roll(s.E), roll(s.I), roll(s.C), roll(s.G), roll(s.R))
+        ro, _ = oracle_lib.step(d, rs, nets)
+        for a, b in [(ro.E, out.E), (ro.I, out.I), (ro.C, out.C), (ro.G, out.G), (ro.R, out.R)]:
+            np.testing.assert_array_equal(a, roll(b))
+
+
+def test_rotation_covariance(oracle_lib):
+    """Rotating the grid 90 degrees counter-clockwise and every rotation by +2
+    commutes with the step (explorer ties aside; random states have none)."""
+    d, s, params = tiny_world(oracle_lib, 9, 7, hidden=8, seed=9, scale=2.0)
+    nets = oracle_lib.nets_for(d, params)
+    out, info = oracle_lib.step(d, s, nets, want_margins=True)
+    # exact explorer ties only matter where they decide a takeover
+    tied = (info["margins"][..., 2] == 0) & (out.G != s.G)
+    assert not tied.any() and info["takeovers"] > 0
+    rot = lambda a: np.rot90(a, 1, axes=(-2, -1)).copy()
+    rs = oracle_lib.State(rot(s.E), rot(s.I), rot(s.C), rot(s.G), ((rot(s.R) + 2) % 8).astype(np.uint8))
+    dr = oracle_lib.Desc(d.height, d.width, d.n_weight_layers, d.hidden)
+    ro, _ = oracle_lib.step(dr, rs, nets)
+    np.testing.assert_array_equal(ro.E, rot(out.E))
+    np.testing.assert_array_equal(ro.I, rot(out.I))
+    np.testing.assert_array_equal(ro.G, rot(out.G))
+    np.testing.assert_array_equal(ro.R, (rot(out.R) + 2) % 8)
+    np.testing.assert_array_equal(ro.C, rot(out.C))
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_uniform_logit_genome_closed_form(oracle_lib):
+    """B = 0 makes every weight and bias 0, so a = 0: sigma = 1/2, softmax = 1/8,
+    explore = position 1 = the cell's own rotation.  The step is then an
+    8-neighbour diffusion of floor(F/8) written with np.roll."""
+    rng = np.random.default_rng(2)
+    W, H = 10, 8
+    E = wl.to_ledger(rng.random((H, W)))
+    I = wl.to_ledger(rng.random((H, W)) ** 4 * (rng.random((H, W)) < 0.5) * 3)
+    R = rng.integers(0, 8, (H, W)).astype(np.uint8)
+    G = rng.integers(0, 2, (H, W)).astype(np.int32)
+    s = oracle_lib.State(E, I, rng.random((4, H, W)), G, R)
+    d = oracle_lib.Desc(W, H, 2, 32)
+    params = rng.standard_normal((2, 56))
+    params[:, 40:] = 0.0
+    out, _ = oracle_lib.step(d, s, oracle_lib.nets_for(d, params))
+
+    rho = d.rho_invest
+    x_inv = np.floor(rho * 0.5 * E.astype(np.float64)).astype(np.int64)
+    x_liq = np.floor(rho * 0.5 * I.astype(np.float64)).astype(np.int64)
+    E1, I1 = E - x_inv + x_liq, I + x_inv - x_liq
+    F = np.floor(0.25 * I1.astype(np.float64)).astype(np.int64)
+    f = F // 8
+    vec = [(1, 0), (1, -1), (0, -1), (-1, -1), (-1, 0), (-1, 1), (0, 1), (1, 1)]
+    # neighbour at direction d of cell (y, x) seen from the target: roll by -vec
+    nb = lambda a, dd: np.roll(a, (-vec[dd][1], -vec[dd][0]), axis=(0, 1))
+    I2 = I1 - 8 * f + sum(nb(f, dd) for dd in range(8))
+    best = np.full((H, W), -1, np.int64)
+    bestg, bestr = G.copy(), R.copy()
+    for dd in range(8):
+        cand = (nb(R.astype(np.int64), dd) == (dd + 4) % 8)
+        v = np.where(cand, nb(f, dd), -1)
+        upd = v > best
+        best = np.where(upd, v, best)
+        bestg = np.where(upd, nb(G, dd), bestg)
+        bestr = np.where(upd, (dd + 4) % 8, bestr)
+    take = (best >= 0) & (best > I1)
+    G2 = np.where(take, bestg, G)
+    R2 = np.where(take, bestr, R)
+    np.testing.assert_array_equal(out.E, E1)
+    np.testing.assert_array_equal(out.I, I2)
+    np.testing.assert_array_equal(out.G, G2)
+    np.testing.assert_array_equal(out.R, R2)
+    np.testing.assert_array_equal(out.C, 0.5)
+    assert take.sum() > 0
+
+
+def test_one_by_one_world(oracle_lib):
+    """Every direction aliases to the cell itself: all flow returns, no takeover."""
+    for seed in range(5):
+        d, s, params = tiny_world(oracle_lib, 1, 1, seed=seed, scale=3.0)
+        out, info = oracle_lib.step(d, s, oracle_lib.nets_for(d, params), want_records=True)
+        rec = info["records"][0, 0]
+        assert out.I[0, 0] == rec["i1"] and out.E[0, 0] == rec["e1"]
+        assert out.E[0, 0] + out.I[0, 0] == s.E[0, 0] + s.I[0, 0]
+        assert out.G[0, 0] == s.G[0, 0] and out.R[0, 0] == s.R[0, 0]
+        assert info["takeovers"] == 0
+
+
+def test_zero_mass_world(oracle_lib):
+    d, s, params = tiny_world(oracle_lib, 6, 5, seed=2)
+    s.E[:] = 0
+    s.I[:] = 0
+    nets = oracle_lib.nets_for(d, params)
+    out, info = oracle_lib.step(d, s, nets, want_act=True)
+    assert (out.E == 0).all() and (out.I == 0).all()
+    np.testing.assert_array_equal(out.G, s.G)
+    np.testing.assert_array_equal(out.R, s.R)
+    a = info["act"]
+    np.testing.assert_allclose(np.moveaxis(out.C, 0, -1), 1 / (1 + np.exp(-a[..., 2:6])),
+                               rtol=1e-15)
+
+
+def test_actuation_by_hand(oracle_lib):
+    """Records for a 1x1 world with hand-set weights: only biases, so a = b."""
+    d = oracle_lib.Desc(1, 1, 2, 8)
+    net = np.zeros(oracle_lib.net_size(d))
+    bias = np.array([0.0, 2.0, -1.0, 0.0, 1.0, 3.0, 0.5, 2.5, 2.5, -1.0, 0.0, 1.0, 0.0, 0.0])
+    net[-14:] = bias
+    E = 1_000_003
+    I = 2_000_005
+    s = oracle_lib.State(np.array([[E]], np.int64), np.array([[I]], np.int64),
+                         np.zeros((4, 1, 1)), np.zeros((1, 1), np.int32),
+                         np.array([[5]], np.uint8))
+    out, info = oracle_lib.step(d, s, net[None], want_records=True)
+    rec = info["records"][0, 0]
+    sg = lambda x: 1 / (1 + math.exp(-x))
+    x_inv = math.floor(d.rho_invest * sg(0.0) * E)
+    x_liq = math.floor(d.rho_liquidate * sg(2.0) * I)
+    assert rec["e1"] == E - x_inv + x_liq and rec["i1"] == I + x_inv - x_liq
+    F = math.floor(0.25 * rec["i1"])
+    lg = bias[6:]
+    w = np.exp(lg - lg.max())
+    w /= w.sum()
+    used, flows = 0, []
+    for p in range(8):
+        f = min(math.floor(w[p] * F), F - used)
+        used += f
+        flows.append(f)
+    order = bf.kernel_order(5)
+    for p in range(8):
+        assert rec["flow"][order[p]] == flows[p]
+    assert rec["explore_pos"] == 2            # logits 2.5 at p=2 and p=3: lowest wins
+    assert rec["explore_dir"] == order[1]
+    np.testing.assert_allclose(out.C.ravel(), [sg(-1.0), sg(0.0), sg(1.0), sg(3.0)], rtol=1e-15)
+
+
+# ---------------------------------------------------------------- physics from records
+
+def test_physics_from_records_matches_step(oracle_lib):
+    d, s, params = tiny_world(oracle_lib, 7, 6, seed=8, scale=2.0)
+    nets = oracle_lib.nets_for(d, params)
+    out, info = oracle_lib.step(d, s, nets, want_records=True)
+    rec = info["records"].ravel()
+    I2, G2, R2, tk = oracle_lib.physics_from_records(d, rec["i1"], rec["flow"],
+                                                     rec["explore_dir"], s.G, s.R)
+    np.testing.assert_array_equal(I2, out.I)
+    np.testing.assert_array_equal(G2, out.G)
+    np.testing.assert_array_equal(R2, out.R)
+    assert tk == info["takeovers"]
+
+
+def test_physics_push_view_conserves(oracle_lib):
+    """Random records: the pull-form physics equals a push-form scatter."""
+    rng = np.random.default_rng(4)
+    W, H = 9, 5
+    d = oracle_lib.Desc(W, H)
+    N = W * H
+    i1 = rng.integers(0, 1 << 30, N)
+    flow = rng.integers(0, 1 << 26, (N, 8))
+    ed = rng.integers(0, 8, N)
+    G = rng.integers(0, 5, (H, W)).astype(np.int32)
+    R = rng.integers(0, 8, (H, W)).astype(np.uint8)
+    I2, G2, R2, _ = oracle_lib.physics_from_records(d, i1, flow, ed, G, R)
+    push = i1 - flow.sum(1)
+    vec = [(1, 0), (1, -1), (0, -1), (-1, -1), (-1, 0), (-1, 1), (0, 1), (1, 1)]
+    for i in range(N):
+        x, y = i % W, i // W
+        for k in range(8):
+            j = ((y + vec[k][1]) % H) * W + (x + vec[k][0]) % W
+            push[j] += flow[i, k]
+    np.testing.assert_array_equal(I2.ravel(), push)
+    assert I2.sum() == i1.sum()
+
+
+# ---------------------------------------------------------------- buckets
+
+@pytest.mark.parametrize("n,cap", [(0, 4), (1, 1), (1000, 7), (4096, 300)])
+def test_buckets_against_numpy(oracle_lib, n, cap):
+    rng = np.random.default_rng(n)
+    G = rng.integers(0, cap, n).astype(np.int32)
+    counts, offsets, perm = oracle_lib.buckets(G, cap)
+    np.testing.assert_array_equal(counts, np.bincount(G, minlength=cap))
+    np.testing.assert_array_equal(offsets, np.concatenate([[0], np.cumsum(counts)]))
+    np.testing.assert_array_equal(perm, np.argsort(G, kind="stable"))
+
+
+# ---------------------------------------------------------------- Philox / radiation draws
+
+def _numpy_block(counter, key):
+    """numpy's Philox4x64-10 increments its 256-bit counter before drawing."""
+    v = sum(int(x) << (64 * k) for k, x in enumerate(counter))
+    v = (v - 1) % (1 << 256)
+    c = [(v >> (64 * k)) & ((1 << 64) - 1) for k in range(4)]
+    g = np.random.Philox(key=np.array(key, np.uint64), counter=np.array(c, np.uint64))
+    return g.random_raw(4)
+
+
+def test_philox_against_numpy(oracle_lib):
+    rng = np.random.default_rng(0)
+    cases = [((0, 0, 0, 0), (0, 0)), ((1, 0, 0, 0), (0, 0)), ((0, 1, 0, 0), (7, 0)),
+             ((12345, 99, 3, 0), (2 ** 64 - 1, 0))]
+    for _ in range(20):
+        cases.append((tuple(int(v) for v in rng.integers(0, 2 ** 63, 4, dtype=np.int64)),
+                      (int(rng.integers(0, 2 ** 63)), 0)))
+    for ctr, key in cases:
+        np.testing.assert_array_equal(oracle_lib.philox(ctr, key), _numpy_block(ctr, key))
+
+
+def test_uniforms_exact_and_open_interval(oracle_lib):
+    for o in [0, 1, (1 << 41) - 1, 1 << 41, (1 << 64) - 1, 0x123456789ABCDEF0]:
+        u = oracle_lib.uniform(o)
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u                  # exact in FP32
+        assert u == (2 * (o >> 41) + 1) / 2.0 ** 24
+
+
+def test_mutation_normals_are_box_muller_of_the_blocks(oracle_lib):
+    seed, i, s = 77, 1234, 9
+    z = oracle_lib.mutation_normals(seed, i, s)
+    for b in range(14):
+        o = _numpy_block((i, s, 1 + b, 0), (seed, 0))
+        u = [(2 * (int(v) >> 41) + 1) / 2.0 ** 24 for v in o]
+        for h in range(2):
+            r = math.sqrt(-2 * math.log(u[2 * h]))
+            assert z[4 * b + 2 * h] == pytest.approx(r * math.cos(2 * math.pi * u[2 * h + 1]), abs=1e-15)
+            assert z[4 * b + 2 * h + 1] == pytest.approx(r * math.sin(2 * math.pi * u[2 * h + 1]), abs=1e-15)
+
+
+def test_mutation_normals_distribution(oracle_lib):
+    from scipy import stats
+    z = np.concatenate([oracle_lib.mutation_normals(3, i, 1) for i in range(4000)])
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 1) < 0.02
+
+
+def test_hit_threshold(oracle_lib):
+    assert oracle_lib.hit_threshold(0.0) == 0
+    assert oracle_lib.hit_threshold(1e-4) == math.floor(1e-4 * 2.0 ** 64)
+    assert oracle_lib.hit_threshold(0.5) == 1 << 63
+    assert oracle_lib.hit_threshold(1.0) == 2 ** 64 - 1
+
+
+def test_radiate_against_bruteforce(oracle_lib):
+    """Hit set from numpy Philox; slot assignment and parameters re-derived."""
+    rng = np.random.default_rng(6)
+    W, H, cap = 40, 30, 20
+    G = rng.integers(0, 8, (H, W)).astype(np.int32)
+    G[G == 5] = 4                       # leave a hole below the highest id
+    params = np.zeros((cap, 56))
+    params[:8] = rng.standard_normal((8, 56))
+    seed, s, rate, sigma = 42, 17, 0.02, 0.1
+    G2, P2, (hc, hs), dropped = oracle_lib.radiate(G, cap, params, seed, s, rate, sigma)
+    T = math.floor(rate * 2.0 ** 64)
+    hits = [i for i in range(W * H) if int(_numpy_block((i, s, 0, 0), (seed, 0))[0]) < T]
+    free = [g for g in range(cap) if g not in set(G.ravel().tolist())]
+    assert hc.tolist() == hits
+    assert len(hits) > len(free)        # capacity exhaustion exercised
+    assert dropped == len(hits) - len(free)
+    Gf = G.ravel().copy()
+    for k, i in enumerate(hits):
+        if k < len(free):
+            assert hs[k] == free[k]
+            z = oracle_lib.mutation_normals(seed, i, s)
+            np.testing.assert_allclose(P2[free[k]], params[Gf[i]] + sigma * z, rtol=0, atol=1e-15)
+            Gf[i] = free[k]
+        else:
+            assert hs[k] == -1
+    np.testing.assert_array_equal(G2.ravel(), Gf)
+
+
+def test_hit_counts_binomial(oracle_lib):
+    """Hits per call follow Binomial(N, rate): one draw per cell."""
+    W = H = 200
+    G = np.zeros((H, W), np.int32)
+    counts = []
+    for s in range(1, 9):
+        _, _, (hc, _), _ = oracle_lib.radiate(G, 2, np.zeros((2, 56)), 5, s, 0.01, 0.1)
+        counts.append(len(hc))
+    n, p = W * H, 0.01
+    mean = np.mean(counts)
+    assert abs(mean - n * p) < 4 * math.sqrt(n * p * (1 - p) / len(counts))
