@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the per-step ecosystem update on one MI355X.
+
+Workload: the 4096x4096 periodic world with 4096 Zipf(s=1.1) genomes over
+65536 Voronoi patches, 54-64-64-14 networks, radiation 1e-4 per cell per
+step with sigma 0.1.  One step = one whole pass of the hot path: genome
+bucketing, sense + network (grouped GEMM on MFMA) + actuator epilogue,
+exploration/takeover physics with the FP64 + int64 mass reduction, then
+radiation (Philox hits, slot assignment, CPPN weight regeneration).  Inputs
+are resident in HBM before timing starts.
+
+value = cell-updates/s with BF16 networks (FP32 accumulation); the FP32
+network form is measured on the same input and reported beside it.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/sec at 4096² (FP32 vs BF16); p50/p99 step latency under serving load"
+PEAK_HBM = 8.0e12            # bytes/s
+PEAK_BF16 = 2.5e15           # dense MFMA FLOP/s
+PEAK_FP32 = 157.3e12         # FLOP/s
+# transcendental ops/s: 256 CUs x 4 SIMDs x 4 lanes/clock (quarter rate) x 2.4 GHz
+PEAK_TRANS = 256 * 4 * 4 * 2.4e9
+RATE, SIGMA = 1e-4, 0.1
+
+
+def flops_per_cell(hidden: int, layers: int) -> int:
+    widths = [54] + [hidden] * (layers - 1) + [14]
+    return 2 * sum(widths[k] * widths[k + 1] for k in range(layers))
+
+
+def trans_per_cell(hidden: int, layers: int) -> int:
+    # tanh = exp + reciprocal per hidden unit; 6 sigmoids (exp + reciprocal);
+    # 8 softmax exponentials and one reciprocal of their sum
+    return 2 * hidden * (layers - 1) + 2 * 6 + 8 + 1
+
+
+def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bool):
+    import torch
+
+    from paper_2406_09654_amd.world import World
+
+    w = World.from_init(init, stream=stream, precision=precision)
+    tuning = w.autotune() if autotune else None
+    step_index = 0
+    for _ in range(warmup):
+        w.step(1)
+        step_index += 1
+        w.radiate(RATE, SIGMA, step_index, stats=False)
+    w.sync()
+    w.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w.step(1)
+        step_index += 1
+        w.radiate(RATE, SIGMA, step_index, stats=False)
+    w.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = w.profile()
+    st = w.stats()
+    w.set_profiling(False)
+    w.close()
+    del w
+    torch.cuda.empty_cache()
+    N = init.spec.width * init.spec.height
+    elapsed = t1 - t0
+    return {
+        "value": N * steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "phase_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
+        "stats": st,
+        "tuning": tuning,
+    }
+
+
+def cpu_baseline(init, target_s: float = 12.0):
+    """The FP64 oracle (as it stands) on a band of rows of the same state."""
+    import numpy as np
+
+    import oracle
+
+    d = oracle.Desc.from_spec(init.spec)
+    s = oracle.State.from_init(init)
+    H = init.spec.height
+    rows = 16
+    nets = np.zeros((init.params.shape[0], oracle.net_size(d)))
+    have = set()
+    while True:
+        need = np.unique(init.G[max(0, H // 2 - rows // 2 - 1): H // 2 + rows // 2 + 1])
+        for g in need:
+            if int(g) not in have:
+                nets[g] = oracle.cppn_to_net(d, init.params[g].astype(np.float64))
+                have.add(int(g))
+        y0 = H // 2 - rows // 2
+        t0 = time.perf_counter()
+        oracle.step(d, s, nets, rows=(y0, y0 + rows))
+        dt = time.perf_counter() - t0
+        if dt >= target_s or rows >= H // 2:
+            break
+        rows = min(H // 2, max(rows * 2, int(rows * target_s / max(dt, 1e-3) * 1.1)))
+    cells = rows * init.spec.width
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle step (sense, network, actuation, physics) on %d full rows "
+                      "(%d cells) of the same 4096x4096 state, %.1f s; radiation not included"
+                      % (rows, cells, dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=4096, help="grid side (4096 = the named workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--bf16-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    side = args.size
+    patches = max(1, 65536 * side * side // (4096 * 4096))
+    print("[bench] generating %dx%d workload" % (side, side), file=sys.stderr, flush=True)
+    init = wl.config_zipf_4096(precision=1, width=side, height=side, n_patches=patches)
+    stream = torch.cuda.Stream()
+    N = side * side
+    hidden, layers = init.spec.hidden, init.spec.n_weight_layers
+
+    forms = {}
+    for prec, name in ([(1, "bf16")] if args.bf16_only else [(1, "bf16"), (0, "fp32")]):
+        print("[bench] %s: warmup %d, timed %d steps" % (name, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        forms[name] = run_form(init, prec, args.steps, args.warmup, stream, not args.no_autotune)
+        print("[bench] %s: %.3e cell-updates/s, %.3f ms/step, phases %s" % (
+            name, forms[name]["value"], forms[name]["ms_per_step"], forms[name]["phase_ms"]),
+            file=sys.stderr, flush=True)
+
+    bf = forms["bf16"]
+    act_ms = bf["phase_ms"]["act"]
+    trans = trans_per_cell(hidden, layers) * N
+    roof = {"kernel": "k_act (sense + grouped MLP + epilogue)", "bound": "alu",
+            "achieved": trans / (act_ms * 1e-3), "peak": PEAK_TRANS,
+            "unit": "transcendental op/s", "frac": trans / (act_ms * 1e-3) / PEAK_TRANS,
+            "traffic": None,
+            "per_unit": "%d transcendental ops per cell (tanh, sigmoid, softmax), %d cells per launch"
+                        % (trans_per_cell(hidden, layers), N),
+            "mfma_frac_bf16": flops_per_cell(hidden, layers) * N / (act_ms * 1e-3) / PEAK_BF16}
+    out = {
+        "metric": METRIC,
+        "value": bf["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": bf["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "%dx%d periodic world, 4096 Zipf(1.1) genomes over %d Voronoi "
+                               "patches, 54-64-64-14 networks (BF16 MFMA, FP32 accumulate), "
+                               "int64 ledger physics, radiation 1e-4/cell/step sigma 0.1"
+                               % (side, side, patches),
+                   "cells": N, "genomes": 4096, "network": "54-64-64-14"},
+        "roofline": roof,
+        "phase_ms_per_step": bf["phase_ms"],
+        "tuning": bf["tuning"],
+    }
+    if "fp32" in forms:
+        f = forms["fp32"]
+        fa = f["phase_ms"]["act"]
+        fl = flops_per_cell(hidden, layers) * N
+        out["fp32"] = {"value": f["value"], "ms_per_step": f["ms_per_step"],
+                       "phase_ms_per_step": f["phase_ms"], "tuning": f["tuning"],
+                       "roofline": {"kernel": "k_act", "bound": "mfma", "achieved": fl / (fa * 1e-3) / 1e12,
+                                    "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                                    "frac": fl / (fa * 1e-3) / PEAK_FP32, "traffic": None}}
+        out["bf16_over_fp32"] = bf["value"] / f["value"]
+    phys_ms = bf["phase_ms"]["physics"]
+    out["physics_roofline"] = {"bound": "hbm", "achieved": 59 * N / (phys_ms * 1e-3) / 1e9,
+                               "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                               "frac": 59 * N / (phys_ms * 1e-3) / PEAK_HBM,
+                               "per_unit": "59 B per cell"}
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(init)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,215 @@
+/*
+ * coralai.h -- C ABI of the MI355X (gfx950) per-step ecosystem update of
+ * Coralai (Barbieux & Canaan, "Coralai: Intrinsic Evolution of Embodied
+ * Neural Cellular Automata Ecosystems", ALIFE 2024).
+ *
+ * The operation (System Design): every cell of a W x H substrate gathers the
+ * Kernel neighbourhood of its Sensor channels, runs the dense network that
+ * its integer GenomeIndex selects -- weights and biases generated per genome
+ * by a CPPN, HyperNEAT style -- and the Physics turns the Actuator outputs
+ * into substrate change (Experiment: invest / liquidate, sigmoid
+ * communication, exploration with takeover).  Radiation mutates CPPN genomes
+ * and regenerates their weights (Fig. 1, panel C).
+ *
+ * Substrate representation (row-major, cell index i = y*W + x, y pointing
+ * down, periodic in both axes):
+ *   E, I   int64  mass ledger in quanta of 2^-24 mass units (energy,
+ *                 infrastructure); sum(E+I) is conserved exactly by a step;
+ *   C      float  4 communication planes, plane c at offset c*W*H;
+ *   G      int32  GenomeIndex, a slot id in [0, genome_capacity);
+ *   R      uint8  Rotation in 0..7 (multiples of 45 degrees counter-clockwise
+ *                 from +x).
+ * CPPN parameters: 56 floats per genome, A (8x5 row-major) then B (2x8).
+ *
+ * Conventions for every entry point:
+ *   - returns CORALAI_OK (0) or a negative CORALAI_E_* code; the message of
+ *     the last failure on the calling thread is coralai_last_error();
+ *   - host pointers are borrowed for the duration of the call only;
+ *   - device pointers are HIP device addresses on the world's device;
+ *   - work is enqueued on the stream given at creation; a call that returns
+ *     data to the host (stats, get_*) waits for that stream;
+ *   - a world is used by one thread at a time; a concurrent call on the same
+ *     world returns CORALAI_E_BUSY;
+ *   - device-side faults in the data (genome id out of range or naming a
+ *     slot with no parameters, ledger overflow, non-finite network output)
+ *     set bits of an error word that the next call returning stats reports
+ *     as CORALAI_E_GENOME / CORALAI_E_NUMERIC (and then clears).
+ */
+#ifndef CORALAI_H
+#define CORALAI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct coralai_world coralai_world; /* opaque; owns no device memory */
+typedef struct coralai_batch coralai_batch; /* opaque; owns no device memory */
+
+enum { CORALAI_FP32 = 0, CORALAI_BF16 = 1 };
+
+enum {
+    CORALAI_OK = 0,
+    CORALAI_E_INVALID = -1, /* bad argument; nothing was enqueued */
+    CORALAI_E_NOMEM = -2,   /* arena smaller than coralai_world_bytes() */
+    CORALAI_E_GENOME = -3,  /* a cell named an out-of-range or unset genome slot */
+    CORALAI_E_NUMERIC = -4, /* non-finite network output or ledger overflow */
+    CORALAI_E_HIP = -5,     /* a HIP runtime call failed */
+    CORALAI_E_BUSY = -6     /* the world is in use by another thread */
+};
+
+/* Bits of coralai_stats.error_word. */
+enum {
+    CORALAI_ERR_GENOME_RANGE = 1u,
+    CORALAI_ERR_GENOME_UNSET = 2u,
+    CORALAI_ERR_LEDGER = 4u,    /* negative stock or a flow budget >= 2^32 quanta */
+    CORALAI_ERR_NONFINITE = 8u  /* network output or CPPN weight not finite */
+};
+
+/* World description.  The physics constants are the recorded readings of
+ * the Experiment section (which names the actuators but not their rates):
+ * invest / liquidate move floor(rho * sigmoid(a) * stock) quanta, the
+ * exploration budget is floor(kappa * I1) quanta. */
+typedef struct {
+    int32_t width, height;    /* >= 1 each; W*H <= 2^30 */
+    int32_t n_weight_layers;  /* 2: 54-h-14, 3: 54-h-h-14 */
+    int32_t hidden;           /* 32 or 64 */
+    int32_t genome_capacity;  /* slot ids in [0, capacity), 1 .. 2^22 */
+    int32_t precision;        /* CORALAI_FP32 or CORALAI_BF16 (network GEMMs only) */
+    uint64_t seed;            /* Philox key word 0 for radiation */
+    float rho_invest;         /* default 0.1 */
+    float rho_liquidate;      /* default 0.1 */
+    float kappa_flow;         /* default 0.25 */
+    int32_t reserved;         /* must be 0 */
+} coralai_world_desc;
+
+/* Per-world statistics, as of the last completed step or radiation call. */
+typedef struct {
+    int64_t mass_quanta;     /* exact sum(E+I) after the last step */
+    double mass_fp64;        /* the same sum reduced in FP64 on the GPU */
+    int64_t steps;           /* steps completed since creation */
+    int32_t live_genomes;    /* distinct genomes in the state the last step read */
+    int32_t takeovers;       /* cells that changed genome in the last step */
+    int32_t hits;            /* radiation hits in the last radiate call */
+    int32_t dropped_hits;    /* hits that found no free slot */
+    uint32_t error_word;     /* CORALAI_ERR_* bits since the last report */
+    int32_t reserved;
+} coralai_stats;
+
+/* HBM bytes a world of this description needs (0 if the description is
+ * invalid).  Used for admission by footprint. */
+size_t coralai_world_bytes(const coralai_world_desc* desc);
+
+/* Create a world inside a caller-owned device arena of at least
+ * coralai_world_bytes(desc) bytes (any alignment is accepted; the library
+ * aligns internally).  hip_stream is a hipStream_t (NULL = default stream).
+ * The state is zeroed, no genome slot is set.  The arena must outlive the
+ * world; destroy frees only the host handle. */
+int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t arena_bytes,
+                         void* hip_stream, coralai_world** out);
+int coralai_world_destroy(coralai_world* w);
+
+/* Copy a whole state in (set) or out (get).  Arrays as described above, each
+ * of W*H elements (comm4: 4*W*H).  on_device = 1: the pointers are device
+ * addresses (copied device-to-device); 0: host memory.  Rotation values are
+ * taken mod 8; genome ids are checked at the next step. */
+int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, const float* comm4,
+                      const int32_t* genome, const uint8_t* rotation, int on_device);
+int coralai_get_state(coralai_world* w, int64_t* e_q, int64_t* i_q, float* comm4,
+                      int32_t* genome, uint8_t* rotation, int on_device);
+
+/* HyperNEAT (System Design): store n genomes' CPPN parameters (host, n x 56
+ * floats) in slots slot_ids[0..n) and generate each one's dense network on
+ * the GPU: W_l[o][j] = CPPN_w(x_{l,j}, y_l, x_{l+1,o}, y_{l+1}) / sqrt(L_l),
+ * b_l[o] = CPPN_b(0, y_l, x_{l+1,o}, y_{l+1}), neuron j of layer l at
+ * x = -1 + 2j/(L_l - 1), y_l = -1 + 2l/n_weight_layers.  Marks the slots set.
+ * Returns after the weights are generated. */
+int coralai_set_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids,
+                        const float* cppn_params);
+int coralai_get_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids,
+                        float* cppn_params_out);
+
+/* n_steps updates (System Design; Fig. 1 A and B): bucket cells by genome,
+ * sense the rotation-ordered 3x3 Moore kernel, run the genome's network,
+ * apply invest / liquidate / communication / exploration, then the
+ * exploration-and-takeover physics, and reduce the total mass.  Asynchronous
+ * when out is NULL; otherwise waits and fills *out. */
+int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out);
+
+/* Radiation after step step_index (Fig. 1 C): cell i is hit when the first
+ * word of Philox4x64-10(counter (i, step_index, 0, 0), key (seed, 0)) is
+ * below floor(rate * 2^64); the k-th hit in ascending i takes the k-th free
+ * slot (ascending slot ids whose genome count is zero), whose CPPN
+ * parameters become the parent's plus sigma * N(0,1) (Box-Muller on Philox
+ * blocks (i, step_index, 1+b, 0), b = 0..13) and whose network is
+ * regenerated; G[i] becomes that slot.  Hits beyond the free slots are
+ * dropped and counted.  rate in [0, 1], sigma >= 0.  Waits when out != NULL. */
+int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_index,
+                    coralai_stats* out);
+
+/* Wait for the world's stream; report (and clear) device error bits. */
+int coralai_sync(coralai_world* w);
+int coralai_get_stats(coralai_world* w, coralai_stats* out);
+
+/* Batched form: many worlds advanced together by one captured HIP graph of
+ * persistent kernels over a device-side world table.  All worlds of a batch
+ * share one device, one network shape (layers, hidden) and one precision;
+ * the batch's stream is used for the whole step.  The table holds up to
+ * max_worlds entries; set_worlds may change the set between steps without a
+ * new graph.  The batch's arena (coralai_batch_bytes) is caller-owned. */
+size_t coralai_batch_bytes(int32_t max_worlds);
+int coralai_batch_create(int32_t max_worlds, void* dev_arena, size_t arena_bytes,
+                         void* hip_stream, coralai_batch** out);
+int coralai_batch_set_worlds(coralai_batch* b, coralai_world* const* worlds, int32_t n);
+int coralai_batch_step(coralai_batch* b, int32_t n_steps);
+int coralai_batch_sync(coralai_batch* b);
+int coralai_batch_destroy(coralai_batch* b);
+
+/* Launch tuning.  coralai_autotune times the candidate configurations on the
+ * world's current state (without advancing it) and keeps the fastest;
+ * coralai_set_tuning forces one (act_cells: column groups of 16 cells
+ * processed together, 1, 2 or 4; phys_tile: 0 = 64x4, 1 = 32x8, 2 = 16x16). */
+int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* phys_tile_out);
+int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t phys_tile);
+
+/* Live phase timing.  While profiling is on, coralai_step and coralai_radiate
+ * launch their kernels directly (no graph) with HIP events recorded on the
+ * world's stream between the phases; coralai_get_profile waits for the
+ * stream and returns, per phase, the summed milliseconds and the number of
+ * timed launches since profiling was switched on.  Phases:
+ * 0 bucketing (histogram, scans, compaction), 1 sense+act (network),
+ * 2 physics, 3 step finalisation, 4 radiation (incl. weight regeneration). */
+enum { CORALAI_PHASES = 5 };
+int coralai_set_profiling(coralai_world* w, int on);
+int coralai_get_profile(coralai_world* w, double* ms_sum, int64_t* launches);
+
+const char* coralai_last_error(void);
+const char* coralai_version(void);
+
+/* Parity hooks (tests).  All wait for the stream.
+ *  debug_buckets:   genome counts [capacity], exclusive offsets [capacity+1]
+ *                   and the bucket order perm [W*H] of the current state
+ *                   (cells grouped by genome; order inside a genome is not
+ *                   specified);
+ *  debug_actuators: raw network outputs [W*H x 14] for the current state;
+ *  debug_set_weights / debug_get_weights: one slot's network in the flat
+ *                   layout [W_0 (h x 54) row-major, b_0, W_1, b_1, ...] as
+ *                   float; set marks the slot set;
+ *  debug_physics:   run the physics alone from given records -- I1 [W*H]
+ *                   int64, flows [W*H x 8] uint32 toward absolute directions
+ *                   0..7, explore direction [W*H] uint8 -- on the current G,
+ *                   R; the result becomes the current state with E and C
+ *                   unchanged. */
+int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, int32_t* perm);
+int coralai_debug_actuators(coralai_world* w, float* act);
+int coralai_debug_set_weights(coralai_world* w, int32_t slot, const float* flat);
+int coralai_debug_get_weights(coralai_world* w, int32_t slot, float* flat);
+int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* flows8,
+                          const uint8_t* explore_dir);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CORALAI_H */

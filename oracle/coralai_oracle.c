@@ -54,6 +54,8 @@ typedef struct {
     int32_t explore_dir;   /* absolute direction of the argmax explore */
     int32_t explore_pos;   /* kernel position p* in 1..8 */
     double logit_gap;      /* top-1 minus top-2 flow logit (FP64) */
+    int32_t runner_dir;    /* absolute direction of the second-largest logit */
+    int32_t pad;
 } orc_record;
 
 /* Directions: d at 45*d degrees counter-clockwise from +x, y pointing down. */
@@ -220,9 +222,12 @@ void orc_actuate(const orc_desc* d, int64_t e, int64_t i, int r, const double* a
     for (int k = 1; k < 8; ++k)
         if (lg[k] > m) { m = lg[k]; best = k; }
     double second = -INFINITY;
+    int runner = best == 0 ? 1 : 0;
     for (int k = 0; k < 8; ++k)
-        if (k != best && lg[k] > second) second = lg[k];
+        if (k != best && lg[k] > second) { second = lg[k]; runner = k; }
     rec->logit_gap = m - second;
+    rec->runner_dir = orc_kernel_dir(r, runner + 1);
+    rec->pad = 0;
     double ex[8], s = 0.0;
     for (int k = 0; k < 8; ++k) { ex[k] = exp(lg[k] - m); s += ex[k]; }
     int64_t F = (int64_t)floor(d->kappa_flow * (double)rec->i1);
@@ -257,11 +262,13 @@ static void cell_record(const orc_desc* d, const int64_t* E, const int64_t* I, c
  * maximal investment wins (lowest d on ties) and takes the cell over when it
  * strictly exceeds I1(t), t adopting n's genome and the exploration
  * direction as its rotation.  E2 = E1.  Returns the takeover flag and the
- * decision margins (FP64 quanta) used by the near-tie protocol. */
+ * decision margins used by the near-tie protocol: |v_win - I1(t)| and, when
+ * the winner takes over, v_win - v_second (both in quanta), and the size
+ * max(v_win, I1(t)) they are measured against. */
 static int cell_physics(const orc_desc* d, const orc_record* rec_t, const orc_record* const nrec[8],
                         const int32_t* G, const uint8_t* R, const int64_t nidx[8], int64_t t,
                         int64_t* i2, int32_t* g2, uint8_t* r2, double* margin_take,
-                        double* margin_rank) {
+                        double* margin_rank, double* magnitude) {
     int64_t out = 0, in = 0;
     for (int k = 0; k < 8; ++k) out += rec_t->flow[k];
     int win = -1;
@@ -286,10 +293,12 @@ static int cell_physics(const orc_desc* d, const orc_record* rec_t, const orc_re
     *r2 = R[t];
     *margin_take = INFINITY;
     *margin_rank = INFINITY;
+    *magnitude = 0.0;
     int took = 0;
     if (win >= 0) {
         *margin_take = fabs((double)vbest - (double)rec_t->i1);
-        if (vsecond >= 0) *margin_rank = (double)(vbest - vsecond);
+        *magnitude = (double)(vbest > rec_t->i1 ? vbest : rec_t->i1);
+        if (vsecond >= 0 && vbest > rec_t->i1) *margin_rank = (double)(vbest - vsecond);
         if (vbest > rec_t->i1) {
             *g2 = G[nidx[win]];
             *r2 = (uint8_t)((win + 4) & 7);
@@ -305,8 +314,9 @@ static int cell_physics(const orc_desc* d, const orc_record* rec_t, const orc_re
  *   E2, I2 (int64), C2 (4 planes, double), G2, R2;
  *   act (N x 14, nullable): raw network outputs of the rows;
  *   rec_out (N, nullable): per-cell records of the rows;
- *   margins (N x 3, nullable): per target (min neighbour logit gap,
- *   |v_win - I1|, v_win - v_second).
+ *   margins (N x 4, nullable): per target (smallest flow-logit gap among the
+ *   neighbours whose top two explore directions include t, |v_win - I1|,
+ *   v_win - v_second when the winner takes over, max(v_win, I1)).
  * Returns the number of takeovers in the rows, or -1 on a bad genome id. */
 int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, const double* C,
                       const int32_t* G, const uint8_t* R, const double* nets, int32_t n_genomes,
@@ -336,21 +346,28 @@ int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, con
         int64_t y = (y0 + k / W) % H, x = k % W, t = y * W + x;
         int64_t nidx[8];
         const orc_record* nrec[8];
-        double gap = INFINITY; /* t's own argmax does not decide t's genome */
+        /* a neighbour's near-tied argmax matters to t only if one of its two
+         * leading explore directions points at t */
+        double gap = INFINITY;
         for (int dd = 0; dd < 8; ++dd) {
             nidx[dd] = nbr(d, t, dd);
             nrec[dd] = &rec[nidx[dd]];
-            if (nrec[dd]->logit_gap < gap) gap = nrec[dd]->logit_gap;
+            const int back = (dd + 4) & 7;
+            if ((nrec[dd]->explore_dir == back || nrec[dd]->runner_dir == back) &&
+                nrec[dd]->logit_gap < gap)
+                gap = nrec[dd]->logit_gap;
         }
-        double mt, mr;
-        takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt, &mr);
+        double mt, mr, mg;
+        takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt,
+                                  &mr, &mg);
         E2[t] = rec[t].e1;
         for (int c = 0; c < 4; ++c) C2[c * N + t] = cn[c * N + t];
         if (rec_out) rec_out[t] = rec[t];
         if (margins) {
-            margins[t * 3 + 0] = gap;
-            margins[t * 3 + 1] = mt;
-            margins[t * 3 + 2] = mr;
+            margins[t * 4 + 0] = gap;
+            margins[t * 4 + 1] = mt;
+            margins[t * 4 + 2] = mr;
+            margins[t * 4 + 3] = mg;
         }
     }
     free(rec);
@@ -372,6 +389,8 @@ int64_t orc_physics_from_records(const orc_desc* d, const int64_t* i1, const int
         rec[i].explore_dir = explore_dir[i];
         rec[i].explore_pos = 0;
         rec[i].logit_gap = 0;
+        rec[i].runner_dir = 0;
+        rec[i].pad = 0;
     }
     int64_t takeovers = 0;
     for (int64_t t = 0; t < N; ++t) {
@@ -381,8 +400,9 @@ int64_t orc_physics_from_records(const orc_desc* d, const int64_t* i1, const int
             nidx[dd] = nbr(d, t, dd);
             nrec[dd] = &rec[nidx[dd]];
         }
-        double mt, mr;
-        takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt, &mr);
+        double mt, mr, mg;
+        takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt,
+                                  &mr, &mg);
     }
     free(rec);
     return takeovers;

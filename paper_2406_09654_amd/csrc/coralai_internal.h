@@ -1,0 +1,222 @@
+// Internal structures of the gfx950 Coralai library: the device-resident
+// world table, the per-world control block, and small device helpers.
+// Everything here is plain data shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace coralai {
+
+constexpr int kNParam = 56;   // CPPN parameters: A (8x5) then B (2x8)
+constexpr int kNIn = 54;      // 9 kernel positions x 6 sensor channels
+constexpr int kNOut = 14;     // invest, liquidate, 4 comm, 8 flow logits
+constexpr int kGroupCells = 64;   // cells per network work unit (one wavefront)
+constexpr int kChunkCells = 64;   // cells per bucketing unit (one wavefront)
+constexpr int kRadBlockCells = 4096;  // cells per radiation hit block (256 x 16)
+constexpr int kPrecFP32 = 0;
+constexpr int kPrecBF16 = 1;
+
+constexpr uint32_t kErrGenomeRange = 1u, kErrGenomeUnset = 2u, kErrLedger = 4u,
+                   kErrNonFinite = 8u;
+
+// Per-world control block (device memory, inside the world's arena).
+struct Ctl {
+    int32_t cur;            // index (0/1) of the current state buffer
+    int32_t total_groups;   // network work units of this step
+    int32_t live;           // genomes with a nonzero count in the current state
+    int32_t n_free;         // free slots (radiation)
+    int32_t hits;           // radiation hits of the last call
+    int32_t n_new;          // hits that received a slot
+    int32_t dropped;        // hits beyond the free slots
+    uint32_t err;           // sticky CORALAI_ERR_* bits
+    int64_t acc_mass;       // step accumulators
+    double acc_mass_f64;
+    int64_t acc_takeovers;
+    int64_t mass;           // published after each step
+    double mass_f64;
+    int64_t steps;
+    int32_t takeovers;
+    int32_t live_pub;
+    int32_t hits_pub;
+    int32_t dropped_pub;
+};
+
+// One world as the kernels see it (device memory).  All planes are
+// row-major over the W x H torus.
+struct WorldDev {
+    int32_t W, H, N, cap;
+    int32_t NL, HID, prec, n_rad_blocks;
+    float rho_i, rho_l, kappa;
+    int32_t pad0;
+    uint64_t seed;
+    int64_t* E[2];
+    int64_t* I[2];
+    float* C[2];          // 4 planes each
+    int32_t* G[2];
+    uint8_t* R[2];
+    uint32_t* flow;       // 8 planes: outflow toward absolute direction k
+    int64_t* I1;          // infrastructure after invest / liquidate
+    uint8_t* X;           // explore direction
+    int32_t* perm;        // cells grouped by genome
+    int32_t* counts;      // [cap]
+    int32_t* offsets;     // [cap + 1]
+    int32_t* cursor;      // [cap]
+    int32_t* gofs;        // [cap + 1] exclusive prefix of network units per genome
+    uint8_t* slot_set;    // [cap]
+    float* params;        // [cap][56]
+    uint8_t* wfrag;       // [cap][wfrag_stride] weights in MFMA fragment order
+    float* bias;          // [cap][bias_stride]
+    int64_t wfrag_stride;
+    int32_t bias_stride;
+    int32_t pad1;
+    uint16_t* hit_bits;   // [n_rad_blocks * 256]
+    int32_t* blk_hits;    // [n_rad_blocks]
+    int32_t* blk_ofs;     // [n_rad_blocks + 1]
+    int32_t* free_list;   // [cap]
+    int32_t* new_slots;   // [cap]
+    int32_t* stage_slots; // [cap] slot list for set_genomes
+    float* stage_params;  // [cap][56]
+    Ctl* ctl;
+};
+
+// A batch of worlds sharing one launch sequence (device memory).
+struct BatchDev {
+    int32_t n_worlds;
+    int32_t pad;
+    WorldDev* worlds;         // [max_worlds]
+    int64_t* chunk_prefix;    // [max_worlds + 1] bucketing units
+    int64_t* tile_prefix;     // [max_worlds + 1] physics tiles
+    int32_t* group_prefix;    // [max_worlds + 1] network units (device computed)
+    int32_t* tiles_x;         // [max_worlds] physics tiles per row
+};
+
+// Network fragment geometry.  Weights are stored per genome in the order
+// the MFMA A operand is loaded: fragment f = (layer, 16-row tile, K-step),
+// 64 lanes x (8 bf16 | 1 float).  BF16 uses v_mfma_f32_16x16x32_bf16
+// (K-step 32), FP32 uses v_mfma_f32_16x16x4_f32 (K-step 4).  The 54 inputs
+// take 2 bf16 K-steps or 14 fp32 K-steps (inputs 54, 55 are zero padding).
+__host__ __device__ constexpr int net_mt(int hid) { return hid / 16; }
+__host__ __device__ constexpr int net_ks0(int prec) { return prec == kPrecBF16 ? 2 : 14; }
+__host__ __device__ constexpr int net_ksh(int hid, int prec) {
+    return prec == kPrecBF16 ? hid / 32 : hid / 4;
+}
+__host__ __device__ constexpr int net_frags(int nl, int hid, int prec) {
+    return net_mt(hid) * net_ks0(prec) + (nl == 3 ? net_mt(hid) * net_ksh(hid, prec) : 0) +
+           net_ksh(hid, prec);
+}
+__host__ __device__ constexpr int net_frag_bytes(int prec) { return prec == kPrecBF16 ? 1024 : 256; }
+__host__ __device__ constexpr int net_frag_elems(int prec) { return prec == kPrecBF16 ? 512 : 64; }
+// bias block per genome: [layer 0 rows (hid)] [layer 1 rows (hid), 3 layers only] [16 out rows]
+__host__ __device__ constexpr int net_bias_floats(int nl, int hid) {
+    return hid + (nl == 3 ? hid : 0) + 16;
+}
+// Flat (natural) network size: per layer W (out x in) then b (out).
+__host__ __device__ constexpr int net_flat_size(int nl, int hid) {
+    return nl == 2 ? hid * kNIn + hid + kNOut * hid + kNOut
+                   : hid * kNIn + hid + hid * hid + hid + kNOut * hid + kNOut;
+}
+
+struct FragCoord {
+    int layer, row, col;
+};
+
+// Which weight W_layer[row][col] the fragment element e of a genome holds.
+// Layer 0 columns: bf16 (K-step s, lane group q, element i) -> 16q + 8s + i,
+// fp32 (s, q) -> 4s + q.  Hidden-input layers follow the MFMA output layout
+// (lane group q holds rows 4q..4q+3 of each 16-row tile), so the previous
+// layer's accumulators feed the next MFMA without data movement:
+// bf16 -> 16(2s + i/4) + 4q + i%4, fp32 -> 16(s/4) + 4q + s%4.
+__host__ __device__ inline FragCoord frag_coord(int nl, int hid, int prec, int e) {
+    const bool bf = prec == kPrecBF16;
+    const int epl = bf ? 8 : 1;
+    const int f = e / (64 * epl), r = e % (64 * epl);
+    const int lane = r / epl, i = r % epl;
+    const int q = lane >> 4, m = lane & 15;
+    const int MT = net_mt(hid), KS0 = net_ks0(prec), KSH = net_ksh(hid, prec);
+    const int F0 = MT * KS0, F1 = nl == 3 ? MT * KSH : 0;
+    int layer, mt, s;
+    if (f < F0) {
+        layer = 0; mt = f / KS0; s = f % KS0;
+    } else if (f < F0 + F1) {
+        layer = 1; mt = (f - F0) / KSH; s = (f - F0) % KSH;
+    } else {
+        layer = nl - 1; mt = 0; s = f - F0 - F1;
+    }
+    int col;
+    if (layer == 0) col = bf ? 16 * q + 8 * s + i : 4 * s + q;
+    else col = bf ? 16 * (2 * s + (i >> 2)) + 4 * q + (i & 3) : 16 * (s >> 2) + 4 * q + (s & 3);
+    return {layer, 16 * mt + m, col};
+}
+
+// Direction d points 45*d degrees counter-clockwise from +x, y pointing down.
+__device__ __forceinline__ int dir_dx(int d) { return (int)((0x440052u >> (d * 3)) & 7) - 1; }
+__device__ __forceinline__ int dir_dy(int d) { return (int)((0x491001u >> (d * 3)) & 7) - 1; }
+// Kernel position p (1..8) of rotation r: r, r+1, r-1, r+2, r-2, r+3, r-3, r+4.
+__device__ __forceinline__ int kernel_dir(int r, int p) {
+    // offsets {0, +1, -1, +2, -2, +3, -3, +4} packed as (off & 7) in 3 bits
+    return (r + (int)((0x95e5c8u >> (p * 3 - 3)) & 7)) & 7;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Block index remapped so that each XCD (blocks are dealt round-robin over
+// the 8 XCDs) owns a contiguous range of work: neighbouring tiles then share
+// an L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (nb & 7) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename T>
+__device__ __forceinline__ int find_world(const T* prefix, int n, T u) {
+    // largest w in [0, n) with prefix[w] <= u
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Host-side launch shapes ----------------------------------------------------
+
+struct LaunchShape {
+    int n_cu;
+    int act_blocks;
+    int phys_blocks;
+    int chunk_blocks;
+    int misc_blocks;
+    int max_worlds;
+    int max_cap;
+};
+
+// Launchers implemented in the kernel translation units.
+void launch_step_kernels(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
+                         int act_cells, int phys_tile, hipStream_t s, float* debug_act);
+void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
+void launch_act_only(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
+                     int act_cells, hipStream_t s, float* debug_act);
+void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
+                         hipStream_t s);
+void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
+void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
+void launch_cppn(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s);
+void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
+void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
+                    int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s);
+void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
+                         hipStream_t s);
+void launch_flip(const BatchDev* bdev, hipStream_t s);
+
+int phys_tile_w(int t);
+int phys_tile_h(int t);
+
+}  // namespace coralai

@@ -1,0 +1,474 @@
+// Sense -> act: the per-cell network of the cell's genome, run as a grouped
+// GEMM on MFMA, followed by the actuator epilogue (System Design: each cell
+// sends its Kernel neighbourhood of Sensor channels to its network and
+// receives Actuator values; Experiment: invest / liquidate, sigmoid
+// communication, explore actuators one per kernel offset).
+//
+// Work unit: 64 cells of one genome taken from the bucket order (one
+// wavefront).  Each wavefront owns a contiguous range of units, so it keeps
+// its genome's weights in registers across units and reloads them only at
+// genome boundaries.  Per unit:
+//   1. every lane gathers its cell's 54 sensor values (rotation-ordered 3x3
+//      Moore kernel, periodic) straight from HBM/L2 and writes them to the
+//      wavefront's LDS stage as one row (bf16 or fp32);
+//   2. the cells are the MFMA B operand (16 per column group), the weights
+//      the A operand; hidden layers stay in registers because the MFMA
+//      output layout is reused as the next layer's B layout (tanh in FP32,
+//      then RNE to bf16 in the BF16 form);
+//   3. the 14 actuators go through LDS back to one cell per lane, and the
+//      epilogue computes the ledger conversion, the sigmoid communication,
+//      the quantised softmax flow plan and the argmax exploration, writing
+//      E', C' and the boundary record (I1, 8 flows, explore direction).
+#include <type_traits>
+
+#include "coralai_internal.h"
+
+namespace coralai {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int NL, int HID, int PREC>
+struct Net {
+    static constexpr bool kBF = PREC == kPrecBF16;
+    static constexpr int MT = HID / 16;
+    static constexpr int KS0 = net_ks0(PREC);
+    static constexpr int KSH = net_ksh(HID, PREC);
+    static constexpr int F0 = MT * KS0;
+    static constexpr int F1 = NL == 3 ? MT * KSH : 0;
+    static constexpr int FRAG_BYTES = net_frag_bytes(PREC);
+    static constexpr int STAGE_ROW = kBF ? 144 : 272;  // bytes per cell row (padded)
+    static constexpr int STAGE_BYTES = 64 * STAGE_ROW;
+    static constexpr int ACT_ROW = 80;                 // 16 floats + 4 pad, conflict free
+    using frag_t = typename std::conditional<kBF, bf16x8, float>::type;
+};
+
+// tanh(x) = 1 - 2 / (exp(2x) + 1): one exp and one reciprocal, exact limits.
+__device__ __forceinline__ float fast_tanh(float x) {
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+__device__ __forceinline__ float sigmoid_f(float x) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * -1.4426950408889634f));
+}
+
+__device__ __forceinline__ floatx4 mfma(const bf16x8& a, const bf16x8& b, const floatx4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma(float a, float b, const floatx4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NL, int HID, int PREC, int CGI, bool DEBUG>
+__global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
+                                             float* __restrict__ dbg) {
+    using NT = Net<NL, HID, PREC>;
+    using frag_t = typename NT::frag_t;
+    constexpr int MT = NT::MT, KS0 = NT::KS0, KSH = NT::KSH;
+    constexpr int MT1 = NL == 3 ? MT : 1;
+    static_assert(4 % CGI == 0, "column groups per pass must divide 4");
+
+    __shared__ __attribute__((aligned(16))) uint8_t smem[4 * NT::STAGE_BYTES];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, n16 = lane & 15;
+    uint8_t* stage = smem + wv * NT::STAGE_BYTES;
+
+    const int nworlds = b->n_worlds;
+    if (nworlds <= 0) return;
+    const int total = b->group_prefix[nworlds];
+    const int nwaves = gridDim.x * 4;
+    const int per = (total + nwaves - 1) / nwaves;
+    int u = uniform_i32((xcd_block() * 4 + wv) * per);
+    const int uend = min(total, u + per);
+    if (u >= uend) return;  // no block-wide barriers below: waves are independent
+
+    frag_t w0[MT][KS0];
+    frag_t w1[MT1][KSH];
+    frag_t wo[KSH];
+    floatx4 b0[MT], b1[MT1], bo;
+
+    int wi = uniform_i32(find_world(b->group_prefix, nworlds, u));
+    int world_lo = 0, world_hi = -1;
+    int g = -1, g_lo = 0, g_hi = -1;
+    int64_t acc_mass = 0;
+    double acc_f64 = 0.0;
+    uint32_t err = 0;
+
+    // world fields kept in registers
+    int Wd = 0, Hd = 0, Nd = 0, cap = 0;
+    float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
+    const int64_t *Ec = nullptr, *Ic = nullptr;
+    const float* Cc = nullptr;
+    const uint8_t* Rc = nullptr;
+    int64_t *En = nullptr, *I1p = nullptr;
+    float* Cn = nullptr;
+    uint32_t* flow = nullptr;
+    uint8_t* Xp = nullptr;
+    const int32_t *perm = nullptr, *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
+    const uint8_t* wfrag = nullptr;
+    const float* bias = nullptr;
+    int64_t wstride = 0;
+    int bstride = 0;
+    Ctl* ctl = nullptr;
+
+    auto flush = [&]() {
+        const int64_t m = wave_sum_i64(acc_mass);
+        const double mf = wave_sum_f64(acc_f64);
+        if (lane == 0 && ctl != nullptr) {
+            atomicAdd((unsigned long long*)&ctl->acc_mass, (unsigned long long)m);
+            atomicAdd(&ctl->acc_mass_f64, mf);
+        }
+        if (err && ctl != nullptr) atomicOr(&ctl->err, err);
+        acc_mass = 0;
+        acc_f64 = 0.0;
+        err = 0;
+    };
+
+    for (; u < uend; ++u) {
+        if (u >= world_hi) {
+            flush();
+            while (b->group_prefix[wi + 1] <= u) ++wi;
+            wi = uniform_i32(wi);
+            world_lo = b->group_prefix[wi];
+            world_hi = b->group_prefix[wi + 1];
+            const WorldDev* W = &b->worlds[wi];
+            Wd = W->W; Hd = W->H; Nd = W->N; cap = W->cap;
+            rho_i = W->rho_i; rho_l = W->rho_l; kappa = W->kappa;
+            ctl = W->ctl;
+            const int cur = ctl->cur, nxt = cur ^ 1;
+            Ec = W->E[cur]; Ic = W->I[cur]; Cc = W->C[cur]; Rc = W->R[cur];
+            En = W->E[nxt]; Cn = W->C[nxt];
+            I1p = W->I1; flow = W->flow; Xp = W->X;
+            perm = W->perm; counts = W->counts; offsets = W->offsets; gofs = W->gofs;
+            wfrag = W->wfrag; bias = W->bias; wstride = W->wfrag_stride; bstride = W->bias_stride;
+            g = -1;
+            g_hi = -1;
+        }
+        const int k = u - world_lo;
+        if (k >= g_hi) {
+            // next genome: short linear probe, else binary search over gofs
+            int gn = -1;
+            if (g >= 0) {
+#pragma unroll 1
+                for (int t = g + 1; t < min(cap, g + 5); ++t)
+                    if (gofs[t + 1] > k) { gn = t; break; }
+            }
+            if (gn < 0) {
+                int lo = 0, hi = cap - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (gofs[mid] <= k) lo = mid; else hi = mid - 1;
+                }
+                gn = lo;
+            }
+            g = uniform_i32(gn);
+            g_lo = gofs[g];
+            g_hi = gofs[g + 1];
+            // weights of genome g -> registers
+            const uint8_t* wb = wfrag + (int64_t)g * wstride + lane * (NT::FRAG_BYTES / 64);
+            const float* bb = bias + (int64_t)g * bstride + 4 * q;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int s = 0; s < KS0; ++s)
+                    w0[mt][s] = *(const frag_t*)(wb + (mt * KS0 + s) * NT::FRAG_BYTES);
+            if constexpr (NL == 3) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int s = 0; s < KSH; ++s)
+                        w1[mt][s] = *(const frag_t*)(wb + (NT::F0 + mt * KSH + s) * NT::FRAG_BYTES);
+            }
+#pragma unroll
+            for (int s = 0; s < KSH; ++s)
+                wo[s] = *(const frag_t*)(wb + (NT::F0 + NT::F1 + s) * NT::FRAG_BYTES);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) b0[mt] = *(const floatx4*)(bb + 16 * mt);
+            if constexpr (NL == 3) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) b1[mt] = *(const floatx4*)(bb + HID + 16 * mt);
+            }
+            bo = *(const floatx4*)(bb + (NL == 3 ? 2 * HID : HID));
+        }
+        const int j = k - g_lo;
+        const int cell0 = offsets[g] + j * kGroupCells;
+        const int cnt = min(kGroupCells, counts[g] - j * kGroupCells);
+        const bool valid = lane < cnt;
+        const int i = perm[cell0 + (valid ? lane : 0)];
+
+        // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
+        const int y = i / Wd, x = i - y * Wd;
+        const int r = Rc[i] & 7;
+        float uvec[kNIn];
+        int64_t e_own = 0, i_own = 0;
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            int nidx = i;
+            if (p > 0) {
+                const int d = kernel_dir(r, p);
+                int nx = x + dir_dx(d), ny = y + dir_dy(d);
+                nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
+                ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
+                nidx = ny * Wd + nx;
+            }
+            const int64_t ev = Ec[nidx], iv = Ic[nidx];
+            if (p == 0) { e_own = ev; i_own = iv; }
+            uvec[6 * p + 0] = (float)ev * 0x1p-24f;
+            uvec[6 * p + 1] = (float)iv * 0x1p-24f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = Cc[(int64_t)c * Nd + nidx];
+        }
+        if constexpr (NT::kBF) {
+            bf16x8 row[8];
+#pragma unroll
+            for (int kk = 0; kk < 64; ++kk) row[kk >> 3][kk & 7] = (__bf16)(kk < kNIn ? uvec[kk] : 0.0f);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) *(bf16x8*)(stage + lane * NT::STAGE_ROW + 16 * t) = row[t];
+        } else {
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                floatx4 v[4];
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const int kk = 4 * s + qq;
+                    v[s >> 2][s & 3] = (s < 14 && kk < kNIn) ? uvec[kk] : 0.0f;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    *(floatx4*)(stage + lane * NT::STAGE_ROW + qq * 64 + 16 * t) = v[t];
+            }
+        }
+        wave_lds_sync();
+
+        // ---- 2. the network, CGI column groups of 16 cells at a time
+        floatx4 outv[4];
+#pragma unroll
+        for (int cb = 0; cb < 4 / CGI; ++cb) {
+            floatx4 acc[CGI][MT];
+#pragma unroll
+            for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = b0[mt];
+            if constexpr (NT::kBF) {
+                bf16x8 xin[CGI][KS0];
+#pragma unroll
+                for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                    for (int s = 0; s < KS0; ++s)
+                        xin[cc][s] = *(const bf16x8*)(stage + (16 * (cb * CGI + cc) + n16) * NT::STAGE_ROW +
+                                                      (16 * q + 8 * s) * 2);
+#pragma unroll
+                for (int s = 0; s < KS0; ++s)
+#pragma unroll
+                    for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], acc[cc][mt]);
+            } else {
+                float xin[CGI][16];
+#pragma unroll
+                for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const floatx4 v = *(const floatx4*)(stage + (16 * (cb * CGI + cc) + n16) * NT::STAGE_ROW +
+                                                            q * 64 + 16 * t);
+                        xin[cc][4 * t + 0] = v[0]; xin[cc][4 * t + 1] = v[1];
+                        xin[cc][4 * t + 2] = v[2]; xin[cc][4 * t + 3] = v[3];
+                    }
+#pragma unroll
+                for (int s = 0; s < KS0; ++s)
+#pragma unroll
+                    for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], acc[cc][mt]);
+            }
+            // hidden layers
+#pragma unroll
+            for (int layer = 1; layer < NL; ++layer) {
+                const bool last = layer == NL - 1;
+                if constexpr (NT::kBF) {
+                    bf16x8 h[CGI][KSH];
+#pragma unroll
+                    for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                        for (int s = 0; s < KSH; ++s)
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                h[cc][s][t] = (__bf16)fast_tanh(acc[cc][2 * s][t]);
+                                h[cc][s][4 + t] = (__bf16)fast_tanh(acc[cc][2 * s + 1][t]);
+                            }
+                    if (last) {
+#pragma unroll
+                        for (int cc = 0; cc < CGI; ++cc) {
+                            floatx4 o = bo;
+#pragma unroll
+                            for (int s = 0; s < KSH; ++s) o = mfma(wo[s], h[cc][s], o);
+                            outv[cb * CGI + cc] = o;
+                        }
+                    } else {
+#pragma unroll
+                        for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = b1[mt % MT1];
+#pragma unroll
+                        for (int s = 0; s < KSH; ++s)
+#pragma unroll
+                            for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                                for (int mt = 0; mt < MT; ++mt)
+                                    acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s], acc[cc][mt]);
+                    }
+                } else {
+                    float h[CGI][MT][4];
+#pragma unroll
+                    for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) h[cc][mt][t] = fast_tanh(acc[cc][mt][t]);
+                    if (last) {
+#pragma unroll
+                        for (int cc = 0; cc < CGI; ++cc) {
+                            floatx4 o = bo;
+#pragma unroll
+                            for (int s = 0; s < KSH; ++s) o = mfma(wo[s], h[cc][s >> 2][s & 3], o);
+                            outv[cb * CGI + cc] = o;
+                        }
+                    } else {
+#pragma unroll
+                        for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = b1[mt % MT1];
+#pragma unroll
+                        for (int s = 0; s < KSH; ++s)
+#pragma unroll
+                            for (int cc = 0; cc < CGI; ++cc)
+#pragma unroll
+                                for (int mt = 0; mt < MT; ++mt)
+                                    acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s >> 2][s & 3], acc[cc][mt]);
+                    }
+                }
+            }
+        }
+        wave_lds_sync();  // all stage reads done before the actuator rows overwrite them
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            *(floatx4*)(stage + (16 * c + n16) * NT::ACT_ROW + 16 * q) = outv[c];
+        wave_lds_sync();
+        float a[16];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const floatx4 v = *(const floatx4*)(stage + lane * NT::ACT_ROW + 16 * t);
+            a[4 * t] = v[0]; a[4 * t + 1] = v[1]; a[4 * t + 2] = v[2]; a[4 * t + 3] = v[3];
+        }
+        wave_lds_sync();  // actuator rows read before the next unit's stage writes
+
+        // ---- 3. epilogue: one cell per lane
+        if (valid) {
+            if constexpr (DEBUG) {
+#pragma unroll
+                for (int t = 0; t < kNOut; ++t) dbg[(int64_t)i * kNOut + t] = a[t];
+            }
+            bool finite = true;
+#pragma unroll
+            for (int t = 0; t < kNOut; ++t) finite = finite && __builtin_isfinite(a[t]);
+            if (!finite) {
+                err |= kErrNonFinite;
+#pragma unroll
+                for (int t = 0; t < kNOut; ++t) a[t] = __builtin_isfinite(a[t]) ? a[t] : 0.0f;
+            }
+            if (e_own < 0 || i_own < 0) err |= kErrLedger;
+            // invest / liquidate: sigmoid-gated fractions of the pre-step stocks
+            const float se = sigmoid_f(a[0]), sl = sigmoid_f(a[1]);
+            int64_t xi = (int64_t)floorf(rho_i * se * (float)e_own);
+            int64_t xl = (int64_t)floorf(rho_l * sl * (float)i_own);
+            xi = xi > e_own ? e_own : xi;
+            xl = xl > i_own ? i_own : xl;
+            xi = xi < 0 ? 0 : xi;
+            xl = xl < 0 ? 0 : xl;
+            const int64_t E1 = e_own - xi + xl, I1 = i_own + xi - xl;
+            // communication: sigmoid of the comm actuators
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Cn[(int64_t)c * Nd + i] = sigmoid_f(a[2 + c]);
+            // exploration: softmax split of the flow budget, argmax explore
+            float m = a[6];
+            int best = 0;
+#pragma unroll
+            for (int t = 1; t < 8; ++t)
+                if (a[6 + t] > m) { m = a[6 + t]; best = t; }
+            float ex[8], ssum = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) { ex[t] = __expf(a[6 + t] - m); ssum += ex[t]; }
+            int64_t F = (int64_t)floorf(kappa * (float)I1);
+            if (F < 0) F = 0;
+            if (F > 0xffffffffll) { err |= kErrLedger; F = 0xffffffffll; }
+            const float fF = (float)F;
+            int64_t used = 0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                int64_t f = (int64_t)floorf((ex[t] / ssum) * fF);
+                f = f > F - used ? F - used : f;
+                f = f < 0 ? 0 : f;
+                used += f;
+                flow[(int64_t)kernel_dir(r, t + 1) * Nd + i] = (uint32_t)f;
+            }
+            En[i] = E1;
+            I1p[i] = I1;
+            Xp[i] = (uint8_t)kernel_dir(r, best + 1);
+            acc_mass += E1;
+            acc_f64 += (double)E1;
+        }
+    }
+    flush();
+}
+
+template <int NL, int HID, int PREC, bool DEBUG>
+static void launch_act_t(const BatchDev* bdev, const LaunchShape& ls, int act_cells, hipStream_t s,
+                         float* dbg) {
+    switch (act_cells) {
+        case 1: hipLaunchKernelGGL((k_act<NL, HID, PREC, 1, DEBUG>), dim3(ls.act_blocks), dim3(256), 0, s, bdev, dbg); break;
+        case 2: hipLaunchKernelGGL((k_act<NL, HID, PREC, 2, DEBUG>), dim3(ls.act_blocks), dim3(256), 0, s, bdev, dbg); break;
+        default: hipLaunchKernelGGL((k_act<NL, HID, PREC, 4, DEBUG>), dim3(ls.act_blocks), dim3(256), 0, s, bdev, dbg); break;
+    }
+}
+
+template <bool DEBUG>
+static void launch_act_d(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
+                         int act_cells, hipStream_t s, float* dbg) {
+    if (prec == kPrecBF16) {
+        if (NL == 2 && HID == 32) launch_act_t<2, 32, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
+        else if (NL == 2 && HID == 64) launch_act_t<2, 64, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
+        else if (NL == 3 && HID == 32) launch_act_t<3, 32, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
+        else launch_act_t<3, 64, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
+    } else {
+        if (NL == 2 && HID == 32) launch_act_t<2, 32, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
+        else if (NL == 2 && HID == 64) launch_act_t<2, 64, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
+        else if (NL == 3 && HID == 32) launch_act_t<3, 32, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
+        else launch_act_t<3, 64, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
+    }
+}
+
+void launch_act_only(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
+                     int act_cells, hipStream_t s, float* debug_act) {
+    if (debug_act) launch_act_d<true>(bdev, ls, NL, HID, prec, act_cells, s, debug_act);
+    else launch_act_d<false>(bdev, ls, NL, HID, prec, act_cells, s, nullptr);
+}
+
+}  // namespace coralai

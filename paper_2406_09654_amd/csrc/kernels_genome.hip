@@ -1,0 +1,353 @@
+// Genome kernels: CPPN -> network weights (HyperNEAT, System Design), the
+// parameter scatter of coralai_set_genomes, debug weight packing, and
+// radiation -> mutation (Fig. 1, panel C).
+//
+// CPPN: inputs z = (x1, y1, x2, y2, 1), 8 hidden nodes phi_k(A_k . z) with
+// phi = sin, gauss (exp(-s^2)), tanh, identity for k mod 4 = 0..3, two linear
+// outputs (weight, bias) = B h, evaluated in FP64 for FP32 networks.  Neuron j of layer l sits at
+// (-1 + 2j/(L_l - 1), -1 + 2l/n); W_l[o][j] = CPPN_w(x_j, y_l, x_o, y_{l+1}) /
+// sqrt(L_l) and b_l[o] = CPPN_b(0, y_l, x_o, y_{l+1}).  One thread per weight
+// element, written straight into the MFMA fragment order of the act kernel.
+//
+// Radiation: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
+// (seed, 0) at counter (i, step, 0, 0); a hit when the first word is below
+// floor(rate 2^64).  Hits are ranked in ascending cell order and take the
+// free slots (zero count) in ascending order; the new genome is the parent's
+// CPPN plus sigma * N(0,1) from Box-Muller on the Philox blocks
+// (i, step, 1 + b, 0), b = 0..13, and its network is regenerated at once.
+#include "coralai_internal.h"
+
+namespace coralai {
+
+// T = double for FP32 worlds (weights then rounded once to FP32), float for
+// BF16 worlds (whose weights are rounded to bf16 anyway).
+template <typename T>
+__device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, T x2, T y2, int out) {
+    T s_out = T(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const T s = T(p[5 * k]) * x1 + T(p[5 * k + 1]) * y1 + T(p[5 * k + 2]) * x2 +
+                    T(p[5 * k + 3]) * y2 + T(p[5 * k + 4]);
+        T h;
+        switch (k & 3) {
+            case 0: h = sin(s); break;
+            case 1: h = exp(-s * s); break;
+            case 2: h = tanh(s); break;
+            default: h = s; break;
+        }
+        s_out += T(p[40 + 8 * out + k]) * h;
+    }
+    return s_out;
+}
+
+template <typename T>
+__device__ __forceinline__ T neuron_x(int j, int L) { return T(-1) + T(2) * T(j) / T(L - 1); }
+
+template <typename T>
+__device__ __forceinline__ float cppn_weight(const float* p, int layer, int nl, int row, int lout,
+                                             int col, int lin) {
+    const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
+    return (float)(cppn_eval<T>(p, neuron_x<T>(col, lin), yi, neuron_x<T>(row, lout), yo, 0) /
+                   sqrt(T(lin)));
+}
+
+template <typename T>
+__device__ __forceinline__ float cppn_bias(const float* p, int layer, int nl, int row, int lout) {
+    const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
+    return (float)cppn_eval<T>(p, T(0), yi, neuron_x<T>(row, lout), yo, 1);
+}
+
+// Layer geometry of a bias element index.
+__device__ __forceinline__ void bias_coord(int nl, int hid, int bidx, int* layer, int* row) {
+    if (bidx < hid) { *layer = 0; *row = bidx; return; }
+    if (nl == 3 && bidx < 2 * hid) { *layer = 1; *row = bidx - hid; return; }
+    *layer = nl - 1;
+    *row = bidx - (nl == 3 ? 2 * hid : hid);
+}
+
+__device__ __forceinline__ int layer_in(int nl, int hid, int l) { return l == 0 ? kNIn : hid; }
+__device__ __forceinline__ int layer_out(int nl, int hid, int l) { return l == nl - 1 ? kNOut : hid; }
+
+// Offset of W_l and b_l in the flat layout [W_0, b_0, W_1, b_1, ...].
+__device__ __forceinline__ int flat_w_offset(int nl, int hid, int l) {
+    int o = 0;
+    for (int k = 0; k < l; ++k) o += layer_out(nl, hid, k) * layer_in(nl, hid, k) + layer_out(nl, hid, k);
+    return o;
+}
+
+// from_radiation = 0: the n_host slots listed by coralai_set_genomes;
+// 1: the slots the last radiation call assigned (count on the device).
+__global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, int from_radiation,
+                                              int n_host) {
+    const int nl = w->NL, hid = w->HID, prec = w->prec;
+    const int n = from_radiation ? w->ctl->n_new : n_host;
+    const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
+    const int ew = net_frags(nl, hid, prec) * net_frag_elems(prec);
+    const int eb = net_bias_floats(nl, hid);
+    const int per_genome = (ew + eb + 255) / 256;
+    const int64_t units = (int64_t)n * per_genome;
+    const bool bf = prec == kPrecBF16;
+    for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
+        const int si = (int)(unit / per_genome);
+        const int e = (int)(unit - (int64_t)si * per_genome) * 256 + threadIdx.x;
+        const int slot = uniform_i32(slots[si]);
+        const float* p = w->params + (int64_t)slot * kNParam;
+        if (e < ew) {
+            const FragCoord fc = frag_coord(nl, hid, prec, e);
+            const int lin = layer_in(nl, hid, fc.layer), lout = layer_out(nl, hid, fc.layer);
+            float v = 0.0f;
+            if (fc.row < lout && fc.col < lin)
+                v = bf ? cppn_weight<float>(p, fc.layer, nl, fc.row, lout, fc.col, lin)
+                       : cppn_weight<double>(p, fc.layer, nl, fc.row, lout, fc.col, lin);
+            if (!__builtin_isfinite(v)) { atomicOr(&w->ctl->err, kErrNonFinite); v = 0.0f; }
+            uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
+            if (bf) ((__bf16*)dst)[e] = (__bf16)v;
+            else ((float*)dst)[e] = v;
+        } else if (e < ew + eb) {
+            int layer, row;
+            bias_coord(nl, hid, e - ew, &layer, &row);
+            const int lout = layer_out(nl, hid, layer);
+            float v = 0.0f;
+            if (row < lout)
+                v = bf ? cppn_bias<float>(p, layer, nl, row, lout)
+                       : cppn_bias<double>(p, layer, nl, row, lout);
+            if (!__builtin_isfinite(v)) { atomicOr(&w->ctl->err, kErrNonFinite); v = 0.0f; }
+            w->bias[(int64_t)slot * w->bias_stride + (e - ew)] = v;
+        }
+    }
+}
+
+// Debug: natural flat layout <-> fragment layout of one slot.
+__global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, int slot,
+                                              const float* __restrict__ flat, int unpack,
+                                              float* __restrict__ out) {
+    const int nl = w->NL, hid = w->HID, prec = w->prec;
+    const int ew = net_frags(nl, hid, prec) * net_frag_elems(prec);
+    const int eb = net_bias_floats(nl, hid);
+    const bool bf = prec == kPrecBF16;
+    uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < ew + eb; e += gridDim.x * 256) {
+        if (e < ew) {
+            const FragCoord fc = frag_coord(nl, hid, prec, e);
+            const int lin = layer_in(nl, hid, fc.layer), lout = layer_out(nl, hid, fc.layer);
+            const bool ok = fc.row < lout && fc.col < lin;
+            const int fi = flat_w_offset(nl, hid, fc.layer) + fc.row * lin + fc.col;
+            if (!unpack) {
+                const float v = ok ? flat[fi] : 0.0f;
+                if (bf) ((__bf16*)dst)[e] = (__bf16)v;
+                else ((float*)dst)[e] = v;
+            } else if (ok) {
+                out[fi] = bf ? (float)((const __bf16*)dst)[e] : ((const float*)dst)[e];
+            }
+        } else {
+            int layer, row;
+            bias_coord(nl, hid, e - ew, &layer, &row);
+            const int lin = layer_in(nl, hid, layer), lout = layer_out(nl, hid, layer);
+            const bool ok = row < lout;
+            const int fi = flat_w_offset(nl, hid, layer) + lout * lin + row;
+            float* bp = w->bias + (int64_t)slot * w->bias_stride + (e - ew);
+            if (!unpack) *bp = ok ? flat[fi] : 0.0f;
+            else if (ok) out[fi] = *bp;
+        }
+    }
+    if (!unpack && blockIdx.x == 0 && threadIdx.x == 0) w->slot_set[slot] = 1;
+}
+
+__global__ __launch_bounds__(256) void k_scatter_params(const WorldDev* __restrict__ w, int n) {
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < n * kNParam; e += gridDim.x * 256) {
+        const int k = e / kNParam, m = e - k * kNParam;
+        const int slot = w->stage_slots[k];
+        w->params[(int64_t)slot * kNParam + m] = w->stage_params[e];
+        if (m == 0) w->slot_set[slot] = 1;
+    }
+}
+
+// ------------------------------------------------------------------ Philox
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+}
+
+// Odd multiple of 2^-24 from the top 23 bits: exact in FP32, inside (0, 1).
+__device__ __forceinline__ float philox_uniform(uint64_t o) {
+    return (float)(2u * (uint32_t)(o >> 41) + 1u) * 0x1p-24f;
+}
+
+__global__ __launch_bounds__(256) void k_rad_hits(const WorldDev* __restrict__ w, uint64_t T,
+                                                  uint64_t step) {
+    __shared__ int s_cnt;
+    const int N = w->N;
+    for (int blk = blockIdx.x; blk < w->n_rad_blocks; blk += gridDim.x) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        const int64_t base = (int64_t)blk * kRadBlockCells + 16 * threadIdx.x;
+        uint32_t bits = 0;
+        for (int j = 0; j < 16; ++j) {
+            const int64_t i = base + j;
+            if (i >= N) break;
+            uint64_t c[4] = {(uint64_t)i, step, 0ull, 0ull};
+            philox4x64_10(c, w->seed, 0ull);
+            if (c[0] < T) bits |= 1u << j;
+        }
+        w->hit_bits[(int64_t)blk * 256 + threadIdx.x] = (uint16_t)bits;
+        if (bits) atomicAdd(&s_cnt, __popc(bits));
+        __syncthreads();
+        if (threadIdx.x == 0) w->blk_hits[blk] = s_cnt;
+        __syncthreads();
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ int block_scan_excl(int v, int* total, int* s_tmp) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_tmp[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int y = lane < NT / 64 ? s_tmp[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < NT / 64; o <<= 1) {
+            int z = __shfl_up(y, o, 64);
+            if (lane >= o) y += z;
+        }
+        if (lane < NT / 64) s_tmp[lane] = y;
+    }
+    __syncthreads();
+    const int before = wid > 0 ? s_tmp[wid - 1] : 0;
+    *total = s_tmp[NT / 64 - 1];
+    __syncthreads();
+    return before + x - v;
+}
+
+// Free slots (zero count) in ascending order.
+__global__ __launch_bounds__(1024) void k_rad_free(const WorldDev* __restrict__ w) {
+    __shared__ int s_tmp[16];
+    const int cap = w->cap;
+    const int per = (cap + 1023) / 1024;
+    const int beg = min(cap, (int)threadIdx.x * per), end = min(cap, beg + per);
+    int c = 0;
+    for (int g = beg; g < end; ++g) c += w->counts[g] == 0;
+    int tot;
+    int o = block_scan_excl<1024>(c, &tot, s_tmp);
+    for (int g = beg; g < end; ++g)
+        if (w->counts[g] == 0) w->free_list[o++] = g;
+    if (threadIdx.x == 0) w->ctl->n_free = tot;
+}
+
+// Hit ranks: exclusive scan of the per-block hit counts.
+__global__ __launch_bounds__(1024) void k_rad_scan(const WorldDev* __restrict__ w) {
+    __shared__ int s_tmp[16];
+    const int nb = w->n_rad_blocks;
+    const int per = (nb + 1023) / 1024;
+    const int beg = min(nb, (int)threadIdx.x * per), end = min(nb, beg + per);
+    int c = 0;
+    for (int k = beg; k < end; ++k) c += w->blk_hits[k];
+    int tot;
+    int o = block_scan_excl<1024>(c, &tot, s_tmp);
+    for (int k = beg; k < end; ++k) {
+        w->blk_ofs[k] = o;
+        o += w->blk_hits[k];
+    }
+    if (threadIdx.x == 0) {
+        w->blk_ofs[nb] = tot;
+        Ctl* ctl = w->ctl;
+        const int nn = min(tot, ctl->n_free);
+        ctl->hits = tot;
+        ctl->n_new = nn;
+        ctl->dropped = tot - nn;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__ w, uint64_t step,
+                                                    float sigma) {
+    __shared__ int s_tmp[4];
+    const Ctl* ctl = w->ctl;
+    const int cur = ctl->cur;
+    const int n_new = ctl->n_new;
+    int32_t* G = w->G[cur];
+    for (int blk = blockIdx.x; blk < w->n_rad_blocks; blk += gridDim.x) {
+        if (w->blk_hits[blk] == 0) continue;  // block-uniform
+        const uint32_t bits = w->hit_bits[(int64_t)blk * 256 + threadIdx.x];
+        int tot;
+        int rank = w->blk_ofs[blk] + block_scan_excl<256>(__popc(bits), &tot, s_tmp);
+        for (int j = 0; j < 16; ++j) {
+            if (!((bits >> j) & 1u)) continue;
+            const int64_t i = (int64_t)blk * kRadBlockCells + 16 * threadIdx.x + j;
+            const int parent = G[i];
+            if (rank < n_new) w->new_slots[rank] = w->free_list[rank];  // every listed slot is valid
+            if (parent < 0 || parent >= w->cap) {  // invalid id: flagged, never dereferenced
+                atomicOr(&w->ctl->err, kErrGenomeRange);
+            } else if (rank < n_new) {
+                const int slot = w->free_list[rank];
+                const float* pp = w->params + (int64_t)parent * kNParam;
+                float* np = w->params + (int64_t)slot * kNParam;
+                for (int bb = 0; bb < 14; ++bb) {
+                    uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(1 + bb), 0ull};
+                    philox4x64_10(c, w->seed, 0ull);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
+                        const float rr = sqrtf(-2.0f * logf(u1));
+                        float sn, cs;
+                        sincospif(2.0f * u2, &sn, &cs);
+                        const int m = 4 * bb + 2 * h;
+                        np[m] = pp[m] + sigma * (rr * cs);
+                        np[m + 1] = pp[m + 1] + sigma * (rr * sn);
+                    }
+                }
+                G[i] = slot;
+                w->slot_set[slot] = 1;
+            }
+            ++rank;
+        }
+    }
+}
+
+__global__ void k_rad_finalize(const WorldDev* __restrict__ w) {
+    Ctl* ctl = w->ctl;
+    ctl->hits_pub = ctl->hits;
+    ctl->dropped_pub = ctl->dropped;
+}
+
+void launch_cppn(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s) {
+    hipLaunchKernelGGL(k_cppn, dim3(n_cu * 8), dim3(256), 0, s, wdev, from_radiation, n_host);
+}
+
+void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s) {
+    const int blocks = max(1, min(1024, (n * kNParam + 255) / 256));
+    hipLaunchKernelGGL(k_scatter_params, dim3(blocks), dim3(256), 0, s, wdev, n);
+}
+
+void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_pack, dim3(64), dim3(256), 0, s, wdev, slot, flat, unpack, out);
+}
+
+void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
+                    int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s) {
+    // genome counts of the current state (the completed step's result)
+    launch_hist_only(bdev, ls, s);
+    hipLaunchKernelGGL(k_rad_free, dim3(1), dim3(1024), 0, s, wdev);
+    const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
+    hipLaunchKernelGGL(k_rad_hits, dim3(hb), dim3(256), 0, s, wdev, T, step);
+    hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
+    hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev, step, sigma);
+    launch_cppn(wdev, 1, 0, ls.n_cu, s);
+    hipLaunchKernelGGL(k_rad_finalize, dim3(1), dim3(1), 0, s, wdev);
+}
+
+}  // namespace coralai

@@ -1,0 +1,867 @@
+// Host runtime and C ABI of the gfx950 Coralai library: arena carving,
+// world and batch objects, launch orchestration (direct launches or a
+// captured HIP graph of persistent kernels), the autotuner, stats and error
+// reporting, and the parity hooks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/coralai.h"
+#include "coralai_internal.h"
+
+using namespace coralai;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(CORALAI_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t E[2], I[2], C[2], G[2], R[2];
+    size_t flow, I1, X, perm;
+    size_t counts, offsets, cursor, gofs, slot_set, params, wfrag, bias;
+    size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
+    size_t ctl, wdev, bdev, chunk_prefix, tile_prefix, group_prefix, tiles_x;
+    size_t total;
+    int64_t wfrag_stride;
+    int bias_stride;
+    int n_rad_blocks;
+};
+
+bool desc_valid(const coralai_world_desc* d, std::string* why) {
+    auto bad = [&](const char* m) { if (why) *why = m; return false; };
+    if (!d) return bad("desc is NULL");
+    if (d->width < 1 || d->height < 1) return bad("width and height must be >= 1");
+    if ((int64_t)d->width * d->height > (1ll << 30)) return bad("W*H must be <= 2^30");
+    if (d->n_weight_layers != 2 && d->n_weight_layers != 3) return bad("n_weight_layers must be 2 or 3");
+    if (d->hidden != 32 && d->hidden != 64) return bad("hidden must be 32 or 64");
+    if (d->genome_capacity < 1 || d->genome_capacity > (1 << 22)) return bad("genome_capacity must be in [1, 2^22]");
+    if (d->precision != CORALAI_FP32 && d->precision != CORALAI_BF16) return bad("precision must be CORALAI_FP32 or CORALAI_BF16");
+    if (d->reserved != 0) return bad("reserved must be 0");
+    for (float v : {d->rho_invest, d->rho_liquidate, d->kappa_flow})
+        if (!(v >= 0.0f && v <= 1.0f)) return bad("rho_invest, rho_liquidate, kappa_flow must be in [0, 1]");
+    return true;
+}
+
+Layout make_layout(const coralai_world_desc* d) {
+    Layout L{};
+    const size_t N = (size_t)d->width * d->height, cap = (size_t)d->genome_capacity;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = align_up(off, kAlign); size_t o = off; off += bytes; return o; };
+    for (int k = 0; k < 2; ++k) {
+        L.E[k] = take(8 * N);
+        L.I[k] = take(8 * N);
+        L.C[k] = take(16 * N);
+        L.G[k] = take(4 * N);
+        L.R[k] = take(N);
+    }
+    L.flow = take(32 * N);
+    L.I1 = take(8 * N);
+    L.X = take(N);
+    L.perm = take(4 * N);
+    L.counts = take(4 * cap);
+    L.offsets = take(4 * (cap + 1));
+    L.cursor = take(4 * cap);
+    L.gofs = take(4 * (cap + 1));
+    L.slot_set = take(cap);
+    L.params = take(4 * kNParam * cap);
+    L.wfrag_stride = (int64_t)net_frags(d->n_weight_layers, d->hidden, d->precision) *
+                     net_frag_bytes(d->precision);
+    L.wfrag = take((size_t)L.wfrag_stride * cap);
+    L.bias_stride = net_bias_floats(d->n_weight_layers, d->hidden);
+    L.bias = take(4 * (size_t)L.bias_stride * cap);
+    L.n_rad_blocks = (int)((N + kRadBlockCells - 1) / kRadBlockCells);
+    L.hit_bits = take(2 * 256 * (size_t)L.n_rad_blocks);
+    L.blk_hits = take(4 * (size_t)L.n_rad_blocks);
+    L.blk_ofs = take(4 * ((size_t)L.n_rad_blocks + 1));
+    L.free_list = take(4 * cap);
+    L.new_slots = take(4 * cap);
+    L.stage_slots = take(4 * cap);
+    L.stage_params = take(4 * kNParam * cap);
+    L.ctl = take(sizeof(Ctl));
+    L.wdev = take(sizeof(WorldDev));
+    L.bdev = take(sizeof(BatchDev));
+    L.chunk_prefix = take(16);
+    L.tile_prefix = take(16);
+    L.group_prefix = take(8);
+    L.tiles_x = take(4);
+    L.total = align_up(off, kAlign);
+    return L;
+}
+
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        return 256;
+    return n;
+}
+
+LaunchShape make_shape(int max_worlds, int max_cap) {
+    LaunchShape ls{};
+    ls.n_cu = device_cus();
+    ls.act_blocks = ls.n_cu * 2;
+    ls.phys_blocks = ls.n_cu * 4;
+    ls.chunk_blocks = ls.n_cu * 4;
+    ls.misc_blocks = ls.n_cu;
+    ls.max_worlds = max_worlds;
+    ls.max_cap = max_cap;
+    return ls;
+}
+
+struct BusyGuard {
+    std::atomic<int>* flag;
+    bool ok;
+    explicit BusyGuard(std::atomic<int>* f) : flag(f) {
+        int expect = 0;
+        ok = flag->compare_exchange_strong(expect, 1);
+    }
+    ~BusyGuard() { if (ok) flag->store(0); }
+};
+
+}  // namespace
+
+struct coralai_world {
+    coralai_world_desc desc;
+    Layout L;
+    hipStream_t stream;
+    uint8_t* base;
+    WorldDev host;       // the device table entry, host copy
+    WorldDev* wdev;
+    BatchDev* bdev;
+    LaunchShape ls;
+    int act_cells = 2;
+    int phys_tile = 0;
+    hipGraphExec_t graph = nullptr;
+    int graph_act = -1, graph_phys = -1;
+    Ctl* pinned = nullptr;
+    // live phase timing
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double prof_ms[CORALAI_PHASES] = {0, 0, 0, 0, 0};
+    int64_t prof_n[CORALAI_PHASES] = {0, 0, 0, 0, 0};
+    std::atomic<int> busy{0};
+};
+
+struct coralai_batch {
+    int max_worlds;
+    hipStream_t stream;
+    uint8_t* base;
+    BatchDev* bdev;
+    WorldDev* table;
+    int64_t* chunk_prefix;
+    int64_t* tile_prefix;
+    int32_t* group_prefix;
+    int32_t* tiles_x;
+    int n = 0;
+    int NL = 0, HID = 0, prec = 0;
+    int act_cells = 2, phys_tile = 0;
+    LaunchShape ls;
+    hipGraphExec_t graph = nullptr;
+    int graph_act = -1, graph_phys = -1;
+    std::vector<coralai_world*> worlds;
+    std::atomic<int> busy{0};
+};
+
+namespace {
+
+int tiles_for(int W, int H, int phys_tile, int* tx) {
+    const int tw = phys_tile_w(phys_tile), th = phys_tile_h(phys_tile);
+    *tx = (W + tw - 1) / tw;
+    return *tx * ((H + th - 1) / th);
+}
+
+int write_world_tables(coralai_world* w) {
+    // single-world batch: table = the world itself
+    int tx = 0;
+    const int64_t tiles = tiles_for(w->desc.width, w->desc.height, w->phys_tile, &tx);
+    const int64_t chunks = ((int64_t)w->host.N + kChunkCells - 1) / kChunkCells;
+    int64_t cp[2] = {0, chunks}, tp[2] = {0, tiles};
+    BatchDev hb{};
+    hb.n_worlds = 1;
+    hb.worlds = w->wdev;
+    hb.chunk_prefix = (int64_t*)(w->base + w->L.chunk_prefix);
+    hb.tile_prefix = (int64_t*)(w->base + w->L.tile_prefix);
+    hb.group_prefix = (int32_t*)(w->base + w->L.group_prefix);
+    hb.tiles_x = (int32_t*)(w->base + w->L.tiles_x);
+    HIP_TRY(hipMemcpyAsync(w->wdev, &w->host, sizeof(WorldDev), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->bdev, &hb, sizeof(BatchDev), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(hb.chunk_prefix, cp, sizeof cp, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(hb.tile_prefix, tp, sizeof tp, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(hb.tiles_x, &tx, sizeof tx, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int read_ctl(coralai_world* w) {
+    HIP_TRY(hipMemcpyAsync(w->pinned, w->host.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int report_errors(coralai_world* w, uint32_t* word_out) {
+    int rc = read_ctl(w);
+    if (rc) return rc;
+    const uint32_t e = w->pinned->err;
+    if (word_out) *word_out = e;
+    if (e) {
+        HIP_TRY(hipMemsetAsync(&w->host.ctl->err, 0, sizeof(uint32_t), w->stream));
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        if (e & (CORALAI_ERR_GENOME_RANGE | CORALAI_ERR_GENOME_UNSET))
+            return fail(CORALAI_E_GENOME, "a cell names a genome slot outside [0, capacity) or without parameters (error word 0x%x)", e);
+        return fail(CORALAI_E_NUMERIC, "non-finite network output / CPPN weight or ledger overflow (error word 0x%x)", e);
+    }
+    return CORALAI_OK;
+}
+
+void fill_stats(const Ctl& c, coralai_stats* out) {
+    out->mass_quanta = c.mass;
+    out->mass_fp64 = c.mass_f64;
+    out->steps = c.steps;
+    out->live_genomes = c.live_pub;
+    out->takeovers = c.takeovers;
+    out->hits = c.hits_pub;
+    out->dropped_hits = c.dropped_pub;
+    out->error_word = c.err;
+    out->reserved = 0;
+}
+
+int check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CORALAI_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return CORALAI_OK;
+}
+
+int current_buffer(coralai_world* w, int* cur) {
+    int rc = read_ctl(w);
+    if (rc) return rc;
+    *cur = w->pinned->cur & 1;
+    return CORALAI_OK;
+}
+
+int take_event(coralai_world* w, hipEvent_t* e) {
+    if (!w->ev_pool.empty()) {
+        *e = w->ev_pool.back();
+        w->ev_pool.pop_back();
+        return CORALAI_OK;
+    }
+    HIP_TRY(hipEventCreate(e));
+    return CORALAI_OK;
+}
+
+// Harvest finished phase timings into the sums and recycle their events.
+int harvest_profile(coralai_world* w) {
+    if (w->ev_pending.empty()) return CORALAI_OK;
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    for (auto& r : w->ev_pending) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.second.first, r.second.second));
+        w->prof_ms[r.first] += ms;
+        w->prof_n[r.first] += 1;
+        w->ev_pool.push_back(r.second.first);
+        w->ev_pool.push_back(r.second.second);
+    }
+    w->ev_pending.clear();
+    return CORALAI_OK;
+}
+
+// Run fn between two events recorded on the world's stream (phase timing).
+template <typename F>
+int timed_phase(coralai_world* w, int phase, F&& fn) {
+    if (!w->profiling) { fn(); return CORALAI_OK; }
+    if (w->ev_pending.size() >= 512) {
+        int rc = harvest_profile(w);
+        if (rc) return rc;
+    }
+    hipEvent_t a, b;
+    int rc = take_event(w, &a);
+    if (!rc) rc = take_event(w, &b);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(a, w->stream));
+    fn();
+    HIP_TRY(hipEventRecord(b, w->stream));
+    w->ev_pending.push_back({phase, {a, b}});
+    return CORALAI_OK;
+}
+
+void destroy_graph(hipGraphExec_t* g) {
+    if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+}
+
+// Capture the step sequence once; every size it needs is read on the device.
+int capture_step(hipStream_t s, const BatchDev* bdev, const LaunchShape& ls, int NL, int HID,
+                 int prec, int act_cells, int phys_tile, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    launch_step_kernels(bdev, ls, NL, HID, prec, act_cells, phys_tile, s, nullptr);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) return fail(CORALAI_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CORALAI_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    return CORALAI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* coralai_last_error(void) { return g_last_error.c_str(); }
+const char* coralai_version(void) { return "coralai-gfx950 1.0"; }
+
+size_t coralai_world_bytes(const coralai_world_desc* desc) {
+    if (!desc_valid(desc, nullptr)) return 0;
+    return make_layout(desc).total + kAlign;
+}
+
+int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t arena_bytes,
+                         void* hip_stream, coralai_world** out) {
+    std::string why;
+    if (!out) return fail(CORALAI_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!desc_valid(desc, &why)) return fail(CORALAI_E_INVALID, "invalid world description: %s", why.c_str());
+    if (!dev_arena) return fail(CORALAI_E_INVALID, "dev_arena is NULL");
+    const size_t need = coralai_world_bytes(desc);
+    if (arena_bytes < need)
+        return fail(CORALAI_E_NOMEM, "arena of %zu bytes is smaller than the %zu bytes the world needs", arena_bytes, need);
+    coralai_world* w = new coralai_world();
+    w->desc = *desc;
+    w->L = make_layout(desc);
+    w->stream = (hipStream_t)hip_stream;
+    w->base = (uint8_t*)align_up((uintptr_t)dev_arena, kAlign);
+    if (hipHostMalloc((void**)&w->pinned, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        delete w;
+        return fail(CORALAI_E_HIP, "hipHostMalloc of the stats block failed");
+    }
+    const Layout& L = w->L;
+    uint8_t* b = w->base;
+    WorldDev& h = w->host;
+    memset(&h, 0, sizeof h);
+    h.W = desc->width; h.H = desc->height; h.N = desc->width * desc->height; h.cap = desc->genome_capacity;
+    h.NL = desc->n_weight_layers; h.HID = desc->hidden; h.prec = desc->precision;
+    h.n_rad_blocks = L.n_rad_blocks;
+    h.rho_i = desc->rho_invest; h.rho_l = desc->rho_liquidate; h.kappa = desc->kappa_flow;
+    h.seed = desc->seed;
+    for (int k = 0; k < 2; ++k) {
+        h.E[k] = (int64_t*)(b + L.E[k]);
+        h.I[k] = (int64_t*)(b + L.I[k]);
+        h.C[k] = (float*)(b + L.C[k]);
+        h.G[k] = (int32_t*)(b + L.G[k]);
+        h.R[k] = (uint8_t*)(b + L.R[k]);
+    }
+    h.flow = (uint32_t*)(b + L.flow);
+    h.I1 = (int64_t*)(b + L.I1);
+    h.X = (uint8_t*)(b + L.X);
+    h.perm = (int32_t*)(b + L.perm);
+    h.counts = (int32_t*)(b + L.counts);
+    h.offsets = (int32_t*)(b + L.offsets);
+    h.cursor = (int32_t*)(b + L.cursor);
+    h.gofs = (int32_t*)(b + L.gofs);
+    h.slot_set = (uint8_t*)(b + L.slot_set);
+    h.params = (float*)(b + L.params);
+    h.wfrag = (uint8_t*)(b + L.wfrag);
+    h.bias = (float*)(b + L.bias);
+    h.wfrag_stride = L.wfrag_stride;
+    h.bias_stride = L.bias_stride;
+    h.hit_bits = (uint16_t*)(b + L.hit_bits);
+    h.blk_hits = (int32_t*)(b + L.blk_hits);
+    h.blk_ofs = (int32_t*)(b + L.blk_ofs);
+    h.free_list = (int32_t*)(b + L.free_list);
+    h.new_slots = (int32_t*)(b + L.new_slots);
+    h.stage_slots = (int32_t*)(b + L.stage_slots);
+    h.stage_params = (float*)(b + L.stage_params);
+    h.ctl = (Ctl*)(b + L.ctl);
+    w->wdev = (WorldDev*)(b + L.wdev);
+    w->bdev = (BatchDev*)(b + L.bdev);
+    w->ls = make_shape(1, h.cap);
+    int rc = CORALAI_OK;
+    if (hipMemsetAsync(b, 0, L.total, w->stream) != hipSuccess) rc = fail(CORALAI_E_HIP, "arena clear failed");
+    if (!rc) rc = write_world_tables(w);
+    if (rc) {
+        (void)hipHostFree(w->pinned);
+        delete w;
+        return rc;
+    }
+    *out = w;
+    return CORALAI_OK;
+}
+
+int coralai_world_destroy(coralai_world* w) {
+    if (!w) return fail(CORALAI_E_INVALID, "world is NULL");
+    BusyGuard g(&w->busy);
+    if (!g.ok) return fail(CORALAI_E_BUSY, "world is in use");
+    (void)hipStreamSynchronize(w->stream);
+    destroy_graph(&w->graph);
+    for (auto& r : w->ev_pending) { (void)hipEventDestroy(r.second.first); (void)hipEventDestroy(r.second.second); }
+    for (hipEvent_t e : w->ev_pool) (void)hipEventDestroy(e);
+    (void)hipHostFree(w->pinned);
+    g.ok = false;
+    delete w;
+    return CORALAI_OK;
+}
+
+#define WORLD_GUARD(w)                                                            \
+    if (!(w)) return fail(CORALAI_E_INVALID, "world is NULL");                    \
+    BusyGuard guard_(&(w)->busy);                                                 \
+    if (!guard_.ok) return fail(CORALAI_E_BUSY, "world is in use by another thread")
+
+int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, const float* comm4,
+                      const int32_t* genome, const uint8_t* rotation, int on_device) {
+    WORLD_GUARD(w);
+    if (!e_q || !i_q || !comm4 || !genome || !rotation) return fail(CORALAI_E_INVALID, "a state array is NULL");
+    int cur = 0, rc = current_buffer(w, &cur);
+    if (rc) return rc;
+    const size_t N = (size_t)w->host.N;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(hipMemcpyAsync(w->host.E[cur], e_q, 8 * N, k, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.I[cur], i_q, 8 * N, k, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.C[cur], comm4, 16 * N, k, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.G[cur], genome, 4 * N, k, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.R[cur], rotation, N, k, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int coralai_get_state(coralai_world* w, int64_t* e_q, int64_t* i_q, float* comm4, int32_t* genome,
+                      uint8_t* rotation, int on_device) {
+    WORLD_GUARD(w);
+    int cur = 0, rc = current_buffer(w, &cur);
+    if (rc) return rc;
+    const size_t N = (size_t)w->host.N;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (e_q) HIP_TRY(hipMemcpyAsync(e_q, w->host.E[cur], 8 * N, k, w->stream));
+    if (i_q) HIP_TRY(hipMemcpyAsync(i_q, w->host.I[cur], 8 * N, k, w->stream));
+    if (comm4) HIP_TRY(hipMemcpyAsync(comm4, w->host.C[cur], 16 * N, k, w->stream));
+    if (genome) HIP_TRY(hipMemcpyAsync(genome, w->host.G[cur], 4 * N, k, w->stream));
+    if (rotation) HIP_TRY(hipMemcpyAsync(rotation, w->host.R[cur], N, k, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int coralai_set_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids, const float* cppn_params) {
+    WORLD_GUARD(w);
+    if (n < 0 || n > w->host.cap) return fail(CORALAI_E_INVALID, "n must be in [0, capacity]");
+    if (n == 0) return CORALAI_OK;
+    if (!slot_ids || !cppn_params) return fail(CORALAI_E_INVALID, "slot_ids / cppn_params is NULL");
+    for (int k = 0; k < n; ++k)
+        if (slot_ids[k] < 0 || slot_ids[k] >= w->host.cap)
+            return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", slot_ids[k], w->host.cap);
+    HIP_TRY(hipMemcpyAsync(w->host.stage_slots, slot_ids, 4 * (size_t)n, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.stage_params, cppn_params, 4 * (size_t)kNParam * n, hipMemcpyHostToDevice, w->stream));
+    launch_scatter_params(w->wdev, n, w->stream);
+    launch_cppn(w->wdev, 0, n, w->ls.n_cu, w->stream);
+    int rc = check_launch();
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return report_errors(w, nullptr);
+}
+
+int coralai_get_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids, float* out) {
+    WORLD_GUARD(w);
+    if (n < 0) return fail(CORALAI_E_INVALID, "n < 0");
+    for (int k = 0; k < n; ++k) {
+        if (slot_ids[k] < 0 || slot_ids[k] >= w->host.cap)
+            return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", slot_ids[k], w->host.cap);
+        HIP_TRY(hipMemcpyAsync(out + (size_t)k * kNParam, w->host.params + (size_t)slot_ids[k] * kNParam,
+                               4 * kNParam, hipMemcpyDeviceToHost, w->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
+    WORLD_GUARD(w);
+    if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
+    const bool use_graph = w->stream != nullptr && !w->profiling;
+    if (use_graph && (w->graph == nullptr || w->graph_act != w->act_cells || w->graph_phys != w->phys_tile)) {
+        destroy_graph(&w->graph);
+        int rc = capture_step(w->stream, w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec,
+                              w->act_cells, w->phys_tile, &w->graph);
+        if (rc) return rc;
+        w->graph_act = w->act_cells;
+        w->graph_phys = w->phys_tile;
+    }
+    for (int k = 0; k < n_steps; ++k) {
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(w->graph, w->stream));
+        } else {
+            const WorldDev& h = w->host;
+            int rc = timed_phase(w, 0, [&] { launch_bucket_only(w->bdev, w->ls, w->stream); });
+            if (!rc) rc = timed_phase(w, 1, [&] {
+                launch_act_only(w->bdev, w->ls, h.NL, h.HID, h.prec, w->act_cells, w->stream, nullptr);
+            });
+            if (!rc) rc = timed_phase(w, 2, [&] { launch_physics_only(w->bdev, w->ls, w->phys_tile, w->stream); });
+            if (!rc) rc = timed_phase(w, 3, [&] { launch_finalize(w->bdev, w->ls, w->stream); });
+            if (rc) return rc;
+        }
+    }
+    int rc = check_launch();
+    if (rc) return rc;
+    if (out) {
+        uint32_t word = 0;
+        rc = report_errors(w, &word);
+        fill_stats(*w->pinned, out);
+        out->error_word = word;
+        return rc;
+    }
+    return CORALAI_OK;
+}
+
+int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_index, coralai_stats* out) {
+    WORLD_GUARD(w);
+    if (!(rate >= 0.0 && rate <= 1.0)) return fail(CORALAI_E_INVALID, "rate must be in [0, 1]");
+    if (!(sigma >= 0.0f) || !std::isfinite(sigma)) return fail(CORALAI_E_INVALID, "sigma must be finite and >= 0");
+    uint64_t T;
+    if (rate <= 0.0) T = 0;
+    else if (rate >= 1.0) T = UINT64_MAX;
+    else T = (uint64_t)std::floor(rate * 18446744073709551616.0);
+    int rc = timed_phase(w, 4, [&] {
+        launch_radiate(w->bdev, w->wdev, w->ls, w->L.n_rad_blocks, T, sigma, step_index, w->stream);
+    });
+    if (rc) return rc;
+    rc = check_launch();
+    if (rc) return rc;
+    if (out) {
+        uint32_t word = 0;
+        rc = report_errors(w, &word);
+        fill_stats(*w->pinned, out);
+        out->error_word = word;
+        return rc;
+    }
+    return CORALAI_OK;
+}
+
+int coralai_sync(coralai_world* w) {
+    WORLD_GUARD(w);
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return report_errors(w, nullptr);
+}
+
+int coralai_get_stats(coralai_world* w, coralai_stats* out) {
+    WORLD_GUARD(w);
+    if (!out) return fail(CORALAI_E_INVALID, "out is NULL");
+    uint32_t word = 0;
+    int rc = report_errors(w, &word);
+    fill_stats(*w->pinned, out);
+    out->error_word = word;
+    return rc;
+}
+
+int coralai_set_profiling(coralai_world* w, int on) {
+    WORLD_GUARD(w);
+    int rc = harvest_profile(w);
+    if (rc) return rc;
+    w->profiling = on != 0;
+    for (int k = 0; k < CORALAI_PHASES; ++k) { w->prof_ms[k] = 0.0; w->prof_n[k] = 0; }
+    return CORALAI_OK;
+}
+
+int coralai_get_profile(coralai_world* w, double* ms_sum, int64_t* launches) {
+    WORLD_GUARD(w);
+    int rc = harvest_profile(w);
+    if (rc) return rc;
+    for (int k = 0; k < CORALAI_PHASES; ++k) {
+        if (ms_sum) ms_sum[k] = w->prof_ms[k];
+        if (launches) launches[k] = w->prof_n[k];
+    }
+    return CORALAI_OK;
+}
+
+int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t phys_tile) {
+    WORLD_GUARD(w);
+    if (act_cells != 1 && act_cells != 2 && act_cells != 4) return fail(CORALAI_E_INVALID, "act_cells must be 1, 2 or 4");
+    if (phys_tile < 0 || phys_tile > 2) return fail(CORALAI_E_INVALID, "phys_tile must be 0, 1 or 2");
+    w->act_cells = act_cells;
+    w->phys_tile = phys_tile;
+    return write_world_tables(w);
+}
+
+int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* phys_tile_out) {
+    WORLD_GUARD(w);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto timed = [&](auto&& fn) -> float {
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, w->stream);
+            fn();
+            (void)hipEventRecord(e1, w->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    // the kernels are idempotent on the current state until the buffers swap
+    launch_bucket_only(w->bdev, w->ls, w->stream);
+    float best_act = 1e30f;
+    int act = 2;
+    for (int c : {1, 2, 4}) {
+        float t = timed([&] { launch_act_only(w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec, c, w->stream, nullptr); });
+        if (t < best_act) { best_act = t; act = c; }
+    }
+    float best_phys = 1e30f;
+    int pt = 0;
+    for (int t = 0; t < 3; ++t) {
+        w->phys_tile = t;
+        int rc = write_world_tables(w);
+        if (rc) return rc;
+        float ms = timed([&] { launch_physics_only(w->bdev, w->ls, t, w->stream); });
+        if (ms < best_phys) { best_phys = ms; pt = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    w->act_cells = act;
+    w->phys_tile = pt;
+    int rc = write_world_tables(w);
+    if (rc) return rc;
+    rc = check_launch();
+    if (rc) return rc;
+    if (act_cells_out) *act_cells_out = act;
+    if (phys_tile_out) *phys_tile_out = pt;
+    return report_errors(w, nullptr);
+}
+
+// ------------------------------------------------------------------ batches
+
+size_t coralai_batch_bytes(int32_t max_worlds) {
+    if (max_worlds < 1 || max_worlds > (1 << 16)) return 0;
+    const size_t m = (size_t)max_worlds;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = align_up(off, kAlign); off += bytes; };
+    take(sizeof(BatchDev));
+    take(sizeof(WorldDev) * m);
+    take(8 * (m + 1));
+    take(8 * (m + 1));
+    take(4 * (m + 1));
+    take(4 * m);
+    return align_up(off, kAlign) + kAlign;
+}
+
+int coralai_batch_create(int32_t max_worlds, void* dev_arena, size_t arena_bytes, void* hip_stream,
+                         coralai_batch** out) {
+    if (!out) return fail(CORALAI_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const size_t need = coralai_batch_bytes(max_worlds);
+    if (!need) return fail(CORALAI_E_INVALID, "max_worlds must be in [1, 65536]");
+    if (!dev_arena) return fail(CORALAI_E_INVALID, "dev_arena is NULL");
+    if (arena_bytes < need) return fail(CORALAI_E_NOMEM, "batch arena of %zu bytes < %zu", arena_bytes, need);
+    coralai_batch* b = new coralai_batch();
+    b->max_worlds = max_worlds;
+    b->stream = (hipStream_t)hip_stream;
+    b->base = (uint8_t*)align_up((uintptr_t)dev_arena, kAlign);
+    const size_t m = (size_t)max_worlds;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = align_up(off, kAlign); size_t o = off; off += bytes; return b->base + o; };
+    b->bdev = (BatchDev*)take(sizeof(BatchDev));
+    b->table = (WorldDev*)take(sizeof(WorldDev) * m);
+    b->chunk_prefix = (int64_t*)take(8 * (m + 1));
+    b->tile_prefix = (int64_t*)take(8 * (m + 1));
+    b->group_prefix = (int32_t*)take(4 * (m + 1));
+    b->tiles_x = (int32_t*)take(4 * m);
+    b->ls = make_shape(max_worlds, 1 << 14);
+    BatchDev hb{};
+    hb.n_worlds = 0;
+    hb.worlds = b->table;
+    hb.chunk_prefix = b->chunk_prefix;
+    hb.tile_prefix = b->tile_prefix;
+    hb.group_prefix = b->group_prefix;
+    hb.tiles_x = b->tiles_x;
+    if (hipMemcpyAsync(b->bdev, &hb, sizeof hb, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        delete b;
+        return fail(CORALAI_E_HIP, "batch table upload failed");
+    }
+    *out = b;
+    return CORALAI_OK;
+}
+
+int coralai_batch_set_worlds(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
+    if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
+    BusyGuard guard_(&b->busy);
+    if (!guard_.ok) return fail(CORALAI_E_BUSY, "batch is in use");
+    if (n < 0 || n > b->max_worlds) return fail(CORALAI_E_INVALID, "n must be in [0, max_worlds]");
+    if (n > 0 && !worlds) return fail(CORALAI_E_INVALID, "worlds is NULL");
+    std::vector<WorldDev> tab(n);
+    std::vector<int64_t> cp(n + 1, 0), tp(n + 1, 0);
+    std::vector<int32_t> tx(std::max(n, 1), 0);
+    for (int k = 0; k < n; ++k) {
+        coralai_world* w = worlds[k];
+        if (!w) return fail(CORALAI_E_INVALID, "world %d is NULL", k);
+        if (k == 0) { b->NL = w->host.NL; b->HID = w->host.HID; b->prec = w->host.prec; }
+        if (w->host.NL != b->NL || w->host.HID != b->HID || w->host.prec != b->prec)
+            return fail(CORALAI_E_INVALID, "world %d: a batch needs one network shape and precision", k);
+        tab[k] = w->host;
+        cp[k + 1] = cp[k] + ((int64_t)w->host.N + kChunkCells - 1) / kChunkCells;
+        int t = 0;
+        tp[k + 1] = tp[k] + tiles_for(w->host.W, w->host.H, b->phys_tile, &t);
+        tx[k] = t;
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (n > 0) {
+        HIP_TRY(hipMemcpyAsync(b->table, tab.data(), sizeof(WorldDev) * n, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->tiles_x, tx.data(), 4 * (size_t)n, hipMemcpyHostToDevice, b->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(b->chunk_prefix, cp.data(), 8 * (size_t)(n + 1), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->tile_prefix, tp.data(), 8 * (size_t)(n + 1), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(&b->bdev->n_worlds, &n, sizeof n, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->n = n;
+    b->worlds.assign(worlds, worlds + n);
+    return CORALAI_OK;
+}
+
+int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
+    if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
+    BusyGuard guard_(&b->busy);
+    if (!guard_.ok) return fail(CORALAI_E_BUSY, "batch is in use");
+    if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
+    if (b->n == 0 || n_steps == 0) return CORALAI_OK;
+    const bool use_graph = b->stream != nullptr;
+    if (use_graph && (b->graph == nullptr || b->graph_act != b->act_cells || b->graph_phys != b->phys_tile)) {
+        destroy_graph(&b->graph);
+        int rc = capture_step(b->stream, b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells,
+                              b->phys_tile, &b->graph);
+        if (rc) return rc;
+        b->graph_act = b->act_cells;
+        b->graph_phys = b->phys_tile;
+    }
+    for (int k = 0; k < n_steps; ++k) {
+        if (use_graph) HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+        else launch_step_kernels(b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells, b->phys_tile, b->stream, nullptr);
+    }
+    return check_launch();
+}
+
+int coralai_batch_sync(coralai_batch* b) {
+    if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return CORALAI_OK;
+}
+
+int coralai_batch_destroy(coralai_batch* b) {
+    if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
+    (void)hipStreamSynchronize(b->stream);
+    destroy_graph(&b->graph);
+    delete b;
+    return CORALAI_OK;
+}
+
+// ------------------------------------------------------------------ parity hooks
+
+int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, int32_t* perm) {
+    WORLD_GUARD(w);
+    launch_bucket_only(w->bdev, w->ls, w->stream);
+    int rc = check_launch();
+    if (rc) return rc;
+    const size_t cap = (size_t)w->host.cap, N = (size_t)w->host.N;
+    if (counts) HIP_TRY(hipMemcpyAsync(counts, w->host.counts, 4 * cap, hipMemcpyDeviceToHost, w->stream));
+    if (offsets) HIP_TRY(hipMemcpyAsync(offsets, w->host.offsets, 4 * (cap + 1), hipMemcpyDeviceToHost, w->stream));
+    if (perm) HIP_TRY(hipMemcpyAsync(perm, w->host.perm, 4 * N, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return report_errors(w, nullptr);
+}
+
+int coralai_debug_actuators(coralai_world* w, float* act) {
+    WORLD_GUARD(w);
+    if (!act) return fail(CORALAI_E_INVALID, "act is NULL");
+    const size_t N = (size_t)w->host.N;
+    float* d = nullptr;
+    HIP_TRY(hipMalloc((void**)&d, 4 * kNOut * N));
+    launch_bucket_only(w->bdev, w->ls, w->stream);
+    launch_act_only(w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec, w->act_cells, w->stream, d);
+    int rc = check_launch();
+    if (!rc && hipMemcpyAsync(act, d, 4 * kNOut * N, hipMemcpyDeviceToHost, w->stream) != hipSuccess)
+        rc = fail(CORALAI_E_HIP, "actuator copy failed");
+    if (!rc && hipStreamSynchronize(w->stream) != hipSuccess) rc = fail(CORALAI_E_HIP, "sync failed");
+    (void)hipFree(d);
+    if (rc) return rc;
+    return report_errors(w, nullptr);
+}
+
+int coralai_debug_set_weights(coralai_world* w, int32_t slot, const float* flat) {
+    WORLD_GUARD(w);
+    if (slot < 0 || slot >= w->host.cap || !flat) return fail(CORALAI_E_INVALID, "bad slot or NULL weights");
+    const size_t n = (size_t)net_flat_size(w->host.NL, w->host.HID);
+    float* d = nullptr;
+    HIP_TRY(hipMalloc((void**)&d, 4 * n));
+    int rc = CORALAI_OK;
+    if (hipMemcpyAsync(d, flat, 4 * n, hipMemcpyHostToDevice, w->stream) != hipSuccess) rc = fail(CORALAI_E_HIP, "copy failed");
+    if (!rc) {
+        launch_pack_weights(w->wdev, slot, d, 0, nullptr, w->stream);
+        rc = check_launch();
+    }
+    if (!rc && hipStreamSynchronize(w->stream) != hipSuccess) rc = fail(CORALAI_E_HIP, "sync failed");
+    (void)hipFree(d);
+    return rc;
+}
+
+int coralai_debug_get_weights(coralai_world* w, int32_t slot, float* flat) {
+    WORLD_GUARD(w);
+    if (slot < 0 || slot >= w->host.cap || !flat) return fail(CORALAI_E_INVALID, "bad slot or NULL output");
+    const size_t n = (size_t)net_flat_size(w->host.NL, w->host.HID);
+    float* d = nullptr;
+    HIP_TRY(hipMalloc((void**)&d, 4 * n));
+    launch_pack_weights(w->wdev, slot, nullptr, 1, d, w->stream);
+    int rc = check_launch();
+    if (!rc && hipMemcpyAsync(flat, d, 4 * n, hipMemcpyDeviceToHost, w->stream) != hipSuccess) rc = fail(CORALAI_E_HIP, "copy failed");
+    if (!rc && hipStreamSynchronize(w->stream) != hipSuccess) rc = fail(CORALAI_E_HIP, "sync failed");
+    (void)hipFree(d);
+    return rc;
+}
+
+int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* flows8, const uint8_t* explore_dir) {
+    WORLD_GUARD(w);
+    if (!i1 || !flows8 || !explore_dir) return fail(CORALAI_E_INVALID, "a record array is NULL");
+    int cur = 0, rc = current_buffer(w, &cur);
+    if (rc) return rc;
+    const size_t N = (size_t)w->host.N;
+    std::vector<uint32_t> planes(8 * N);
+    for (size_t i = 0; i < N; ++i)
+        for (int k = 0; k < 8; ++k) planes[k * N + i] = flows8[i * 8 + k];
+    const int nxt = cur ^ 1;
+    HIP_TRY(hipMemcpyAsync(w->host.flow, planes.data(), 4 * 8 * N, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.I1, i1, 8 * N, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.X, explore_dir, N, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.E[nxt], w->host.E[cur], 8 * N, hipMemcpyDeviceToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.C[nxt], w->host.C[cur], 16 * N, hipMemcpyDeviceToDevice, w->stream));
+    launch_physics_only(w->bdev, w->ls, w->phys_tile, w->stream);
+    launch_flip(w->bdev, w->stream);
+    rc = check_launch();
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+"""Convenience wrappers over the C ABI: a World owns its torch-allocated
+device arena and its library handle; a Batch groups worlds for the batched
+form.  All compute happens in libcoralai.so."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def make_desc(width: int, height: int, n_weight_layers: int = 2, hidden: int = 32,
+              genome_capacity: int = 16, precision: int = 0, seed: int = 0,
+              rho_invest: float = 0.1, rho_liquidate: float = 0.1,
+              kappa_flow: float = 0.25) -> B.coralai_world_desc:
+    return B.coralai_world_desc(width, height, n_weight_layers, hidden, genome_capacity,
+                                precision, seed, rho_invest, rho_liquidate, kappa_flow, 0)
+
+
+def desc_from_spec(spec) -> B.coralai_world_desc:
+    return make_desc(spec.width, spec.height, spec.n_weight_layers, spec.hidden,
+                     spec.genome_capacity, spec.precision, spec.seed, spec.rho_invest,
+                     spec.rho_liquidate, spec.kappa_flow)
+
+
+class World:
+    def __init__(self, desc: B.coralai_world_desc, stream: torch.cuda.Stream | None = None,
+                 device: str = "cuda"):
+        self.desc = desc
+        self.nbytes = B.coralai_world_bytes(desc)
+        if self.nbytes == 0:
+            raise ValueError("invalid world description")
+        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        sp = stream.cuda_stream if stream is not None else 0
+        torch.cuda.synchronize()
+        self.h = B.coralai_world_create(desc, self.arena.data_ptr(), self.nbytes, sp)
+        self.W, self.H = desc.width, desc.height
+        self.N = self.W * self.H
+
+    @classmethod
+    def from_init(cls, init, stream=None, precision: int | None = None) -> "World":
+        d = desc_from_spec(init.spec)
+        if precision is not None:
+            d.precision = precision
+        w = cls(d, stream)
+        w.set_state(init.E, init.I, init.C, init.G, init.R)
+        w.set_genomes(init.slots, init.params)
+        return w
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None:
+            B.coralai_world_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, E, I, C, G, R) -> None:
+        c = lambda a, t: np.ascontiguousarray(a, dtype=t)
+        B.coralai_set_state(self.h, c(E, np.int64), c(I, np.int64), c(C, np.float32),
+                            c(G, np.int32), c(R, np.uint8), 0)
+
+    def get_state(self) -> dict:
+        H, W = self.H, self.W
+        E = np.empty((H, W), np.int64)
+        I = np.empty((H, W), np.int64)
+        C = np.empty((4, H, W), np.float32)
+        G = np.empty((H, W), np.int32)
+        R = np.empty((H, W), np.uint8)
+        B.coralai_get_state(self.h, E, I, C, G, R, 0)
+        return {"E": E, "I": I, "C": C, "G": G, "R": R}
+
+    def set_genomes(self, slots, params) -> None:
+        B.coralai_set_genomes(self.h, np.ascontiguousarray(slots, dtype=np.int32),
+                              np.ascontiguousarray(params, dtype=np.float32))
+
+    def get_genomes(self, slots) -> np.ndarray:
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        out = np.empty((s.size, 56), np.float32)
+        B.coralai_get_genomes(self.h, s, out)
+        return out
+
+    def step(self, n: int = 1, stats: bool = False) -> dict | None:
+        if stats:
+            st = B.coralai_stats()
+            B.coralai_step(self.h, n, st)
+            return st.as_dict()
+        B.coralai_step(self.h, n, None)
+        return None
+
+    def radiate(self, rate: float, sigma: float, step_index: int, stats: bool = True):
+        if stats:
+            st = B.coralai_stats()
+            B.coralai_radiate(self.h, rate, sigma, step_index, st)
+            return st.as_dict()
+        B.coralai_radiate(self.h, rate, sigma, step_index, None)
+        return None
+
+    def sync(self) -> None:
+        B.coralai_sync(self.h)
+
+    def stats(self) -> dict:
+        st = B.coralai_stats()
+        B.coralai_get_stats(self.h, st)
+        return st.as_dict()
+
+    def autotune(self) -> tuple[int, int]:
+        return B.coralai_autotune(self.h)
+
+    def set_tuning(self, act_cells: int, phys_tile: int) -> None:
+        B.coralai_set_tuning(self.h, act_cells, phys_tile)
+
+    def set_profiling(self, on: bool) -> None:
+        B.coralai_set_profiling(self.h, on)
+
+    def profile(self) -> dict:
+        """{phase: (summed ms, launches)} of the steps timed since profiling began."""
+        return B.coralai_get_profile(self.h)
+
+    # parity hooks
+    def debug_buckets(self):
+        cap = self.desc.genome_capacity
+        counts = np.empty(cap, np.int32)
+        offsets = np.empty(cap + 1, np.int32)
+        perm = np.empty(self.N, np.int32)
+        B.coralai_debug_buckets(self.h, counts, offsets, perm)
+        return counts, offsets, perm
+
+    def debug_actuators(self) -> np.ndarray:
+        act = np.empty((self.N, 14), np.float32)
+        B.coralai_debug_actuators(self.h, act)
+        return act.reshape(self.H, self.W, 14)
+
+    def debug_set_weights(self, slot: int, flat) -> None:
+        B.coralai_debug_set_weights(self.h, slot, np.ascontiguousarray(flat, dtype=np.float32))
+
+    def debug_get_weights(self, slot: int, size: int) -> np.ndarray:
+        out = np.zeros(size, np.float32)
+        B.coralai_debug_get_weights(self.h, slot, out)
+        return out
+
+    def debug_physics(self, i1, flows8, explore) -> None:
+        B.coralai_debug_physics(self.h, np.ascontiguousarray(i1, dtype=np.int64).ravel(),
+                                np.ascontiguousarray(flows8, dtype=np.uint32).reshape(-1, 8),
+                                np.ascontiguousarray(explore, dtype=np.uint8).ravel())
+
+
+class Batch:
+    def __init__(self, max_worlds: int, stream: torch.cuda.Stream | None = None,
+                 device: str = "cuda"):
+        self.nbytes = B.coralai_batch_bytes(max_worlds)
+        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        torch.cuda.synchronize()
+        self.h = B.coralai_batch_create(max_worlds, self.arena.data_ptr(), self.nbytes,
+                                        stream.cuda_stream if stream is not None else 0)
+        self.worlds: list[World] = []
+
+    def set_worlds(self, worlds: list[World]) -> None:
+        self.worlds = list(worlds)
+        B.coralai_batch_set_worlds(self.h, [w.h for w in worlds])
+
+    def step(self, n: int = 1) -> None:
+        B.coralai_batch_step(self.h, n)
+
+    def sync(self) -> None:
+        B.coralai_batch_sync(self.h)
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None:
+            B.coralai_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,99 @@
+"""Shared helpers of the GPU parity tests: world construction from a seeded
+input, oracle runs on the same input, and the comparison rules.
+
+Comparison rules (floating point: normwise per channel; integers: exact
+outside the near-tie band):
+  * C', E, I:  max|gpu - oracle| <= TOL * max|oracle| per channel, TOL = 1e-5;
+  * G, R:      bit-exact wherever the oracle's FP64 decision margins are
+               outside the near-tie band -- the flow-logit gap of every
+               neighbour whose top two explore directions include the cell
+               is >= 1e-4, |v_win - I1| >= 1e-5 * max(v_win, I1) + 64 quanta,
+               and, when the winner takes over, v_win - v_second is as large;
+               cells inside the band are counted and must be rare;
+  * mass:      exact (int64 sum of the GPU state == the input's sum; the GPU's
+               FP64 reduction equals it exactly).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import workloads as wl
+
+TOL = 1e-5
+GAP_BAND = 1e-4
+
+
+def oracle_desc(spec) -> "oracle.Desc":
+    return oracle.Desc.from_spec(spec)
+
+
+def make_world(init, stream=None, precision=None):
+    from paper_2406_09654_amd.world import World
+    return World.from_init(init, stream=stream, precision=precision)
+
+
+def oracle_state_from(st: dict) -> "oracle.State":
+    return oracle.State(st["E"].astype(np.int64), st["I"].astype(np.int64),
+                        st["C"].astype(np.float64), st["G"].astype(np.int32),
+                        st["R"].astype(np.uint8))
+
+
+def band_mask(margins: np.ndarray) -> np.ndarray:
+    thr = 1e-5 * margins[..., 3] + 64.0
+    return (margins[..., 0] < GAP_BAND) | (margins[..., 1] < thr) | (margins[..., 2] < thr)
+
+
+def normwise(gpu: np.ndarray, ref: np.ndarray) -> float:
+    scale = float(np.max(np.abs(ref))) if ref.size else 0.0
+    err = float(np.max(np.abs(gpu.astype(np.float64) - ref.astype(np.float64)))) if ref.size else 0.0
+    return err / scale if scale > 0 else err
+
+
+def compare_step(gpu_out: dict, ref: "oracle.State", margins: np.ndarray, rows=None,
+                 tol: float = TOL, max_band_frac: float = 1e-3):
+    """Assert one step's parity; returns a report dict."""
+    sl = slice(None) if rows is None else slice(rows[0], rows[1])
+    rep = {}
+    for ch in ("E", "I"):
+        rep[ch] = normwise(gpu_out[ch][sl], getattr(ref, ch)[sl])
+    rep["C"] = max(normwise(gpu_out["C"][c][sl], ref.C[c][sl]) for c in range(4))
+    band = band_mask(margins[sl])
+    g_bad = (gpu_out["G"][sl] != ref.G[sl]) & ~band
+    r_bad = (gpu_out["R"][sl] != ref.R[sl]) & ~band
+    rep["band_cells"] = int(band.sum())
+    rep["band_frac"] = float(band.mean()) if band.size else 0.0
+    rep["G_mismatch_outside_band"] = int(g_bad.sum())
+    rep["R_mismatch_outside_band"] = int(r_bad.sum())
+    rep["G_mismatch_total"] = int((gpu_out["G"][sl] != ref.G[sl]).sum())
+    assert rep["E"] <= tol and rep["I"] <= tol and rep["C"] <= tol, rep
+    assert rep["G_mismatch_outside_band"] == 0 and rep["R_mismatch_outside_band"] == 0, rep
+    assert rep["band_frac"] <= max_band_frac, rep
+    return rep
+
+
+def oracle_nets(d, params: np.ndarray, slots=None, cap=None) -> np.ndarray:
+    """FP64 networks indexed by slot id."""
+    if slots is None:
+        return oracle.nets_for(d, params)
+    cap = cap if cap is not None else int(np.max(slots)) + 1
+    nets = np.zeros((cap, oracle.net_size(d)))
+    for k, s in enumerate(slots):
+        nets[s] = oracle.cppn_to_net(d, params[k])
+    return nets
+
+
+def heterogeneous_world(W, H, n_genomes=4, seed=0, hidden=32, layers=2, precision=0,
+                        capacity=None, scale=1.0) -> "wl.WorldInit":
+    """A world whose infrastructure is sparse and heavy-tailed, random rotations
+    and comm: exercises takeovers and every kernel position."""
+    rng = np.random.default_rng(seed)
+    spec = wl.WorldSpec(W, H, layers, hidden, capacity or n_genomes, precision, seed)
+    E = wl.to_ledger(rng.random((H, W)))
+    inf = rng.random((H, W)) ** 3 * (rng.random((H, W)) < 0.6) * 2.0
+    I = wl.to_ledger(inf)
+    C = rng.random((4, H, W)).astype(np.float32)
+    G = rng.integers(0, n_genomes, size=(H, W)).astype(np.int32)
+    R = rng.integers(0, 8, size=(H, W)).astype(np.uint8)
+    params = (rng.standard_normal((n_genomes, 56)) * scale).astype(np.float32)
+    return wl.WorldInit(spec, E, I, C, G, R, np.arange(n_genomes, dtype=np.int32), params)

@@ -1,0 +1,365 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Sizes span several tiles and ragged tails; the
+full-size workloads are checked on row bands the oracle computes exactly."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def stream():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2406_09654_amd as P
+    P.lib()
+    return torch.cuda.Stream()
+
+
+# ------------------------------------------------------------------ pieces
+
+@pytest.mark.parametrize("layers,hidden,prec", [(2, 32, 0), (3, 64, 0), (2, 64, 1), (3, 32, 1)])
+def test_cppn_weights_match_oracle(stream, layers, hidden, prec):
+    say("cppn", layers, hidden, prec)
+    init = gh.heterogeneous_world(8, 8, n_genomes=5, layers=layers, hidden=hidden, precision=prec,
+                                  seed=3, scale=1.0)
+    w = gh.make_world(init, stream)
+    d = gh.oracle_desc(init.spec)
+    size = oracle.net_size(d)
+    for s in range(5):
+        got = w.debug_get_weights(s, size)
+        ref = oracle.cppn_to_net(d, init.params[s].astype(np.float64))
+        tol = 1e-6 if prec == 0 else 4e-3   # fp32: FP64 CPPN rounded once; bf16: 2^-9 relative
+        assert gh.normwise(got, ref) <= tol, (s, gh.normwise(got, ref))
+    w.close()
+
+
+def test_debug_weights_roundtrip(stream):
+    init = gh.heterogeneous_world(4, 4, n_genomes=2, layers=3, hidden=64, seed=1)
+    w = gh.make_world(init, stream)
+    d = gh.oracle_desc(init.spec)
+    flat = np.random.default_rng(0).standard_normal(oracle.net_size(d)).astype(np.float32)
+    w.debug_set_weights(1, flat)
+    np.testing.assert_array_equal(w.debug_get_weights(1, flat.size), flat)
+    w.close()
+
+
+@pytest.mark.parametrize("W,H,ng,cap", [(1, 1, 1, 1), (37, 23, 5, 9), (64, 64, 16, 16),
+                                        (300, 200, 70, 128)])
+def test_buckets_match_numpy(stream, W, H, ng, cap):
+    say("buckets", W, H)
+    init = gh.heterogeneous_world(W, H, n_genomes=ng, capacity=cap, seed=W)
+    w = gh.make_world(init, stream)
+    counts, offsets, perm = w.debug_buckets()
+    G = init.G.ravel()
+    ref_c = np.bincount(G, minlength=cap)
+    np.testing.assert_array_equal(counts, ref_c)
+    np.testing.assert_array_equal(offsets, np.concatenate([[0], np.cumsum(ref_c)]))
+    # perm: each genome's segment holds exactly its cells (order inside unspecified)
+    assert np.array_equal(np.sort(perm), np.arange(W * H))
+    np.testing.assert_array_equal(G[perm], np.repeat(np.arange(cap), ref_c))
+    w.close()
+
+
+@pytest.mark.parametrize("W,H,layers,hidden,act_cells", [(37, 23, 2, 32, 1), (64, 64, 2, 32, 2),
+                                                         (65, 3, 3, 64, 4), (130, 70, 3, 64, 2),
+                                                         (5, 7, 2, 64, 4)])
+def test_actuators_match_oracle_fp32(stream, W, H, layers, hidden, act_cells):
+    say("act", W, H, layers, hidden, act_cells)
+    init = gh.heterogeneous_world(W, H, n_genomes=7, layers=layers, hidden=hidden, seed=W + H)
+    w = gh.make_world(init, stream)
+    w.set_tuning(act_cells, 0)
+    act = w.debug_actuators()
+    d = gh.oracle_desc(init.spec)
+    s = oracle.State.from_init(init)
+    _, info = oracle.step(d, s, oracle.nets_for(d, init.params), want_act=True)
+    err = gh.normwise(act, info["act"])
+    assert err <= gh.TOL, err
+    w.close()
+
+
+def test_physics_from_oracle_records_is_bit_exact(stream):
+    say("physics from records")
+    for (W, H, tile) in [(37, 23, 0), (64, 64, 1), (70, 33, 2), (1, 1, 0), (2, 2, 1), (3, 5, 2)]:
+        init = gh.heterogeneous_world(W, H, n_genomes=4, seed=W * 7 + H)
+        d = gh.oracle_desc(init.spec)
+        s = oracle.State.from_init(init)
+        _, info = oracle.step(d, s, oracle.nets_for(d, init.params), want_records=True)
+        rec = info["records"].ravel()
+        I2, G2, R2, tk = oracle.physics_from_records(d, rec["i1"], rec["flow"], rec["explore_dir"],
+                                                     init.G, init.R)
+        w = gh.make_world(init, stream)
+        w.set_tuning(2, tile)
+        w.debug_physics(rec["i1"], rec["flow"].astype(np.uint32), rec["explore_dir"].astype(np.uint8))
+        out = w.get_state()
+        np.testing.assert_array_equal(out["I"], I2)
+        np.testing.assert_array_equal(out["G"], G2)
+        np.testing.assert_array_equal(out["R"], R2)
+        np.testing.assert_array_equal(out["E"], init.E)
+        w.close()
+
+
+# ------------------------------------------------------------------ whole step
+
+STEP_CASES = [(1, 1, 2, 32), (2, 2, 2, 32), (3, 5, 3, 64), (37, 23, 2, 32), (64, 64, 3, 64),
+              (130, 70, 2, 32), (257, 65, 3, 64)]
+
+
+@pytest.mark.parametrize("W,H,layers,hidden", STEP_CASES)
+def test_single_step_matches_oracle_fp32(stream, W, H, layers, hidden):
+    say("step", W, H, layers, hidden)
+    init = gh.heterogeneous_world(W, H, n_genomes=6, layers=layers, hidden=hidden, seed=W * 3 + H)
+    w = gh.make_world(init, stream)
+    st = w.step(1, stats=True)
+    out = w.get_state()
+    d = gh.oracle_desc(init.spec)
+    ref, info = oracle.step(d, oracle.State.from_init(init), oracle.nets_for(d, init.params),
+                            want_margins=True)
+    rep = gh.compare_step(out, ref, info["margins"], max_band_frac=0.05)
+    m0 = int(init.E.sum() + init.I.sum())
+    assert int(out["E"].sum() + out["I"].sum()) == m0
+    assert st["mass_quanta"] == m0 and st["mass_fp64"] == float(m0)
+    assert st["error_word"] == 0
+    say("  report", rep, "takeovers gpu", st["takeovers"], "oracle", info["takeovers"])
+    w.close()
+
+
+def test_plain_64_trajectory_snapshots(stream):
+    """The 64x64 plain-method workload: single steps from GPU states taken
+    along a 100-step GPU trajectory (steps 0, 10, 50, 99)."""
+    init = wl.config_plain_64()
+    w = gh.make_world(init, stream)
+    d = gh.oracle_desc(init.spec)
+    nets = oracle.nets_for(d, init.params)
+    m0 = int(init.E.sum() + init.I.sum())
+    done = 0
+    for snap in [0, 10, 50, 99]:
+        if snap > done:
+            w.step(snap - done)
+            done = snap
+        st_in = w.get_state()
+        stats = w.step(1, stats=True)
+        done += 1
+        out = w.get_state()
+        ref, info = oracle.step(d, gh.oracle_state_from(st_in), nets, want_margins=True)
+        rep = gh.compare_step(out, ref, info["margins"])
+        assert stats["mass_quanta"] == m0
+        say("  snapshot", snap, rep)
+    w.close()
+
+
+def test_blobs_1024_step_fp32_and_bf16_error(stream):
+    """1024x1024, 256 genomes: FP32 within tolerance; BF16 error reported."""
+    init = wl.config_blobs_1024(precision=0)
+    d = gh.oracle_desc(init.spec)
+    nets = oracle.nets_for(d, init.params)
+    ref, info = oracle.step(d, oracle.State.from_init(init), nets, want_margins=True)
+    w = gh.make_world(init, stream)
+    w.step(1)
+    rep = gh.compare_step(w.get_state(), ref, info["margins"])
+    say("  fp32 1024:", rep)
+    w.close()
+    wb = gh.make_world(init, stream, precision=1)
+    wb.step(1)
+    out = wb.get_state()
+    err = {ch: gh.normwise(out[ch], getattr(ref, ch)) for ch in ("E", "I")}
+    err["C"] = max(gh.normwise(out["C"][c], ref.C[c]) for c in range(4))
+    err["G_mismatch_rate"] = float((out["G"] != ref.G).mean())
+    say("  bf16 1024 error vs FP64 oracle:", err)
+    assert err["E"] < 1e-2 and err["I"] < 1e-2 and err["C"] < 5e-2
+    assert int(out["E"].sum() + out["I"].sum()) == int(init.E.sum() + init.I.sum())
+    wb.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_zipf_4096_row_bands(stream, prec):
+    """The 4096x4096 workload (4096 Zipf genomes, 54-64-64-14) at full size,
+    in the launch configuration the bench times: rows the oracle computes
+    exactly (top, middle, the wrap rows) compared with the GPU step."""
+    say("zipf 4096 prec", prec)
+    init = wl.config_zipf_4096(precision=prec)
+    w = gh.make_world(init, stream)
+    w.step(1)
+    out = w.get_state()
+    d = gh.oracle_desc(init.spec)
+    used = np.unique(np.concatenate([init.G[:9].ravel(), init.G[2040:2057].ravel(),
+                                     init.G[-9:].ravel()]))
+    nets = gh.oracle_nets(d, init.params[used], slots=used, cap=init.params.shape[0])
+    s = oracle.State.from_init(init)
+    for rows in [(0, 8), (2044, 2052), (4088, 4096)]:
+        ref, info = oracle.step(d, s, nets, rows=rows, want_margins=True)
+        if prec == 0:
+            rep = gh.compare_step(out, ref, info["margins"], rows=rows)
+        else:
+            sl = slice(*rows)
+            rep = {ch: gh.normwise(out[ch][sl], getattr(ref, ch)[sl]) for ch in ("E", "I")}
+            rep["G_mismatch_rate"] = float((out["G"][sl] != ref.G[sl]).mean())
+            assert rep["E"] < 1e-2 and rep["I"] < 1e-2
+        say("  rows", rows, rep)
+    assert int(out["E"].sum() + out["I"].sum()) == int(init.E.sum() + init.I.sum())
+    w.close()
+
+
+# ------------------------------------------------------------------ invariants on the GPU
+
+def test_translation_invariance_bit_identical(stream):
+    init = gh.heterogeneous_world(96, 64, n_genomes=5, seed=11)
+    w = gh.make_world(init, stream)
+    w.step(1)
+    base = w.get_state()
+    w.close()
+    for dx, dy in [(1, 0), (17, 5), (95, 63)]:
+        roll = lambda a: np.roll(a, (dy, dx), axis=(-2, -1))
+        ri = wl.WorldInit(init.spec, roll(init.E), roll(init.I), roll(init.C), roll(init.G),
+                          roll(init.R), init.slots, init.params)
+        w = gh.make_world(ri, stream)
+        w.step(1)
+        out = w.get_state()
+        for ch in ("E", "I", "C", "G", "R"):
+            np.testing.assert_array_equal(out[ch], roll(base[ch]))
+        w.close()
+
+
+def test_tuning_choices_and_graph_give_identical_results(stream):
+    init = gh.heterogeneous_world(150, 90, n_genomes=9, layers=3, hidden=64, seed=5)
+    outs = []
+    for act, tile, strm in [(1, 0, stream), (2, 1, stream), (4, 2, None), (2, 0, None)]:
+        w = gh.make_world(init, strm)
+        w.set_tuning(act, tile)
+        w.step(3)
+        outs.append(w.get_state())
+        w.close()
+    for o in outs[1:]:
+        for ch in ("E", "I", "C", "G", "R"):
+            np.testing.assert_array_equal(o[ch], outs[0][ch])
+
+
+def test_mass_conserved_many_steps(stream):
+    init = gh.heterogeneous_world(128, 96, n_genomes=8, seed=21)
+    w = gh.make_world(init, stream)
+    m0 = int(init.E.sum() + init.I.sum())
+    for _ in range(5):
+        st = w.step(10, stats=True)
+        assert st["mass_quanta"] == m0 and st["mass_fp64"] == float(m0)
+    out = w.get_state()
+    assert int(out["E"].sum() + out["I"].sum()) == m0
+    assert (out["E"] >= 0).all() and (out["I"] >= 0).all()
+    w.close()
+
+
+def test_autotune_keeps_state(stream):
+    init = gh.heterogeneous_world(200, 120, n_genomes=6, seed=2)
+    w = gh.make_world(init, stream)
+    before = w.get_state()
+    act, tile = w.autotune()
+    assert act in (1, 2, 4) and tile in (0, 1, 2)
+    after = w.get_state()
+    for ch in before:
+        np.testing.assert_array_equal(before[ch], after[ch])
+    w.close()
+
+
+# ------------------------------------------------------------------ radiation
+
+def test_radiate_matches_oracle(stream):
+    say("radiate")
+    W, H, cap = 300, 200, 400
+    init = gh.heterogeneous_world(W, H, n_genomes=40, capacity=cap, layers=3, hidden=64, seed=9,
+                                  scale=1.0)
+    w = gh.make_world(init, stream)
+    step_index, rate, sigma = 7, 2e-3, 0.1
+    st = w.radiate(rate, sigma, step_index)
+    out = w.get_state()
+    P = np.zeros((cap, 56))
+    P[:40] = init.params.astype(np.float64)
+    G2, P2, (hc, hs), dropped = oracle.radiate(init.G, cap, P, init.spec.seed, step_index, rate,
+                                               sigma)
+    np.testing.assert_array_equal(out["G"], G2)                  # hit set and slots: exact
+    assert st["hits"] == len(hc) and st["dropped_hits"] == dropped
+    new = hs[hs >= 0]
+    assert len(new) > 100
+    got = w.get_genomes(new)
+    np.testing.assert_allclose(got, P2[new], rtol=0, atol=2e-6)
+    d = gh.oracle_desc(init.spec)
+    for s in new[:10]:
+        ref = oracle.cppn_to_net(d, P2[s])
+        assert gh.normwise(w.debug_get_weights(int(s), ref.size), ref) <= 1e-5
+    w.close()
+
+
+def test_radiate_capacity_exhaustion_drops_deterministically(stream):
+    W, H, cap = 120, 100, 12
+    init = gh.heterogeneous_world(W, H, n_genomes=10, capacity=cap, seed=4)
+    w = gh.make_world(init, stream)
+    st = w.radiate(0.01, 0.1, 3)
+    G2, _, (hc, hs), dropped = oracle.radiate(init.G, cap, np.pad(init.params.astype(np.float64),
+                                                                  ((0, cap - 10), (0, 0))),
+                                              init.spec.seed, 3, 0.01, 0.1)
+    np.testing.assert_array_equal(w.get_state()["G"], G2)
+    assert st["dropped_hits"] == dropped > 0 and st["hits"] == len(hc)
+    w.close()
+
+
+# ------------------------------------------------------------------ batched form
+
+def test_batch_equals_each_world_alone(stream):
+    from paper_2406_09654_amd.world import Batch
+    inits = [gh.heterogeneous_world(s, s + 7 * k, n_genomes=3 + k, seed=100 + k, precision=1)
+             for k, s in enumerate([64, 96, 33, 130, 1, 200])]
+    alone = []
+    for init in inits:
+        w = gh.make_world(init, stream)
+        w.step(3)
+        alone.append(w.get_state())
+        w.close()
+    worlds = [gh.make_world(init, stream) for init in inits]
+    b = Batch(8, stream)
+    b.set_worlds(worlds)
+    b.step(3)
+    b.sync()
+    for k, w in enumerate(worlds):
+        out = w.get_state()
+        for ch in ("E", "I", "C", "G", "R"):
+            np.testing.assert_array_equal(out[ch], alone[k][ch])
+    # change the set without a new graph: drop two, step again
+    b.set_worlds(worlds[2:])
+    b.step(1)
+    b.sync()
+    for k, w in enumerate(worlds[2:], start=2):
+        w2 = gh.make_world(inits[k], stream)
+        w2.step(4)
+        ref = w2.get_state()
+        out = w.get_state()
+        for ch in ("E", "I", "G"):
+            np.testing.assert_array_equal(out[ch], ref[ch])
+        w2.close()
+    b.close()
+    for w in worlds:
+        w.close()
+
+
+# ------------------------------------------------------------------ error paths
+
+def test_bad_genome_is_reported(stream):
+    from paper_2406_09654_amd.binding import CoralaiError, CORALAI_E_GENOME
+    init = gh.heterogeneous_world(16, 16, n_genomes=3, capacity=4, seed=1)
+    init.G[3, 3] = 3          # slot 3 exists but has no parameters
+    w = gh.make_world(init, stream)
+    with pytest.raises(CoralaiError) as e:
+        w.step(1, stats=True)
+    assert e.value.code == CORALAI_E_GENOME
+    st = w.stats()            # reported once, then cleared
+    assert st["error_word"] == 0
+    w.close()
