@@ -64,7 +64,7 @@ enum {
 enum {
     CORALAI_ERR_GENOME_RANGE = 1u,
     CORALAI_ERR_GENOME_UNSET = 2u,
-    CORALAI_ERR_LEDGER = 4u,    /* negative stock or a flow budget >= 2^32 quanta */
+    CORALAI_ERR_LEDGER = 4u,    /* negative stock or a flow budget >= 2^31 quanta */
     CORALAI_ERR_NONFINITE = 8u  /* network output or CPPN weight not finite */
 };
 
@@ -73,7 +73,7 @@ enum {
  * invest / liquidate move floor(rho * sigmoid(a) * stock) quanta, the
  * exploration budget is floor(kappa * I1) quanta. */
 typedef struct {
-    int32_t width, height;    /* >= 1 each; W*H <= 2^30 */
+    int32_t width, height;    /* >= 1 each; W*H <= 2^28 */
     int32_t n_weight_layers;  /* 2: 54-h-14, 3: 54-h-h-14 */
     int32_t hidden;           /* 32 or 64 */
     int32_t genome_capacity;  /* slot ids in [0, capacity), 1 .. 2^22 */
@@ -170,7 +170,8 @@ int coralai_batch_destroy(coralai_batch* b);
 /* Launch tuning.  coralai_autotune times the candidate configurations on the
  * world's current state (without advancing it) and keeps the fastest;
  * coralai_set_tuning forces one (act_cells: column groups of 16 cells
- * processed together, 1, 2 or 4; phys_tile: 0 = 64x4, 1 = 32x8, 2 = 16x16). */
+ * processed together, 1, 2 or 4; phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8,
+ * 2 = 16x16, or 3 = streaming, one thread per cell without LDS). */
 int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* phys_tile_out);
 int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t phys_tile);
 
@@ -198,8 +199,8 @@ const char* coralai_version(void);
  *                   layout [W_0 (h x 54) row-major, b_0, W_1, b_1, ...] as
  *                   float; set marks the slot set;
  *  debug_physics:   run the physics alone from given records -- I1 [W*H]
- *                   int64, flows [W*H x 8] uint32 toward absolute directions
- *                   0..7, explore direction [W*H] uint8 -- on the current G,
+ *                   int64, flows [W*H x 8] uint32 (< 2^31) toward absolute
+ *                   directions 0..7, explore direction [W*H] uint8 -- on the current G,
  *                   R; the result becomes the current state with E and C
  *                   unchanged. */
 int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, int32_t* perm);

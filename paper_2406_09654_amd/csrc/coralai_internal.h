@@ -13,7 +13,10 @@ constexpr int kNParam = 56;   // CPPN parameters: A (8x5) then B (2x8)
 constexpr int kNIn = 54;      // 9 kernel positions x 6 sensor channels
 constexpr int kNOut = 14;     // invest, liquidate, 4 comm, 8 flow logits
 constexpr int kGroupCells = 64;   // cells per network work unit (one wavefront)
-constexpr int kChunkCells = 64;   // cells per bucketing unit (one wavefront)
+constexpr int kBucketTile = 64;   // bucketing tile: 64 x 64 cells
+constexpr int kBucketGroup = 4;   // tiles per bucketing unit (one block)
+constexpr int kSubCounters = 8;   // per-genome counters, spread to cut atomic contention
+constexpr int kSlotBlock = 4096;  // genome slots per scan block
 constexpr int kRadBlockCells = 4096;  // cells per radiation hit block (256 x 16)
 constexpr int kPrecFP32 = 0;
 constexpr int kPrecBF16 = 1;
@@ -56,13 +59,14 @@ struct WorldDev {
     float* C[2];          // 4 planes each
     int32_t* G[2];
     uint8_t* R[2];
-    uint32_t* flow;       // 8 planes: outflow toward absolute direction k
+    uint32_t* flow;       // 8 planes: (outflow toward direction k) << 1 | (k is explored)
     int64_t* I1;          // infrastructure after invest / liquidate
-    uint8_t* X;           // explore direction
+    uint32_t* out;        // total outflow of the cell
     int32_t* perm;        // cells grouped by genome
-    int32_t* counts;      // [cap]
+    int32_t* counts;      // [cap] cells per genome
     int32_t* offsets;     // [cap + 1]
-    int32_t* cursor;      // [cap]
+    int32_t* sub_counts;  // [kSubCounters][cap] partial counts
+    int32_t* cursor;      // [kSubCounters][cap] next free position of each partial range
     int32_t* gofs;        // [cap + 1] exclusive prefix of network units per genome
     uint8_t* slot_set;    // [cap]
     float* params;        // [cap][56]
@@ -78,6 +82,10 @@ struct WorldDev {
     int32_t* new_slots;   // [cap]
     int32_t* stage_slots; // [cap] slot list for set_genomes
     float* stage_params;  // [cap][56]
+    int32_t* scan_part;   // [n_slot_blocks * 4] per slot-block partial sums / prefixes
+    int32_t n_slot_blocks;
+    int32_t btiles_x;     // bucketing tiles per row
+    int32_t btiles;       // bucketing tiles of the world
     Ctl* ctl;
 };
 
@@ -86,7 +94,8 @@ struct BatchDev {
     int32_t n_worlds;
     int32_t pad;
     WorldDev* worlds;         // [max_worlds]
-    int64_t* chunk_prefix;    // [max_worlds + 1] bucketing units
+    int64_t* chunk_prefix;    // [max_worlds + 1] bucketing units (kBucketGroup tiles of 64 x 64)
+    int64_t* slot_prefix;     // [max_worlds + 1] genome-slot scan blocks
     int64_t* tile_prefix;     // [max_worlds + 1] physics tiles
     int32_t* group_prefix;    // [max_worlds + 1] network units (device computed)
     int32_t* tiles_x;         // [max_worlds] physics tiles per row
@@ -173,18 +182,50 @@ __device__ __forceinline__ int xcd_block() {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Scalar (constant address space) load of data that is invariant while the
+// kernel runs: prefix tables, counters written by earlier kernels.
+template <typename T>
+__device__ __forceinline__ T cld(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ int find_world(const T* prefix, int n, T u) {
     // largest w in [0, n) with prefix[w] <= u
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= u) lo = mid; else hi = mid - 1;
+        if (cld(prefix + mid) <= u) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Loads and stores through the global address space.  Pointers read from the
+// device-side world table are generic; casting them lets the compiler emit
+// global_load / global_store instead of flat accesses (which would also tie
+// up the LDS counter).
+#define CORALAI_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) { return *(const CORALAI_GLOBAL T*)p; }
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) { *(CORALAI_GLOBAL T*)p = v; }
+
+// The world table and the control block do not change while a kernel runs:
+// reading them through the constant address space gives scalar loads, so the
+// world's pointers and sizes stay in SGPRs.
+#define CORALAI_CONST __attribute__((address_space(4)))
+__device__ __forceinline__ const CORALAI_CONST WorldDev* world_at(const BatchDev* b, int wi) {
+    return (const CORALAI_CONST WorldDev*)(b->worlds + wi);
+}
+__device__ __forceinline__ int ctl_cur(const Ctl* c) { return ((const CORALAI_CONST Ctl*)c)->cur; }
+
+// int64 -> float with at most one extra rounding for values >= 2^32 (exact
+// conversion for the common |v| < 2^24, correctly rounded below 2^32).
+__device__ __forceinline__ float i64_to_f32(int64_t v) {
+    return __builtin_fmaf((float)(int32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
+}
 
 // Host-side launch shapes ----------------------------------------------------
 

@@ -18,7 +18,8 @@
 //   3. the 14 actuators go through LDS back to one cell per lane, and the
 //      epilogue computes the ledger conversion, the sigmoid communication,
 //      the quantised softmax flow plan and the argmax exploration, writing
-//      E', C' and the boundary record (I1, 8 flows, explore direction).
+//      E', C' and the boundary record (I1, the 8 flows each tagged with
+//      whether it is the explored direction, the total outflow).
 #include <type_traits>
 
 #include "coralai_internal.h"
@@ -78,8 +79,8 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 }
 
 template <int NL, int HID, int PREC, int CGI, bool DEBUG>
-__global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
-                                             float* __restrict__ dbg) {
+__global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
+    const BatchDev* __restrict__ b, float* __restrict__ dbg) {
     using NT = Net<NL, HID, PREC>;
     using frag_t = typename NT::frag_t;
     constexpr int MT = NT::MT, KS0 = NT::KS0, KSH = NT::KSH;
@@ -91,9 +92,9 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
     const int q = lane >> 4, n16 = lane & 15;
     uint8_t* stage = smem + wv * NT::STAGE_BYTES;
 
-    const int nworlds = b->n_worlds;
+    const int nworlds = cld(&b->n_worlds);
     if (nworlds <= 0) return;
-    const int total = b->group_prefix[nworlds];
+    const int total = cld(b->group_prefix + (nworlds));
     const int nwaves = gridDim.x * 4;
     const int per = (total + nwaves - 1) / nwaves;
     int u = uniform_i32((xcd_block() * 4 + wv) * per);
@@ -103,7 +104,6 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
     frag_t w0[MT][KS0];
     frag_t w1[MT1][KSH];
     frag_t wo[KSH];
-    floatx4 b0[MT], b1[MT1], bo;
 
     int wi = uniform_i32(find_world(b->group_prefix, nworlds, u));
     int world_lo = 0, world_hi = -1;
@@ -121,10 +121,11 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
     int64_t *En = nullptr, *I1p = nullptr;
     float* Cn = nullptr;
     uint32_t* flow = nullptr;
-    uint8_t* Xp = nullptr;
+    uint32_t* outp = nullptr;
     const int32_t *perm = nullptr, *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
+    const float* gbias = nullptr;  // the current genome's bias block
     int64_t wstride = 0;
     int bstride = 0;
     Ctl* ctl = nullptr;
@@ -145,18 +146,18 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
     for (; u < uend; ++u) {
         if (u >= world_hi) {
             flush();
-            while (b->group_prefix[wi + 1] <= u) ++wi;
+            while (cld(b->group_prefix + (wi + 1)) <= u) ++wi;
             wi = uniform_i32(wi);
-            world_lo = b->group_prefix[wi];
-            world_hi = b->group_prefix[wi + 1];
-            const WorldDev* W = &b->worlds[wi];
+            world_lo = cld(b->group_prefix + (wi));
+            world_hi = cld(b->group_prefix + (wi + 1));
+            const auto* W = world_at(b, wi);
             Wd = W->W; Hd = W->H; Nd = W->N; cap = W->cap;
             rho_i = W->rho_i; rho_l = W->rho_l; kappa = W->kappa;
             ctl = W->ctl;
-            const int cur = ctl->cur, nxt = cur ^ 1;
+            const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             Ec = W->E[cur]; Ic = W->I[cur]; Cc = W->C[cur]; Rc = W->R[cur];
             En = W->E[nxt]; Cn = W->C[nxt];
-            I1p = W->I1; flow = W->flow; Xp = W->X;
+            I1p = W->I1; flow = W->flow; outp = W->out;
             perm = W->perm; counts = W->counts; offsets = W->offsets; gofs = W->gofs;
             wfrag = W->wfrag; bias = W->bias; wstride = W->wfrag_stride; bstride = W->bias_stride;
             g = -1;
@@ -169,54 +170,47 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
             if (g >= 0) {
 #pragma unroll 1
                 for (int t = g + 1; t < min(cap, g + 5); ++t)
-                    if (gofs[t + 1] > k) { gn = t; break; }
+                    if (gld(gofs + t + 1) > k) { gn = t; break; }
             }
             if (gn < 0) {
                 int lo = 0, hi = cap - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (gofs[mid] <= k) lo = mid; else hi = mid - 1;
+                    if (gld(gofs + mid) <= k) lo = mid; else hi = mid - 1;
                 }
                 gn = lo;
             }
             g = uniform_i32(gn);
-            g_lo = gofs[g];
-            g_hi = gofs[g + 1];
+            g_lo = gld(gofs + g);
+            g_hi = gld(gofs + g + 1);
             // weights of genome g -> registers
             const uint8_t* wb = wfrag + (int64_t)g * wstride + lane * (NT::FRAG_BYTES / 64);
-            const float* bb = bias + (int64_t)g * bstride + 4 * q;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int s = 0; s < KS0; ++s)
-                    w0[mt][s] = *(const frag_t*)(wb + (mt * KS0 + s) * NT::FRAG_BYTES);
+                    w0[mt][s] = gld((const frag_t*)(wb + (mt * KS0 + s) * NT::FRAG_BYTES));
             if constexpr (NL == 3) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                     for (int s = 0; s < KSH; ++s)
-                        w1[mt][s] = *(const frag_t*)(wb + (NT::F0 + mt * KSH + s) * NT::FRAG_BYTES);
+                        w1[mt][s] = gld((const frag_t*)(wb + (NT::F0 + mt * KSH + s) * NT::FRAG_BYTES));
             }
 #pragma unroll
             for (int s = 0; s < KSH; ++s)
-                wo[s] = *(const frag_t*)(wb + (NT::F0 + NT::F1 + s) * NT::FRAG_BYTES);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) b0[mt] = *(const floatx4*)(bb + 16 * mt);
-            if constexpr (NL == 3) {
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) b1[mt] = *(const floatx4*)(bb + HID + 16 * mt);
-            }
-            bo = *(const floatx4*)(bb + (NL == 3 ? 2 * HID : HID));
+                wo[s] = gld((const frag_t*)(wb + (NT::F0 + NT::F1 + s) * NT::FRAG_BYTES));
+            gbias = bias + (int64_t)g * bstride + 4 * q;
         }
         const int j = k - g_lo;
-        const int cell0 = offsets[g] + j * kGroupCells;
-        const int cnt = min(kGroupCells, counts[g] - j * kGroupCells);
+        const int cell0 = gld(offsets + g) + j * kGroupCells;
+        const int cnt = min(kGroupCells, gld(counts + g) - j * kGroupCells);
         const bool valid = lane < cnt;
-        const int i = perm[cell0 + (valid ? lane : 0)];
+        const int i = gld(perm + cell0 + (valid ? lane : 0));
 
         // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
         const int y = i / Wd, x = i - y * Wd;
-        const int r = Rc[i] & 7;
+        const int r = gld(Rc + i) & 7;
         float uvec[kNIn];
         int64_t e_own = 0, i_own = 0;
 #pragma unroll
@@ -229,19 +223,24 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
                 ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
                 nidx = ny * Wd + nx;
             }
-            const int64_t ev = Ec[nidx], iv = Ic[nidx];
+            const int64_t ev = gld(Ec + nidx), iv = gld(Ic + nidx);
             if (p == 0) { e_own = ev; i_own = iv; }
-            uvec[6 * p + 0] = (float)ev * 0x1p-24f;
-            uvec[6 * p + 1] = (float)iv * 0x1p-24f;
+            uvec[6 * p + 0] = i64_to_f32(ev) * 0x1p-24f;
+            uvec[6 * p + 1] = i64_to_f32(iv) * 0x1p-24f;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = Cc[(int64_t)c * Nd + nidx];
+            for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = gld(Cc + (int64_t)c * Nd + nidx);
         }
         if constexpr (NT::kBF) {
-            bf16x8 row[8];
 #pragma unroll
-            for (int kk = 0; kk < 64; ++kk) row[kk >> 3][kk & 7] = (__bf16)(kk < kNIn ? uvec[kk] : 0.0f);
+            for (int t = 0; t < 8; ++t) {
+                bf16x8 row;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) *(bf16x8*)(stage + lane * NT::STAGE_ROW + 16 * t) = row[t];
+                for (int e = 0; e < 8; ++e) {
+                    const int kk = 8 * t + e;
+                    row[e] = (__bf16)(kk < kNIn ? uvec[kk] : 0.0f);
+                }
+                *(bf16x8*)(stage + lane * NT::STAGE_ROW + 16 * t) = row;
+            }
         } else {
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
@@ -264,9 +263,11 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
         for (int cb = 0; cb < 4 / CGI; ++cb) {
             floatx4 acc[CGI][MT];
 #pragma unroll
-            for (int cc = 0; cc < CGI; ++cc)
+            for (int mt = 0; mt < MT; ++mt) {
+                const floatx4 bv = gld((const floatx4*)(gbias + 16 * mt));
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = b0[mt];
+                for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
+            }
             if constexpr (NT::kBF) {
                 bf16x8 xin[CGI][KS0];
 #pragma unroll
@@ -303,6 +304,7 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
 #pragma unroll
             for (int layer = 1; layer < NL; ++layer) {
                 const bool last = layer == NL - 1;
+                const float* lb = gbias + (last ? (NL == 3 ? 2 * HID : HID) : HID);
                 if constexpr (NT::kBF) {
                     bf16x8 h[CGI][KSH];
 #pragma unroll
@@ -315,18 +317,21 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
                                 h[cc][s][4 + t] = (__bf16)fast_tanh(acc[cc][2 * s + 1][t]);
                             }
                     if (last) {
+                        const floatx4 bv = gld((const floatx4*)lb);
 #pragma unroll
                         for (int cc = 0; cc < CGI; ++cc) {
-                            floatx4 o = bo;
+                            floatx4 o = bv;
 #pragma unroll
                             for (int s = 0; s < KSH; ++s) o = mfma(wo[s], h[cc][s], o);
                             outv[cb * CGI + cc] = o;
                         }
                     } else {
 #pragma unroll
-                        for (int cc = 0; cc < CGI; ++cc)
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const floatx4 bv = gld((const floatx4*)(lb + 16 * mt));
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = b1[mt % MT1];
+                            for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
+                        }
 #pragma unroll
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
@@ -344,18 +349,21 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
 #pragma unroll
                             for (int t = 0; t < 4; ++t) h[cc][mt][t] = fast_tanh(acc[cc][mt][t]);
                     if (last) {
+                        const floatx4 bv = gld((const floatx4*)lb);
 #pragma unroll
                         for (int cc = 0; cc < CGI; ++cc) {
-                            floatx4 o = bo;
+                            floatx4 o = bv;
 #pragma unroll
                             for (int s = 0; s < KSH; ++s) o = mfma(wo[s], h[cc][s >> 2][s & 3], o);
                             outv[cb * CGI + cc] = o;
                         }
                     } else {
 #pragma unroll
-                        for (int cc = 0; cc < CGI; ++cc)
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const floatx4 bv = gld((const floatx4*)(lb + 16 * mt));
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = b1[mt % MT1];
+                            for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
+                        }
 #pragma unroll
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
@@ -397,8 +405,8 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
             if (e_own < 0 || i_own < 0) err |= kErrLedger;
             // invest / liquidate: sigmoid-gated fractions of the pre-step stocks
             const float se = sigmoid_f(a[0]), sl = sigmoid_f(a[1]);
-            int64_t xi = (int64_t)floorf(rho_i * se * (float)e_own);
-            int64_t xl = (int64_t)floorf(rho_l * sl * (float)i_own);
+            int64_t xi = (int64_t)floorf(rho_i * se * i64_to_f32(e_own));
+            int64_t xl = (int64_t)floorf(rho_l * sl * i64_to_f32(i_own));
             xi = xi > e_own ? e_own : xi;
             xl = xl > i_own ? i_own : xl;
             xi = xi < 0 ? 0 : xi;
@@ -406,7 +414,7 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
             const int64_t E1 = e_own - xi + xl, I1 = i_own + xi - xl;
             // communication: sigmoid of the comm actuators
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Cn[(int64_t)c * Nd + i] = sigmoid_f(a[2 + c]);
+            for (int c = 0; c < 4; ++c) gst(Cn + (int64_t)c * Nd + i, sigmoid_f(a[2 + c]));
             // exploration: softmax split of the flow budget, argmax explore
             float m = a[6];
             int best = 0;
@@ -416,22 +424,26 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
             float ex[8], ssum = 0.0f;
 #pragma unroll
             for (int t = 0; t < 8; ++t) { ex[t] = __expf(a[6 + t] - m); ssum += ex[t]; }
-            int64_t F = (int64_t)floorf(kappa * (float)I1);
+            const float inv = __builtin_amdgcn_rcpf(ssum);
+            // flow budget below 2^31 quanta: each flow word carries the
+            // explored flag in its low bit
+            int64_t F = (int64_t)floorf(kappa * i64_to_f32(I1));
             if (F < 0) F = 0;
-            if (F > 0xffffffffll) { err |= kErrLedger; F = 0xffffffffll; }
-            const float fF = (float)F;
+            if (F > 0x7fffffffll) { err |= kErrLedger; F = 0x7fffffffll; }
+            const float fF = (float)(uint32_t)F;
             int64_t used = 0;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                int64_t f = (int64_t)floorf((ex[t] / ssum) * fF);
+                int64_t f = (int64_t)floorf((ex[t] * inv) * fF);
                 f = f > F - used ? F - used : f;
                 f = f < 0 ? 0 : f;
                 used += f;
-                flow[(int64_t)kernel_dir(r, t + 1) * Nd + i] = (uint32_t)f;
+                gst(flow + (int64_t)kernel_dir(r, t + 1) * Nd + i,
+                    ((uint32_t)f << 1) | (uint32_t)(t == best));
             }
-            En[i] = E1;
-            I1p[i] = I1;
-            Xp[i] = (uint8_t)kernel_dir(r, best + 1);
+            gst(En + i, E1);
+            gst(I1p + i, I1);
+            gst(outp + i, (uint32_t)used);
             acc_mass += E1;
             acc_f64 += (double)E1;
         }
@@ -439,13 +451,29 @@ __global__ __launch_bounds__(256) void k_act(const BatchDev* __restrict__ b,
     flush();
 }
 
+// Persistent grid: as many blocks as the kernel keeps resident.
+template <typename K>
+static int resident_blocks(K kernel, int n_cu) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return n_cu * per_cu;
+}
+
+template <int NL, int HID, int PREC, int CGI, bool DEBUG>
+static void launch_act_c(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, float* dbg) {
+    static int blocks = 0;
+    if (blocks == 0) blocks = resident_blocks(k_act<NL, HID, PREC, CGI, DEBUG>, ls.n_cu);
+    hipLaunchKernelGGL((k_act<NL, HID, PREC, CGI, DEBUG>), dim3(blocks), dim3(256), 0, s, bdev, dbg);
+}
+
 template <int NL, int HID, int PREC, bool DEBUG>
 static void launch_act_t(const BatchDev* bdev, const LaunchShape& ls, int act_cells, hipStream_t s,
                          float* dbg) {
     switch (act_cells) {
-        case 1: hipLaunchKernelGGL((k_act<NL, HID, PREC, 1, DEBUG>), dim3(ls.act_blocks), dim3(256), 0, s, bdev, dbg); break;
-        case 2: hipLaunchKernelGGL((k_act<NL, HID, PREC, 2, DEBUG>), dim3(ls.act_blocks), dim3(256), 0, s, bdev, dbg); break;
-        default: hipLaunchKernelGGL((k_act<NL, HID, PREC, 4, DEBUG>), dim3(ls.act_blocks), dim3(256), 0, s, bdev, dbg); break;
+        case 1: launch_act_c<NL, HID, PREC, 1, DEBUG>(bdev, ls, s, dbg); break;
+        case 2: launch_act_c<NL, HID, PREC, 2, DEBUG>(bdev, ls, s, dbg); break;
+        default: launch_act_c<NL, HID, PREC, 4, DEBUG>(bdev, ls, s, dbg); break;
     }
 }
 

@@ -4,14 +4,25 @@
 //
 // Bucketing groups cells by GenomeIndex (System Design: the GenomeIndex
 // channel locates the cell's network parameters) so that each genome's
-// cells can run through its network as one grouped GEMM.  Cells are taken
-// 64 at a time (one wavefront, raster order); inside a wavefront the
-// distinct genomes are found with ballots, so each (wavefront, genome) pair
-// costs one atomic on the genome's counter: with spatially clustered genomes
-// that is 1-3 atomics per 64 cells.
+// cells run through its network as one grouped GEMM.
+//
+// A block owns a 64 x 64 tile; each wavefront takes one 64-cell tile row at
+// a time and run-length encodes it with a lane shuffle and a ballot, so every
+// run of equal genomes is handled by its first lane, all runs in parallel.
+// Per-genome counts are aggregated in an LDS hash table first, so the global counters see one
+// atomic per (tile, genome): Voronoi patches put ~20 genomes in a tile, and
+// a genome owning a sixth of the world costs one atomic per tile instead of
+// one per wavefront.  A genome that finds the table full falls back to
+// direct global atomics (fragmented populations), with identical results.
+// The scan over genome slots is reduce-then-scan over 4096-slot blocks with
+// coalesced loads; it also lists the free (zero-count) slots in ascending
+// order for radiation.
 #include "coralai_internal.h"
 
 namespace coralai {
+
+constexpr int kHashSlots = 2048;
+constexpr int kHashProbes = 64;
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
@@ -47,8 +58,9 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total, int* s_tm
 __global__ __launch_bounds__(256) void k_prep(const BatchDev* __restrict__ b) {
     const int wi = blockIdx.y;
     if (wi >= b->n_worlds) return;
-    const WorldDev& w = b->worlds[wi];
-    for (int g = blockIdx.x * 256 + threadIdx.x; g < w.cap; g += gridDim.x * 256) w.counts[g] = 0;
+    const auto& w = *world_at(b, wi);
+    for (int g = blockIdx.x * 256 + threadIdx.x; g < kSubCounters * w.cap; g += gridDim.x * 256)
+        w.sub_counts[g] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.ctl->acc_mass = 0;
         w.ctl->acc_mass_f64 = 0.0;
@@ -56,89 +68,248 @@ __global__ __launch_bounds__(256) void k_prep(const BatchDev* __restrict__ b) {
     }
 }
 
-// Histogram (scatter = 0) or stable-per-wavefront compaction (scatter = 1)
-// of the current GenomeIndex plane.  Cells naming a genome outside
-// [0, cap) are counted under genome 0 and flagged; cells naming a slot
-// without parameters are flagged.
+// LDS hash of genome -> slot index; returns -1 when the table has no room.
+__device__ __forceinline__ int hash_find(int* s_key, int g, bool insert) {
+    int h = (int)(((uint32_t)g * 2654435761u) >> (32 - 11));
+    for (int p = 0; p < kHashProbes; ++p) {
+        const int k = s_key[h];
+        if (k == g) return h;
+        if (k == -1) {
+            if (!insert) return -1;
+            const int old = atomicCAS(&s_key[h], -1, g);
+            if (old == -1 || old == g) return h;
+        }
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    return -1;
+}
+
+// scatter = 0: histogram into the partial counters.  scatter = 1:
+// compaction into perm, using the cursors the scan set.  A block takes a
+// unit of kBucketGroup consecutive tiles and aggregates its counts over all
+// of them before touching global memory; the unit's partial counter is
+// (unit mod kSubCounters).  The order of a genome's cells in perm follows
+// unit and wavefront arrival, i.e. it is spatially local but not specified.
 __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, int scatter) {
-    const int n = b->n_worlds;
+    __shared__ int s_key[kHashSlots];
+    __shared__ int s_cnt[kHashSlots];
+    __shared__ int s_base[kHashSlots];
+    constexpr int ROWS = kBucketTile / 4;  // tile rows per wavefront
+    const int n = cld(&b->n_worlds);
     if (n <= 0) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t total = b->chunk_prefix[n];
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    for (int64_t u = (int64_t)xcd_block() * 4 + (threadIdx.x >> 6); u < total; u += nwaves) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t total = cld(b->chunk_prefix + (n));
+    for (int64_t u = xcd_block(); u < total; u += gridDim.x) {
         const int wi = find_world(b->chunk_prefix, n, u);
-        const WorldDev& w = b->worlds[wi];
-        const int cur = w.ctl->cur;
-        const int64_t i = (u - b->chunk_prefix[wi]) * kChunkCells + lane;
-        const bool valid = i < w.N;
-        int g = valid ? w.G[cur][i] : 0;
+        const auto& w = *world_at(b, wi);
+        const int cur = ctl_cur(w.ctl);
+        const int64_t unit = u - cld(b->chunk_prefix + (wi));
+        const int sub = (int)(unit % kSubCounters);
+        const int32_t* G = w.G[cur];
+        for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
+        __syncthreads();
         uint32_t bad = 0;
-        if (valid) {
-            if (g < 0 || g >= w.cap) {
-                bad = kErrGenomeRange;
-                g = 0;
-            } else if (!w.slot_set[g]) {
-                bad = kErrGenomeUnset;
+        // the wavefront's rows of the unit's tiles, loaded up front
+        int gv[kBucketGroup][ROWS];
+        int tx[kBucketGroup], ty[kBucketGroup];
+        bool tile_ok[kBucketGroup];
+#pragma unroll
+        for (int tg = 0; tg < kBucketGroup; ++tg) {
+            const int tile = (int)unit * kBucketGroup + tg;
+            tile_ok[tg] = tile < w.btiles;
+            ty[tg] = tile / w.btiles_x;
+            tx[tg] = tile - ty[tg] * w.btiles_x;
+            const int x = tx[tg] * kBucketTile + lane;
+#pragma unroll
+            for (int it = 0; it < ROWS; ++it) {
+                const int y = ty[tg] * kBucketTile + wv + 4 * it;
+                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+                int g = valid ? gld(G + (int64_t)y * w.W + x) : 0;
+                if (valid) {
+                    if (g < 0 || g >= w.cap) { bad |= kErrGenomeRange; g = 0; }
+                    else if (!w.slot_set[g]) bad |= kErrGenomeUnset;
+                }
+                gv[tg][it] = g;
             }
         }
-        if (!scatter) {
-            const uint64_t anybad = __ballot(bad != 0);
-            if (anybad && lane == __ffsll((unsigned long long)anybad) - 1) atomicOr(&w.ctl->err, bad);
-        }
-        uint64_t active = __ballot(valid);
-        while (active) {
-            const int leader = __ffsll((unsigned long long)active) - 1;
-            const int g0 = __builtin_amdgcn_readlane(g, leader);
-            const uint64_t m = __ballot(g == g0) & active;
-            if (!scatter) {
-                if (lane == leader) atomicAdd(&w.counts[g0], (int)__popcll(m));
-            } else {
-                int base = 0;
-                if (lane == leader) base = atomicAdd(&w.cursor[g0], (int)__popcll(m));
-                base = __builtin_amdgcn_readlane(base, leader);
-                if ((m >> lane) & 1ull) w.perm[base + __popcll(m & lanemask_lt(lane))] = (int)i;
+        // 1. per-genome counts of the unit (LDS, global on table overflow).
+        // Each tile row is run-length encoded across the wavefront: the first
+        // lane of each run of equal genomes updates the table for the whole
+        // run, all runs of the row at once.  Valid lanes form a prefix.
+#pragma unroll
+        for (int tg = 0; tg < kBucketGroup; ++tg) {
+            const int x = tx[tg] * kBucketTile + lane;
+#pragma unroll
+            for (int it = 0; it < ROWS; ++it) {
+                const int y = ty[tg] * kBucketTile + wv + 4 * it;
+                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+                const int g = gv[tg][it];
+                const int prev = __shfl_up(g, 1, 64);
+                const bool start = valid && (lane == 0 || prev != g);
+                const uint64_t starts = __ballot(start);
+                const int nvalid = (int)__popcll(__ballot(valid));
+                if (start) {
+                    const uint64_t later = starts & ~((2ull << lane) - 1ull);
+                    const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
+                    const int h = hash_find(s_key, g, true);
+                    if (h >= 0) atomicAdd(&s_cnt[h], len);
+                    else if (!scatter) atomicAdd(&w.sub_counts[sub * w.cap + g], len);
+                }
             }
-            active &= ~m;
         }
+        if (bad && !scatter) atomicOr(&w.ctl->err, bad);
+        __syncthreads();
+        // 2. one global atomic per (unit, genome)
+        for (int k = threadIdx.x; k < kHashSlots; k += 256) {
+            const int g = s_key[k];
+            if (g < 0) continue;
+            if (!scatter) atomicAdd(&w.sub_counts[sub * w.cap + g], s_cnt[k]);
+            else { s_base[k] = atomicAdd(&w.cursor[sub * w.cap + g], s_cnt[k]); s_cnt[k] = 0; }
+        }
+        if (scatter) {
+            __syncthreads();
+            // 3. positions inside each genome's range: the run's first lane
+            // reserves the run, every lane writes at run base + its offset
+#pragma unroll
+            for (int tg = 0; tg < kBucketGroup; ++tg) {
+                const int x = tx[tg] * kBucketTile + lane;
+#pragma unroll
+                for (int it = 0; it < ROWS; ++it) {
+                    const int y = ty[tg] * kBucketTile + wv + 4 * it;
+                    const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+                    const int64_t i = (int64_t)y * w.W + x;
+                    const int g = gv[tg][it];
+                    const int prev = __shfl_up(g, 1, 64);
+                    const bool start = valid && (lane == 0 || prev != g);
+                    const uint64_t starts = __ballot(start);
+                    const int nvalid = (int)__popcll(__ballot(valid));
+                    int base = 0;
+                    if (start) {
+                        const uint64_t later = starts & ~((2ull << lane) - 1ull);
+                        const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
+                        const int h = hash_find(s_key, g, false);
+                        base = h >= 0 ? s_base[h] + atomicAdd(&s_cnt[h], len)
+                                      : atomicAdd(&w.cursor[sub * w.cap + g], len);
+                    }
+                    const uint64_t upto = starts & ((2ull << lane) - 1ull);
+                    const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
+                    const int run_base = __shfl(base, rs, 64);
+                    if (valid) gst(w.perm + run_base + (lane - rs), (int)i);
+                }
+            }
+        }
+        __syncthreads();  // the table is cleared for the next unit
     }
 }
 
-// Per world: offsets = exclusive scan of counts, cursor = offsets, gofs =
-// exclusive scan of the number of 64-cell network units per genome.
-// One 1024-thread block per world; each thread owns a contiguous slot range.
-__global__ __launch_bounds__(1024) void k_scan(const BatchDev* __restrict__ b) {
+// Scan over genome slots, pass A: per 4096-slot block, the number of cells
+// (summing the partial counters into counts), of 64-cell network units, of
+// live genomes and of free slots.
+__global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict__ b) {
+    __shared__ int s_red[4][4];
+    const int n = cld(&b->n_worlds);
+    if (n <= 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t total = cld(b->slot_prefix + (n));
+    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        const int wi = find_world(b->slot_prefix, n, u);
+        const auto& w = *world_at(b, wi);
+        const int sb = (int)(u - cld(b->slot_prefix + (wi)));
+        int c = 0, gsum = 0, live = 0, fr = 0;
+        for (int k = 0; k < kSlotBlock / 256; ++k) {
+            const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
+            if (g < w.cap) {
+                int v = 0;
+#pragma unroll
+                for (int q = 0; q < kSubCounters; ++q) v += w.sub_counts[q * w.cap + g];
+                w.counts[g] = v;
+                c += v;
+                gsum += (v + kGroupCells - 1) / kGroupCells;
+                live += v > 0;
+                fr += v == 0;
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            c += __shfl_xor(c, o, 64);
+            gsum += __shfl_xor(gsum, o, 64);
+            live += __shfl_xor(live, o, 64);
+            fr += __shfl_xor(fr, o, 64);
+        }
+        if (lane == 0) { s_red[wv][0] = c; s_red[wv][1] = gsum; s_red[wv][2] = live; s_red[wv][3] = fr; }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            const int f = threadIdx.x;
+            w.scan_part[sb * 4 + f] = s_red[0][f] + s_red[1][f] + s_red[2][f] + s_red[3][f];
+        }
+        __syncthreads();
+    }
+}
+
+// Pass B: per world, exclusive prefix of the block partials (in place) and
+// the world totals.
+__global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict__ b) {
+    __shared__ int s_tmp[16];
     const int wi = blockIdx.y;
     if (wi >= b->n_worlds) return;
-    __shared__ int s_tmp[16];
-    const WorldDev& w = b->worlds[wi];
-    const int cap = w.cap;
-    const int per = (cap + 1023) / 1024;
-    const int beg = min(cap, (int)threadIdx.x * per), end = min(cap, beg + per);
-    int sc = 0, sg = 0, live = 0;
-    for (int g = beg; g < end; ++g) {
-        const int c = w.counts[g];
-        sc += c;
-        sg += (c + kGroupCells - 1) / kGroupCells;
-        live += c > 0;
+    const auto& w = *world_at(b, wi);
+    const int nb = w.n_slot_blocks;
+    const int t = threadIdx.x;
+    int tot[4];
+    int pre[4];
+    for (int f = 0; f < 4; ++f) {
+        // n_slot_blocks <= 1024: one partial per thread
+        const int v = t < nb ? w.scan_part[t * 4 + f] : 0;
+        pre[f] = block_exclusive_scan<1024>(v, &tot[f], s_tmp);
     }
-    int tc, tg, tl;
-    int oc = block_exclusive_scan<1024>(sc, &tc, s_tmp);
-    int og = block_exclusive_scan<1024>(sg, &tg, s_tmp);
-    block_exclusive_scan<1024>(live, &tl, s_tmp);
-    for (int g = beg; g < end; ++g) {
-        const int c = w.counts[g];
-        w.offsets[g] = oc;
-        w.cursor[g] = oc;
-        w.gofs[g] = og;
-        oc += c;
-        og += (c + kGroupCells - 1) / kGroupCells;
+    if (t < nb)
+        for (int f = 0; f < 4; ++f) w.scan_part[t * 4 + f] = pre[f];
+    if (t == 0) {
+        w.offsets[w.cap] = tot[0];
+        w.gofs[w.cap] = tot[1];
+        w.ctl->total_groups = tot[1];
+        w.ctl->live = tot[2];
+        w.ctl->n_free = tot[3];
     }
-    if (threadIdx.x == 0) {
-        w.offsets[cap] = tc;
-        w.gofs[cap] = tg;
-        w.ctl->total_groups = tg;
-        w.ctl->live = tl;
+}
+
+// Pass C: per 4096-slot block, the exclusive scans themselves (256 slots per
+// round, block-wide scan, running carry), the partial ranges of each genome
+// laid out one after another, plus the free-slot list.
+__global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__ b) {
+    __shared__ int s_tmp[4];
+    const int n = cld(&b->n_worlds);
+    if (n <= 0) return;
+    const int64_t total = cld(b->slot_prefix + (n));
+    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        const int wi = find_world(b->slot_prefix, n, u);
+        const auto& w = *world_at(b, wi);
+        const int sb = (int)(u - cld(b->slot_prefix + (wi)));
+        int oc = w.scan_part[sb * 4 + 0], og = w.scan_part[sb * 4 + 1], of = w.scan_part[sb * 4 + 3];
+        for (int k = 0; k < kSlotBlock / 256; ++k) {
+            const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
+            const int v = g < w.cap ? w.counts[g] : 0;
+            const int units = (v + kGroupCells - 1) / kGroupCells;
+            const int is_free = g < w.cap && v == 0;
+            int tc, tg, tf;
+            const int ec = block_exclusive_scan<256>(v, &tc, s_tmp);
+            const int eg = block_exclusive_scan<256>(units, &tg, s_tmp);
+            const int ef = block_exclusive_scan<256>(is_free, &tf, s_tmp);
+            if (g < w.cap) {
+                int pos = oc + ec;
+                w.offsets[g] = pos;
+#pragma unroll
+                for (int q = 0; q < kSubCounters; ++q) {
+                    w.cursor[q * w.cap + g] = pos;
+                    pos += w.sub_counts[q * w.cap + g];
+                }
+                w.gofs[g] = og + eg;
+                if (is_free) w.free_list[of + ef] = g;
+            }
+            oc += tc;
+            og += tg;
+            of += tf;
+        }
     }
 }
 
@@ -178,19 +349,23 @@ __global__ void k_flip(const BatchDev* __restrict__ b) {
     b->worlds[wi].ctl->cur ^= 1;
 }
 
-void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
-    const int cap_blocks = min(64, max(1, (ls.max_cap + 255) / 256));
-    hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
-    hipLaunchKernelGGL(k_bucket, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev, 0);
-    hipLaunchKernelGGL(k_scan, dim3(1, ls.max_worlds), dim3(1024), 0, s, bdev);
-    hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
-    hipLaunchKernelGGL(k_bucket, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev, 1);
+static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(ls.misc_blocks), dim3(256), 0, s, bdev);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1, ls.max_worlds), dim3(1024), 0, s, bdev);
+    hipLaunchKernelGGL(k_scan_write, dim3(ls.misc_blocks), dim3(256), 0, s, bdev);
 }
 
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
-    const int cap_blocks = min(64, max(1, (ls.max_cap + 255) / 256));
+    const int cap_blocks = min(256, max(1, (kSubCounters * ls.max_cap + 255) / 256));
     hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
     hipLaunchKernelGGL(k_bucket, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev, 0);
+    launch_scan(bdev, ls, s);
+}
+
+void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
+    launch_hist_only(bdev, ls, s);
+    hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
+    hipLaunchKernelGGL(k_bucket, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev, 1);
 }
 
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {

@@ -20,7 +20,17 @@
 namespace coralai {
 
 // T = double for FP32 worlds (weights then rounded once to FP32), float for
-// BF16 worlds (whose weights are rounded to bf16 anyway).
+// BF16 worlds (whose weights are rounded to bf16, 2^-9 relative, so the
+// hardware sin / exp / reciprocal, accurate to ~1e-6 here, suffice).
+__device__ __forceinline__ double node_sin(double s) { return sin(s); }
+__device__ __forceinline__ double node_gauss(double s) { return exp(-s * s); }
+__device__ __forceinline__ double node_tanh(double s) { return tanh(s); }
+__device__ __forceinline__ float node_sin(float s) { return __sinf(s); }
+__device__ __forceinline__ float node_gauss(float s) { return __expf(-s * s); }
+__device__ __forceinline__ float node_tanh(float s) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * s) + 1.0f);
+}
+
 template <typename T>
 __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, T x2, T y2, int out) {
     T s_out = T(0);
@@ -30,9 +40,9 @@ __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, 
                     T(p[5 * k + 3]) * y2 + T(p[5 * k + 4]);
         T h;
         switch (k & 3) {
-            case 0: h = sin(s); break;
-            case 1: h = exp(-s * s); break;
-            case 2: h = tanh(s); break;
+            case 0: h = node_sin(s); break;
+            case 1: h = node_gauss(s); break;
+            case 2: h = node_tanh(s); break;
             default: h = s; break;
         }
         s_out += T(p[40 + 8 * out + k]) * h;
@@ -233,21 +243,6 @@ __device__ __forceinline__ int block_scan_excl(int v, int* total, int* s_tmp) {
     return before + x - v;
 }
 
-// Free slots (zero count) in ascending order.
-__global__ __launch_bounds__(1024) void k_rad_free(const WorldDev* __restrict__ w) {
-    __shared__ int s_tmp[16];
-    const int cap = w->cap;
-    const int per = (cap + 1023) / 1024;
-    const int beg = min(cap, (int)threadIdx.x * per), end = min(cap, beg + per);
-    int c = 0;
-    for (int g = beg; g < end; ++g) c += w->counts[g] == 0;
-    int tot;
-    int o = block_scan_excl<1024>(c, &tot, s_tmp);
-    for (int g = beg; g < end; ++g)
-        if (w->counts[g] == 0) w->free_list[o++] = g;
-    if (threadIdx.x == 0) w->ctl->n_free = tot;
-}
-
 // Hit ranks: exclusive scan of the per-block hit counts.
 __global__ __launch_bounds__(1024) void k_rad_scan(const WorldDev* __restrict__ w) {
     __shared__ int s_tmp[16];
@@ -339,9 +334,9 @@ void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int 
 
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
                     int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s) {
-    // genome counts of the current state (the completed step's result)
+    // genome counts of the current state (the completed step's result) and
+    // its free slots
     launch_hist_only(bdev, ls, s);
-    hipLaunchKernelGGL(k_rad_free, dim3(1), dim3(1024), 0, s, wdev);
     const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
     hipLaunchKernelGGL(k_rad_hits, dim3(hb), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);

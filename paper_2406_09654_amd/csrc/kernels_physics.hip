@@ -9,10 +9,12 @@
 // and n's explore direction; I2 = I1 - sum(own flows) + sum(inflows); the
 // candidate explorers are the neighbours exploring toward t, the largest
 // investment wins (lowest d on ties) and takes t over when it strictly
-// exceeds I1(t).  The tile loads (TW+2) x (TH+2) cells of the 8 flow planes,
-// explore directions and genomes with coalesced row loads; inflows, takeover
-// and the block's share of the total-mass reduction (int64 exact and FP64)
-// follow from LDS.  Pure integer work: bit-exact by construction.
+// exceeds I1(t).  Each flow word is (amount << 1) | explored, so one read per
+// direction gives both the inflow and the candidacy.  The tile loads
+// (TW+2) x (TH+2) cells of the 8 flow planes and the genomes with coalesced
+// row loads; inflows, takeover and the block's share of the total-mass
+// reduction (int64 exact and FP64) follow from LDS.  Pure integer work:
+// bit-exact by construction.
 #include "coralai_internal.h"
 
 namespace coralai {
@@ -23,15 +25,14 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     constexpr int LW = TW + 2, LH = TH + 2, LN = LW * LH;
     __shared__ uint32_t s_flow[8][LN];
     __shared__ int32_t s_g[LN];
-    __shared__ uint8_t s_x[LN];
     __shared__ int64_t s_red_m[NT / 64];
     __shared__ double s_red_f[NT / 64];
     __shared__ int s_red_t[NT / 64];
 
-    const int nworlds = b->n_worlds;
+    const int nworlds = cld(&b->n_worlds);
     if (nworlds <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t total = b->tile_prefix[nworlds];
+    const int64_t total = cld(b->tile_prefix + (nworlds));
     const int blk = xcd_block();
     const int64_t per = (total + gridDim.x - 1) / gridDim.x;
     int64_t tile = (int64_t)blk * per;
@@ -76,7 +77,6 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     int64_t world_lo = 0;
     const uint32_t* flow = nullptr;
     const int64_t* I1p = nullptr;
-    const uint8_t* Xp = nullptr;
     const int32_t* Gc = nullptr;
     const uint8_t* Rc = nullptr;
     int64_t* In = nullptr;
@@ -87,14 +87,14 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
         if (tile >= world_hi) {
             if (wi >= 0) flush();
             wi = find_world(b->tile_prefix, nworlds, tile);
-            world_lo = b->tile_prefix[wi];
-            world_hi = b->tile_prefix[wi + 1];
-            const WorldDev* W = &b->worlds[wi];
+            world_lo = cld(b->tile_prefix + (wi));
+            world_hi = cld(b->tile_prefix + (wi + 1));
+            const auto* W = world_at(b, wi);
             Wd = W->W; Hd = W->H; Nd = W->N;
-            tx_n = b->tiles_x[wi];
+            tx_n = cld(b->tiles_x + (wi));
             ctl = W->ctl;
-            const int cur = ctl->cur, nxt = cur ^ 1;
-            flow = W->flow; I1p = W->I1; Xp = W->X;
+            const int cur = ctl_cur(ctl), nxt = cur ^ 1;
+            flow = W->flow; I1p = W->I1;
             Gc = W->G[cur]; Rc = W->R[cur];
             In = W->I[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
         }
@@ -103,14 +103,21 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
         const int x0 = tx * TW, y0 = ty * TH;
 
         // stage the halo tile
+        const bool small = Wd < TW + 2 || Hd < TH + 2;  // tiny worlds wrap more than once
         for (int idx = tid; idx < LN; idx += NT) {
             const int ly = idx / LW, lx = idx - ly * LW;
-            const int gx = wrap(x0 + lx - 1, Wd), gy = wrap(y0 + ly - 1, Hd);
+            int gx = x0 + lx - 1, gy = y0 + ly - 1;
+            if (small) {
+                gx = wrap(gx, Wd);
+                gy = wrap(gy, Hd);
+            } else {
+                gx = gx < 0 ? gx + Wd : (gx >= Wd ? gx - Wd : gx);
+                gy = gy < 0 ? gy + Hd : (gy >= Hd ? gy - Hd : gy);
+            }
             const int n = gy * Wd + gx;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) s_flow[k][idx] = flow[(int64_t)k * Nd + n];
-            s_g[idx] = Gc[n];
-            s_x[idx] = Xp[n];
+            for (int k = 0; k < 8; ++k) s_flow[k][idx] = gld(flow + (int64_t)k * Nd + n);
+            s_g[idx] = gld(Gc + n);
         }
         __syncthreads();
 
@@ -121,33 +128,145 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             const int own = ly * LW + lx;
             int64_t out = 0, in = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) out += s_flow[k][own];
+            for (int k = 0; k < 8; ++k) out += s_flow[k][own] >> 1;
             int win = -1;
             int64_t vbest = -1;
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const int back = (d + 4) & 7;
                 const int nb = (ly + dir_dy(d)) * LW + (lx + dir_dx(d));
-                const int64_t v = s_flow[back][nb];
+                const uint32_t word = s_flow[back][nb];
+                const int64_t v = word >> 1;
                 in += v;
-                if (s_x[nb] == back && v > vbest) { vbest = v; win = d; }
+                if ((word & 1u) && v > vbest) { vbest = v; win = d; }
             }
-            const int64_t i1 = I1p[t];
+            const int64_t i1 = gld(I1p + t);
             const int64_t i2 = i1 - out + in;
-            int32_t g2 = Gc[t];
-            uint8_t r2 = Rc[t];
+            int32_t g2 = gld(Gc + t);
+            uint8_t r2 = gld(Rc + t);
             if (win >= 0 && vbest > i1) {
                 g2 = s_g[(ly + dir_dy(win)) * LW + (lx + dir_dx(win))];
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
             }
-            In[t] = i2;
-            Gn[t] = g2;
-            Rn[t] = r2;
+            gst(In + t, i2);
+            gst(Gn + t, g2);
+            gst(Rn + t, r2);
             acc_m += i2;
             acc_f += (double)i2;
         }
         __syncthreads();  // LDS reused by the next tile
+    }
+    if (wi >= 0) flush();
+}
+
+// Streaming variant: one thread per cell, no LDS.  The inflow from direction
+// d is plane (d+4) mod 8 read at the neighbour: for a wavefront of
+// consecutive cells every such read is one contiguous (shifted) segment and
+// each plane element is read by exactly one target, so nothing is re-read;
+// the cell's own outflow total comes from the record.  Buffer loads keep the
+// offsets in 32 bits (planes are < 4 GiB) and return 0 outside a plane.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restrict__ b) {
+    __shared__ int64_t s_red_m[4];
+    __shared__ double s_red_f[4];
+    __shared__ int s_red_t[4];
+    const int nworlds = cld(&b->n_worlds);
+    if (nworlds <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t total = cld(b->tile_prefix + (nworlds));
+    int wi = -1;
+    int64_t world_hi = -1, world_lo = 0;
+    int64_t acc_m = 0;
+    double acc_f = 0.0;
+    int acc_t = 0;
+    Ctl* ctl = nullptr;
+    int Wd = 0, Hd = 0, Nd = 0;
+    __amdgpu_buffer_rsrc_t rflow[8], rout, ri1, rg, rr;
+    int64_t* In = nullptr;
+    int32_t* Gn = nullptr;
+    uint8_t* Rn = nullptr;
+    auto flush = [&]() {
+        int64_t m = acc_m;
+        double f = acc_f;
+        int t = acc_t;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            m += __shfl_xor(m, o, 64);
+            f += __shfl_xor(f, o, 64);
+            t += __shfl_xor(t, o, 64);
+        }
+        if (lane == 0) { s_red_m[wid] = m; s_red_f[wid] = f; s_red_t[wid] = t; }
+        __syncthreads();
+        if (tid == 0 && ctl != nullptr) {
+            atomicAdd((unsigned long long*)&ctl->acc_mass,
+                      (unsigned long long)(s_red_m[0] + s_red_m[1] + s_red_m[2] + s_red_m[3]));
+            atomicAdd(&ctl->acc_mass_f64, s_red_f[0] + s_red_f[1] + s_red_f[2] + s_red_f[3]);
+            atomicAdd((unsigned long long*)&ctl->acc_takeovers,
+                      (unsigned long long)(int64_t)(s_red_t[0] + s_red_t[1] + s_red_t[2] + s_red_t[3]));
+        }
+        __syncthreads();
+        acc_m = 0;
+        acc_f = 0.0;
+        acc_t = 0;
+    };
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    int64_t unit = (int64_t)xcd_block() * per;
+    const int64_t uend = min(total, unit + per);
+    for (; unit < uend; ++unit) {
+        if (unit >= world_hi) {
+            if (wi >= 0) flush();
+            wi = find_world(b->tile_prefix, nworlds, unit);
+            world_lo = cld(b->tile_prefix + (wi));
+            world_hi = cld(b->tile_prefix + (wi + 1));
+            const auto* W = world_at(b, wi);
+            Wd = W->W; Hd = W->H; Nd = W->N;
+            ctl = W->ctl;
+            const int cur = ctl_cur(ctl), nxt = cur ^ 1;
+            const uint32_t n4 = 4u * (uint32_t)Nd;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) rflow[k] = plane_rsrc(W->flow + (int64_t)k * Nd, n4);
+            rout = plane_rsrc(W->out, n4);
+            ri1 = plane_rsrc(W->I1, 2u * n4);
+            rg = plane_rsrc(W->G[cur], n4);
+            rr = plane_rsrc(W->R[cur], (uint32_t)Nd);
+            In = W->I[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
+        }
+        const int t = (int)((unit - world_lo) * 256) + tid;
+        if (t < Nd) {  // (no divergent continue: the world fields must stay uniform)
+            const int y = t / Wd, x = t - y * Wd;
+            const int64_t i1 = (int64_t)__builtin_amdgcn_raw_buffer_load_b64(ri1, 8 * t, 0, 0);
+            const uint32_t out = __builtin_amdgcn_raw_buffer_load_b32(rout, 4 * t, 0, 0);
+            int32_t g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * t, 0, 0);
+            uint8_t r2 = __builtin_amdgcn_raw_buffer_load_b8(rr, t, 0, 0);
+            int64_t in = 0, vbest = -1;
+            int win = -1, wn = 0;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int nx = x + dir_dx(d), ny = y + dir_dy(d);
+                nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
+                ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
+                const int n = ny * Wd + nx;
+                const uint32_t word = __builtin_amdgcn_raw_buffer_load_b32(rflow[(d + 4) & 7], 4 * n, 0, 0);
+                const int64_t v = word >> 1;
+                in += v;
+                if ((word & 1u) && v > vbest) { vbest = v; win = d; wn = n; }
+            }
+            const int64_t i2 = i1 - (int64_t)out + in;
+            if (win >= 0 && vbest > i1) {
+                g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * wn, 0, 0);
+                r2 = (uint8_t)((win + 4) & 7);
+                acc_t += 1;
+            }
+            gst(In + t, i2);
+            gst(Gn + t, g2);
+            gst(Rn + t, r2);
+            acc_m += i2;
+            acc_f += (double)i2;
+        }
     }
     if (wi >= 0) flush();
 }
@@ -158,6 +277,7 @@ int phys_tile_h(int t) { return t == 1 ? 8 : (t == 2 ? 16 : 4); }
 void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
                          hipStream_t s) {
     switch (phys_tile) {
+        case 3: hipLaunchKernelGGL(k_physics_stream, dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
         case 1: hipLaunchKernelGGL((k_physics<32, 8>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
         case 2: hipLaunchKernelGGL((k_physics<16, 16>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
         default: hipLaunchKernelGGL((k_physics<64, 4>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;

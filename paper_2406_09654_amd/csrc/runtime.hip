@@ -46,10 +46,11 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     size_t E[2], I[2], C[2], G[2], R[2];
-    size_t flow, I1, X, perm;
-    size_t counts, offsets, cursor, gofs, slot_set, params, wfrag, bias;
+    size_t flow, I1, out, perm;
+    size_t counts, offsets, sub_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
-    size_t ctl, wdev, bdev, chunk_prefix, tile_prefix, group_prefix, tiles_x;
+    size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
+    int n_slot_blocks;
     size_t total;
     int64_t wfrag_stride;
     int bias_stride;
@@ -60,7 +61,7 @@ bool desc_valid(const coralai_world_desc* d, std::string* why) {
     auto bad = [&](const char* m) { if (why) *why = m; return false; };
     if (!d) return bad("desc is NULL");
     if (d->width < 1 || d->height < 1) return bad("width and height must be >= 1");
-    if ((int64_t)d->width * d->height > (1ll << 30)) return bad("W*H must be <= 2^30");
+    if ((int64_t)d->width * d->height > (1ll << 28)) return bad("W*H must be <= 2^28");
     if (d->n_weight_layers != 2 && d->n_weight_layers != 3) return bad("n_weight_layers must be 2 or 3");
     if (d->hidden != 32 && d->hidden != 64) return bad("hidden must be 32 or 64");
     if (d->genome_capacity < 1 || d->genome_capacity > (1 << 22)) return bad("genome_capacity must be in [1, 2^22]");
@@ -85,11 +86,12 @@ Layout make_layout(const coralai_world_desc* d) {
     }
     L.flow = take(32 * N);
     L.I1 = take(8 * N);
-    L.X = take(N);
+    L.out = take(4 * N);
     L.perm = take(4 * N);
     L.counts = take(4 * cap);
     L.offsets = take(4 * (cap + 1));
-    L.cursor = take(4 * cap);
+    L.sub_counts = take(4 * kSubCounters * cap);
+    L.cursor = take(4 * kSubCounters * cap);
     L.gofs = take(4 * (cap + 1));
     L.slot_set = take(cap);
     L.params = take(4 * kNParam * cap);
@@ -106,10 +108,13 @@ Layout make_layout(const coralai_world_desc* d) {
     L.new_slots = take(4 * cap);
     L.stage_slots = take(4 * cap);
     L.stage_params = take(4 * kNParam * cap);
+    L.n_slot_blocks = (int)((cap + kSlotBlock - 1) / kSlotBlock);
+    L.scan_part = take(16 * (size_t)L.n_slot_blocks);
     L.ctl = take(sizeof(Ctl));
     L.wdev = take(sizeof(WorldDev));
     L.bdev = take(sizeof(BatchDev));
     L.chunk_prefix = take(16);
+    L.slot_prefix = take(16);
     L.tile_prefix = take(16);
     L.group_prefix = take(8);
     L.tiles_x = take(4);
@@ -129,7 +134,7 @@ LaunchShape make_shape(int max_worlds, int max_cap) {
     LaunchShape ls{};
     ls.n_cu = device_cus();
     ls.act_blocks = ls.n_cu * 2;
-    ls.phys_blocks = ls.n_cu * 4;
+    ls.phys_blocks = ls.n_cu * 16;
     ls.chunk_blocks = ls.n_cu * 4;
     ls.misc_blocks = ls.n_cu;
     ls.max_worlds = max_worlds;
@@ -179,6 +184,7 @@ struct coralai_batch {
     BatchDev* bdev;
     WorldDev* table;
     int64_t* chunk_prefix;
+    int64_t* slot_prefix;
     int64_t* tile_prefix;
     int32_t* group_prefix;
     int32_t* tiles_x;
@@ -195,6 +201,10 @@ struct coralai_batch {
 namespace {
 
 int tiles_for(int W, int H, int phys_tile, int* tx) {
+    if (phys_tile == 3) {  // streaming physics: 256-cell linear units
+        *tx = 0;
+        return (int)(((int64_t)W * H + 255) / 256);
+    }
     const int tw = phys_tile_w(phys_tile), th = phys_tile_h(phys_tile);
     *tx = (W + tw - 1) / tw;
     return *tx * ((H + th - 1) / th);
@@ -204,18 +214,20 @@ int write_world_tables(coralai_world* w) {
     // single-world batch: table = the world itself
     int tx = 0;
     const int64_t tiles = tiles_for(w->desc.width, w->desc.height, w->phys_tile, &tx);
-    const int64_t chunks = ((int64_t)w->host.N + kChunkCells - 1) / kChunkCells;
-    int64_t cp[2] = {0, chunks}, tp[2] = {0, tiles};
+    const int64_t chunks = (w->host.btiles + kBucketGroup - 1) / kBucketGroup;
+    int64_t cp[2] = {0, chunks}, tp[2] = {0, tiles}, sp[2] = {0, w->host.n_slot_blocks};
     BatchDev hb{};
     hb.n_worlds = 1;
     hb.worlds = w->wdev;
     hb.chunk_prefix = (int64_t*)(w->base + w->L.chunk_prefix);
+    hb.slot_prefix = (int64_t*)(w->base + w->L.slot_prefix);
     hb.tile_prefix = (int64_t*)(w->base + w->L.tile_prefix);
     hb.group_prefix = (int32_t*)(w->base + w->L.group_prefix);
     hb.tiles_x = (int32_t*)(w->base + w->L.tiles_x);
     HIP_TRY(hipMemcpyAsync(w->wdev, &w->host, sizeof(WorldDev), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->bdev, &hb, sizeof(BatchDev), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(hb.chunk_prefix, cp, sizeof cp, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(hb.slot_prefix, sp, sizeof sp, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(hb.tile_prefix, tp, sizeof tp, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(hb.tiles_x, &tx, sizeof tx, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -380,10 +392,11 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     }
     h.flow = (uint32_t*)(b + L.flow);
     h.I1 = (int64_t*)(b + L.I1);
-    h.X = (uint8_t*)(b + L.X);
+    h.out = (uint32_t*)(b + L.out);
     h.perm = (int32_t*)(b + L.perm);
     h.counts = (int32_t*)(b + L.counts);
     h.offsets = (int32_t*)(b + L.offsets);
+    h.sub_counts = (int32_t*)(b + L.sub_counts);
     h.cursor = (int32_t*)(b + L.cursor);
     h.gofs = (int32_t*)(b + L.gofs);
     h.slot_set = (uint8_t*)(b + L.slot_set);
@@ -399,6 +412,10 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     h.new_slots = (int32_t*)(b + L.new_slots);
     h.stage_slots = (int32_t*)(b + L.stage_slots);
     h.stage_params = (float*)(b + L.stage_params);
+    h.scan_part = (int32_t*)(b + L.scan_part);
+    h.n_slot_blocks = L.n_slot_blocks;
+    h.btiles_x = (h.W + kBucketTile - 1) / kBucketTile;
+    h.btiles = h.btiles_x * ((h.H + kBucketTile - 1) / kBucketTile);
     h.ctl = (Ctl*)(b + L.ctl);
     w->wdev = (WorldDev*)(b + L.wdev);
     w->bdev = (BatchDev*)(b + L.bdev);
@@ -599,7 +616,7 @@ int coralai_get_profile(coralai_world* w, double* ms_sum, int64_t* launches) {
 int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t phys_tile) {
     WORLD_GUARD(w);
     if (act_cells != 1 && act_cells != 2 && act_cells != 4) return fail(CORALAI_E_INVALID, "act_cells must be 1, 2 or 4");
-    if (phys_tile < 0 || phys_tile > 2) return fail(CORALAI_E_INVALID, "phys_tile must be 0, 1 or 2");
+    if (phys_tile < 0 || phys_tile > 3) return fail(CORALAI_E_INVALID, "phys_tile must be 0, 1, 2 or 3");
     w->act_cells = act_cells;
     w->phys_tile = phys_tile;
     return write_world_tables(w);
@@ -633,7 +650,7 @@ int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* phys_til
     }
     float best_phys = 1e30f;
     int pt = 0;
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < 4; ++t) {
         w->phys_tile = t;
         int rc = write_world_tables(w);
         if (rc) return rc;
@@ -664,6 +681,7 @@ size_t coralai_batch_bytes(int32_t max_worlds) {
     take(sizeof(WorldDev) * m);
     take(8 * (m + 1));
     take(8 * (m + 1));
+    take(8 * (m + 1));
     take(4 * (m + 1));
     take(4 * m);
     return align_up(off, kAlign) + kAlign;
@@ -687,14 +705,16 @@ int coralai_batch_create(int32_t max_worlds, void* dev_arena, size_t arena_bytes
     b->bdev = (BatchDev*)take(sizeof(BatchDev));
     b->table = (WorldDev*)take(sizeof(WorldDev) * m);
     b->chunk_prefix = (int64_t*)take(8 * (m + 1));
+    b->slot_prefix = (int64_t*)take(8 * (m + 1));
     b->tile_prefix = (int64_t*)take(8 * (m + 1));
     b->group_prefix = (int32_t*)take(4 * (m + 1));
     b->tiles_x = (int32_t*)take(4 * m);
-    b->ls = make_shape(max_worlds, 1 << 14);
+    b->ls = make_shape(max_worlds, 1 << 10);  // kernels stride over larger capacities
     BatchDev hb{};
     hb.n_worlds = 0;
     hb.worlds = b->table;
     hb.chunk_prefix = b->chunk_prefix;
+    hb.slot_prefix = b->slot_prefix;
     hb.tile_prefix = b->tile_prefix;
     hb.group_prefix = b->group_prefix;
     hb.tiles_x = b->tiles_x;
@@ -714,7 +734,7 @@ int coralai_batch_set_worlds(coralai_batch* b, coralai_world* const* worlds, int
     if (n < 0 || n > b->max_worlds) return fail(CORALAI_E_INVALID, "n must be in [0, max_worlds]");
     if (n > 0 && !worlds) return fail(CORALAI_E_INVALID, "worlds is NULL");
     std::vector<WorldDev> tab(n);
-    std::vector<int64_t> cp(n + 1, 0), tp(n + 1, 0);
+    std::vector<int64_t> cp(n + 1, 0), tp(n + 1, 0), sp(n + 1, 0);
     std::vector<int32_t> tx(std::max(n, 1), 0);
     for (int k = 0; k < n; ++k) {
         coralai_world* w = worlds[k];
@@ -723,7 +743,8 @@ int coralai_batch_set_worlds(coralai_batch* b, coralai_world* const* worlds, int
         if (w->host.NL != b->NL || w->host.HID != b->HID || w->host.prec != b->prec)
             return fail(CORALAI_E_INVALID, "world %d: a batch needs one network shape and precision", k);
         tab[k] = w->host;
-        cp[k + 1] = cp[k] + ((int64_t)w->host.N + kChunkCells - 1) / kChunkCells;
+        cp[k + 1] = cp[k] + (w->host.btiles + kBucketGroup - 1) / kBucketGroup;
+        sp[k + 1] = sp[k] + w->host.n_slot_blocks;
         int t = 0;
         tp[k + 1] = tp[k] + tiles_for(w->host.W, w->host.H, b->phys_tile, &t);
         tx[k] = t;
@@ -734,6 +755,7 @@ int coralai_batch_set_worlds(coralai_batch* b, coralai_world* const* worlds, int
         HIP_TRY(hipMemcpyAsync(b->tiles_x, tx.data(), 4 * (size_t)n, hipMemcpyHostToDevice, b->stream));
     }
     HIP_TRY(hipMemcpyAsync(b->chunk_prefix, cp.data(), 8 * (size_t)(n + 1), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->slot_prefix, sp.data(), 8 * (size_t)(n + 1), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->tile_prefix, tp.data(), 8 * (size_t)(n + 1), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(&b->bdev->n_worlds, &n, sizeof n, hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -847,13 +869,24 @@ int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* f
     int cur = 0, rc = current_buffer(w, &cur);
     if (rc) return rc;
     const size_t N = (size_t)w->host.N;
-    std::vector<uint32_t> planes(8 * N);
-    for (size_t i = 0; i < N; ++i)
-        for (int k = 0; k < 8; ++k) planes[k * N + i] = flows8[i * 8 + k];
+    // the record as the act kernel writes it: flow words (amount << 1 |
+    // explored) per direction plane, and the outflow total
+    std::vector<uint32_t> planes(8 * N), outs(N);
+    for (size_t i = 0; i < N; ++i) {
+        uint64_t tot = 0;
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t f = flows8[i * 8 + k];
+            if (f > 0x7fffffffu) return fail(CORALAI_E_INVALID, "flow amounts must be < 2^31");
+            planes[k * N + i] = (f << 1) | (uint32_t)((explore_dir[i] & 7) == k);
+            tot += f;
+        }
+        if (tot > 0xffffffffull) return fail(CORALAI_E_INVALID, "a cell's outflow must be < 2^32");
+        outs[i] = (uint32_t)tot;
+    }
     const int nxt = cur ^ 1;
     HIP_TRY(hipMemcpyAsync(w->host.flow, planes.data(), 4 * 8 * N, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.I1, i1, 8 * N, hipMemcpyHostToDevice, w->stream));
-    HIP_TRY(hipMemcpyAsync(w->host.X, explore_dir, N, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.out, outs.data(), 4 * N, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.E[nxt], w->host.E[cur], 8 * N, hipMemcpyDeviceToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.C[nxt], w->host.C[cur], 16 * N, hipMemcpyDeviceToDevice, w->stream));
     launch_physics_only(w->bdev, w->ls, w->phys_tile, w->stream);

@@ -92,7 +92,8 @@ def test_actuators_match_oracle_fp32(stream, W, H, layers, hidden, act_cells):
 
 def test_physics_from_oracle_records_is_bit_exact(stream):
     say("physics from records")
-    for (W, H, tile) in [(37, 23, 0), (64, 64, 1), (70, 33, 2), (1, 1, 0), (2, 2, 1), (3, 5, 2)]:
+    for (W, H, tile) in [(37, 23, 0), (64, 64, 1), (70, 33, 2), (1, 1, 0), (2, 2, 1), (3, 5, 2),
+                         (37, 23, 3), (1, 1, 3), (2, 3, 3), (130, 67, 3)]:
         init = gh.heterogeneous_world(W, H, n_genomes=4, seed=W * 7 + H)
         d = gh.oracle_desc(init.spec)
         s = oracle.State.from_init(init)
@@ -235,7 +236,8 @@ def test_translation_invariance_bit_identical(stream):
 def test_tuning_choices_and_graph_give_identical_results(stream):
     init = gh.heterogeneous_world(150, 90, n_genomes=9, layers=3, hidden=64, seed=5)
     outs = []
-    for act, tile, strm in [(1, 0, stream), (2, 1, stream), (4, 2, None), (2, 0, None)]:
+    for act, tile, strm in [(1, 0, stream), (2, 1, stream), (4, 2, None), (2, 0, None), (2, 3, stream),
+                            (1, 3, None)]:
         w = gh.make_world(init, strm)
         w.set_tuning(act, tile)
         w.step(3)
@@ -264,7 +266,7 @@ def test_autotune_keeps_state(stream):
     w = gh.make_world(init, stream)
     before = w.get_state()
     act, tile = w.autotune()
-    assert act in (1, 2, 4) and tile in (0, 1, 2)
+    assert act in (1, 2, 4) and tile in (0, 1, 2, 3)
     after = w.get_state()
     for ch in before:
         np.testing.assert_array_equal(before[ch], after[ch])
