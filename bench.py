@@ -126,6 +126,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--bf16-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain device copy of 512 MiB (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -138,6 +140,12 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     side = args.size
     patches = max(1, 65536 * side * side // (4096 * 4096))
     print("[bench] generating %dx%d workload" % (side, side), file=sys.stderr, flush=True)

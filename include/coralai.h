@@ -73,7 +73,7 @@ enum {
  * invest / liquidate move floor(rho * sigmoid(a) * stock) quanta, the
  * exploration budget is floor(kappa * I1) quanta. */
 typedef struct {
-    int32_t width, height;    /* >= 1 each; W*H <= 2^28 */
+    int32_t width, height;    /* >= 1 each; W*H <= 2^26 (8192 x 8192) */
     int32_t n_weight_layers;  /* 2: 54-h-14, 3: 54-h-h-14 */
     int32_t hidden;           /* 32 or 64 */
     int32_t genome_capacity;  /* slot ids in [0, capacity), 1 .. 2^22 */
@@ -169,11 +169,19 @@ int coralai_batch_destroy(coralai_batch* b);
 
 /* Launch tuning.  coralai_autotune times the candidate configurations on the
  * world's current state (without advancing it) and keeps the fastest;
- * coralai_set_tuning forces one (act_cells: column groups of 16 cells
- * processed together, 1, 2 or 4; phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8,
- * 2 = 16x16, or 3 = streaming, one thread per cell without LDS). */
-int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* phys_tile_out);
-int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t phys_tile);
+ * coralai_set_tuning forces one.  act_cells: column groups of 16 cells the
+ * network kernel processes together (1, 2 or 4); act_waves: 0 = fewer
+ * wavefronts per SIMD with more registers each, 1 = more wavefronts;
+ * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 16x16, or 3 = streaming,
+ * one thread per cell without LDS.  The batch versions tune the batch's
+ * single captured step over its current worlds. */
+int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* act_waves_out,
+                     int32_t* phys_tile_out);
+int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t act_waves, int32_t phys_tile);
+int coralai_batch_autotune(coralai_batch* b, int32_t* act_cells_out, int32_t* act_waves_out,
+                           int32_t* phys_tile_out);
+int coralai_batch_set_tuning(coralai_batch* b, int32_t act_cells, int32_t act_waves,
+                             int32_t phys_tile);
 
 /* Live phase timing.  While profiling is on, coralai_step and coralai_radiate
  * launch their kernels directly (no graph) with HIP events recorded on the

@@ -33,7 +33,8 @@ EXPORTED = [
     "coralai_batch_destroy", "coralai_autotune", "coralai_set_tuning", "coralai_last_error",
     "coralai_version", "coralai_debug_buckets", "coralai_debug_actuators",
     "coralai_debug_set_weights", "coralai_debug_get_weights", "coralai_debug_physics",
-    "coralai_set_profiling", "coralai_get_profile",
+    "coralai_set_profiling", "coralai_get_profile", "coralai_batch_autotune",
+    "coralai_batch_set_tuning",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -91,8 +92,10 @@ def lib() -> ct.CDLL:
             "coralai_batch_step": (ct.c_int, [P, I32]),
             "coralai_batch_sync": (ct.c_int, [P]),
             "coralai_batch_destroy": (ct.c_int, [P]),
-            "coralai_autotune": (ct.c_int, [P, ct.POINTER(I32), ct.POINTER(I32)]),
-            "coralai_set_tuning": (ct.c_int, [P, I32, I32]),
+            "coralai_autotune": (ct.c_int, [P, ct.POINTER(I32), ct.POINTER(I32), ct.POINTER(I32)]),
+            "coralai_set_tuning": (ct.c_int, [P, I32, I32, I32]),
+            "coralai_batch_autotune": (ct.c_int, [P, ct.POINTER(I32), ct.POINTER(I32), ct.POINTER(I32)]),
+            "coralai_batch_set_tuning": (ct.c_int, [P, I32, I32, I32]),
             "coralai_last_error": (ct.c_char_p, []),
             "coralai_version": (ct.c_char_p, []),
             "coralai_debug_buckets": (ct.c_int, [P, P, P, P]),
@@ -185,14 +188,24 @@ def coralai_get_stats(h, stats: coralai_stats) -> None:
     _check(lib().coralai_get_stats(h, ct.byref(stats)))
 
 
-def coralai_autotune(h) -> tuple[int, int]:
-    a, p = ct.c_int32(), ct.c_int32()
-    _check(lib().coralai_autotune(h, ct.byref(a), ct.byref(p)))
-    return a.value, p.value
+def coralai_autotune(h) -> tuple[int, int, int]:
+    a, w, p = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _check(lib().coralai_autotune(h, ct.byref(a), ct.byref(w), ct.byref(p)))
+    return a.value, w.value, p.value
 
 
-def coralai_set_tuning(h, act_cells: int, phys_tile: int) -> None:
-    _check(lib().coralai_set_tuning(h, act_cells, phys_tile))
+def coralai_set_tuning(h, act_cells: int, act_waves: int, phys_tile: int) -> None:
+    _check(lib().coralai_set_tuning(h, act_cells, act_waves, phys_tile))
+
+
+def coralai_batch_autotune(b) -> tuple[int, int, int]:
+    a, w, p = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _check(lib().coralai_batch_autotune(b, ct.byref(a), ct.byref(w), ct.byref(p)))
+    return a.value, w.value, p.value
+
+
+def coralai_batch_set_tuning(b, act_cells: int, act_waves: int, phys_tile: int) -> None:
+    _check(lib().coralai_batch_set_tuning(b, act_cells, act_waves, phys_tile))
 
 
 def coralai_batch_bytes(max_worlds: int) -> int:

@@ -127,6 +127,10 @@ __host__ __device__ constexpr int net_flat_size(int nl, int hid) {
                    : hid * kNIn + hid + hid * hid + hid + kNOut * hid + kNOut;
 }
 
+// Hidden layers (all but the last) are stored multiplied by 2 log2(e), so the
+// network kernel evaluates tanh(x) as 1 - 2 / (2^y + 1) on y = 2 log2(e) x.
+constexpr double kTanhScale = 2.8853900817779268;
+
 struct FragCoord {
     int layer, row, col;
 };
@@ -221,6 +225,21 @@ __device__ __forceinline__ const CORALAI_CONST WorldDev* world_at(const BatchDev
 }
 __device__ __forceinline__ int ctl_cur(const Ctl* c) { return ((const CORALAI_CONST Ctl*)c)->cur; }
 
+// Buffer resources over one plane or plane group (< 4 GiB: worlds have at
+// most 2^26 cells).  Buffer accesses take 32-bit offsets next to an SGPR
+// descriptor, and reads outside the range return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+typedef unsigned int coralai_u32x2 __attribute__((__vector_size__(8)));
+__device__ __forceinline__ int64_t buf_ld_i64(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(int64_t, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st_i64(int64_t v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(coralai_u32x2, v), r, off, 0, 0);
+}
+
 // int64 -> float with at most one extra rounding for values >= 2^32 (exact
 // conversion for the common |v| < 2^24, correctly rounded below 2^32).
 __device__ __forceinline__ float i64_to_f32(int64_t v) {
@@ -241,10 +260,11 @@ struct LaunchShape {
 
 // Launchers implemented in the kernel translation units.
 void launch_step_kernels(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
-                         int act_cells, int phys_tile, hipStream_t s, float* debug_act);
+                         int act_cells, int act_waves, int phys_tile, hipStream_t s,
+                         float* debug_act);
 void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
 void launch_act_only(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
-                     int act_cells, hipStream_t s, float* debug_act);
+                     int act_cells, int act_waves, hipStream_t s, float* debug_act);
 void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
                          hipStream_t s);
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);

@@ -39,15 +39,17 @@ struct Net {
     static constexpr int F1 = NL == 3 ? MT * KSH : 0;
     static constexpr int FRAG_BYTES = net_frag_bytes(PREC);
     static constexpr int STAGE_ROW = kBF ? 144 : 272;  // bytes per cell row (padded)
-    static constexpr int STAGE_BYTES = 64 * STAGE_ROW;
+    static constexpr int BIAS_BYTES = 4 * net_bias_floats(NL, HID);
+    static constexpr int STAGE_BYTES = 64 * STAGE_ROW + BIAS_BYTES;  // stage, then the biases
     static constexpr int ACT_ROW = 80;                 // 16 floats + 4 pad, conflict free
     using frag_t = typename std::conditional<kBF, bf16x8, float>::type;
 };
 
-// tanh(x) = 1 - 2 / (exp(2x) + 1): one exp and one reciprocal, exact limits.
-__device__ __forceinline__ float fast_tanh(float x) {
-    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+// tanh(x) = 1 - 2 / (2^(2 log2(e) x) + 1): one exp2 and one reciprocal,
+// exact limits.  The hidden layers' weights and biases are stored multiplied
+// by 2 log2(e) (kTanhScale), so the argument arrives pre-scaled from the MFMA.
+__device__ __forceinline__ float tanh_prescaled(float y) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
 }
 
 __device__ __forceinline__ float sigmoid_f(float x) {
@@ -61,10 +63,13 @@ __device__ __forceinline__ floatx4 mfma(float a, float b, const floatx4& c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// LDS hand-off between lanes of one wavefront: LDS operations of a wave
+// complete in order, so waiting for the LDS counter alone (not for vector
+// memory, whose counter also holds outstanding global stores) suffices.
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt / expcnt unconstrained
+    __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
@@ -78,8 +83,8 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-template <int NL, int HID, int PREC, int CGI, bool DEBUG>
-__global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
+template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG>
+__global__ __launch_bounds__(256, WAVES) void k_act(
     const BatchDev* __restrict__ b, float* __restrict__ dbg) {
     using NT = Net<NL, HID, PREC>;
     using frag_t = typename NT::frag_t;
@@ -91,6 +96,9 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int q = lane >> 4, n16 = lane & 15;
     uint8_t* stage = smem + wv * NT::STAGE_BYTES;
+    // the current genome's biases live in LDS: reading them must not wait on
+    // the vector-memory counter, which also covers the previous unit's stores
+    float* sbias = (float*)(stage + 64 * NT::STAGE_ROW);
 
     const int nworlds = cld(&b->n_worlds);
     if (nworlds <= 0) return;
@@ -111,21 +119,18 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
     int64_t acc_mass = 0;
     double acc_f64 = 0.0;
     uint32_t err = 0;
+    // the next unit's cell and rotation, loaded while this unit computes
+    bool have_pf = false;
+    int i_pf = 0, r_pf = 0;
 
-    // world fields kept in registers
+    // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
-    const int64_t *Ec = nullptr, *Ic = nullptr;
-    const float* Cc = nullptr;
-    const uint8_t* Rc = nullptr;
-    int64_t *En = nullptr, *I1p = nullptr;
-    float* Cn = nullptr;
-    uint32_t* flow = nullptr;
-    uint32_t* outp = nullptr;
-    const int32_t *perm = nullptr, *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
+    __amdgpu_buffer_rsrc_t rE, rI, rC, rR, rP, wE, wC, wI1, wOut, wFlow;
+    const int32_t *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
-    const float* gbias = nullptr;  // the current genome's bias block
+    const float* gbias = sbias + 4 * q;  // this lane's rows of the current genome's biases
     int64_t wstride = 0;
     int bstride = 0;
     Ctl* ctl = nullptr;
@@ -155,10 +160,18 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
             rho_i = W->rho_i; rho_l = W->rho_l; kappa = W->kappa;
             ctl = W->ctl;
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
-            Ec = W->E[cur]; Ic = W->I[cur]; Cc = W->C[cur]; Rc = W->R[cur];
-            En = W->E[nxt]; Cn = W->C[nxt];
-            I1p = W->I1; flow = W->flow; outp = W->out;
-            perm = W->perm; counts = W->counts; offsets = W->offsets; gofs = W->gofs;
+            const uint32_t n4 = 4u * (uint32_t)Nd;
+            rE = buf_rsrc(W->E[cur], 2u * n4);
+            rI = buf_rsrc(W->I[cur], 2u * n4);
+            rC = buf_rsrc(W->C[cur], 4u * n4);
+            rR = buf_rsrc(W->R[cur], (uint32_t)Nd);
+            rP = buf_rsrc(W->perm, n4);
+            wE = buf_rsrc(W->E[nxt], 2u * n4);
+            wC = buf_rsrc(W->C[nxt], 4u * n4);
+            wI1 = buf_rsrc(W->I1, 2u * n4);
+            wOut = buf_rsrc(W->out, n4);
+            wFlow = buf_rsrc(W->flow, 8u * n4);
+            counts = W->counts; offsets = W->offsets; gofs = W->gofs;
             wfrag = W->wfrag; bias = W->bias; wstride = W->wfrag_stride; bstride = W->bias_stride;
             g = -1;
             g_hi = -1;
@@ -170,19 +183,19 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
             if (g >= 0) {
 #pragma unroll 1
                 for (int t = g + 1; t < min(cap, g + 5); ++t)
-                    if (gld(gofs + t + 1) > k) { gn = t; break; }
+                    if (cld(gofs + t + 1) > k) { gn = t; break; }
             }
             if (gn < 0) {
                 int lo = 0, hi = cap - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (gld(gofs + mid) <= k) lo = mid; else hi = mid - 1;
+                    if (cld(gofs + mid) <= k) lo = mid; else hi = mid - 1;
                 }
                 gn = lo;
             }
             g = uniform_i32(gn);
-            g_lo = gld(gofs + g);
-            g_hi = gld(gofs + g + 1);
+            g_lo = cld(gofs + g);
+            g_hi = cld(gofs + g + 1);
             // weights of genome g -> registers
             const uint8_t* wb = wfrag + (int64_t)g * wstride + lane * (NT::FRAG_BYTES / 64);
 #pragma unroll
@@ -200,17 +213,34 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
 #pragma unroll
             for (int s = 0; s < KSH; ++s)
                 wo[s] = gld((const frag_t*)(wb + (NT::F0 + NT::F1 + s) * NT::FRAG_BYTES));
-            gbias = bias + (int64_t)g * bstride + 4 * q;
+            const float* gb = bias + (int64_t)g * bstride;
+            for (int t = lane; t < net_bias_floats(NL, HID) / 4; t += 64)
+                *(floatx4*)(sbias + 4 * t) = gld((const floatx4*)(gb + 4 * t));
+            wave_lds_sync();
         }
         const int j = k - g_lo;
-        const int cell0 = gld(offsets + g) + j * kGroupCells;
-        const int cnt = min(kGroupCells, gld(counts + g) - j * kGroupCells);
+        const int gcount = cld(counts + g);
+        const int cell0 = cld(offsets + g) + j * kGroupCells;
+        const int cnt = min(kGroupCells, gcount - j * kGroupCells);
         const bool valid = lane < cnt;
-        const int i = gld(perm + cell0 + (valid ? lane : 0));
+        int i, r;
+        if (have_pf) {
+            i = i_pf;
+            r = r_pf;
+        } else {
+            i = (int)__builtin_amdgcn_raw_buffer_load_b32(rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
+            r = __builtin_amdgcn_raw_buffer_load_b8(rR, i, 0, 0) & 7;
+        }
+        // prefetch the next unit's cell index when it continues this genome
+        have_pf = (u + 1 < uend) && (u + 1 < world_hi) && (k + 1 < g_hi);
+        if (have_pf) {
+            const int cnt_n = min(kGroupCells, gcount - (j + 1) * kGroupCells);
+            i_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rP, 4 * (cell0 + kGroupCells + (lane < cnt_n ? lane : 0)), 0, 0);
+        }
 
         // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
         const int y = i / Wd, x = i - y * Wd;
-        const int r = gld(Rc + i) & 7;
         float uvec[kNIn];
         int64_t e_own = 0, i_own = 0;
 #pragma unroll
@@ -223,12 +253,14 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
                 ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
                 nidx = ny * Wd + nx;
             }
-            const int64_t ev = gld(Ec + nidx), iv = gld(Ic + nidx);
+            const int64_t ev = buf_ld_i64(rE, 8 * nidx), iv = buf_ld_i64(rI, 8 * nidx);
             if (p == 0) { e_own = ev; i_own = iv; }
             uvec[6 * p + 0] = i64_to_f32(ev) * 0x1p-24f;
             uvec[6 * p + 1] = i64_to_f32(iv) * 0x1p-24f;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = gld(Cc + (int64_t)c * Nd + nidx);
+            for (int c = 0; c < 4; ++c)
+                uvec[6 * p + 2 + c] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rC, 4 * nidx, c * 4 * Nd, 0));
         }
         if constexpr (NT::kBF) {
 #pragma unroll
@@ -264,7 +296,7 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
             floatx4 acc[CGI][MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const floatx4 bv = gld((const floatx4*)(gbias + 16 * mt));
+                const floatx4 bv = *(const floatx4*)(gbias + 16 * mt);
 #pragma unroll
                 for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
             }
@@ -313,11 +345,11 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
                             for (int t = 0; t < 4; ++t) {
-                                h[cc][s][t] = (__bf16)fast_tanh(acc[cc][2 * s][t]);
-                                h[cc][s][4 + t] = (__bf16)fast_tanh(acc[cc][2 * s + 1][t]);
+                                h[cc][s][t] = (__bf16)tanh_prescaled(acc[cc][2 * s][t]);
+                                h[cc][s][4 + t] = (__bf16)tanh_prescaled(acc[cc][2 * s + 1][t]);
                             }
                     if (last) {
-                        const floatx4 bv = gld((const floatx4*)lb);
+                        const floatx4 bv = *(const floatx4*)lb;
 #pragma unroll
                         for (int cc = 0; cc < CGI; ++cc) {
                             floatx4 o = bv;
@@ -328,7 +360,7 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
                     } else {
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
-                            const floatx4 bv = gld((const floatx4*)(lb + 16 * mt));
+                            const floatx4 bv = *(const floatx4*)(lb + 16 * mt);
 #pragma unroll
                             for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
                         }
@@ -347,9 +379,9 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) h[cc][mt][t] = fast_tanh(acc[cc][mt][t]);
+                            for (int t = 0; t < 4; ++t) h[cc][mt][t] = tanh_prescaled(acc[cc][mt][t]);
                     if (last) {
-                        const floatx4 bv = gld((const floatx4*)lb);
+                        const floatx4 bv = *(const floatx4*)lb;
 #pragma unroll
                         for (int cc = 0; cc < CGI; ++cc) {
                             floatx4 o = bv;
@@ -360,7 +392,7 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
                     } else {
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
-                            const floatx4 bv = gld((const floatx4*)(lb + 16 * mt));
+                            const floatx4 bv = *(const floatx4*)(lb + 16 * mt);
 #pragma unroll
                             for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
                         }
@@ -375,6 +407,7 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
                 }
             }
         }
+        if (have_pf) r_pf = __builtin_amdgcn_raw_buffer_load_b8(rR, i_pf, 0, 0) & 7;
         wave_lds_sync();  // all stage reads done before the actuator rows overwrite them
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -414,7 +447,9 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
             const int64_t E1 = e_own - xi + xl, I1 = i_own + xi - xl;
             // communication: sigmoid of the comm actuators
 #pragma unroll
-            for (int c = 0; c < 4; ++c) gst(Cn + (int64_t)c * Nd + i, sigmoid_f(a[2 + c]));
+            for (int c = 0; c < 4; ++c)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sigmoid_f(a[2 + c])), wC,
+                                                      4 * i, c * 4 * Nd, 0);
             // exploration: softmax split of the flow budget, argmax explore
             float m = a[6];
             int best = 0;
@@ -438,12 +473,12 @@ __global__ __launch_bounds__(256, PREC == kPrecBF16 ? 2 : 1) void k_act(
                 f = f > F - used ? F - used : f;
                 f = f < 0 ? 0 : f;
                 used += f;
-                gst(flow + (int64_t)kernel_dir(r, t + 1) * Nd + i,
-                    ((uint32_t)f << 1) | (uint32_t)(t == best));
+                __builtin_amdgcn_raw_buffer_store_b32(((uint32_t)f << 1) | (uint32_t)(t == best), wFlow,
+                                                      4 * (kernel_dir(r, t + 1) * Nd + i), 0, 0);
             }
-            gst(En + i, E1);
-            gst(I1p + i, I1);
-            gst(outp + i, (uint32_t)used);
+            buf_st_i64(E1, wE, 8 * i);
+            buf_st_i64(I1, wI1, 8 * i);
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)used, wOut, 4 * i, 0, 0);
             acc_mass += E1;
             acc_f64 += (double)E1;
         }
@@ -460,43 +495,54 @@ static int resident_blocks(K kernel, int n_cu) {
     return n_cu * per_cu;
 }
 
-template <int NL, int HID, int PREC, int CGI, bool DEBUG>
+template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG>
 static void launch_act_c(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, float* dbg) {
     static int blocks = 0;
-    if (blocks == 0) blocks = resident_blocks(k_act<NL, HID, PREC, CGI, DEBUG>, ls.n_cu);
-    hipLaunchKernelGGL((k_act<NL, HID, PREC, CGI, DEBUG>), dim3(blocks), dim3(256), 0, s, bdev, dbg);
+    if (blocks == 0) blocks = resident_blocks(k_act<NL, HID, PREC, CGI, WAVES, DEBUG>, ls.n_cu);
+    hipLaunchKernelGGL((k_act<NL, HID, PREC, CGI, WAVES, DEBUG>), dim3(blocks), dim3(256), 0, s, bdev, dbg);
 }
 
+// act_cells: column groups of 16 cells processed together (1, 2, 4);
+// act_waves: 0 = fewer waves per SIMD with more registers each, 1 = more waves.
 template <int NL, int HID, int PREC, bool DEBUG>
-static void launch_act_t(const BatchDev* bdev, const LaunchShape& ls, int act_cells, hipStream_t s,
-                         float* dbg) {
-    switch (act_cells) {
-        case 1: launch_act_c<NL, HID, PREC, 1, DEBUG>(bdev, ls, s, dbg); break;
-        case 2: launch_act_c<NL, HID, PREC, 2, DEBUG>(bdev, ls, s, dbg); break;
-        default: launch_act_c<NL, HID, PREC, 4, DEBUG>(bdev, ls, s, dbg); break;
+static void launch_act_t(const BatchDev* bdev, const LaunchShape& ls, int act_cells, int act_waves,
+                         hipStream_t s, float* dbg) {
+    constexpr int LO = PREC == kPrecBF16 ? 2 : 1, HI = LO + 1;
+    if (act_waves) {
+        switch (act_cells) {
+            case 1: launch_act_c<NL, HID, PREC, 1, HI, DEBUG>(bdev, ls, s, dbg); break;
+            case 2: launch_act_c<NL, HID, PREC, 2, HI, DEBUG>(bdev, ls, s, dbg); break;
+            default: launch_act_c<NL, HID, PREC, 4, HI, DEBUG>(bdev, ls, s, dbg); break;
+        }
+    } else {
+        switch (act_cells) {
+            case 1: launch_act_c<NL, HID, PREC, 1, LO, DEBUG>(bdev, ls, s, dbg); break;
+            case 2: launch_act_c<NL, HID, PREC, 2, LO, DEBUG>(bdev, ls, s, dbg); break;
+            default: launch_act_c<NL, HID, PREC, 4, LO, DEBUG>(bdev, ls, s, dbg); break;
+        }
     }
 }
 
 template <bool DEBUG>
 static void launch_act_d(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
-                         int act_cells, hipStream_t s, float* dbg) {
+                         int act_cells, int act_waves, hipStream_t s, float* dbg) {
     if (prec == kPrecBF16) {
-        if (NL == 2 && HID == 32) launch_act_t<2, 32, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
-        else if (NL == 2 && HID == 64) launch_act_t<2, 64, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
-        else if (NL == 3 && HID == 32) launch_act_t<3, 32, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
-        else launch_act_t<3, 64, kPrecBF16, DEBUG>(bdev, ls, act_cells, s, dbg);
+        if (NL == 2 && HID == 32) launch_act_t<2, 32, kPrecBF16, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
+        else if (NL == 2 && HID == 64) launch_act_t<2, 64, kPrecBF16, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
+        else if (NL == 3 && HID == 32) launch_act_t<3, 32, kPrecBF16, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
+        else launch_act_t<3, 64, kPrecBF16, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
     } else {
-        if (NL == 2 && HID == 32) launch_act_t<2, 32, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
-        else if (NL == 2 && HID == 64) launch_act_t<2, 64, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
-        else if (NL == 3 && HID == 32) launch_act_t<3, 32, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
-        else launch_act_t<3, 64, kPrecFP32, DEBUG>(bdev, ls, act_cells, s, dbg);
+        if (NL == 2 && HID == 32) launch_act_t<2, 32, kPrecFP32, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
+        else if (NL == 2 && HID == 64) launch_act_t<2, 64, kPrecFP32, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
+        else if (NL == 3 && HID == 32) launch_act_t<3, 32, kPrecFP32, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
+        else launch_act_t<3, 64, kPrecFP32, DEBUG>(bdev, ls, act_cells, act_waves, s, dbg);
     }
 }
 
 void launch_act_only(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
-                     int act_cells, hipStream_t s, float* debug_act) {
-    if (debug_act) launch_act_d<true>(bdev, ls, NL, HID, prec, act_cells, s, debug_act);
-    else launch_act_d<false>(bdev, ls, NL, HID, prec, act_cells, s, nullptr);
+                     int act_cells, int act_waves, hipStream_t s, float* debug_act) {
+    if (debug_act) launch_act_d<true>(bdev, ls, NL, HID, prec, act_cells, act_waves, s, debug_act);
+    else launch_act_d<false>(bdev, ls, NL, HID, prec, act_cells, act_waves, s, nullptr);
 }
 
 }  // namespace coralai

@@ -53,18 +53,22 @@ __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, 
 template <typename T>
 __device__ __forceinline__ T neuron_x(int j, int L) { return T(-1) + T(2) * T(j) / T(L - 1); }
 
+// Stored value of a weight / bias: hidden layers carry the tanh argument
+// scale (kTanhScale), applied before the single rounding to FP32 or bf16.
 template <typename T>
 __device__ __forceinline__ float cppn_weight(const float* p, int layer, int nl, int row, int lout,
                                              int col, int lin) {
     const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
+    const T sc = layer < nl - 1 ? T(kTanhScale) : T(1);
     return (float)(cppn_eval<T>(p, neuron_x<T>(col, lin), yi, neuron_x<T>(row, lout), yo, 0) /
-                   sqrt(T(lin)));
+                   sqrt(T(lin)) * sc);
 }
 
 template <typename T>
 __device__ __forceinline__ float cppn_bias(const float* p, int layer, int nl, int row, int lout) {
     const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
-    return (float)cppn_eval<T>(p, T(0), yi, neuron_x<T>(row, lout), yo, 1);
+    const T sc = layer < nl - 1 ? T(kTanhScale) : T(1);
+    return (float)(cppn_eval<T>(p, T(0), yi, neuron_x<T>(row, lout), yo, 1) * sc);
 }
 
 // Layer geometry of a bias element index.
@@ -127,7 +131,8 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     }
 }
 
-// Debug: natural flat layout <-> fragment layout of one slot.
+// Debug: natural flat layout <-> fragment layout of one slot (the stored
+// hidden layers carry kTanhScale; the flat layout does not).
 __global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, int slot,
                                               const float* __restrict__ flat, int unpack,
                                               float* __restrict__ out) {
@@ -142,12 +147,13 @@ __global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, in
             const int lin = layer_in(nl, hid, fc.layer), lout = layer_out(nl, hid, fc.layer);
             const bool ok = fc.row < lout && fc.col < lin;
             const int fi = flat_w_offset(nl, hid, fc.layer) + fc.row * lin + fc.col;
+            const double sc = fc.layer < nl - 1 ? kTanhScale : 1.0;
             if (!unpack) {
-                const float v = ok ? flat[fi] : 0.0f;
+                const float v = ok ? (float)((double)flat[fi] * sc) : 0.0f;
                 if (bf) ((__bf16*)dst)[e] = (__bf16)v;
                 else ((float*)dst)[e] = v;
             } else if (ok) {
-                out[fi] = bf ? (float)((const __bf16*)dst)[e] : ((const float*)dst)[e];
+                out[fi] = (float)((bf ? (double)(float)((const __bf16*)dst)[e] : (double)((const float*)dst)[e]) / sc);
             }
         } else {
             int layer, row;
@@ -155,9 +161,10 @@ __global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, in
             const int lin = layer_in(nl, hid, layer), lout = layer_out(nl, hid, layer);
             const bool ok = row < lout;
             const int fi = flat_w_offset(nl, hid, layer) + lout * lin + row;
+            const double sc = layer < nl - 1 ? kTanhScale : 1.0;
             float* bp = w->bias + (int64_t)slot * w->bias_stride + (e - ew);
-            if (!unpack) *bp = ok ? flat[fi] : 0.0f;
-            else if (ok) out[fi] = *bp;
+            if (!unpack) *bp = ok ? (float)((double)flat[fi] * sc) : 0.0f;
+            else if (ok) out[fi] = (float)((double)*bp / sc);
         }
     }
     if (!unpack && blockIdx.x == 0 && threadIdx.x == 0) w->slot_set[slot] = 1;

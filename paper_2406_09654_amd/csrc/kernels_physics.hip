@@ -166,9 +166,6 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
 // each plane element is read by exactly one target, so nothing is re-read;
 // the cell's own outflow total comes from the record.  Buffer loads keep the
 // offsets in 32 bits (planes are < 4 GiB) and return 0 outside a plane.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
 
 __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restrict__ b) {
     __shared__ int64_t s_red_m[4];
@@ -228,17 +225,17 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             const uint32_t n4 = 4u * (uint32_t)Nd;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) rflow[k] = plane_rsrc(W->flow + (int64_t)k * Nd, n4);
-            rout = plane_rsrc(W->out, n4);
-            ri1 = plane_rsrc(W->I1, 2u * n4);
-            rg = plane_rsrc(W->G[cur], n4);
-            rr = plane_rsrc(W->R[cur], (uint32_t)Nd);
+            for (int k = 0; k < 8; ++k) rflow[k] = buf_rsrc(W->flow + (int64_t)k * Nd, n4);
+            rout = buf_rsrc(W->out, n4);
+            ri1 = buf_rsrc(W->I1, 2u * n4);
+            rg = buf_rsrc(W->G[cur], n4);
+            rr = buf_rsrc(W->R[cur], (uint32_t)Nd);
             In = W->I[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
         }
         const int t = (int)((unit - world_lo) * 256) + tid;
         if (t < Nd) {  // (no divergent continue: the world fields must stay uniform)
             const int y = t / Wd, x = t - y * Wd;
-            const int64_t i1 = (int64_t)__builtin_amdgcn_raw_buffer_load_b64(ri1, 8 * t, 0, 0);
+            const int64_t i1 = buf_ld_i64(ri1, 8 * t);
             const uint32_t out = __builtin_amdgcn_raw_buffer_load_b32(rout, 4 * t, 0, 0);
             int32_t g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * t, 0, 0);
             uint8_t r2 = __builtin_amdgcn_raw_buffer_load_b8(rr, t, 0, 0);
@@ -285,9 +282,10 @@ void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_t
 }
 
 void launch_step_kernels(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
-                         int act_cells, int phys_tile, hipStream_t s, float* debug_act) {
+                         int act_cells, int act_waves, int phys_tile, hipStream_t s,
+                         float* debug_act) {
     launch_bucket_only(bdev, ls, s);
-    launch_act_only(bdev, ls, NL, HID, prec, act_cells, s, debug_act);
+    launch_act_only(bdev, ls, NL, HID, prec, act_cells, act_waves, s, debug_act);
     launch_physics_only(bdev, ls, phys_tile, s);
     launch_finalize(bdev, ls, s);
 }

@@ -61,7 +61,7 @@ bool desc_valid(const coralai_world_desc* d, std::string* why) {
     auto bad = [&](const char* m) { if (why) *why = m; return false; };
     if (!d) return bad("desc is NULL");
     if (d->width < 1 || d->height < 1) return bad("width and height must be >= 1");
-    if ((int64_t)d->width * d->height > (1ll << 28)) return bad("W*H must be <= 2^28");
+    if ((int64_t)d->width * d->height > (1ll << 26)) return bad("W*H must be <= 2^26");
     if (d->n_weight_layers != 2 && d->n_weight_layers != 3) return bad("n_weight_layers must be 2 or 3");
     if (d->hidden != 32 && d->hidden != 64) return bad("hidden must be 32 or 64");
     if (d->genome_capacity < 1 || d->genome_capacity > (1 << 22)) return bad("genome_capacity must be in [1, 2^22]");
@@ -164,9 +164,10 @@ struct coralai_world {
     BatchDev* bdev;
     LaunchShape ls;
     int act_cells = 2;
+    int act_waves = 0;
     int phys_tile = 0;
     hipGraphExec_t graph = nullptr;
-    int graph_act = -1, graph_phys = -1;
+    int graph_key = -1;
     Ctl* pinned = nullptr;
     // live phase timing
     bool profiling = false;
@@ -190,10 +191,10 @@ struct coralai_batch {
     int32_t* tiles_x;
     int n = 0;
     int NL = 0, HID = 0, prec = 0;
-    int act_cells = 2, phys_tile = 0;
+    int act_cells = 2, act_waves = 0, phys_tile = 0;
     LaunchShape ls;
     hipGraphExec_t graph = nullptr;
-    int graph_act = -1, graph_phys = -1;
+    int graph_key = -1;
     std::vector<coralai_world*> worlds;
     std::atomic<int> busy{0};
 };
@@ -330,11 +331,15 @@ void destroy_graph(hipGraphExec_t* g) {
 }
 
 // Capture the step sequence once; every size it needs is read on the device.
+int tuning_key(int act_cells, int act_waves, int phys_tile) {
+    return act_cells * 100 + act_waves * 10 + phys_tile;
+}
+
 int capture_step(hipStream_t s, const BatchDev* bdev, const LaunchShape& ls, int NL, int HID,
-                 int prec, int act_cells, int phys_tile, hipGraphExec_t* out) {
+                 int prec, int act_cells, int act_waves, int phys_tile, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    launch_step_kernels(bdev, ls, NL, HID, prec, act_cells, phys_tile, s, nullptr);
+    launch_step_kernels(bdev, ls, NL, HID, prec, act_cells, act_waves, phys_tile, s, nullptr);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) return fail(CORALAI_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -519,13 +524,13 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
     WORLD_GUARD(w);
     if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
     const bool use_graph = w->stream != nullptr && !w->profiling;
-    if (use_graph && (w->graph == nullptr || w->graph_act != w->act_cells || w->graph_phys != w->phys_tile)) {
+    const int key = tuning_key(w->act_cells, w->act_waves, w->phys_tile);
+    if (use_graph && (w->graph == nullptr || w->graph_key != key)) {
         destroy_graph(&w->graph);
         int rc = capture_step(w->stream, w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec,
-                              w->act_cells, w->phys_tile, &w->graph);
+                              w->act_cells, w->act_waves, w->phys_tile, &w->graph);
         if (rc) return rc;
-        w->graph_act = w->act_cells;
-        w->graph_phys = w->phys_tile;
+        w->graph_key = key;
     }
     for (int k = 0; k < n_steps; ++k) {
         if (use_graph) {
@@ -534,7 +539,8 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
             const WorldDev& h = w->host;
             int rc = timed_phase(w, 0, [&] { launch_bucket_only(w->bdev, w->ls, w->stream); });
             if (!rc) rc = timed_phase(w, 1, [&] {
-                launch_act_only(w->bdev, w->ls, h.NL, h.HID, h.prec, w->act_cells, w->stream, nullptr);
+                launch_act_only(w->bdev, w->ls, h.NL, h.HID, h.prec, w->act_cells, w->act_waves,
+                                w->stream, nullptr);
             });
             if (!rc) rc = timed_phase(w, 2, [&] { launch_physics_only(w->bdev, w->ls, w->phys_tile, w->stream); });
             if (!rc) rc = timed_phase(w, 3, [&] { launch_finalize(w->bdev, w->ls, w->stream); });
@@ -613,26 +619,36 @@ int coralai_get_profile(coralai_world* w, double* ms_sum, int64_t* launches) {
     return CORALAI_OK;
 }
 
-int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t phys_tile) {
+int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t act_waves, int32_t phys_tile) {
     WORLD_GUARD(w);
     if (act_cells != 1 && act_cells != 2 && act_cells != 4) return fail(CORALAI_E_INVALID, "act_cells must be 1, 2 or 4");
+    if (act_waves != 0 && act_waves != 1) return fail(CORALAI_E_INVALID, "act_waves must be 0 or 1");
     if (phys_tile < 0 || phys_tile > 3) return fail(CORALAI_E_INVALID, "phys_tile must be 0, 1, 2 or 3");
     w->act_cells = act_cells;
+    w->act_waves = act_waves;
     w->phys_tile = phys_tile;
     return write_world_tables(w);
 }
 
-int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* phys_tile_out) {
-    WORLD_GUARD(w);
+}  // extern "C"
+
+namespace {
+
+// Times every network-kernel variant and every physics variant on the
+// current state (the kernels only write the next buffers and the record, so
+// repeating them leaves the state unchanged) and returns the fastest.
+template <typename SetTile>
+int autotune_run(hipStream_t st, const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
+                 SetTile&& set_tile, int* act_cells, int* act_waves, int* phys_tile) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     auto timed = [&](auto&& fn) -> float {
         float best = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
-            (void)hipEventRecord(e0, w->stream);
+            (void)hipEventRecord(e0, st);
             fn();
-            (void)hipEventRecord(e1, w->stream);
+            (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
@@ -640,32 +656,42 @@ int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* phys_til
         }
         return best;
     };
-    // the kernels are idempotent on the current state until the buffers swap
-    launch_bucket_only(w->bdev, w->ls, w->stream);
+    launch_bucket_only(bdev, ls, st);
     float best_act = 1e30f;
-    int act = 2;
-    for (int c : {1, 2, 4}) {
-        float t = timed([&] { launch_act_only(w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec, c, w->stream, nullptr); });
-        if (t < best_act) { best_act = t; act = c; }
-    }
+    for (int wv : {0, 1})
+        for (int c : {1, 2, 4}) {
+            float t = timed([&] { launch_act_only(bdev, ls, NL, HID, prec, c, wv, st, nullptr); });
+            if (t < best_act) { best_act = t; *act_cells = c; *act_waves = wv; }
+        }
     float best_phys = 1e30f;
-    int pt = 0;
     for (int t = 0; t < 4; ++t) {
-        w->phys_tile = t;
-        int rc = write_world_tables(w);
+        int rc = set_tile(t);
         if (rc) return rc;
-        float ms = timed([&] { launch_physics_only(w->bdev, w->ls, t, w->stream); });
-        if (ms < best_phys) { best_phys = ms; pt = t; }
+        float ms = timed([&] { launch_physics_only(bdev, ls, t, st); });
+        if (ms < best_phys) { best_phys = ms; *phys_tile = t; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    w->act_cells = act;
-    w->phys_tile = pt;
-    int rc = write_world_tables(w);
+    return set_tile(*phys_tile);
+}
+
+}  // namespace
+
+extern "C" {
+
+int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* act_waves_out,
+                     int32_t* phys_tile_out) {
+    WORLD_GUARD(w);
+    int ac = 2, aw = 0, pt = 0;
+    int rc = autotune_run(w->stream, w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec,
+                          [&](int t) { w->phys_tile = t; return write_world_tables(w); }, &ac, &aw, &pt);
     if (rc) return rc;
+    w->act_cells = ac;
+    w->act_waves = aw;
     rc = check_launch();
     if (rc) return rc;
-    if (act_cells_out) *act_cells_out = act;
+    if (act_cells_out) *act_cells_out = ac;
+    if (act_waves_out) *act_waves_out = aw;
     if (phys_tile_out) *phys_tile_out = pt;
     return report_errors(w, nullptr);
 }
@@ -727,10 +753,56 @@ int coralai_batch_create(int32_t max_worlds, void* dev_arena, size_t arena_bytes
     return CORALAI_OK;
 }
 
+}  // extern "C"
+namespace {
+int batch_upload(coralai_batch* b, coralai_world* const* worlds, int32_t n);
+}
+extern "C" {
+
 int coralai_batch_set_worlds(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
     if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
     BusyGuard guard_(&b->busy);
     if (!guard_.ok) return fail(CORALAI_E_BUSY, "batch is in use");
+    return batch_upload(b, worlds, n);
+}
+
+int coralai_batch_autotune(coralai_batch* b, int32_t* act_cells_out, int32_t* act_waves_out,
+                           int32_t* phys_tile_out) {
+    if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
+    BusyGuard guard_(&b->busy);
+    if (!guard_.ok) return fail(CORALAI_E_BUSY, "batch is in use");
+    if (b->n == 0) return fail(CORALAI_E_INVALID, "the batch has no worlds");
+    std::vector<coralai_world*> ws = b->worlds;
+    int ac = 2, aw = 0, pt = 0;
+    int rc = autotune_run(b->stream, b->bdev, b->ls, b->NL, b->HID, b->prec,
+                          [&](int t) { b->phys_tile = t; return batch_upload(b, ws.data(), (int)ws.size()); },
+                          &ac, &aw, &pt);
+    if (rc) return rc;
+    b->act_cells = ac;
+    b->act_waves = aw;
+    if (act_cells_out) *act_cells_out = ac;
+    if (act_waves_out) *act_waves_out = aw;
+    if (phys_tile_out) *phys_tile_out = pt;
+    return check_launch();
+}
+
+int coralai_batch_set_tuning(coralai_batch* b, int32_t act_cells, int32_t act_waves, int32_t phys_tile) {
+    if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
+    BusyGuard guard_(&b->busy);
+    if (!guard_.ok) return fail(CORALAI_E_BUSY, "batch is in use");
+    if (act_cells != 1 && act_cells != 2 && act_cells != 4) return fail(CORALAI_E_INVALID, "act_cells must be 1, 2 or 4");
+    if (act_waves != 0 && act_waves != 1) return fail(CORALAI_E_INVALID, "act_waves must be 0 or 1");
+    if (phys_tile < 0 || phys_tile > 3) return fail(CORALAI_E_INVALID, "phys_tile must be 0, 1, 2 or 3");
+    b->act_cells = act_cells;
+    b->act_waves = act_waves;
+    b->phys_tile = phys_tile;
+    std::vector<coralai_world*> ws = b->worlds;
+    return batch_upload(b, ws.data(), (int)ws.size());
+}
+
+}  // extern "C"
+namespace {
+int batch_upload(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
     if (n < 0 || n > b->max_worlds) return fail(CORALAI_E_INVALID, "n must be in [0, max_worlds]");
     if (n > 0 && !worlds) return fail(CORALAI_E_INVALID, "worlds is NULL");
     std::vector<WorldDev> tab(n);
@@ -763,6 +835,8 @@ int coralai_batch_set_worlds(coralai_batch* b, coralai_world* const* worlds, int
     b->worlds.assign(worlds, worlds + n);
     return CORALAI_OK;
 }
+}  // namespace
+extern "C" {
 
 int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
     if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
@@ -771,17 +845,18 @@ int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
     if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
     if (b->n == 0 || n_steps == 0) return CORALAI_OK;
     const bool use_graph = b->stream != nullptr;
-    if (use_graph && (b->graph == nullptr || b->graph_act != b->act_cells || b->graph_phys != b->phys_tile)) {
+    const int key = tuning_key(b->act_cells, b->act_waves, b->phys_tile);
+    if (use_graph && (b->graph == nullptr || b->graph_key != key)) {
         destroy_graph(&b->graph);
         int rc = capture_step(b->stream, b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells,
-                              b->phys_tile, &b->graph);
+                              b->act_waves, b->phys_tile, &b->graph);
         if (rc) return rc;
-        b->graph_act = b->act_cells;
-        b->graph_phys = b->phys_tile;
+        b->graph_key = key;
     }
     for (int k = 0; k < n_steps; ++k) {
         if (use_graph) HIP_TRY(hipGraphLaunch(b->graph, b->stream));
-        else launch_step_kernels(b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells, b->phys_tile, b->stream, nullptr);
+        else launch_step_kernels(b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells, b->act_waves,
+                                 b->phys_tile, b->stream, nullptr);
     }
     return check_launch();
 }
@@ -822,7 +897,8 @@ int coralai_debug_actuators(coralai_world* w, float* act) {
     float* d = nullptr;
     HIP_TRY(hipMalloc((void**)&d, 4 * kNOut * N));
     launch_bucket_only(w->bdev, w->ls, w->stream);
-    launch_act_only(w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec, w->act_cells, w->stream, d);
+    launch_act_only(w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec, w->act_cells, w->act_waves,
+                    w->stream, d);
     int rc = check_launch();
     if (!rc && hipMemcpyAsync(act, d, 4 * kNOut * N, hipMemcpyDeviceToHost, w->stream) != hipSuccess)
         rc = fail(CORALAI_E_HIP, "actuator copy failed");

@@ -108,11 +108,12 @@ class World:
         B.coralai_get_stats(self.h, st)
         return st.as_dict()
 
-    def autotune(self) -> tuple[int, int]:
+    def autotune(self) -> tuple[int, int, int]:
+        """(act_cells, act_waves, phys_tile) chosen by timing on the current state."""
         return B.coralai_autotune(self.h)
 
-    def set_tuning(self, act_cells: int, phys_tile: int) -> None:
-        B.coralai_set_tuning(self.h, act_cells, phys_tile)
+    def set_tuning(self, act_cells: int, phys_tile: int, act_waves: int = 0) -> None:
+        B.coralai_set_tuning(self.h, act_cells, act_waves, phys_tile)
 
     def set_profiling(self, on: bool) -> None:
         B.coralai_set_profiling(self.h, on)
@@ -166,6 +167,12 @@ class Batch:
 
     def step(self, n: int = 1) -> None:
         B.coralai_batch_step(self.h, n)
+
+    def autotune(self) -> tuple[int, int, int]:
+        return B.coralai_batch_autotune(self.h)
+
+    def set_tuning(self, act_cells: int, phys_tile: int, act_waves: int = 0) -> None:
+        B.coralai_batch_set_tuning(self.h, act_cells, act_waves, phys_tile)
 
     def sync(self) -> None:
         B.coralai_batch_sync(self.h)

@@ -46,13 +46,18 @@ def test_cppn_weights_match_oracle(stream, layers, hidden, prec):
     w.close()
 
 
-def test_debug_weights_roundtrip(stream):
-    init = gh.heterogeneous_world(4, 4, n_genomes=2, layers=3, hidden=64, seed=1)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_debug_weights_roundtrip(stream, prec):
+    """Flat weights in, flat weights out: exact up to the one rounding of the
+    stored value (hidden layers are stored times 2 log2 e)."""
+    init = gh.heterogeneous_world(4, 4, n_genomes=2, layers=3, hidden=64, seed=1, precision=prec)
     w = gh.make_world(init, stream)
     d = gh.oracle_desc(init.spec)
     flat = np.random.default_rng(0).standard_normal(oracle.net_size(d)).astype(np.float32)
     w.debug_set_weights(1, flat)
-    np.testing.assert_array_equal(w.debug_get_weights(1, flat.size), flat)
+    got = w.debug_get_weights(1, flat.size)
+    rtol = 2.5e-7 if prec == 0 else 2 ** -8
+    np.testing.assert_allclose(got, flat, rtol=rtol, atol=0)
     w.close()
 
 
@@ -236,10 +241,11 @@ def test_translation_invariance_bit_identical(stream):
 def test_tuning_choices_and_graph_give_identical_results(stream):
     init = gh.heterogeneous_world(150, 90, n_genomes=9, layers=3, hidden=64, seed=5)
     outs = []
-    for act, tile, strm in [(1, 0, stream), (2, 1, stream), (4, 2, None), (2, 0, None), (2, 3, stream),
-                            (1, 3, None)]:
+    for act, waves, tile, strm in [(1, 0, 0, stream), (2, 1, 1, stream), (4, 0, 2, None),
+                                   (2, 0, 0, None), (2, 1, 3, stream), (1, 1, 3, None),
+                                   (4, 1, 3, stream)]:
         w = gh.make_world(init, strm)
-        w.set_tuning(act, tile)
+        w.set_tuning(act, tile, waves)
         w.step(3)
         outs.append(w.get_state())
         w.close()
@@ -265,8 +271,8 @@ def test_autotune_keeps_state(stream):
     init = gh.heterogeneous_world(200, 120, n_genomes=6, seed=2)
     w = gh.make_world(init, stream)
     before = w.get_state()
-    act, tile = w.autotune()
-    assert act in (1, 2, 4) and tile in (0, 1, 2, 3)
+    act, waves, tile = w.autotune()
+    assert act in (1, 2, 4) and waves in (0, 1) and tile in (0, 1, 2, 3)
     after = w.get_state()
     for ch in before:
         np.testing.assert_array_equal(before[ch], after[ch])
