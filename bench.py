@@ -44,13 +44,16 @@ def trans_per_cell(hidden: int, layers: int) -> int:
     return 2 * hidden * (layers - 1) + 2 * 6 + 8 + 1
 
 
-def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bool):
+def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bool, tuning=None):
     import torch
 
     from paper_2406_09654_amd.world import World
 
     w = World.from_init(init, stream=stream, precision=precision)
-    tuning = w.autotune() if autotune else None
+    if tuning is not None:
+        w.set_tuning(*tuning)
+    elif autotune:
+        tuning = w.autotune()
     step_index = 0
     for _ in range(warmup):
         w.step(1)
@@ -82,6 +85,82 @@ def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bo
         "stats": st,
         "tuning": tuning,
     }
+
+
+def run_batched(n_worlds: int, steps: int, warmup: int, alone_steps: int):
+    """512 uneven worlds (side U{64..512}, 8..128 genomes, 54-32-14 BF16 nets)
+    advanced by one captured batched step, against the same worlds stepped one
+    by one on the same stream."""
+    import torch
+
+    import workloads as wl
+    from paper_2406_09654_amd.world import Batch, World
+
+    specs = wl.batched_world_specs(n_worlds)
+    print("[bench] batched: generating %d worlds" % n_worlds, file=sys.stderr, flush=True)
+    inits = [wl.batched_world(side, ng, seed, precision=1) for side, ng, seed in specs]
+    stream = torch.cuda.Stream()
+    worlds = [World.from_init(i, stream=stream, precision=1) for i in inits]
+    cells = sum(w.N for w in worlds)
+    b = Batch(n_worlds, stream)
+    b.set_worlds(worlds)
+    tuning = b.autotune()
+    b.step(warmup)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t_b = time.perf_counter() - t0
+    b.set_worlds([])
+    for w in worlds:
+        w.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(alone_steps):
+        for w in worlds:
+            w.step(1)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter() - t0
+    b.close()
+    for w in worlds:
+        w.close()
+    del worlds
+    torch.cuda.empty_cache()
+    return {"worlds": n_worlds, "cells_per_step": cells, "steps": steps, "tuning": tuning,
+            "value": cells * steps / t_b, "ms_per_step": 1e3 * t_b / steps,
+            "one_by_one_value": cells * alone_steps / t_a,
+            "one_by_one_ms_per_step": 1e3 * t_a / alone_steps,
+            "speedup_vs_one_by_one": (cells * steps / t_b) / (cells * alone_steps / t_a),
+            "unit": "cell-updates/s", "dtype": "bf16"}
+
+
+def run_serving(n_requests: int, rate: float):
+    """Poisson request stream (side log-uniform 128..2048, 16..1024 genomes,
+    10..1000 steps, blob states), served by continuous batching in FP32 and
+    in BF16."""
+    import torch
+
+    import workloads as wl
+    from paper_2406_09654_amd.serving import Server
+
+    reqs = wl.poisson_requests(n_requests, rate)
+    print("[bench] serving: generating %d requests" % n_requests, file=sys.stderr, flush=True)
+    inits = {r.rid: wl.request_world(r) for r in reqs}
+    out = {"requests": n_requests, "rate_per_s": rate,
+           "cell_updates": int(sum(r.side * r.side * r.n_steps for r in reqs))}
+    for prec, name in [(0, "fp32"), (1, "bf16")]:
+        srv = Server(precision=prec, max_worlds=64)
+        # warm the graph and the kernels on a tiny request set
+        srv.run(reqs[:2], inits, arrivals="step")
+        rep = srv.run(reqs, inits)
+        srv.close()
+        torch.cuda.empty_cache()
+        out[name] = {k: rep[k] for k in ("step_latency_ms_p50", "step_latency_ms_p99",
+                                         "time_to_completion_s_p50", "time_to_completion_s_p99",
+                                         "cell_updates_per_s", "cell_updates_per_gpu_busy_s",
+                                         "wall_s", "batched_steps", "mean_resident")}
+        print("[bench] serving %s: %s" % (name, out[name]), file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(init, target_s: float = 12.0):
@@ -126,6 +205,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--bf16-only", action="store_true")
+    ap.add_argument("--tuning-bf16", default=None,
+                    help="act_cells,act_waves,phys_tile for the BF16 form instead of autotuning")
+    ap.add_argument("--tuning-fp32", default=None,
+                    help="act_cells,act_waves,phys_tile for the FP32 form instead of autotuning")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-world batched form")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving form")
+    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-rate", type=float, default=20.0, help="Poisson arrivals per second")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -155,10 +242,13 @@ def main() -> int:
     hidden, layers = init.spec.hidden, init.spec.n_weight_layers
 
     forms = {}
+    fixed = {"bf16": args.tuning_bf16, "fp32": args.tuning_fp32}
     for prec, name in ([(1, "bf16")] if args.bf16_only else [(1, "bf16"), (0, "fp32")]):
         print("[bench] %s: warmup %d, timed %d steps" % (name, args.warmup, args.steps),
               file=sys.stderr, flush=True)
-        forms[name] = run_form(init, prec, args.steps, args.warmup, stream, not args.no_autotune)
+        tun = tuple(int(v) for v in fixed[name].split(",")) if fixed[name] else None
+        forms[name] = run_form(init, prec, args.steps, args.warmup, stream,
+                               not args.no_autotune, tun)
         print("[bench] %s: %.3e cell-updates/s, %.3f ms/step, phases %s" % (
             name, forms[name]["value"], forms[name]["ms_per_step"], forms[name]["phase_ms"]),
             file=sys.stderr, flush=True)
@@ -210,6 +300,11 @@ def main() -> int:
                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                                "frac": 59 * N / (phys_ms * 1e-3) / PEAK_HBM,
                                "per_unit": "59 B per cell"}
+    if not args.no_batched:
+        out["batched"] = run_batched(512, 20, 3, 3)
+        print("[bench] batched: %s" % out["batched"], file=sys.stderr, flush=True)
+    if not args.no_serving:
+        out["serving"] = run_serving(args.serving_requests, args.serving_rate)
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(init)

@@ -158,7 +158,12 @@ int coralai_get_stats(coralai_world* w, coralai_stats* out);
  * share one device, one network shape (layers, hidden) and one precision;
  * the batch's stream is used for the whole step.  The table holds up to
  * max_worlds entries; set_worlds may change the set between steps without a
- * new graph.  The batch's arena (coralai_batch_bytes) is caller-owned. */
+ * new graph.  The batch's arena (coralai_batch_bytes) is caller-owned.
+ * Worlds may live on streams other than the batch's: set_worlds makes the
+ * batch's stream wait for work already queued on each world's stream, and
+ * batch_step makes each world's stream wait for the steps it queued, so a
+ * later call on a world (get_state, step) sees their result.  A world must
+ * leave the batch (set_worlds without it) before coralai_world_destroy. */
 size_t coralai_batch_bytes(int32_t max_worlds);
 int coralai_batch_create(int32_t max_worlds, void* dev_arena, size_t arena_bytes,
                          void* hip_stream, coralai_batch** out);
@@ -174,7 +179,8 @@ int coralai_batch_destroy(coralai_batch* b);
  * wavefronts per SIMD with more registers each, 1 = more wavefronts;
  * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 16x16, or 3 = streaming,
  * one thread per cell without LDS.  The batch versions tune the batch's
- * single captured step over its current worlds. */
+ * single captured step over its current worlds.  Defaults before any call:
+ * act_cells 2, act_waves 0, phys_tile 3. */
 int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* act_waves_out,
                      int32_t* phys_tile_out);
 int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t act_waves, int32_t phys_tile);

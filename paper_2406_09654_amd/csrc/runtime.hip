@@ -165,7 +165,7 @@ struct coralai_world {
     LaunchShape ls;
     int act_cells = 2;
     int act_waves = 0;
-    int phys_tile = 0;
+    int phys_tile = 3;
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
     Ctl* pinned = nullptr;
@@ -191,10 +191,12 @@ struct coralai_batch {
     int32_t* tiles_x;
     int n = 0;
     int NL = 0, HID = 0, prec = 0;
-    int act_cells = 2, act_waves = 0, phys_tile = 0;
+    int act_cells = 2, act_waves = 0, phys_tile = 3;
     LaunchShape ls;
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
+    // orders work between the batch's stream and its worlds' own streams
+    hipEvent_t ev_order = nullptr;
     std::vector<coralai_world*> worlds;
     std::atomic<int> busy{0};
 };
@@ -744,8 +746,13 @@ int coralai_batch_create(int32_t max_worlds, void* dev_arena, size_t arena_bytes
     hb.tile_prefix = b->tile_prefix;
     hb.group_prefix = b->group_prefix;
     hb.tiles_x = b->tiles_x;
+    if (hipEventCreateWithFlags(&b->ev_order, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return fail(CORALAI_E_HIP, "event creation failed");
+    }
     if (hipMemcpyAsync(b->bdev, &hb, sizeof hb, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
+        (void)hipEventDestroy(b->ev_order);
         delete b;
         return fail(CORALAI_E_HIP, "batch table upload failed");
     }
@@ -821,6 +828,13 @@ int batch_upload(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
         tp[k + 1] = tp[k] + tiles_for(w->host.W, w->host.H, b->phys_tile, &t);
         tx[k] = t;
     }
+    // work already queued on a world's own stream (state upload, genomes)
+    // completes before the batch's next step touches the world
+    for (int k = 0; k < n; ++k) {
+        if (worlds[k]->stream == b->stream) continue;
+        HIP_TRY(hipEventRecord(b->ev_order, worlds[k]->stream));
+        HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_order, 0));
+    }
     HIP_TRY(hipStreamSynchronize(b->stream));
     if (n > 0) {
         HIP_TRY(hipMemcpyAsync(b->table, tab.data(), sizeof(WorldDev) * n, hipMemcpyHostToDevice, b->stream));
@@ -858,7 +872,17 @@ int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
         else launch_step_kernels(b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells, b->act_waves,
                                  b->phys_tile, b->stream, nullptr);
     }
-    return check_launch();
+    int rc = check_launch();
+    if (rc) return rc;
+    // later calls on a world's own stream (get_state, step, ...) wait for these steps
+    bool other = false;
+    for (coralai_world* w : b->worlds) other = other || w->stream != b->stream;
+    if (other) {
+        HIP_TRY(hipEventRecord(b->ev_order, b->stream));
+        for (coralai_world* w : b->worlds)
+            if (w->stream != b->stream) HIP_TRY(hipStreamWaitEvent(w->stream, b->ev_order, 0));
+    }
+    return CORALAI_OK;
 }
 
 int coralai_batch_sync(coralai_batch* b) {
@@ -871,6 +895,7 @@ int coralai_batch_destroy(coralai_batch* b) {
     if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
     (void)hipStreamSynchronize(b->stream);
     destroy_graph(&b->graph);
+    if (b->ev_order) (void)hipEventDestroy(b->ev_order);
     delete b;
     return CORALAI_OK;
 }

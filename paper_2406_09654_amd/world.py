@@ -9,6 +9,14 @@ import torch
 from . import binding as B
 
 
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
+
+
 def make_desc(width: int, height: int, n_weight_layers: int = 2, hidden: int = 32,
               genome_capacity: int = 16, precision: int = 0, seed: int = 0,
               rho_invest: float = 0.1, rho_liquidate: float = 0.1,
@@ -25,25 +33,32 @@ def desc_from_spec(spec) -> B.coralai_world_desc:
 
 class World:
     def __init__(self, desc: B.coralai_world_desc, stream: torch.cuda.Stream | None = None,
-                 device: str = "cuda"):
+                 device: str = "cuda", sync: bool = True):
+        """sync=False allocates the arena in the stream's order instead of
+        waiting for the whole device (the arena then belongs to that stream)."""
         self.desc = desc
         self.nbytes = B.coralai_world_bytes(desc)
         if self.nbytes == 0:
             raise ValueError("invalid world description")
-        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         self.stream = stream
+        if sync or stream is None:
+            self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+            torch.cuda.synchronize()
+        else:
+            with torch.cuda.stream(stream):
+                self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         sp = stream.cuda_stream if stream is not None else 0
-        torch.cuda.synchronize()
         self.h = B.coralai_world_create(desc, self.arena.data_ptr(), self.nbytes, sp)
         self.W, self.H = desc.width, desc.height
         self.N = self.W * self.H
 
     @classmethod
-    def from_init(cls, init, stream=None, precision: int | None = None) -> "World":
+    def from_init(cls, init, stream=None, precision: int | None = None,
+                  sync: bool = True) -> "World":
         d = desc_from_spec(init.spec)
         if precision is not None:
             d.precision = precision
-        w = cls(d, stream)
+        w = cls(d, stream, sync=sync)
         w.set_state(init.E, init.I, init.C, init.G, init.R)
         w.set_genomes(init.slots, init.params)
         return w
@@ -63,6 +78,19 @@ class World:
         c = lambda a, t: np.ascontiguousarray(a, dtype=t)
         B.coralai_set_state(self.h, c(E, np.int64), c(I, np.int64), c(C, np.float32),
                             c(G, np.int32), c(R, np.uint8), 0)
+
+    def get_state_device(self) -> dict:
+        """Copy of the current state into new device tensors (stream-ordered)."""
+        H, W = self.H, self.W
+        ctx = torch.cuda.stream(self.stream) if self.stream is not None else _nullctx()
+        with ctx:
+            out = {"E": torch.empty((H, W), dtype=torch.int64, device="cuda"),
+                   "I": torch.empty((H, W), dtype=torch.int64, device="cuda"),
+                   "C": torch.empty((4, H, W), dtype=torch.float32, device="cuda"),
+                   "G": torch.empty((H, W), dtype=torch.int32, device="cuda"),
+                   "R": torch.empty((H, W), dtype=torch.uint8, device="cuda")}
+        B.coralai_get_state(self.h, *(out[k].data_ptr() for k in ("E", "I", "C", "G", "R")), 1)
+        return out
 
     def get_state(self) -> dict:
         H, W = self.H, self.W
@@ -112,7 +140,8 @@ class World:
         """(act_cells, act_waves, phys_tile) chosen by timing on the current state."""
         return B.coralai_autotune(self.h)
 
-    def set_tuning(self, act_cells: int, phys_tile: int, act_waves: int = 0) -> None:
+    def set_tuning(self, act_cells: int, act_waves: int, phys_tile: int) -> None:
+        """Fix the launch choices (same order as autotune returns them)."""
         B.coralai_set_tuning(self.h, act_cells, act_waves, phys_tile)
 
     def set_profiling(self, on: bool) -> None:
@@ -171,7 +200,7 @@ class Batch:
     def autotune(self) -> tuple[int, int, int]:
         return B.coralai_batch_autotune(self.h)
 
-    def set_tuning(self, act_cells: int, phys_tile: int, act_waves: int = 0) -> None:
+    def set_tuning(self, act_cells: int, act_waves: int, phys_tile: int) -> None:
         B.coralai_batch_set_tuning(self.h, act_cells, act_waves, phys_tile)
 
     def sync(self) -> None:

@@ -85,7 +85,7 @@ def test_actuators_match_oracle_fp32(stream, W, H, layers, hidden, act_cells):
     say("act", W, H, layers, hidden, act_cells)
     init = gh.heterogeneous_world(W, H, n_genomes=7, layers=layers, hidden=hidden, seed=W + H)
     w = gh.make_world(init, stream)
-    w.set_tuning(act_cells, 0)
+    w.set_tuning(act_cells, 0, 0)
     act = w.debug_actuators()
     d = gh.oracle_desc(init.spec)
     s = oracle.State.from_init(init)
@@ -107,7 +107,7 @@ def test_physics_from_oracle_records_is_bit_exact(stream):
         I2, G2, R2, tk = oracle.physics_from_records(d, rec["i1"], rec["flow"], rec["explore_dir"],
                                                      init.G, init.R)
         w = gh.make_world(init, stream)
-        w.set_tuning(2, tile)
+        w.set_tuning(2, 0, tile)
         w.debug_physics(rec["i1"], rec["flow"].astype(np.uint32), rec["explore_dir"].astype(np.uint8))
         out = w.get_state()
         np.testing.assert_array_equal(out["I"], I2)
@@ -245,7 +245,7 @@ def test_tuning_choices_and_graph_give_identical_results(stream):
                                    (2, 0, 0, None), (2, 1, 3, stream), (1, 1, 3, None),
                                    (4, 1, 3, stream)]:
         w = gh.make_world(init, strm)
-        w.set_tuning(act, tile, waves)
+        w.set_tuning(act, waves, tile)
         w.step(3)
         outs.append(w.get_state())
         w.close()
