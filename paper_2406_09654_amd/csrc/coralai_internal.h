@@ -12,6 +12,9 @@ namespace coralai {
 constexpr int kNParam = 56;   // CPPN parameters: A (8x5) then B (2x8)
 constexpr int kNIn = 54;      // 9 kernel positions x 6 sensor channels
 constexpr int kNOut = 14;     // invest, liquidate, 4 comm, 8 flow logits
+// perm entries: cell index in bits 0..25 (W*H <= 2^26), rotation in 26..28
+constexpr int kPermRotShift = 26;
+constexpr int kPermIndexMask = (1 << kPermRotShift) - 1;
 constexpr int kGroupCells = 64;   // cells per network work unit (one wavefront)
 constexpr int kBucketTile = 64;   // bucketing tile: 64 x 64 cells
 constexpr int kBucketGroup = 4;   // tiles per bucketing unit (one block)
@@ -56,7 +59,7 @@ struct WorldDev {
     uint64_t seed;
     int64_t* E[2];
     int64_t* I[2];
-    float* C[2];          // 4 planes each
+    float* C[2];          // [N][4]: the 4 communication channels of a cell together
     int32_t* G[2];
     uint8_t* R[2];
     uint32_t* flow;       // 8 planes: (outflow toward direction k) << 1 | (k is explored)
@@ -239,6 +242,14 @@ __device__ __forceinline__ int64_t buf_ld_i64(__amdgpu_buffer_rsrc_t r, int off)
 __device__ __forceinline__ void buf_st_i64(int64_t v, __amdgpu_buffer_rsrc_t r, int off) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(coralai_u32x2, v), r, off, 0, 0);
 }
+typedef unsigned int coralai_u32x4 __attribute__((__vector_size__(16)));
+typedef float coralai_f32x4 __attribute__((__vector_size__(16)));
+__device__ __forceinline__ coralai_f32x4 buf_ld_f32x4(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(coralai_f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st_f32x4(coralai_f32x4 v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(coralai_u32x4, v), r, off, 0, 0);
+}
 
 // int64 -> float with at most one extra rounding for values >= 2^32 (exact
 // conversion for the common |v| < 2^24, correctly rounded below 2^32).
@@ -276,6 +287,9 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
 void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
                          hipStream_t s);
 void launch_flip(const BatchDev* bdev, hipStream_t s);
+// communication channels: planar [4][N] (the C ABI's layout) <-> interleaved
+// [N][4] (the device layout: one 16-byte load per cell)
+void launch_comm_layout(const float* src, float* dst, int64_t n, int to_interleaved, hipStream_t s);
 
 int phys_tile_w(int t);
 int phys_tile_h(int t);

@@ -119,14 +119,21 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     int64_t acc_mass = 0;
     double acc_f64 = 0.0;
     uint32_t err = 0;
-    // the next unit's cell and rotation, loaded while this unit computes
+    // the next unit's perm entry (cell index | rotation), loaded while this unit computes
     bool have_pf = false;
-    int i_pf = 0, r_pf = 0;
+    int e_pf = 0;
+    // Stores of a unit are issued after the next unit's loads: one counter
+    // tracks vector loads and stores in issue order, so a load issued after
+    // a store could not be waited for without waiting for the store too.
+    bool st_pending = false;
+    int st_i = 0;
+    uint32_t st_c[4], st_f[8], st_fo[8], st_used = 0;
+    int64_t st_E1 = 0, st_I1 = 0;
 
     // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
-    __amdgpu_buffer_rsrc_t rE, rI, rC, rR, rP, wE, wC, wI1, wOut, wFlow;
+    __amdgpu_buffer_rsrc_t rE, rI, rC, rP, wE, wC, wI1, wOut, wFlow;
     const int32_t *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
@@ -148,8 +155,24 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         err = 0;
     };
 
+    auto store_results = [&]() {
+        const uint32_t ofs = 4u * (uint32_t)st_i;
+        if (st_i >= 0) {
+            buf_st_f32x4(coralai_f32x4{__builtin_bit_cast(float, st_c[0]), __builtin_bit_cast(float, st_c[1]),
+                                       __builtin_bit_cast(float, st_c[2]), __builtin_bit_cast(float, st_c[3])},
+                         wC, 4 * ofs);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) __builtin_amdgcn_raw_buffer_store_b32(st_f[t], wFlow, st_fo[t], 0, 0);
+            buf_st_i64(st_E1, wE, 2u * ofs);
+            buf_st_i64(st_I1, wI1, 2u * ofs);
+            __builtin_amdgcn_raw_buffer_store_b32(st_used, wOut, ofs, 0, 0);
+        }
+        st_pending = false;
+    };
+
     for (; u < uend; ++u) {
         if (u >= world_hi) {
+            if (st_pending) store_results();  // the buffers below change with the world
             flush();
             while (cld(b->group_prefix + (wi + 1)) <= u) ++wi;
             wi = uniform_i32(wi);
@@ -164,7 +187,6 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             rE = buf_rsrc(W->E[cur], 2u * n4);
             rI = buf_rsrc(W->I[cur], 2u * n4);
             rC = buf_rsrc(W->C[cur], 4u * n4);
-            rR = buf_rsrc(W->R[cur], (uint32_t)Nd);
             rP = buf_rsrc(W->perm, n4);
             wE = buf_rsrc(W->E[nxt], 2u * n4);
             wC = buf_rsrc(W->C[nxt], 4u * n4);
@@ -223,26 +245,22 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         const int cell0 = cld(offsets + g) + j * kGroupCells;
         const int cnt = min(kGroupCells, gcount - j * kGroupCells);
         const bool valid = lane < cnt;
-        int i, r;
-        if (have_pf) {
-            i = i_pf;
-            r = r_pf;
-        } else {
-            i = (int)__builtin_amdgcn_raw_buffer_load_b32(rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
-            r = __builtin_amdgcn_raw_buffer_load_b8(rR, i, 0, 0) & 7;
-        }
+        const int entry = have_pf ? e_pf
+                                  : (int)__builtin_amdgcn_raw_buffer_load_b32(
+                                        rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
+        const int i = entry & kPermIndexMask, r = (entry >> kPermRotShift) & 7;
         // prefetch the next unit's cell index when it continues this genome
         have_pf = (u + 1 < uend) && (u + 1 < world_hi) && (k + 1 < g_hi);
         if (have_pf) {
             const int cnt_n = min(kGroupCells, gcount - (j + 1) * kGroupCells);
-            i_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(
+            e_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(
                 rP, 4 * (cell0 + kGroupCells + (lane < cnt_n ? lane : 0)), 0, 0);
         }
 
         // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
         const int y = i / Wd, x = i - y * Wd;
-        float uvec[kNIn];
-        int64_t e_own = 0, i_own = 0;
+        int64_t gE[9], gI[9];
+        float gC[9][4];
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
             int nidx = i;
@@ -253,14 +271,23 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                 ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
                 nidx = ny * Wd + nx;
             }
-            const int64_t ev = buf_ld_i64(rE, 8 * nidx), iv = buf_ld_i64(rI, 8 * nidx);
-            if (p == 0) { e_own = ev; i_own = iv; }
-            uvec[6 * p + 0] = i64_to_f32(ev) * 0x1p-24f;
-            uvec[6 * p + 1] = i64_to_f32(iv) * 0x1p-24f;
+            gE[p] = buf_ld_i64(rE, 8 * nidx);
+            gI[p] = buf_ld_i64(rI, 8 * nidx);
+            const coralai_f32x4 cv = buf_ld_f32x4(rC, 16 * nidx);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                uvec[6 * p + 2 + c] = __builtin_bit_cast(
-                    float, __builtin_amdgcn_raw_buffer_load_b32(rC, 4 * nidx, c * 4 * Nd, 0));
+            for (int c = 0; c < 4; ++c) gC[p][c] = cv[c];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (st_pending) store_results();
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t e_own = gE[0], i_own = gI[0];
+        float uvec[kNIn];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            uvec[6 * p + 0] = i64_to_f32(gE[p]) * 0x1p-24f;
+            uvec[6 * p + 1] = i64_to_f32(gI[p]) * 0x1p-24f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = gC[p][c];
         }
         if constexpr (NT::kBF) {
 #pragma unroll
@@ -407,7 +434,6 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                 }
             }
         }
-        if (have_pf) r_pf = __builtin_amdgcn_raw_buffer_load_b8(rR, i_pf, 0, 0) & 7;
         wave_lds_sync();  // all stage reads done before the actuator rows overwrite them
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -421,7 +447,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         }
         wave_lds_sync();  // actuator rows read before the next unit's stage writes
 
-        // ---- 3. epilogue: one cell per lane
+        // ---- 3. epilogue: one cell per lane, results held for the stores
+        st_i = valid ? i : -1;
+        st_pending = true;
         if (valid) {
             if constexpr (DEBUG) {
 #pragma unroll
@@ -445,11 +473,11 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             xi = xi < 0 ? 0 : xi;
             xl = xl < 0 ? 0 : xl;
             const int64_t E1 = e_own - xi + xl, I1 = i_own + xi - xl;
+            st_E1 = E1;
+            st_I1 = I1;
             // communication: sigmoid of the comm actuators
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, sigmoid_f(a[2 + c])), wC,
-                                                      4 * i, c * 4 * Nd, 0);
+            for (int c = 0; c < 4; ++c) st_c[c] = __builtin_bit_cast(uint32_t, sigmoid_f(a[2 + c]));
             // exploration: softmax split of the flow budget, argmax explore
             float m = a[6];
             int best = 0;
@@ -465,24 +493,28 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             int64_t F = (int64_t)floorf(kappa * i64_to_f32(I1));
             if (F < 0) F = 0;
             if (F > 0x7fffffffll) { err |= kErrLedger; F = 0x7fffffffll; }
-            const float fF = (float)(uint32_t)F;
-            int64_t used = 0;
+            // all amounts are below 2^31: 32-bit integers suffice, and the
+            // truncating conversion of a non-negative float is its floor
+            const uint32_t Fu = (uint32_t)F;
+            const float fF = (float)Fu;
+            const uint32_t plane = 4u * (uint32_t)Nd, own = 4u * (uint32_t)i;
+            uint32_t used = 0;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                int64_t f = (int64_t)floorf((ex[t] * inv) * fF);
-                f = f > F - used ? F - used : f;
-                f = f < 0 ? 0 : f;
+                const float share = (ex[t] * inv) * fF;  // >= 0 and finite
+                uint32_t f = (uint32_t)share;
+                const uint32_t rem = Fu - used;
+                f = f < rem ? f : rem;
                 used += f;
-                __builtin_amdgcn_raw_buffer_store_b32(((uint32_t)f << 1) | (uint32_t)(t == best), wFlow,
-                                                      4 * (kernel_dir(r, t + 1) * Nd + i), 0, 0);
+                st_f[t] = (f << 1) | (uint32_t)(t == best);
+                st_fo[t] = (uint32_t)kernel_dir(r, t + 1) * plane + own;
             }
-            buf_st_i64(E1, wE, 8 * i);
-            buf_st_i64(I1, wI1, 8 * i);
-            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)used, wOut, 4 * i, 0, 0);
+            st_used = used;
             acc_mass += E1;
             acc_f64 += (double)E1;
         }
     }
+    if (st_pending) store_results();
     flush();
 }
 

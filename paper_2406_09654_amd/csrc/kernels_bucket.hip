@@ -194,7 +194,11 @@ __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, 
                     const uint64_t upto = starts & ((2ull << lane) - 1ull);
                     const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
                     const int run_base = __shfl(base, rs, 64);
-                    if (valid) gst(w.perm + run_base + (lane - rs), (int)i);
+                    // the entry carries the cell's rotation in bits 26..28, so
+                    // the network kernel needs no dependent load for it
+                    if (valid)
+                        gst(w.perm + run_base + (lane - rs),
+                            (int)i | ((int)(gld(w.R[cur] + i) & 7) << kPermRotShift));
                 }
             }
         }

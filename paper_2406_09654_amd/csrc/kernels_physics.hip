@@ -290,4 +290,27 @@ void launch_step_kernels(const BatchDev* bdev, const LaunchShape& ls, int NL, in
     launch_finalize(bdev, ls, s);
 }
 
+// Communication channels between the C ABI's planar layout and the device's
+// interleaved one (set_state / get_state only).
+__global__ __launch_bounds__(256) void k_comm_layout(const float* __restrict__ src, float* __restrict__ dst,
+                                                     int64_t n, int to_interleaved) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (to_interleaved) {
+            float4 v;
+            v.x = src[i]; v.y = src[n + i]; v.z = src[2 * n + i]; v.w = src[3 * n + i];
+            reinterpret_cast<float4*>(dst)[i] = v;
+        } else {
+            const float4 v = reinterpret_cast<const float4*>(src)[i];
+            dst[i] = v.x; dst[n + i] = v.y; dst[2 * n + i] = v.z; dst[3 * n + i] = v.w;
+        }
+    }
+}
+
+void launch_comm_layout(const float* src, float* dst, int64_t n, int to_interleaved, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t want = (n + 255) / 256;
+    const int blocks = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_comm_layout, dim3(blocks), dim3(256), 0, s, src, dst, n, to_interleaved);
+}
+
 }  // namespace coralai

@@ -468,7 +468,14 @@ int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, 
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIP_TRY(hipMemcpyAsync(w->host.E[cur], e_q, 8 * N, k, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.I[cur], i_q, 8 * N, k, w->stream));
-    HIP_TRY(hipMemcpyAsync(w->host.C[cur], comm4, 16 * N, k, w->stream));
+    // comm4 is planar; the device keeps [N][4].  Host data is staged through
+    // the flow planes, which hold nothing between steps.
+    const float* csrc = comm4;
+    if (!on_device) {
+        HIP_TRY(hipMemcpyAsync(w->host.flow, comm4, 16 * N, hipMemcpyHostToDevice, w->stream));
+        csrc = (const float*)w->host.flow;
+    }
+    launch_comm_layout(csrc, w->host.C[cur], (int64_t)N, 1, w->stream);
     HIP_TRY(hipMemcpyAsync(w->host.G[cur], genome, 4 * N, k, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.R[cur], rotation, N, k, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -484,7 +491,14 @@ int coralai_get_state(coralai_world* w, int64_t* e_q, int64_t* i_q, float* comm4
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (e_q) HIP_TRY(hipMemcpyAsync(e_q, w->host.E[cur], 8 * N, k, w->stream));
     if (i_q) HIP_TRY(hipMemcpyAsync(i_q, w->host.I[cur], 8 * N, k, w->stream));
-    if (comm4) HIP_TRY(hipMemcpyAsync(comm4, w->host.C[cur], 16 * N, k, w->stream));
+    if (comm4) {
+        if (on_device) {
+            launch_comm_layout(w->host.C[cur], comm4, (int64_t)N, 0, w->stream);
+        } else {
+            launch_comm_layout(w->host.C[cur], (float*)w->host.flow, (int64_t)N, 0, w->stream);
+            HIP_TRY(hipMemcpyAsync(comm4, w->host.flow, 16 * N, hipMemcpyDeviceToHost, w->stream));
+        }
+    }
     if (genome) HIP_TRY(hipMemcpyAsync(genome, w->host.G[cur], 4 * N, k, w->stream));
     if (rotation) HIP_TRY(hipMemcpyAsync(rotation, w->host.R[cur], N, k, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -912,6 +926,8 @@ int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, i
     if (offsets) HIP_TRY(hipMemcpyAsync(offsets, w->host.offsets, 4 * (cap + 1), hipMemcpyDeviceToHost, w->stream));
     if (perm) HIP_TRY(hipMemcpyAsync(perm, w->host.perm, 4 * N, hipMemcpyDeviceToHost, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
+    if (perm)  // drop the rotation bits the network kernel reads with each index
+        for (size_t k = 0; k < N; ++k) perm[k] &= kPermIndexMask;
     return report_errors(w, nullptr);
 }
 
