@@ -57,13 +57,12 @@ struct WorldDev {
     float rho_i, rho_l, kappa;
     int32_t pad0;
     uint64_t seed;
-    int64_t* E[2];
-    int64_t* I[2];
+    int64_t* EI[2];       // [N][2]: energy and infrastructure quanta of a cell together
     float* C[2];          // [N][4]: the 4 communication channels of a cell together
     int32_t* G[2];
     uint8_t* R[2];
     uint32_t* flow;       // 8 planes: (outflow toward direction k) << 1 | (k is explored)
-    int64_t* I1;          // infrastructure after invest / liquidate
+    int64_t* EI1;         // [N][2]: energy and infrastructure after invest / liquidate
     uint32_t* out;        // total outflow of the cell
     int32_t* perm;        // cells grouped by genome
     int32_t* counts;      // [cap] cells per genome
@@ -243,6 +242,13 @@ __device__ __forceinline__ void buf_st_i64(int64_t v, __amdgpu_buffer_rsrc_t r, 
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(coralai_u32x2, v), r, off, 0, 0);
 }
 typedef unsigned int coralai_u32x4 __attribute__((__vector_size__(16)));
+typedef long long i64x2 __attribute__((__vector_size__(16)));
+__device__ __forceinline__ i64x2 buf_ld_i64x2(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(i64x2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st_i64x2(i64x2 v, __amdgpu_buffer_rsrc_t r, int off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(coralai_u32x4, v), r, off, 0, 0);
+}
 typedef float coralai_f32x4 __attribute__((__vector_size__(16)));
 __device__ __forceinline__ coralai_f32x4 buf_ld_f32x4(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(coralai_f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
@@ -290,6 +296,11 @@ void launch_flip(const BatchDev* bdev, hipStream_t s);
 // communication channels: planar [4][N] (the C ABI's layout) <-> interleaved
 // [N][4] (the device layout: one 16-byte load per cell)
 void launch_comm_layout(const float* src, float* dst, int64_t n, int to_interleaved, hipStream_t s);
+// ledger pairs: dst[2i] = e[i * e_stride], dst[2i+1] = v[i * v_stride]
+void launch_ledger_pack(const int64_t* e, int e_stride, const int64_t* v, int v_stride, int64_t* dst,
+                        int64_t n, hipStream_t s);
+// and back: e[i] = src[2i], v[i] = src[2i+1] (either may be null)
+void launch_ledger_unpack(const int64_t* src, int64_t* e, int64_t* v, int64_t n, hipStream_t s);
 
 int phys_tile_w(int t);
 int phys_tile_h(int t);

@@ -18,7 +18,7 @@
 //   3. the 14 actuators go through LDS back to one cell per lane, and the
 //      epilogue computes the ledger conversion, the sigmoid communication,
 //      the quantised softmax flow plan and the argmax exploration, writing
-//      E', C' and the boundary record (I1, the 8 flows each tagged with
+//      C' and the boundary record (E1 and I1 as one ledger pair, the 8 flows each tagged with
 //      whether it is the explored direction, the total outflow).
 #include <type_traits>
 
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
-    __amdgpu_buffer_rsrc_t rE, rI, rC, rP, wE, wC, wI1, wOut, wFlow;
+    __amdgpu_buffer_rsrc_t rEI, rC, rP, wC, wEI1, wOut, wFlow;
     const int32_t *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
@@ -163,8 +163,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                          wC, 4 * ofs);
 #pragma unroll
             for (int t = 0; t < 8; ++t) __builtin_amdgcn_raw_buffer_store_b32(st_f[t], wFlow, st_fo[t], 0, 0);
-            buf_st_i64(st_E1, wE, 2u * ofs);
-            buf_st_i64(st_I1, wI1, 2u * ofs);
+            buf_st_i64x2(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
             __builtin_amdgcn_raw_buffer_store_b32(st_used, wOut, ofs, 0, 0);
         }
         st_pending = false;
@@ -184,13 +183,11 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             ctl = W->ctl;
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             const uint32_t n4 = 4u * (uint32_t)Nd;
-            rE = buf_rsrc(W->E[cur], 2u * n4);
-            rI = buf_rsrc(W->I[cur], 2u * n4);
+            rEI = buf_rsrc(W->EI[cur], 4u * n4);
             rC = buf_rsrc(W->C[cur], 4u * n4);
             rP = buf_rsrc(W->perm, n4);
-            wE = buf_rsrc(W->E[nxt], 2u * n4);
             wC = buf_rsrc(W->C[nxt], 4u * n4);
-            wI1 = buf_rsrc(W->I1, 2u * n4);
+            wEI1 = buf_rsrc(W->EI1, 4u * n4);
             wOut = buf_rsrc(W->out, n4);
             wFlow = buf_rsrc(W->flow, 8u * n4);
             counts = W->counts; offsets = W->offsets; gofs = W->gofs;
@@ -271,8 +268,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                 ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
                 nidx = ny * Wd + nx;
             }
-            gE[p] = buf_ld_i64(rE, 8 * nidx);
-            gI[p] = buf_ld_i64(rI, 8 * nidx);
+            const i64x2 ei = buf_ld_i64x2(rEI, 16 * nidx);
+            gE[p] = ei[0];
+            gI[p] = ei[1];
             const coralai_f32x4 cv = buf_ld_f32x4(rC, 16 * nidx);
 #pragma unroll
             for (int c = 0; c < 4; ++c) gC[p][c] = cv[c];

@@ -9,7 +9,8 @@
 // and n's explore direction; I2 = I1 - sum(own flows) + sum(inflows); the
 // candidate explorers are the neighbours exploring toward t, the largest
 // investment wins (lowest d on ties) and takes t over when it strictly
-// exceeds I1(t).  Each flow word is (amount << 1) | explored, so one read per
+// exceeds I1(t).  The next state's ledger pair is (E1, I2): energy does not
+// move.  Each flow word is (amount << 1) | explored, so one read per
 // direction gives both the inflow and the candidacy.  The tile loads
 // (TW+2) x (TH+2) cells of the 8 flow planes and the genomes with coalesced
 // row loads; inflows, takeover and the block's share of the total-mass
@@ -76,10 +77,10 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     int Wd = 0, Hd = 0, Nd = 0, tx_n = 1;
     int64_t world_lo = 0;
     const uint32_t* flow = nullptr;
-    const int64_t* I1p = nullptr;
+    const int64_t* EI1p = nullptr;
     const int32_t* Gc = nullptr;
     const uint8_t* Rc = nullptr;
-    int64_t* In = nullptr;
+    int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
 
@@ -94,9 +95,9 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             tx_n = cld(b->tiles_x + (wi));
             ctl = W->ctl;
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
-            flow = W->flow; I1p = W->I1;
+            flow = W->flow; EI1p = W->EI1;
             Gc = W->G[cur]; Rc = W->R[cur];
-            In = W->I[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
+            EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
         }
         const int64_t lt = tile - world_lo;
         const int ty = (int)(lt / tx_n), tx = (int)(lt - (int64_t)ty * tx_n);
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
                 in += v;
                 if ((word & 1u) && v > vbest) { vbest = v; win = d; }
             }
-            const int64_t i1 = gld(I1p + t);
+            const int64_t e1 = gld(EI1p + 2 * (int64_t)t), i1 = gld(EI1p + 2 * (int64_t)t + 1);
             const int64_t i2 = i1 - out + in;
             int32_t g2 = gld(Gc + t);
             uint8_t r2 = gld(Rc + t);
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
             }
-            gst(In + t, i2);
+            gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);
             acc_m += i2;
@@ -182,8 +183,8 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     int acc_t = 0;
     Ctl* ctl = nullptr;
     int Wd = 0, Hd = 0, Nd = 0;
-    __amdgpu_buffer_rsrc_t rflow[8], rout, ri1, rg, rr;
-    int64_t* In = nullptr;
+    __amdgpu_buffer_rsrc_t rflow[8], rout, rei1, rg, rr;
+    int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
     auto flush = [&]() {
@@ -227,15 +228,16 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
 #pragma unroll
             for (int k = 0; k < 8; ++k) rflow[k] = buf_rsrc(W->flow + (int64_t)k * Nd, n4);
             rout = buf_rsrc(W->out, n4);
-            ri1 = buf_rsrc(W->I1, 2u * n4);
+            rei1 = buf_rsrc(W->EI1, 4u * n4);
             rg = buf_rsrc(W->G[cur], n4);
             rr = buf_rsrc(W->R[cur], (uint32_t)Nd);
-            In = W->I[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
+            EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
         }
         const int t = (int)((unit - world_lo) * 256) + tid;
         if (t < Nd) {  // (no divergent continue: the world fields must stay uniform)
             const int y = t / Wd, x = t - y * Wd;
-            const int64_t i1 = buf_ld_i64(ri1, 8 * t);
+            const i64x2 ei1 = buf_ld_i64x2(rei1, 16 * t);
+            const int64_t e1 = ei1[0], i1 = ei1[1];
             const uint32_t out = __builtin_amdgcn_raw_buffer_load_b32(rout, 4 * t, 0, 0);
             int32_t g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * t, 0, 0);
             uint8_t r2 = __builtin_amdgcn_raw_buffer_load_b8(rr, t, 0, 0);
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
             }
-            gst(In + t, i2);
+            gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);
             acc_m += i2;
@@ -304,6 +306,38 @@ __global__ __launch_bounds__(256) void k_comm_layout(const float* __restrict__ s
             dst[i] = v.x; dst[n + i] = v.y; dst[2 * n + i] = v.z; dst[3 * n + i] = v.w;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_ledger_pack(const int64_t* __restrict__ e, int e_stride,
+                                                     const int64_t* __restrict__ v, int v_stride,
+                                                     int64_t* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        reinterpret_cast<i64x2*>(dst)[i] = i64x2{e[i * e_stride], v[i * v_stride]};
+}
+
+__global__ __launch_bounds__(256) void k_ledger_unpack(const int64_t* __restrict__ src, int64_t* __restrict__ e,
+                                                       int64_t* __restrict__ v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const i64x2 p = reinterpret_cast<const i64x2*>(src)[i];
+        if (e) e[i] = p[0];
+        if (v) v[i] = p[1];
+    }
+}
+
+static int layout_blocks(int64_t n) {
+    const int64_t want = (n + 255) / 256;
+    return (int)(want < 4096 ? want : 4096);
+}
+
+void launch_ledger_pack(const int64_t* e, int e_stride, const int64_t* v, int v_stride, int64_t* dst,
+                        int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ledger_pack, dim3(layout_blocks(n)), dim3(256), 0, s, e, e_stride, v, v_stride, dst, n);
+}
+
+void launch_ledger_unpack(const int64_t* src, int64_t* e, int64_t* v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ledger_unpack, dim3(layout_blocks(n)), dim3(256), 0, s, src, e, v, n);
 }
 
 void launch_comm_layout(const float* src, float* dst, int64_t n, int to_interleaved, hipStream_t s) {

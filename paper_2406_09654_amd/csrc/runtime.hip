@@ -45,8 +45,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t E[2], I[2], C[2], G[2], R[2];
-    size_t flow, I1, out, perm;
+    size_t EI[2], C[2], G[2], R[2];
+    size_t flow, EI1, out, perm;
     size_t counts, offsets, sub_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
     size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
@@ -78,14 +78,13 @@ Layout make_layout(const coralai_world_desc* d) {
     size_t off = 0;
     auto take = [&](size_t bytes) { off = align_up(off, kAlign); size_t o = off; off += bytes; return o; };
     for (int k = 0; k < 2; ++k) {
-        L.E[k] = take(8 * N);
-        L.I[k] = take(8 * N);
+        L.EI[k] = take(16 * N);
         L.C[k] = take(16 * N);
         L.G[k] = take(4 * N);
         L.R[k] = take(N);
     }
     L.flow = take(32 * N);
-    L.I1 = take(8 * N);
+    L.EI1 = take(16 * N);
     L.out = take(4 * N);
     L.perm = take(4 * N);
     L.counts = take(4 * cap);
@@ -391,14 +390,13 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     h.rho_i = desc->rho_invest; h.rho_l = desc->rho_liquidate; h.kappa = desc->kappa_flow;
     h.seed = desc->seed;
     for (int k = 0; k < 2; ++k) {
-        h.E[k] = (int64_t*)(b + L.E[k]);
-        h.I[k] = (int64_t*)(b + L.I[k]);
+        h.EI[k] = (int64_t*)(b + L.EI[k]);
         h.C[k] = (float*)(b + L.C[k]);
         h.G[k] = (int32_t*)(b + L.G[k]);
         h.R[k] = (uint8_t*)(b + L.R[k]);
     }
     h.flow = (uint32_t*)(b + L.flow);
-    h.I1 = (int64_t*)(b + L.I1);
+    h.EI1 = (int64_t*)(b + L.EI1);
     h.out = (uint32_t*)(b + L.out);
     h.perm = (int32_t*)(b + L.perm);
     h.counts = (int32_t*)(b + L.counts);
@@ -466,8 +464,21 @@ int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, 
     if (rc) return rc;
     const size_t N = (size_t)w->host.N;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIP_TRY(hipMemcpyAsync(w->host.E[cur], e_q, 8 * N, k, w->stream));
-    HIP_TRY(hipMemcpyAsync(w->host.I[cur], i_q, 8 * N, k, w->stream));
+    // e_q, i_q are planes; the device keeps [N][2] ledger pairs.  Host data is
+    // staged through the flow planes (32N bytes), which hold nothing between
+    // steps; each staging copy is ordered on the stream after the kernel
+    // that consumed the previous one.
+    {
+        const int64_t *es = e_q, *is = i_q;
+        if (!on_device) {
+            int64_t* st = (int64_t*)w->host.flow;
+            HIP_TRY(hipMemcpyAsync(st, e_q, 8 * N, hipMemcpyHostToDevice, w->stream));
+            HIP_TRY(hipMemcpyAsync(st + N, i_q, 8 * N, hipMemcpyHostToDevice, w->stream));
+            es = st;
+            is = st + N;
+        }
+        launch_ledger_pack(es, 1, is, 1, w->host.EI[cur], (int64_t)N, w->stream);
+    }
     // comm4 is planar; the device keeps [N][4].  Host data is staged through
     // the flow planes, which hold nothing between steps.
     const float* csrc = comm4;
@@ -489,8 +500,16 @@ int coralai_get_state(coralai_world* w, int64_t* e_q, int64_t* i_q, float* comm4
     if (rc) return rc;
     const size_t N = (size_t)w->host.N;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (e_q) HIP_TRY(hipMemcpyAsync(e_q, w->host.E[cur], 8 * N, k, w->stream));
-    if (i_q) HIP_TRY(hipMemcpyAsync(i_q, w->host.I[cur], 8 * N, k, w->stream));
+    if (e_q || i_q) {
+        if (on_device) {
+            launch_ledger_unpack(w->host.EI[cur], e_q, i_q, (int64_t)N, w->stream);
+        } else {
+            int64_t* st = (int64_t*)w->host.flow;
+            launch_ledger_unpack(w->host.EI[cur], st, st + N, (int64_t)N, w->stream);
+            if (e_q) HIP_TRY(hipMemcpyAsync(e_q, st, 8 * N, hipMemcpyDeviceToHost, w->stream));
+            if (i_q) HIP_TRY(hipMemcpyAsync(i_q, st + N, 8 * N, hipMemcpyDeviceToHost, w->stream));
+        }
+    }
     if (comm4) {
         if (on_device) {
             launch_comm_layout(w->host.C[cur], comm4, (int64_t)N, 0, w->stream);
@@ -1002,9 +1021,11 @@ int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* f
     }
     const int nxt = cur ^ 1;
     HIP_TRY(hipMemcpyAsync(w->host.flow, planes.data(), 4 * 8 * N, hipMemcpyHostToDevice, w->stream));
-    HIP_TRY(hipMemcpyAsync(w->host.I1, i1, 8 * N, hipMemcpyHostToDevice, w->stream));
+    // boundary ledger pairs: the current energy (no conversion) and the given I1,
+    // staged through the next state's ledger, which physics overwrites
+    HIP_TRY(hipMemcpyAsync(w->host.EI[nxt], i1, 8 * N, hipMemcpyHostToDevice, w->stream));
+    launch_ledger_pack(w->host.EI[cur], 2, w->host.EI[nxt], 1, w->host.EI1, (int64_t)N, w->stream);
     HIP_TRY(hipMemcpyAsync(w->host.out, outs.data(), 4 * N, hipMemcpyHostToDevice, w->stream));
-    HIP_TRY(hipMemcpyAsync(w->host.E[nxt], w->host.E[cur], 8 * N, hipMemcpyDeviceToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.C[nxt], w->host.C[cur], 16 * N, hipMemcpyDeviceToDevice, w->stream));
     launch_physics_only(w->bdev, w->ls, w->phys_tile, w->stream);
     launch_flip(w->bdev, w->stream);
