@@ -288,8 +288,11 @@ void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s)
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
 void launch_cppn(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s);
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
+// counts_fresh: the genome counts equal the histogram of the current state
+// (true right after a step, whose physics keeps them up to date)
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
-                    int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s);
+                    int n_rad_blocks, int n_slot_blocks, bool counts_fresh, uint64_t T, float sigma,
+                    uint64_t step, hipStream_t s);
 void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
                          hipStream_t s);
 void launch_flip(const BatchDev* bdev, hipStream_t s);

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
+    int32_t* cnt = nullptr;
 
     for (; tile < tend; ++tile) {
         if (tile >= world_hi) {
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             flow = W->flow; EI1p = W->EI1;
             Gc = W->G[cur]; Rc = W->R[cur];
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
+            cnt = W->counts;
         }
         const int64_t lt = tile - world_lo;
         const int ty = (int)(lt / tx_n), tx = (int)(lt - (int64_t)ty * tx_n);
@@ -146,9 +148,13 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             int32_t g2 = gld(Gc + t);
             uint8_t r2 = gld(Rc + t);
             if (win >= 0 && vbest > i1) {
+                const int32_t g_old = g2;
                 g2 = s_g[(ly + dir_dy(win)) * LW + (lx + dir_dx(win))];
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
+                // the step's genome counts follow the takeover (radiation reads them)
+                atomicAdd(cnt + g_old, -1);
+                atomicAdd(cnt + g2, 1);
             }
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
@@ -184,6 +190,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     Ctl* ctl = nullptr;
     int Wd = 0, Hd = 0, Nd = 0;
     __amdgpu_buffer_rsrc_t rflow[8], rout, rei1, rg, rr;
+    int32_t* cnt = nullptr;
     int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
@@ -232,6 +239,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             rg = buf_rsrc(W->G[cur], n4);
             rr = buf_rsrc(W->R[cur], (uint32_t)Nd);
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
+            cnt = W->counts;
         }
         const int t = (int)((unit - world_lo) * 256) + tid;
         if (t < Nd) {  // (no divergent continue: the world fields must stay uniform)
@@ -256,9 +264,13 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             }
             const int64_t i2 = i1 - (int64_t)out + in;
             if (win >= 0 && vbest > i1) {
+                const int32_t g_old = g2;
                 g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * wn, 0, 0);
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
+                // the step's genome counts follow the takeover (radiation reads them)
+                atomicAdd(cnt + g_old, -1);
+                atomicAdd(cnt + g2, 1);
             }
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);

@@ -167,6 +167,9 @@ struct coralai_world {
     int phys_tile = 3;
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
+    // the device genome counts equal the histogram of the current state
+    // (set by steps, whose physics keeps them current; radiation uses them)
+    bool counts_fresh = false;
     Ctl* pinned = nullptr;
     // live phase timing
     bool profiling = false;
@@ -459,6 +462,7 @@ int coralai_world_destroy(coralai_world* w) {
 int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, const float* comm4,
                       const int32_t* genome, const uint8_t* rotation, int on_device) {
     WORLD_GUARD(w);
+    w->counts_fresh = false;
     if (!e_q || !i_q || !comm4 || !genome || !rotation) return fail(CORALAI_E_INVALID, "a state array is NULL");
     int cur = 0, rc = current_buffer(w, &cur);
     if (rc) return rc;
@@ -584,6 +588,7 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
     }
     int rc = check_launch();
     if (rc) return rc;
+    if (n_steps > 0) w->counts_fresh = true;
     if (out) {
         uint32_t word = 0;
         rc = report_errors(w, &word);
@@ -603,8 +608,10 @@ int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_in
     else if (rate >= 1.0) T = UINT64_MAX;
     else T = (uint64_t)std::floor(rate * 18446744073709551616.0);
     int rc = timed_phase(w, 4, [&] {
-        launch_radiate(w->bdev, w->wdev, w->ls, w->L.n_rad_blocks, T, sigma, step_index, w->stream);
+        launch_radiate(w->bdev, w->wdev, w->ls, w->L.n_rad_blocks, w->L.n_slot_blocks, w->counts_fresh, T,
+                       sigma, step_index, w->stream);
     });
+    w->counts_fresh = false;  // hits moved cells to new genomes
     if (rc) return rc;
     rc = check_launch();
     if (rc) return rc;
@@ -717,6 +724,7 @@ extern "C" {
 int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* act_waves_out,
                      int32_t* phys_tile_out) {
     WORLD_GUARD(w);
+    w->counts_fresh = false;
     int ac = 2, aw = 0, pt = 0;
     int rc = autotune_run(w->stream, w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec,
                           [&](int t) { w->phys_tile = t; return write_world_tables(w); }, &ac, &aw, &pt);
@@ -813,6 +821,7 @@ int coralai_batch_autotune(coralai_batch* b, int32_t* act_cells_out, int32_t* ac
     if (!guard_.ok) return fail(CORALAI_E_BUSY, "batch is in use");
     if (b->n == 0) return fail(CORALAI_E_INVALID, "the batch has no worlds");
     std::vector<coralai_world*> ws = b->worlds;
+    for (coralai_world* w : ws) w->counts_fresh = false;
     int ac = 2, aw = 0, pt = 0;
     int rc = autotune_run(b->stream, b->bdev, b->ls, b->NL, b->HID, b->prec,
                           [&](int t) { b->phys_tile = t; return batch_upload(b, ws.data(), (int)ws.size()); },
@@ -907,6 +916,7 @@ int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
     }
     int rc = check_launch();
     if (rc) return rc;
+    for (coralai_world* w : b->worlds) w->counts_fresh = true;
     // later calls on a world's own stream (get_state, step, ...) wait for these steps
     bool other = false;
     for (coralai_world* w : b->worlds) other = other || w->stream != b->stream;
@@ -937,6 +947,7 @@ int coralai_batch_destroy(coralai_batch* b) {
 
 int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, int32_t* perm) {
     WORLD_GUARD(w);
+    w->counts_fresh = false;
     launch_bucket_only(w->bdev, w->ls, w->stream);
     int rc = check_launch();
     if (rc) return rc;
@@ -952,6 +963,7 @@ int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, i
 
 int coralai_debug_actuators(coralai_world* w, float* act) {
     WORLD_GUARD(w);
+    w->counts_fresh = false;
     if (!act) return fail(CORALAI_E_INVALID, "act is NULL");
     const size_t N = (size_t)w->host.N;
     float* d = nullptr;
@@ -1001,6 +1013,7 @@ int coralai_debug_get_weights(coralai_world* w, int32_t slot, float* flat) {
 
 int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* flows8, const uint8_t* explore_dir) {
     WORLD_GUARD(w);
+    w->counts_fresh = false;
     if (!i1 || !flows8 || !explore_dir) return fail(CORALAI_E_INVALID, "a record array is NULL");
     int cur = 0, rc = current_buffer(w, &cur);
     if (rc) return rc;

@@ -307,6 +307,41 @@ def test_radiate_matches_oracle(stream):
     w.close()
 
 
+def test_radiate_after_steps_uses_the_counts_the_steps_kept(stream):
+    """Right after a step, radiation takes its free slots from the genome
+    counts that physics kept up to date through the takeovers (genomes that
+    lost their last cell become free); the result equals radiating the same
+    state from a new histogram, and the oracle's."""
+    from paper_2406_09654_amd.world import World
+    ng, cap = 1000, 1008      # ~2 cells per genome: takeovers empty whole genomes
+    init = gh.heterogeneous_world(48, 40, n_genomes=ng, capacity=cap, seed=21)
+    w = gh.make_world(init, stream)
+    tk = sum(w.step(1, stats=True)["takeovers"] for _ in range(3))
+    mid = w.get_state()
+    c0 = np.bincount(init.G.ravel(), minlength=cap)
+    c1 = np.bincount(mid["G"].ravel(), minlength=cap)
+    assert tk > 100 and int(((c0 > 0) & (c1 == 0)).sum()) > 20
+    rate, sigma, step_index = 0.1, 0.1, 4
+    st = w.radiate(rate, sigma, step_index)
+    assert st["hits"] > int((c0 == 0).sum())   # the freed slots are needed
+    out = w.get_state()
+    ref_w = World.from_init(init, stream=stream)
+    ref_w.set_state(mid["E"], mid["I"], mid["C"], mid["G"], mid["R"])
+    st2 = ref_w.radiate(rate, sigma, step_index)
+    ref = ref_w.get_state()
+    np.testing.assert_array_equal(out["G"], ref["G"])
+    assert (st["hits"], st["dropped_hits"]) == (st2["hits"], st2["dropped_hits"])
+    P = np.zeros((cap, 56))
+    P[:ng] = init.params.astype(np.float64)
+    G2, P2, (hc, hs), dropped = oracle.radiate(mid["G"], cap, P, init.spec.seed, step_index, rate, sigma)
+    np.testing.assert_array_equal(out["G"], G2)
+    assert st["hits"] == len(hc) and st["dropped_hits"] == dropped
+    new = hs[hs >= 0]
+    np.testing.assert_array_equal(w.get_genomes(new), ref_w.get_genomes(new))
+    w.close()
+    ref_w.close()
+
+
 def test_radiate_capacity_exhaustion_drops_deterministically(stream):
     W, H, cap = 120, 100, 12
     init = gh.heterogeneous_world(W, H, n_genomes=10, capacity=cap, seed=4)
