@@ -289,30 +289,37 @@ __global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__
         const int wi = find_world(b->slot_prefix, n, u);
         const auto& w = *world_at(b, wi);
         const int sb = (int)(u - cld(b->slot_prefix + (wi)));
-        int oc = w.scan_part[sb * 4 + 0], og = w.scan_part[sb * 4 + 1], of = w.scan_part[sb * 4 + 3];
-        for (int k = 0; k < kSlotBlock / 256; ++k) {
-            const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
+        // each thread owns kSlotBlock / 256 consecutive slots: serial sums,
+        // one block-wide scan per quantity, then serial writes
+        constexpr int PER = kSlotBlock / 256;
+        const int g0 = sb * kSlotBlock + threadIdx.x * PER;
+        int sc = 0, sg = 0, sf = 0;
+        for (int k = 0; k < PER; ++k) {
+            const int g = g0 + k;
             const int v = g < w.cap ? w.counts[g] : 0;
-            const int units = (v + kGroupCells - 1) / kGroupCells;
-            const int is_free = g < w.cap && v == 0;
-            int tc, tg, tf;
-            const int ec = block_exclusive_scan<256>(v, &tc, s_tmp);
-            const int eg = block_exclusive_scan<256>(units, &tg, s_tmp);
-            const int ef = block_exclusive_scan<256>(is_free, &tf, s_tmp);
-            if (g < w.cap) {
-                int pos = oc + ec;
-                w.offsets[g] = pos;
+            sc += v;
+            sg += (v + kGroupCells - 1) / kGroupCells;
+            sf += g < w.cap && v == 0;
+        }
+        int tc, tg, tf;
+        int oc = w.scan_part[sb * 4 + 0] + block_exclusive_scan<256>(sc, &tc, s_tmp);
+        int og = w.scan_part[sb * 4 + 1] + block_exclusive_scan<256>(sg, &tg, s_tmp);
+        int of = w.scan_part[sb * 4 + 3] + block_exclusive_scan<256>(sf, &tf, s_tmp);
+        for (int k = 0; k < PER; ++k) {
+            const int g = g0 + k;
+            if (g >= w.cap) break;
+            const int v = w.counts[g];
+            int pos = oc;
+            w.offsets[g] = pos;
 #pragma unroll
-                for (int q = 0; q < kSubCounters; ++q) {
-                    w.cursor[q * w.cap + g] = pos;
-                    pos += w.sub_counts[q * w.cap + g];
-                }
-                w.gofs[g] = og + eg;
-                if (is_free) w.free_list[of + ef] = g;
+            for (int q = 0; q < kSubCounters; ++q) {
+                w.cursor[q * w.cap + g] = pos;
+                pos += w.sub_counts[q * w.cap + g];
             }
-            oc += tc;
-            og += tg;
-            of += tf;
+            w.gofs[g] = og;
+            if (v == 0) w.free_list[of++] = g;
+            oc += v;
+            og += (v + kGroupCells - 1) / kGroupCells;
         }
     }
 }

@@ -274,13 +274,17 @@ __global__ __launch_bounds__(1024) void k_rad_scan(const WorldDev* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__ w, uint64_t step,
-                                                    float sigma) {
+// The k-th hit (cells in ascending order) takes the k-th free slot: the
+// cell's genome becomes the slot, and the hit's cell and parent are listed
+// for the mutation kernel.
+__global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__ w) {
     __shared__ int s_tmp[4];
     const Ctl* ctl = w->ctl;
     const int cur = ctl->cur;
     const int n_new = ctl->n_new;
     int32_t* G = w->G[cur];
+    int32_t* hit_cell = w->stage_slots;                   // free during radiation
+    int32_t* hit_parent = (int32_t*)w->stage_params;      // free during radiation
     for (int blk = blockIdx.x; blk < w->n_rad_blocks; blk += gridDim.x) {
         if (w->blk_hits[blk] == 0) continue;  // block-uniform
         const uint32_t bits = w->hit_bits[(int64_t)blk * 256 + threadIdx.x];
@@ -288,33 +292,51 @@ __global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__
         int rank = w->blk_ofs[blk] + block_scan_excl<256>(__popc(bits), &tot, s_tmp);
         for (int j = 0; j < 16; ++j) {
             if (!((bits >> j) & 1u)) continue;
-            const int64_t i = (int64_t)blk * kRadBlockCells + 16 * threadIdx.x + j;
+            const int i = blk * kRadBlockCells + 16 * threadIdx.x + j;
             const int parent = G[i];
             if (rank < n_new) w->new_slots[rank] = w->free_list[rank];  // every listed slot is valid
             if (parent < 0 || parent >= w->cap) {  // invalid id: flagged, never dereferenced
                 atomicOr(&w->ctl->err, kErrGenomeRange);
+                if (rank < n_new) hit_parent[rank] = -1;
             } else if (rank < n_new) {
                 const int slot = w->free_list[rank];
-                const float* pp = w->params + (int64_t)parent * kNParam;
-                float* np = w->params + (int64_t)slot * kNParam;
-                for (int bb = 0; bb < 14; ++bb) {
-                    uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(1 + bb), 0ull};
-                    philox4x64_10(c, w->seed, 0ull);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
-                        const float rr = sqrtf(-2.0f * logf(u1));
-                        float sn, cs;
-                        sincospif(2.0f * u2, &sn, &cs);
-                        const int m = 4 * bb + 2 * h;
-                        np[m] = pp[m] + sigma * (rr * cs);
-                        np[m + 1] = pp[m + 1] + sigma * (rr * sn);
-                    }
-                }
+                hit_cell[rank] = i;
+                hit_parent[rank] = parent;
                 G[i] = slot;
                 w->slot_set[slot] = 1;
             }
             ++rank;
+        }
+    }
+}
+
+// New parameters of every assigned hit: parent + sigma * N(0, 1), one
+// wavefront per hit, lane b < 14 drawing Philox block (i, step, 1 + b, 0)
+// whose two pairs of uniforms give normals 4b .. 4b+3 by Box-Muller.
+__global__ __launch_bounds__(256) void k_rad_mutate(const WorldDev* __restrict__ w, uint64_t step,
+                                                    float sigma) {
+    const int n_new = w->ctl->n_new;
+    const int lane = threadIdx.x & 63;
+    const int32_t* hit_cell = w->stage_slots;
+    const int32_t* hit_parent = (const int32_t*)w->stage_params;
+    for (int r = blockIdx.x * 4 + (threadIdx.x >> 6); r < n_new; r += gridDim.x * 4) {
+        const int parent = hit_parent[r];
+        if (parent < 0 || lane >= 14) continue;
+        const int i = hit_cell[r];
+        const int slot = w->new_slots[r];
+        const float* pp = w->params + (int64_t)parent * kNParam;
+        float* np = w->params + (int64_t)slot * kNParam;
+        uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(1 + lane), 0ull};
+        philox4x64_10(c, w->seed, 0ull);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
+            const float rr = sqrtf(-2.0f * logf(u1));
+            float sn, cs;
+            sincospif(2.0f * u2, &sn, &cs);
+            const int m = 4 * lane + 2 * h;
+            np[m] = pp[m] + sigma * (rr * cs);
+            np[m + 1] = pp[m + 1] + sigma * (rr * sn);
         }
     }
 }
@@ -350,15 +372,15 @@ __global__ __launch_bounds__(1024) void k_free_scan(const WorldDev* __restrict__
 __global__ __launch_bounds__(256) void k_free_write(const WorldDev* __restrict__ w) {
     __shared__ int s_tmp[4];
     for (int sb = blockIdx.x; sb < w->n_slot_blocks; sb += gridDim.x) {
-        int of = w->scan_part[sb * 4 + 3];
-        for (int k = 0; k < kSlotBlock / 256; ++k) {
-            const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
-            const int is_free = g < w->cap && w->counts[g] == 0;
-            int tf;
-            const int ef = block_scan_excl<256>(is_free, &tf, s_tmp);
-            if (is_free) w->free_list[of + ef] = g;
-            of += tf;
-        }
+        constexpr int PER = kSlotBlock / 256;  // consecutive slots per thread
+        const int g0 = sb * kSlotBlock + threadIdx.x * PER;
+        int c = 0;
+        for (int k = 0; k < PER; ++k) c += g0 + k < w->cap && w->counts[g0 + k] == 0;
+        int tf;
+        int of = w->scan_part[sb * 4 + 3] + block_scan_excl<256>(c, &tf, s_tmp);
+        for (int k = 0; k < PER; ++k)
+            if (g0 + k < w->cap && w->counts[g0 + k] == 0) w->free_list[of++] = g0 + k;
+        __syncthreads();
     }
 }
 
@@ -398,7 +420,8 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
     const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
     hipLaunchKernelGGL(k_rad_hits, dim3(hb), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
-    hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev, step, sigma);
+    hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev);
+    hipLaunchKernelGGL(k_rad_mutate, dim3(ls.n_cu), dim3(256), 0, s, wdev, step, sigma);
     launch_cppn(wdev, 1, 0, ls.n_cu, s);
     hipLaunchKernelGGL(k_rad_finalize, dim3(1), dim3(1), 0, s, wdev);
 }
