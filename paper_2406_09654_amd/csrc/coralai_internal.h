@@ -129,9 +129,28 @@ __host__ __device__ constexpr int net_flat_size(int nl, int hid) {
                    : hid * kNIn + hid + hid * hid + hid + kNOut * hid + kNOut;
 }
 
-// Hidden layers (all but the last) are stored multiplied by 2 log2(e), so the
-// network kernel evaluates tanh(x) as 1 - 2 / (2^y + 1) on y = 2 log2(e) x.
+// Stored network weights are the generated ones times factors that move
+// arithmetic out of the network kernel (one rounding of the product):
+//  * rows of hidden layers carry kTanhScale = 2 log2(e): the kernel computes
+//    r = 1 / (2^y + 1) on y = 2 log2(e) x, and tanh(x) = 1 - 2r;
+//  * layers after a hidden layer therefore take r as input: their columns
+//    carry -2, and the kernel adds -1/2 of each stored row's sum to its bias
+//    when it loads a genome (sum_j w_j tanh_j = sum_j w_j - 2 sum_j w_j r_j);
+//  * output rows 0..5 (sigmoid actuators) carry -log2(e) and rows 6..13 (flow
+//    logits) +log2(e): sigmoid and softmax then need one exp2 each;
+//  * layer-0 columns of the energy and infrastructure channels carry 2^-24,
+//    so the ledger quanta enter the network unscaled.
+// Biases carry their row's factor.  The debug weight hooks undo all of it.
 constexpr double kTanhScale = 2.8853900817779268;
+constexpr double kLog2e = 1.4426950408889634;
+__host__ __device__ inline double stored_row_scale(int nl, int layer, int row) {
+    if (layer < nl - 1) return kTanhScale;
+    return row < 6 ? -kLog2e : (row < kNOut ? kLog2e : 1.0);
+}
+__host__ __device__ inline double stored_col_scale(int layer, int col) {
+    if (layer > 0) return -2.0;
+    return col % 6 < 2 ? 0x1p-24 : 1.0;
+}
 
 struct FragCoord {
     int layer, row, col;

@@ -45,15 +45,17 @@ struct Net {
     using frag_t = typename std::conditional<kBF, bf16x8, float>::type;
 };
 
-// tanh(x) = 1 - 2 / (2^(2 log2(e) x) + 1): one exp2 and one reciprocal,
-// exact limits.  The hidden layers' weights and biases are stored multiplied
-// by 2 log2(e) (kTanhScale), so the argument arrives pre-scaled from the MFMA.
-__device__ __forceinline__ float tanh_prescaled(float y) {
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
+// Hidden activation r = 1 / (2^y + 1) = (1 - tanh(x)) / 2 on y = 2 log2(e) x:
+// one exp2 and one reciprocal, exact limits.  The stored weights carry the
+// argument scale, and the next layer's weights the -2 and the row-sum bias
+// correction that turn r back into tanh.
+__device__ __forceinline__ float tanh_r(float y) {
+    return __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
 }
 
-__device__ __forceinline__ float sigmoid_f(float x) {
-    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * -1.4426950408889634f));
+// sigmoid on an actuator stored times -log2(e): 1 / (1 + 2^x)
+__device__ __forceinline__ float sigmoid_s(float x) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x));
 }
 
 __device__ __forceinline__ floatx4 mfma(const bf16x8& a, const bf16x8& b, const floatx4& c) {
@@ -169,7 +171,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         st_pending = false;
     };
 
-    for (; u < uend; ++u) {
+    // Outer loop: one run of units of a single genome (weights loaded once,
+    // loop-invariant in the inner loop); inner loop: the run's units.
+    while (u < uend) {
         if (u >= world_hi) {
             if (st_pending) store_results();  // the buffers below change with the world
             flush();
@@ -195,20 +199,20 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             g = -1;
             g_hi = -1;
         }
-        const int k = u - world_lo;
-        if (k >= g_hi) {
-            // next genome: short linear probe, else binary search over gofs
+        {
+            const int k0 = u - world_lo;
+            // the run's genome: short linear probe, else binary search over gofs
             int gn = -1;
             if (g >= 0) {
 #pragma unroll 1
                 for (int t = g + 1; t < min(cap, g + 5); ++t)
-                    if (cld(gofs + t + 1) > k) { gn = t; break; }
+                    if (cld(gofs + t + 1) > k0) { gn = t; break; }
             }
             if (gn < 0) {
                 int lo = 0, hi = cap - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (cld(gofs + mid) <= k) lo = mid; else hi = mid - 1;
+                    if (cld(gofs + mid) <= k0) lo = mid; else hi = mid - 1;
                 }
                 gn = lo;
             }
@@ -236,10 +240,45 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             for (int t = lane; t < net_bias_floats(NL, HID) / 4; t += 64)
                 *(floatx4*)(sbias + 4 * t) = gld((const floatx4*)(gb + 4 * t));
             wave_lds_sync();
+            // layers after a hidden layer read r = (1 - tanh) / 2 through
+            // weights stored times -2: their biases gain -1/2 of the stored
+            // row sums (an MFMA against a ones operand)
+            {
+                frag_t ones;
+                if constexpr (NT::kBF) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+                } else {
+                    ones = 1.0f;
+                }
+                if constexpr (NL == 3) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        floatx4 rs = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int s = 0; s < KSH; ++s) rs = mfma(w1[mt][s], ones, rs);
+                        if (n16 == 0) {
+                            floatx4* bp = (floatx4*)(sbias + HID + 16 * mt + 4 * q);
+                            *bp = *bp - 0.5f * rs;
+                        }
+                    }
+                }
+                floatx4 rs = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KSH; ++s) rs = mfma(wo[s], ones, rs);
+                if (n16 == 0) {
+                    floatx4* bp = (floatx4*)(sbias + (NL == 3 ? 2 * HID : HID) + 4 * q);
+                    *bp = *bp - 0.5f * rs;
+                }
+                wave_lds_sync();
+            }
         }
-        const int j = k - g_lo;
+        const int u_run_end = min(uend, world_lo + g_hi);
         const int gcount = cld(counts + g);
-        const int cell0 = cld(offsets + g) + j * kGroupCells;
+        const int goff = cld(offsets + g);
+        for (; u < u_run_end; ++u) {
+        const int j = u - world_lo - g_lo;
+        const int cell0 = goff + j * kGroupCells;
         const int cnt = min(kGroupCells, gcount - j * kGroupCells);
         const bool valid = lane < cnt;
         const int entry = have_pf ? e_pf
@@ -247,7 +286,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                                         rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
         const int i = entry & kPermIndexMask, r = (entry >> kPermRotShift) & 7;
         // prefetch the next unit's cell index when it continues this genome
-        have_pf = (u + 1 < uend) && (u + 1 < world_hi) && (k + 1 < g_hi);
+        have_pf = u + 1 < u_run_end;
         if (have_pf) {
             const int cnt_n = min(kGroupCells, gcount - (j + 1) * kGroupCells);
             e_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(
@@ -282,8 +321,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         float uvec[kNIn];
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
-            uvec[6 * p + 0] = i64_to_f32(gE[p]) * 0x1p-24f;
-            uvec[6 * p + 1] = i64_to_f32(gI[p]) * 0x1p-24f;
+            uvec[6 * p + 0] = i64_to_f32(gE[p]);  // the 2^-24 quantum is in the weights
+            uvec[6 * p + 1] = i64_to_f32(gI[p]);
 #pragma unroll
             for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = gC[p][c];
         }
@@ -319,12 +358,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
         for (int cb = 0; cb < 4 / CGI; ++cb) {
             floatx4 acc[CGI][MT];
+            floatx4 bv0[MT];  // the biases enter as the first MFMA's accumulator
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const floatx4 bv = *(const floatx4*)(gbias + 16 * mt);
-#pragma unroll
-                for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
-            }
+            for (int mt = 0; mt < MT; ++mt) bv0[mt] = *(const floatx4*)(gbias + 16 * mt);
             if constexpr (NT::kBF) {
                 bf16x8 xin[CGI][KS0];
 #pragma unroll
@@ -338,7 +374,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
                     for (int cc = 0; cc < CGI; ++cc)
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], acc[cc][mt]);
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], s == 0 ? bv0[mt] : acc[cc][mt]);
             } else {
                 float xin[CGI][16];
 #pragma unroll
@@ -355,7 +392,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
                     for (int cc = 0; cc < CGI; ++cc)
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], acc[cc][mt]);
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], s == 0 ? bv0[mt] : acc[cc][mt]);
             }
             // hidden layers
 #pragma unroll
@@ -370,32 +408,29 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
                             for (int t = 0; t < 4; ++t) {
-                                h[cc][s][t] = (__bf16)tanh_prescaled(acc[cc][2 * s][t]);
-                                h[cc][s][4 + t] = (__bf16)tanh_prescaled(acc[cc][2 * s + 1][t]);
+                                h[cc][s][t] = (__bf16)tanh_r(acc[cc][2 * s][t]);
+                                h[cc][s][4 + t] = (__bf16)tanh_r(acc[cc][2 * s + 1][t]);
                             }
                     if (last) {
                         const floatx4 bv = *(const floatx4*)lb;
 #pragma unroll
                         for (int cc = 0; cc < CGI; ++cc) {
-                            floatx4 o = bv;
+                            floatx4 o = mfma(wo[0], h[cc][0], bv);
 #pragma unroll
-                            for (int s = 0; s < KSH; ++s) o = mfma(wo[s], h[cc][s], o);
+                            for (int s = 1; s < KSH; ++s) o = mfma(wo[s], h[cc][s], o);
                             outv[cb * CGI + cc] = o;
                         }
                     } else {
+                        floatx4 bvh[MT];
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) {
-                            const floatx4 bv = *(const floatx4*)(lb + 16 * mt);
-#pragma unroll
-                            for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
-                        }
+                        for (int mt = 0; mt < MT; ++mt) bvh[mt] = *(const floatx4*)(lb + 16 * mt);
 #pragma unroll
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
                             for (int cc = 0; cc < CGI; ++cc)
 #pragma unroll
                                 for (int mt = 0; mt < MT; ++mt)
-                                    acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s], acc[cc][mt]);
+                                    acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s], s == 0 ? bvh[mt] : acc[cc][mt]);
                     }
                 } else {
                     float h[CGI][MT][4];
@@ -404,30 +439,28 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) h[cc][mt][t] = tanh_prescaled(acc[cc][mt][t]);
+                            for (int t = 0; t < 4; ++t) h[cc][mt][t] = tanh_r(acc[cc][mt][t]);
                     if (last) {
                         const floatx4 bv = *(const floatx4*)lb;
 #pragma unroll
                         for (int cc = 0; cc < CGI; ++cc) {
-                            floatx4 o = bv;
+                            floatx4 o = mfma(wo[0], h[cc][0][0], bv);
 #pragma unroll
-                            for (int s = 0; s < KSH; ++s) o = mfma(wo[s], h[cc][s >> 2][s & 3], o);
+                            for (int s = 1; s < KSH; ++s) o = mfma(wo[s], h[cc][s >> 2][s & 3], o);
                             outv[cb * CGI + cc] = o;
                         }
                     } else {
+                        floatx4 bvh[MT];
 #pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) {
-                            const floatx4 bv = *(const floatx4*)(lb + 16 * mt);
-#pragma unroll
-                            for (int cc = 0; cc < CGI; ++cc) acc[cc][mt] = bv;
-                        }
+                        for (int mt = 0; mt < MT; ++mt) bvh[mt] = *(const floatx4*)(lb + 16 * mt);
 #pragma unroll
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
                             for (int cc = 0; cc < CGI; ++cc)
 #pragma unroll
                                 for (int mt = 0; mt < MT; ++mt)
-                                    acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s >> 2][s & 3], acc[cc][mt]);
+                                    acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s >> 2][s & 3],
+                                                       s == 0 ? bvh[mt] : acc[cc][mt]);
                     }
                 }
             }
@@ -449,9 +482,10 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         st_i = valid ? i : -1;
         st_pending = true;
         if (valid) {
-            if constexpr (DEBUG) {
+            if constexpr (DEBUG) {  // the actuators without their stored scale
+                constexpr float kLn2 = 0.69314718055994531f;
 #pragma unroll
-                for (int t = 0; t < kNOut; ++t) dbg[(int64_t)i * kNOut + t] = a[t];
+                for (int t = 0; t < kNOut; ++t) dbg[(int64_t)i * kNOut + t] = a[t] * (t < 6 ? -kLn2 : kLn2);
             }
             bool finite = true;
 #pragma unroll
@@ -463,7 +497,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             }
             if (e_own < 0 || i_own < 0) err |= kErrLedger;
             // invest / liquidate: sigmoid-gated fractions of the pre-step stocks
-            const float se = sigmoid_f(a[0]), sl = sigmoid_f(a[1]);
+            const float se = sigmoid_s(a[0]), sl = sigmoid_s(a[1]);
             int64_t xi = (int64_t)floorf(rho_i * se * i64_to_f32(e_own));
             int64_t xl = (int64_t)floorf(rho_l * sl * i64_to_f32(i_own));
             xi = xi > e_own ? e_own : xi;
@@ -475,7 +509,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             st_I1 = I1;
             // communication: sigmoid of the comm actuators
 #pragma unroll
-            for (int c = 0; c < 4; ++c) st_c[c] = __builtin_bit_cast(uint32_t, sigmoid_f(a[2 + c]));
+            for (int c = 0; c < 4; ++c) st_c[c] = __builtin_bit_cast(uint32_t, sigmoid_s(a[2 + c]));
             // exploration: softmax split of the flow budget, argmax explore
             float m = a[6];
             int best = 0;
@@ -484,7 +518,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                 if (a[6 + t] > m) { m = a[6 + t]; best = t; }
             float ex[8], ssum = 0.0f;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) { ex[t] = __expf(a[6 + t] - m); ssum += ex[t]; }
+            // flow logits are stored times log2(e): exp(a - max) = 2^(a' - max')
+            for (int t = 0; t < 8; ++t) { ex[t] = __builtin_amdgcn_exp2f(a[6 + t] - m); ssum += ex[t]; }
             const float inv = __builtin_amdgcn_rcpf(ssum);
             // flow budget below 2^31 quanta: each flow word carries the
             // explored flag in its low bit
@@ -494,12 +529,12 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             // all amounts are below 2^31: 32-bit integers suffice, and the
             // truncating conversion of a non-negative float is its floor
             const uint32_t Fu = (uint32_t)F;
-            const float fF = (float)Fu;
+            const float per = inv * (float)Fu;  // budget per unit of softmax weight
             const uint32_t plane = 4u * (uint32_t)Nd, own = 4u * (uint32_t)i;
             uint32_t used = 0;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const float share = (ex[t] * inv) * fF;  // >= 0 and finite
+                const float share = ex[t] * per;  // >= 0 and finite
                 uint32_t f = (uint32_t)share;
                 const uint32_t rem = Fu - used;
                 f = f < rem ? f : rem;
@@ -511,6 +546,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             acc_mass += E1;
             acc_f64 += (double)E1;
         }
+        }  // units of the run
     }
     if (st_pending) store_results();
     flush();

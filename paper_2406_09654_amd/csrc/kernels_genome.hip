@@ -53,13 +53,14 @@ __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, 
 template <typename T>
 __device__ __forceinline__ T neuron_x(int j, int L) { return T(-1) + T(2) * T(j) / T(L - 1); }
 
-// Stored value of a weight / bias: hidden layers carry the tanh argument
-// scale (kTanhScale), applied before the single rounding to FP32 or bf16.
+// Stored value of a weight / bias: the generated value times the stored
+// scale factors (stored_row_scale, stored_col_scale), then one rounding to
+// FP32 or bf16.
 template <typename T>
 __device__ __forceinline__ float cppn_weight(const float* p, int layer, int nl, int row, int lout,
                                              int col, int lin) {
     const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
-    const T sc = layer < nl - 1 ? T(kTanhScale) : T(1);
+    const T sc = T(stored_row_scale(nl, layer, row) * stored_col_scale(layer, col));
     return (float)(cppn_eval<T>(p, neuron_x<T>(col, lin), yi, neuron_x<T>(row, lout), yo, 0) /
                    sqrt(T(lin)) * sc);
 }
@@ -67,7 +68,7 @@ __device__ __forceinline__ float cppn_weight(const float* p, int layer, int nl, 
 template <typename T>
 __device__ __forceinline__ float cppn_bias(const float* p, int layer, int nl, int row, int lout) {
     const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
-    const T sc = layer < nl - 1 ? T(kTanhScale) : T(1);
+    const T sc = T(stored_row_scale(nl, layer, row));
     return (float)(cppn_eval<T>(p, T(0), yi, neuron_x<T>(row, lout), yo, 1) * sc);
 }
 
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
 }
 
 // Debug: natural flat layout <-> fragment layout of one slot (the stored
-// hidden layers carry kTanhScale; the flat layout does not).
+// values carry the stored scale factors; the flat layout does not).
 __global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, int slot,
                                               const float* __restrict__ flat, int unpack,
                                               float* __restrict__ out) {
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, in
             const int lin = layer_in(nl, hid, fc.layer), lout = layer_out(nl, hid, fc.layer);
             const bool ok = fc.row < lout && fc.col < lin;
             const int fi = flat_w_offset(nl, hid, fc.layer) + fc.row * lin + fc.col;
-            const double sc = fc.layer < nl - 1 ? kTanhScale : 1.0;
+            const double sc = stored_row_scale(nl, fc.layer, fc.row) * stored_col_scale(fc.layer, fc.col);
             if (!unpack) {
                 const float v = ok ? (float)((double)flat[fi] * sc) : 0.0f;
                 if (bf) ((__bf16*)dst)[e] = (__bf16)v;
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, in
             const int lin = layer_in(nl, hid, layer), lout = layer_out(nl, hid, layer);
             const bool ok = row < lout;
             const int fi = flat_w_offset(nl, hid, layer) + lout * lin + row;
-            const double sc = layer < nl - 1 ? kTanhScale : 1.0;
+            const double sc = stored_row_scale(nl, layer, row);
             float* bp = w->bias + (int64_t)slot * w->bias_stride + (e - ew);
             if (!unpack) *bp = ok ? (float)((double)flat[fi] * sc) : 0.0f;
             else if (ok) out[fi] = (float)((double)*bp / sc);
