@@ -44,6 +44,41 @@ def trans_per_cell(hidden: int, layers: int) -> int:
     return 2 * hidden * (layers - 1) + 2 * 6 + 8 + 1
 
 
+ACT_SOURCES = ["paper_2406_09654_amd/csrc/kernels_act.hip", "paper_2406_09654_amd/csrc/coralai_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_act_bf16_4096_hbm_traffic.md")
+
+
+def act_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ACT_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def act_traffic(tuning):
+    """HBM bytes per launch of the BF16 network kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy
+    calibration).  None when the summary is missing, was taken for another
+    launch configuration, or the kernel's sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    fields = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("traffic:"):
+                for kv in line.split()[1:]:
+                    k, _, v = kv.partition("=")
+                    fields[k] = v
+    if fields.get("source_sha256") != act_sources_sha256():
+        return None, "kernel changed since the counters were taken"
+    if tuning is not None and fields.get("tuning") != ",".join(str(v) for v in tuning):
+        return None, "counters taken for tuning %s" % fields.get("tuning")
+    return int(fields["bytes_per_launch"]), "FETCH_SIZE x %s + WRITE_SIZE x %s per launch, %s" % (
+        fields.get("fetch_factor"), fields.get("write_factor"), os.path.relpath(TRAFFIC_FILE, ROOT))
+
+
 def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bool, tuning=None):
     import torch
 
@@ -268,10 +303,11 @@ def main() -> int:
     bf = forms["bf16"]
     act_ms = bf["phase_ms"]["act"]
     trans = trans_per_cell(hidden, layers) * N
+    traffic, traffic_note = act_traffic(bf["tuning"])
     roof = {"kernel": "k_act (sense + grouped MLP + epilogue)", "bound": "alu",
             "achieved": trans / (act_ms * 1e-3), "peak": PEAK_TRANS,
             "unit": "transcendental op/s", "frac": trans / (act_ms * 1e-3) / PEAK_TRANS,
-            "traffic": None,
+            "traffic": traffic, "traffic_note": traffic_note,
             "per_unit": "%d transcendental ops per cell (tanh, sigmoid, softmax), %d cells per launch"
                         % (trans_per_cell(hidden, layers), N),
             "mfma_frac_bf16": flops_per_cell(hidden, layers) * N / (act_ms * 1e-3) / PEAK_BF16}

@@ -18,7 +18,6 @@ constexpr int kPermIndexMask = (1 << kPermRotShift) - 1;
 constexpr int kGroupCells = 64;   // cells per network work unit (one wavefront)
 constexpr int kBucketTile = 64;   // bucketing tile: 64 x 64 cells
 constexpr int kBucketGroup = 4;   // tiles per bucketing unit (one block)
-constexpr int kSubCounters = 8;   // per-genome counters, spread to cut atomic contention
 constexpr int kSlotBlock = 4096;  // genome slots per scan block
 constexpr int kRadBlockCells = 4096;  // cells per radiation hit block (256 x 16)
 constexpr int kPrecFP32 = 0;
@@ -37,6 +36,8 @@ struct Ctl {
     int32_t n_new;          // hits that received a slot
     int32_t dropped;        // hits beyond the free slots
     uint32_t err;           // sticky CORALAI_ERR_* bits
+    int32_t counts_valid;   // counts[] is the histogram of the current state's genomes
+    int32_t pad_ctl;
     int64_t acc_mass;       // step accumulators
     double acc_mass_f64;
     int64_t acc_takeovers;
@@ -65,10 +66,9 @@ struct WorldDev {
     int64_t* EI1;         // [N][2]: energy and infrastructure after invest / liquidate
     uint32_t* out;        // total outflow of the cell
     int32_t* perm;        // cells grouped by genome
-    int32_t* counts;      // [cap] cells per genome
+    int32_t* counts;      // [cap] cells per genome (kept current by physics and radiation)
     int32_t* offsets;     // [cap + 1]
-    int32_t* sub_counts;  // [kSubCounters][cap] partial counts
-    int32_t* cursor;      // [kSubCounters][cap] next free position of each partial range
+    int32_t* cursor;      // [cap] next free position of each genome's range (scatter)
     int32_t* gofs;        // [cap + 1] exclusive prefix of network units per genome
     uint8_t* slot_set;    // [cap]
     float* params;        // [cap][56]
@@ -307,11 +307,8 @@ void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s)
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
 void launch_cppn(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s);
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
-// counts_fresh: the genome counts equal the histogram of the current state
-// (true right after a step, whose physics keeps them up to date)
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
-                    int n_rad_blocks, int n_slot_blocks, bool counts_fresh, uint64_t T, float sigma,
-                    uint64_t step, hipStream_t s);
+                    int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s);
 void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
                          hipStream_t s);
 void launch_flip(const BatchDev* bdev, hipStream_t s);

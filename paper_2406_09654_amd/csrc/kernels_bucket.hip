@@ -54,13 +54,15 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total, int* s_tm
     return before + x - v;
 }
 
-// Zero the genome histogram and the step accumulators of every world.
+// Zero the step accumulators of every world, and its genome histogram
+// unless the counts already describe the current state (physics and
+// radiation keep them current; only a new state from the host does not).
 __global__ __launch_bounds__(256) void k_prep(const BatchDev* __restrict__ b) {
     const int wi = blockIdx.y;
     if (wi >= b->n_worlds) return;
     const auto& w = *world_at(b, wi);
-    for (int g = blockIdx.x * 256 + threadIdx.x; g < kSubCounters * w.cap; g += gridDim.x * 256)
-        w.sub_counts[g] = 0;
+    if (!w.ctl->counts_valid)
+        for (int g = blockIdx.x * 256 + threadIdx.x; g < w.cap; g += gridDim.x * 256) w.counts[g] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.ctl->acc_mass = 0;
         w.ctl->acc_mass_f64 = 0.0;
@@ -87,9 +89,11 @@ __device__ __forceinline__ int hash_find(int* s_key, int g, bool insert) {
 // scatter = 0: histogram into the partial counters.  scatter = 1:
 // compaction into perm, using the cursors the scan set.  A block takes a
 // unit of kBucketGroup consecutive tiles and aggregates its counts over all
-// of them before touching global memory; the unit's partial counter is
-// (unit mod kSubCounters).  The order of a genome's cells in perm follows
-// unit and wavefront arrival, i.e. it is spatially local but not specified.
+// of them before touching global memory: one atomic per (unit, genome) on
+// the genome's cursor.  The order of a genome's cells in perm follows unit
+// and wavefront arrival, i.e. it is spatially local but not specified.  The
+// counting pass is skipped while the counts are current (the flag the scan
+// sets, and that set_state clears).
 __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, int scatter) {
     __shared__ int s_key[kHashSlots];
     __shared__ int s_cnt[kHashSlots];
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, 
         const auto& w = *world_at(b, wi);
         const int cur = ctl_cur(w.ctl);
         const int64_t unit = u - cld(b->chunk_prefix + (wi));
-        const int sub = (int)(unit % kSubCounters);
+        if (!scatter && w.ctl->counts_valid) continue;  // block-uniform: nothing to count
         const int32_t* G = w.G[cur];
         for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
         __syncthreads();
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, 
                     const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
                     const int h = hash_find(s_key, g, true);
                     if (h >= 0) atomicAdd(&s_cnt[h], len);
-                    else if (!scatter) atomicAdd(&w.sub_counts[sub * w.cap + g], len);
+                    else if (!scatter) atomicAdd(&w.counts[g], len);
                 }
             }
         }
@@ -163,8 +167,8 @@ __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, 
         for (int k = threadIdx.x; k < kHashSlots; k += 256) {
             const int g = s_key[k];
             if (g < 0) continue;
-            if (!scatter) atomicAdd(&w.sub_counts[sub * w.cap + g], s_cnt[k]);
-            else { s_base[k] = atomicAdd(&w.cursor[sub * w.cap + g], s_cnt[k]); s_cnt[k] = 0; }
+            if (!scatter) atomicAdd(&w.counts[g], s_cnt[k]);
+            else { s_base[k] = atomicAdd(&w.cursor[g], s_cnt[k]); s_cnt[k] = 0; }
         }
         if (scatter) {
             __syncthreads();
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, 
                         const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
                         const int h = hash_find(s_key, g, false);
                         base = h >= 0 ? s_base[h] + atomicAdd(&s_cnt[h], len)
-                                      : atomicAdd(&w.cursor[sub * w.cap + g], len);
+                                      : atomicAdd(&w.cursor[g], len);
                     }
                     const uint64_t upto = starts & ((2ull << lane) - 1ull);
                     const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
@@ -223,10 +227,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict_
         for (int k = 0; k < kSlotBlock / 256; ++k) {
             const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
             if (g < w.cap) {
-                int v = 0;
-#pragma unroll
-                for (int q = 0; q < kSubCounters; ++q) v += w.sub_counts[q * w.cap + g];
-                w.counts[g] = v;
+                const int v = w.counts[g];
                 c += v;
                 gsum += (v + kGroupCells - 1) / kGroupCells;
                 live += v > 0;
@@ -269,6 +270,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict
     if (t < nb)
         for (int f = 0; f < 4; ++f) w.scan_part[t * 4 + f] = pre[f];
     if (t == 0) {
+        w.ctl->counts_valid = 1;
         w.offsets[w.cap] = tot[0];
         w.gofs[w.cap] = tot[1];
         w.ctl->total_groups = tot[1];
@@ -309,13 +311,8 @@ __global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__
             const int g = g0 + k;
             if (g >= w.cap) break;
             const int v = w.counts[g];
-            int pos = oc;
-            w.offsets[g] = pos;
-#pragma unroll
-            for (int q = 0; q < kSubCounters; ++q) {
-                w.cursor[q * w.cap + g] = pos;
-                pos += w.sub_counts[q * w.cap + g];
-            }
+            w.offsets[g] = oc;
+            w.cursor[g] = oc;
             w.gofs[g] = og;
             if (v == 0) w.free_list[of++] = g;
             oc += v;
@@ -367,7 +364,7 @@ static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t
 }
 
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
-    const int cap_blocks = min(256, max(1, (kSubCounters * ls.max_cap + 255) / 256));
+    const int cap_blocks = min(256, max(1, (ls.max_cap + 255) / 256));
     hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
     hipLaunchKernelGGL(k_bucket, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev, 0);
     launch_scan(bdev, ls, s);

@@ -305,6 +305,8 @@ __global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__
                 hit_parent[rank] = parent;
                 G[i] = slot;
                 w->slot_set[slot] = 1;
+                atomicAdd(w->counts + parent, -1);  // the counts stay current
+                atomicAdd(w->counts + slot, 1);
             }
             ++rank;
         }
@@ -342,49 +344,6 @@ __global__ __launch_bounds__(256) void k_rad_mutate(const WorldDev* __restrict__
     }
 }
 
-// Free slots (count 0, ascending) from the genome counts the step left:
-// zero-count slots per 4096-slot block, their exclusive prefix, the list.
-__global__ __launch_bounds__(256) void k_free_count(const WorldDev* __restrict__ w) {
-    __shared__ int s_tmp[4];
-    for (int sb = blockIdx.x; sb < w->n_slot_blocks; sb += gridDim.x) {
-        int c = 0;
-        for (int k = 0; k < kSlotBlock / 256; ++k) {
-            const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
-            c += g < w->cap && w->counts[g] == 0;
-        }
-        int tot;
-        block_scan_excl<256>(c, &tot, s_tmp);
-        if (threadIdx.x == 0) w->scan_part[sb * 4 + 3] = tot;
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_free_scan(const WorldDev* __restrict__ w) {
-    __shared__ int s_tmp[16];
-    const int nb = w->n_slot_blocks;  // <= 1024
-    const int t = threadIdx.x;
-    const int v = t < nb ? w->scan_part[t * 4 + 3] : 0;
-    int tot;
-    const int pre = block_scan_excl<1024>(v, &tot, s_tmp);
-    if (t < nb) w->scan_part[t * 4 + 3] = pre;
-    if (t == 0) w->ctl->n_free = tot;
-}
-
-__global__ __launch_bounds__(256) void k_free_write(const WorldDev* __restrict__ w) {
-    __shared__ int s_tmp[4];
-    for (int sb = blockIdx.x; sb < w->n_slot_blocks; sb += gridDim.x) {
-        constexpr int PER = kSlotBlock / 256;  // consecutive slots per thread
-        const int g0 = sb * kSlotBlock + threadIdx.x * PER;
-        int c = 0;
-        for (int k = 0; k < PER; ++k) c += g0 + k < w->cap && w->counts[g0 + k] == 0;
-        int tf;
-        int of = w->scan_part[sb * 4 + 3] + block_scan_excl<256>(c, &tf, s_tmp);
-        for (int k = 0; k < PER; ++k)
-            if (g0 + k < w->cap && w->counts[g0 + k] == 0) w->free_list[of++] = g0 + k;
-        __syncthreads();
-    }
-}
-
 __global__ void k_rad_finalize(const WorldDev* __restrict__ w) {
     Ctl* ctl = w->ctl;
     ctl->hits_pub = ctl->hits;
@@ -406,18 +365,11 @@ void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int 
 }
 
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
-                    int n_rad_blocks, int n_slot_blocks, bool counts_fresh, uint64_t T, float sigma,
-                    uint64_t step, hipStream_t s) {
-    // free slots of the current state (the completed step's result): from the
-    // counts the step kept up to date, else from a new histogram
-    if (counts_fresh) {
-        const int fb = max(1, min(n_slot_blocks, ls.n_cu));
-        hipLaunchKernelGGL(k_free_count, dim3(fb), dim3(256), 0, s, wdev);
-        hipLaunchKernelGGL(k_free_scan, dim3(1), dim3(1024), 0, s, wdev);
-        hipLaunchKernelGGL(k_free_write, dim3(fb), dim3(256), 0, s, wdev);
-    } else {
-        launch_hist_only(bdev, ls, s);
-    }
+                    int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s) {
+    // free slots of the current state (the completed step's result), listed by
+    // the slot scan; the counting pass inside runs only if the counts are not
+    // current (right after a step they are)
+    launch_hist_only(bdev, ls, s);
     const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
     hipLaunchKernelGGL(k_rad_hits, dim3(hb), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);

@@ -47,7 +47,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t EI[2], C[2], G[2], R[2];
     size_t flow, EI1, out, perm;
-    size_t counts, offsets, sub_counts, cursor, gofs, slot_set, params, wfrag, bias;
+    size_t counts, offsets, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
     size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
     int n_slot_blocks;
@@ -89,8 +89,7 @@ Layout make_layout(const coralai_world_desc* d) {
     L.perm = take(4 * N);
     L.counts = take(4 * cap);
     L.offsets = take(4 * (cap + 1));
-    L.sub_counts = take(4 * kSubCounters * cap);
-    L.cursor = take(4 * kSubCounters * cap);
+    L.cursor = take(4 * cap);
     L.gofs = take(4 * (cap + 1));
     L.slot_set = take(cap);
     L.params = take(4 * kNParam * cap);
@@ -167,9 +166,6 @@ struct coralai_world {
     int phys_tile = 3;
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
-    // the device genome counts equal the histogram of the current state
-    // (set by steps, whose physics keeps them current; radiation uses them)
-    bool counts_fresh = false;
     Ctl* pinned = nullptr;
     // live phase timing
     bool profiling = false;
@@ -275,6 +271,13 @@ void fill_stats(const Ctl& c, coralai_stats* out) {
 int check_launch() {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CORALAI_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return CORALAI_OK;
+}
+
+// The device genome counts no longer describe the current state (new state
+// from the host, or trial launches that ran physics without committing it).
+int invalidate_counts(coralai_world* w) {
+    HIP_TRY(hipMemsetAsync(&w->host.ctl->counts_valid, 0, sizeof(int32_t), w->stream));
     return CORALAI_OK;
 }
 
@@ -404,7 +407,6 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     h.perm = (int32_t*)(b + L.perm);
     h.counts = (int32_t*)(b + L.counts);
     h.offsets = (int32_t*)(b + L.offsets);
-    h.sub_counts = (int32_t*)(b + L.sub_counts);
     h.cursor = (int32_t*)(b + L.cursor);
     h.gofs = (int32_t*)(b + L.gofs);
     h.slot_set = (uint8_t*)(b + L.slot_set);
@@ -462,7 +464,10 @@ int coralai_world_destroy(coralai_world* w) {
 int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, const float* comm4,
                       const int32_t* genome, const uint8_t* rotation, int on_device) {
     WORLD_GUARD(w);
-    w->counts_fresh = false;
+    {
+        const int irc = invalidate_counts(w);
+        if (irc) return irc;
+    }
     if (!e_q || !i_q || !comm4 || !genome || !rotation) return fail(CORALAI_E_INVALID, "a state array is NULL");
     int cur = 0, rc = current_buffer(w, &cur);
     if (rc) return rc;
@@ -588,7 +593,6 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
     }
     int rc = check_launch();
     if (rc) return rc;
-    if (n_steps > 0) w->counts_fresh = true;
     if (out) {
         uint32_t word = 0;
         rc = report_errors(w, &word);
@@ -608,10 +612,8 @@ int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_in
     else if (rate >= 1.0) T = UINT64_MAX;
     else T = (uint64_t)std::floor(rate * 18446744073709551616.0);
     int rc = timed_phase(w, 4, [&] {
-        launch_radiate(w->bdev, w->wdev, w->ls, w->L.n_rad_blocks, w->L.n_slot_blocks, w->counts_fresh, T,
-                       sigma, step_index, w->stream);
+        launch_radiate(w->bdev, w->wdev, w->ls, w->L.n_rad_blocks, T, sigma, step_index, w->stream);
     });
-    w->counts_fresh = false;  // hits moved cells to new genomes
     if (rc) return rc;
     rc = check_launch();
     if (rc) return rc;
@@ -724,10 +726,12 @@ extern "C" {
 int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* act_waves_out,
                      int32_t* phys_tile_out) {
     WORLD_GUARD(w);
-    w->counts_fresh = false;
     int ac = 2, aw = 0, pt = 0;
     int rc = autotune_run(w->stream, w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec,
                           [&](int t) { w->phys_tile = t; return write_world_tables(w); }, &ac, &aw, &pt);
+    if (rc) return rc;
+    // the trial physics launches moved the genome counts off the state
+    rc = invalidate_counts(w);
     if (rc) return rc;
     w->act_cells = ac;
     w->act_waves = aw;
@@ -821,12 +825,14 @@ int coralai_batch_autotune(coralai_batch* b, int32_t* act_cells_out, int32_t* ac
     if (!guard_.ok) return fail(CORALAI_E_BUSY, "batch is in use");
     if (b->n == 0) return fail(CORALAI_E_INVALID, "the batch has no worlds");
     std::vector<coralai_world*> ws = b->worlds;
-    for (coralai_world* w : ws) w->counts_fresh = false;
     int ac = 2, aw = 0, pt = 0;
     int rc = autotune_run(b->stream, b->bdev, b->ls, b->NL, b->HID, b->prec,
                           [&](int t) { b->phys_tile = t; return batch_upload(b, ws.data(), (int)ws.size()); },
                           &ac, &aw, &pt);
     if (rc) return rc;
+    // the trial physics launches moved the worlds' genome counts off their states
+    for (coralai_world* w : ws)
+        HIP_TRY(hipMemsetAsync(&w->host.ctl->counts_valid, 0, sizeof(int32_t), b->stream));
     b->act_cells = ac;
     b->act_waves = aw;
     if (act_cells_out) *act_cells_out = ac;
@@ -916,7 +922,6 @@ int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
     }
     int rc = check_launch();
     if (rc) return rc;
-    for (coralai_world* w : b->worlds) w->counts_fresh = true;
     // later calls on a world's own stream (get_state, step, ...) wait for these steps
     bool other = false;
     for (coralai_world* w : b->worlds) other = other || w->stream != b->stream;
@@ -947,7 +952,10 @@ int coralai_batch_destroy(coralai_batch* b) {
 
 int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, int32_t* perm) {
     WORLD_GUARD(w);
-    w->counts_fresh = false;
+    {
+        const int irc = invalidate_counts(w);
+        if (irc) return irc;
+    }
     launch_bucket_only(w->bdev, w->ls, w->stream);
     int rc = check_launch();
     if (rc) return rc;
@@ -963,7 +971,10 @@ int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, i
 
 int coralai_debug_actuators(coralai_world* w, float* act) {
     WORLD_GUARD(w);
-    w->counts_fresh = false;
+    {
+        const int irc = invalidate_counts(w);
+        if (irc) return irc;
+    }
     if (!act) return fail(CORALAI_E_INVALID, "act is NULL");
     const size_t N = (size_t)w->host.N;
     float* d = nullptr;
@@ -1013,7 +1024,10 @@ int coralai_debug_get_weights(coralai_world* w, int32_t slot, float* flat) {
 
 int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* flows8, const uint8_t* explore_dir) {
     WORLD_GUARD(w);
-    w->counts_fresh = false;
+    {
+        const int irc = invalidate_counts(w);
+        if (irc) return irc;
+    }
     if (!i1 || !flows8 || !explore_dir) return fail(CORALAI_E_INVALID, "a record array is NULL");
     int cur = 0, rc = current_buffer(w, &cur);
     if (rc) return rc;
