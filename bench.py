@@ -87,13 +87,21 @@ def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bo
     w = World.from_init(init, stream=stream, precision=precision)
     if tuning is not None:
         w.set_tuning(*tuning)
-    elif autotune:
-        tuning = w.autotune()
     step_index = 0
-    for _ in range(warmup):
-        w.step(1)
-        step_index += 1
-        w.radiate(RATE, SIGMA, step_index, stats=False)
+
+    def advance(n):
+        nonlocal step_index
+        for _ in range(n):
+            w.step(1)
+            step_index += 1
+            w.radiate(RATE, SIGMA, step_index, stats=False)
+
+    advance(warmup)
+    if tuning is None and autotune:
+        # tuned on a state past the first steps (which take over a large share
+        # of the random initial grid), then two more untimed steps
+        tuning = w.autotune()
+        advance(2)
     w.sync()
     w.set_profiling(True)
     torch.cuda.synchronize()

@@ -86,18 +86,14 @@ __device__ __forceinline__ int hash_find(int* s_key, int g, bool insert) {
     return -1;
 }
 
-// scatter = 0: histogram into the partial counters.  scatter = 1:
-// compaction into perm, using the cursors the scan set.  A block takes a
-// unit of kBucketGroup consecutive tiles and aggregates its counts over all
-// of them before touching global memory: one atomic per (unit, genome) on
-// the genome's cursor.  The order of a genome's cells in perm follows unit
-// and wavefront arrival, i.e. it is spatially local but not specified.  The
-// counting pass is skipped while the counts are current (the flag the scan
-// sets, and that set_state clears).
-__global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, int scatter) {
+// Genome histogram.  A block takes a unit of kBucketGroup consecutive tiles
+// and aggregates its counts over all of them before touching global memory:
+// one atomic per (unit, genome).  Genome ids are checked here (out of range,
+// unset slot).  Skipped while the counts are current: the scan sets the
+// flag, physics and radiation keep the counts current, set_state clears it.
+__global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
     __shared__ int s_key[kHashSlots];
     __shared__ int s_cnt[kHashSlots];
-    __shared__ int s_base[kHashSlots];
     constexpr int ROWS = kBucketTile / 4;  // tile rows per wavefront
     const int n = cld(&b->n_worlds);
     if (n <= 0) return;
@@ -108,7 +104,7 @@ __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, 
         const auto& w = *world_at(b, wi);
         const int cur = ctl_cur(w.ctl);
         const int64_t unit = u - cld(b->chunk_prefix + (wi));
-        if (!scatter && w.ctl->counts_valid) continue;  // block-uniform: nothing to count
+        if (w.ctl->counts_valid) continue;  // block-uniform: nothing to count
         const int32_t* G = w.G[cur];
         for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
         __syncthreads();
@@ -157,52 +153,111 @@ __global__ __launch_bounds__(256) void k_bucket(const BatchDev* __restrict__ b, 
                     const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
                     const int h = hash_find(s_key, g, true);
                     if (h >= 0) atomicAdd(&s_cnt[h], len);
-                    else if (!scatter) atomicAdd(&w.counts[g], len);
+                    else atomicAdd(&w.counts[g], len);
                 }
             }
         }
-        if (bad && !scatter) atomicOr(&w.ctl->err, bad);
+        if (bad) atomicOr(&w.ctl->err, bad);
         __syncthreads();
         // 2. one global atomic per (unit, genome)
         for (int k = threadIdx.x; k < kHashSlots; k += 256) {
             const int g = s_key[k];
             if (g < 0) continue;
-            if (!scatter) atomicAdd(&w.counts[g], s_cnt[k]);
-            else { s_base[k] = atomicAdd(&w.cursor[g], s_cnt[k]); s_cnt[k] = 0; }
+            atomicAdd(&w.counts[g], s_cnt[k]);
         }
-        if (scatter) {
-            __syncthreads();
-            // 3. positions inside each genome's range: the run's first lane
-            // reserves the run, every lane writes at run base + its offset
+        __syncthreads();  // the table is cleared for the next unit
+    }
+}
+
+// Compaction into perm in one pass over the unit.  Each run of equal
+// genomes in a tile row takes its offset inside the unit's chunk of its
+// genome with one LDS atomic (by the run's first lane, after a hash insert);
+// every cell keeps (hash slot, rank) in registers.  Then one global atomic
+// per (unit, genome) on the genome's cursor gives the chunk's base, and the
+// cells are written at base + rank with no second hash lookup.  A genome
+// that finds the table full takes its run's positions straight from the
+// global cursor.  Perm entries carry the cell's rotation in the high bits.
+static_assert(kBucketGroup * kBucketTile * kBucketTile <= (1 << 14), "ranks inside a unit take 14 bits");
+__global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b) {
+    __shared__ int s_key[kHashSlots];
+    __shared__ int s_cnt[kHashSlots];
+    __shared__ int s_base[kHashSlots];
+    constexpr int ROWS = kBucketTile / 4;  // tile rows per wavefront
+    constexpr uint32_t kAbs = 0x80000000u;  // rank field holds an absolute position
+    const int n = cld(&b->n_worlds);
+    if (n <= 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t total = cld(b->chunk_prefix + (n));
+    for (int64_t u = xcd_block(); u < total; u += gridDim.x) {
+        const int wi = find_world(b->chunk_prefix, n, u);
+        const auto& w = *world_at(b, wi);
+        const int cur = ctl_cur(w.ctl);
+        const int64_t unit = u - cld(b->chunk_prefix + (wi));
+        const int32_t* G = w.G[cur];
+        const uint8_t* Rc = w.R[cur];
+        for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
+        __syncthreads();
+        uint32_t pk[kBucketGroup][ROWS];  // (slot << 14 | rank) or (kAbs | position)
+        int tx[kBucketGroup], ty[kBucketGroup];
+        bool tile_ok[kBucketGroup];
 #pragma unroll
-            for (int tg = 0; tg < kBucketGroup; ++tg) {
-                const int x = tx[tg] * kBucketTile + lane;
+        for (int tg = 0; tg < kBucketGroup; ++tg) {
+            const int tile = (int)unit * kBucketGroup + tg;
+            tile_ok[tg] = tile < w.btiles;
+            ty[tg] = tile / w.btiles_x;
+            tx[tg] = tile - ty[tg] * w.btiles_x;
+        }
 #pragma unroll
-                for (int it = 0; it < ROWS; ++it) {
-                    const int y = ty[tg] * kBucketTile + wv + 4 * it;
-                    const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+        for (int tg = 0; tg < kBucketGroup; ++tg) {
+            const int x = tx[tg] * kBucketTile + lane;
+            int gv[ROWS];
+#pragma unroll
+            for (int it = 0; it < ROWS; ++it) {
+                const int y = ty[tg] * kBucketTile + wv + 4 * it;
+                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+                const int g = valid ? gld(G + (int64_t)y * w.W + x) : 0;
+                gv[it] = (g < 0 || g >= w.cap) ? 0 : g;  // ids were checked when counted
+            }
+#pragma unroll
+            for (int it = 0; it < ROWS; ++it) {
+                const int y = ty[tg] * kBucketTile + wv + 4 * it;
+                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+                const int g = gv[it];
+                const int prev = __shfl_up(g, 1, 64);
+                const bool start = valid && (lane == 0 || prev != g);
+                const uint64_t starts = __ballot(start);
+                const int nvalid = (int)__popcll(__ballot(valid));
+                uint32_t mine = 0;
+                if (start) {
+                    const uint64_t later = starts & ~((2ull << lane) - 1ull);
+                    const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
+                    const int h = hash_find(s_key, g, true);
+                    mine = h >= 0 ? ((uint32_t)h << 14) | (uint32_t)atomicAdd(&s_cnt[h], len)
+                                  : kAbs | (uint32_t)atomicAdd(&w.cursor[g], len);
+                }
+                const uint64_t upto = starts & ((2ull << lane) - 1ull);
+                const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
+                pk[tg][it] = __shfl(mine, rs, 64) + (uint32_t)(lane - rs);
+            }
+        }
+        __syncthreads();
+        // one global atomic per (unit, genome)
+        for (int k = threadIdx.x; k < kHashSlots; k += 256) {
+            const int g = s_key[k];
+            if (g >= 0) s_base[k] = atomicAdd(&w.cursor[g], s_cnt[k]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tg = 0; tg < kBucketGroup; ++tg) {
+            const int x = tx[tg] * kBucketTile + lane;
+#pragma unroll
+            for (int it = 0; it < ROWS; ++it) {
+                const int y = ty[tg] * kBucketTile + wv + 4 * it;
+                if (tile_ok[tg] && x < w.W && y < w.H) {
+                    const uint32_t v = pk[tg][it];
+                    const int pos = (v & kAbs) ? (int)(v & ~kAbs) : s_base[v >> 14] + (int)(v & 0x3fffu);
                     const int64_t i = (int64_t)y * w.W + x;
-                    const int g = gv[tg][it];
-                    const int prev = __shfl_up(g, 1, 64);
-                    const bool start = valid && (lane == 0 || prev != g);
-                    const uint64_t starts = __ballot(start);
-                    const int nvalid = (int)__popcll(__ballot(valid));
-                    int base = 0;
-                    if (start) {
-                        const uint64_t later = starts & ~((2ull << lane) - 1ull);
-                        const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
-                        const int h = hash_find(s_key, g, false);
-                        base = h >= 0 ? s_base[h] + atomicAdd(&s_cnt[h], len)
-                                      : atomicAdd(&w.cursor[g], len);
-                    }
-                    const uint64_t upto = starts & ((2ull << lane) - 1ull);
-                    const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
-                    const int run_base = __shfl(base, rs, 64);
-                    // the entry carries the cell's rotation in bits 26..28, so
-                    // the network kernel needs no dependent load for it
-                    if (valid)
-                        gst(w.perm + run_base + (lane - rs),
-                            (int)i | ((int)(gld(w.R[cur] + i) & 7) << kPermRotShift));
+                    gst(w.perm + pos, (int)i | ((int)(gld(Rc + i) & 7) << kPermRotShift));
                 }
             }
         }
@@ -366,14 +421,14 @@ static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
     const int cap_blocks = min(256, max(1, (ls.max_cap + 255) / 256));
     hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
-    hipLaunchKernelGGL(k_bucket, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev, 0);
+    hipLaunchKernelGGL(k_count, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
     launch_scan(bdev, ls, s);
 }
 
 void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
     launch_hist_only(bdev, ls, s);
     hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
-    hipLaunchKernelGGL(k_bucket, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev, 1);
+    hipLaunchKernelGGL(k_scatter, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
 }
 
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {

@@ -20,6 +20,22 @@
 
 namespace coralai {
 
+// counts[g] += d for every lane with `on`, one atomic per distinct genome of
+// the wavefront: takeovers cluster on a few genomes (early steps from a
+// random state take over a large share of the grid), and per-lane atomics on
+// one address would serialise.  Call with the whole wavefront converged.
+__device__ __forceinline__ void wave_count_add(int32_t* counts, int g, int d, bool on) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(on);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int gl = __shfl(g, leader, 64);
+        const uint64_t same = __ballot(on && g == gl) & pending;
+        if (lane == leader) atomicAdd(counts + gl, d * (int)__popcll(same));
+        pending &= ~same;
+    }
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict__ b) {
     constexpr int NT = TW * TH;
@@ -126,6 +142,8 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
 
         const int lx = tid % TW + 1, ly = tid / TW + 1;
         const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+        bool took = false;
+        int32_t g_from = 0, g_to = 0;
         if (gx < Wd && gy < Hd) {
             const int t = gy * Wd + gx;
             const int own = ly * LW + lx;
@@ -148,13 +166,12 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             int32_t g2 = gld(Gc + t);
             uint8_t r2 = gld(Rc + t);
             if (win >= 0 && vbest > i1) {
-                const int32_t g_old = g2;
+                g_from = g2;
                 g2 = s_g[(ly + dir_dy(win)) * LW + (lx + dir_dx(win))];
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
-                // the step's genome counts follow the takeover (radiation reads them)
-                atomicAdd(cnt + g_old, -1);
-                atomicAdd(cnt + g2, 1);
+                took = true;
+                g_to = g2;
             }
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
@@ -162,6 +179,9 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             acc_m += i2;
             acc_f += (double)i2;
         }
+        // the genome counts follow the takeovers (the next step and radiation use them)
+        wave_count_add(cnt, g_from, -1, took);
+        wave_count_add(cnt, g_to, 1, took);
         __syncthreads();  // LDS reused by the next tile
     }
     if (wi >= 0) flush();
@@ -242,6 +262,8 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             cnt = W->counts;
         }
         const int t = (int)((unit - world_lo) * 256) + tid;
+        bool took = false;
+        int32_t g_from = 0, g_to = 0;
         if (t < Nd) {  // (no divergent continue: the world fields must stay uniform)
             const int y = t / Wd, x = t - y * Wd;
             const i64x2 ei1 = buf_ld_i64x2(rei1, 16 * t);
@@ -264,13 +286,12 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             }
             const int64_t i2 = i1 - (int64_t)out + in;
             if (win >= 0 && vbest > i1) {
-                const int32_t g_old = g2;
+                g_from = g2;
                 g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * wn, 0, 0);
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
-                // the step's genome counts follow the takeover (radiation reads them)
-                atomicAdd(cnt + g_old, -1);
-                atomicAdd(cnt + g2, 1);
+                took = true;
+                g_to = g2;
             }
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
@@ -278,6 +299,9 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             acc_m += i2;
             acc_f += (double)i2;
         }
+        // the genome counts follow the takeovers (the next step and radiation use them)
+        wave_count_add(cnt, g_from, -1, took);
+        wave_count_add(cnt, g_to, 1, took);
     }
     if (wi >= 0) flush();
 }
