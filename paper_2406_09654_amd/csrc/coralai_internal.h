@@ -322,6 +322,9 @@ void launch_ledger_pack(const int64_t* e, int e_stride, const int64_t* v, int v_
 void launch_ledger_unpack(const int64_t* src, int64_t* e, int64_t* v, int64_t n, hipStream_t s);
 
 int phys_tile_w(int t);
+// cells per 256-thread unit of the streaming physics: 4 per thread when the
+// width is a multiple of 4 (aligned 16-byte plane loads), else 1
+inline int phys_stream_cells(int W) { return (W & 3) == 0 ? 1024 : 256; }
 int phys_tile_h(int t);
 
 }  // namespace coralai

@@ -261,6 +261,81 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
             cnt = W->counts;
         }
+        if ((Wd & 3) == 0) {
+            // four consecutive cells of one row per thread.  For direction d
+            // the inflow words come from plane (d+4) mod 8 at the four cells
+            // shifted by (dx, dy): the aligned 16-byte vector of the group's
+            // columns in row y+dy, plus, for dx = +-1, the one word beyond
+            // the group's edge (wrapping around the row).
+            const int t0 = (int)((unit - world_lo) * 1024) + 4 * tid;
+            bool took[4] = {false, false, false, false};
+            int32_t g_from[4] = {0, 0, 0, 0}, g_to[4] = {0, 0, 0, 0};
+            if (t0 < Nd) {
+                const int y = t0 / Wd, x0 = t0 - y * Wd;
+                const int row[3] = {(y == 0 ? Hd - 1 : y - 1) * Wd, y * Wd, (y == Hd - 1 ? 0 : y + 1) * Wd};
+                const int xl = x0 == 0 ? Wd - 1 : x0 - 1, xr = x0 + 4 == Wd ? 0 : x0 + 4;
+                uint32_t fw[8][4];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int dx = dir_dx(d), base = row[dir_dy(d) + 1];
+                    const __amdgpu_buffer_rsrc_t rp = rflow[(d + 4) & 7];
+                    const coralai_u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rp, 4 * (base + x0), 0, 0);
+                    if (dx == 0) {
+                        fw[d][0] = a[0]; fw[d][1] = a[1]; fw[d][2] = a[2]; fw[d][3] = a[3];
+                    } else if (dx > 0) {
+                        const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rp, 4 * (base + xr), 0, 0);
+                        fw[d][0] = a[1]; fw[d][1] = a[2]; fw[d][2] = a[3]; fw[d][3] = e;
+                    } else {
+                        const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rp, 4 * (base + xl), 0, 0);
+                        fw[d][0] = e; fw[d][1] = a[0]; fw[d][2] = a[1]; fw[d][3] = a[2];
+                    }
+                }
+                i64x2 ei1[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ei1[j] = buf_ld_i64x2(rei1, 16 * (t0 + j));
+                const coralai_u32x4 outs = __builtin_amdgcn_raw_buffer_load_b128(rout, 4 * t0, 0, 0);
+                coralai_u32x4 gs = __builtin_amdgcn_raw_buffer_load_b128(rg, 4 * t0, 0, 0);
+                uint32_t rs = __builtin_amdgcn_raw_buffer_load_b32(rr, t0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int64_t in = 0, vbest = -1;
+                    int win = -1;
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        const uint32_t word = fw[d][j];
+                        const int64_t v = word >> 1;
+                        in += v;
+                        if ((word & 1u) && v > vbest) { vbest = v; win = d; }
+                    }
+                    const int64_t e1 = ei1[j][0], i1 = ei1[j][1];
+                    const int64_t i2 = i1 - (int64_t)outs[j] + in;
+                    if (win >= 0 && vbest > i1) {
+                        const int x = x0 + j;
+                        int nx = x + dir_dx(win);
+                        nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
+                        const int n = row[dir_dy(win) + 1] + nx;
+                        g_from[j] = (int32_t)gs[j];
+                        gs[j] = __builtin_amdgcn_raw_buffer_load_b32(rg, 4 * n, 0, 0);
+                        g_to[j] = (int32_t)gs[j];
+                        rs = (rs & ~(0xffu << (8 * j))) | ((uint32_t)((win + 4) & 7) << (8 * j));
+                        took[j] = true;
+                        acc_t += 1;
+                    }
+                    gst((i64x2*)EIn + t0 + j, i64x2{e1, i2});
+                    acc_m += i2;
+                    acc_f += (double)i2;
+                }
+                gst((coralai_u32x4*)Gn + t0 / 4, gs);
+                gst((uint32_t*)Rn + t0 / 4, rs);
+            }
+            // the genome counts follow the takeovers (the next step and radiation use them)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                wave_count_add(cnt, g_from[j], -1, took[j]);
+                wave_count_add(cnt, g_to[j], 1, took[j]);
+            }
+            continue;
+        }
         const int t = (int)((unit - world_lo) * 256) + tid;
         bool took = false;
         int32_t g_from = 0, g_to = 0;

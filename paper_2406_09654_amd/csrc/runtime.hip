@@ -202,9 +202,10 @@ struct coralai_batch {
 namespace {
 
 int tiles_for(int W, int H, int phys_tile, int* tx) {
-    if (phys_tile == 3) {  // streaming physics: 256-cell linear units
+    if (phys_tile == 3) {  // streaming physics: linear units of 256 threads
         *tx = 0;
-        return (int)(((int64_t)W * H + 255) / 256);
+        const int64_t cells = (int64_t)W * H, per = phys_stream_cells(W);
+        return (int)((cells + per - 1) / per);
     }
     const int tw = phys_tile_w(phys_tile), th = phys_tile_h(phys_tile);
     *tx = (W + tw - 1) / tw;

@@ -98,7 +98,9 @@ def test_actuators_match_oracle_fp32(stream, W, H, layers, hidden, act_cells):
 def test_physics_from_oracle_records_is_bit_exact(stream):
     say("physics from records")
     for (W, H, tile) in [(37, 23, 0), (64, 64, 1), (70, 33, 2), (1, 1, 0), (2, 2, 1), (3, 5, 2),
-                         (37, 23, 3), (1, 1, 3), (2, 3, 3), (130, 67, 3)]:
+                         (37, 23, 3), (1, 1, 3), (2, 3, 3), (130, 67, 3),
+                         # widths divisible by 4 take four cells per thread (row wrap at both ends)
+                         (4, 1, 3), (4, 4, 3), (8, 3, 3), (64, 64, 3), (128, 33, 3)]:
         init = gh.heterogeneous_world(W, H, n_genomes=4, seed=W * 7 + H)
         d = gh.oracle_desc(init.spec)
         s = oracle.State.from_init(init)
@@ -238,8 +240,9 @@ def test_translation_invariance_bit_identical(stream):
         w.close()
 
 
-def test_tuning_choices_and_graph_give_identical_results(stream):
-    init = gh.heterogeneous_world(150, 90, n_genomes=9, layers=3, hidden=64, seed=5)
+@pytest.mark.parametrize("W", [150, 152])
+def test_tuning_choices_and_graph_give_identical_results(stream, W):
+    init = gh.heterogeneous_world(W, 90, n_genomes=9, layers=3, hidden=64, seed=5)
     outs = []
     for act, waves, tile, strm in [(1, 0, 0, stream), (2, 1, 1, stream), (4, 0, 2, None),
                                    (2, 0, 0, None), (2, 1, 3, stream), (1, 1, 3, None),
