@@ -18,6 +18,7 @@ constexpr int kPermIndexMask = (1 << kPermRotShift) - 1;
 constexpr int kGroupCells = 64;   // cells per network work unit (one wavefront)
 constexpr int kBucketTile = 64;   // bucketing tile: 64 x 64 cells
 constexpr int kBucketGroup = 4;   // tiles per bucketing unit (one block)
+constexpr int kStripes = 8;       // genome counts and cursors split by bucketing unit (unit mod 8)
 constexpr int kSlotBlock = 4096;  // genome slots per scan block
 constexpr int kRadBlockCells = 4096;  // cells per radiation hit block (256 x 16)
 constexpr int kPrecFP32 = 0;
@@ -66,9 +67,11 @@ struct WorldDev {
     int64_t* EI1;         // [N][2]: energy and infrastructure after invest / liquidate
     uint32_t* out;        // total outflow of the cell
     int32_t* perm;        // cells grouped by genome
-    int32_t* counts;      // [cap] cells per genome (kept current by physics and radiation)
+    int32_t* counts;      // [cap] cells per genome (sum of the stripes)
     int32_t* offsets;     // [cap + 1]
-    int32_t* cursor;      // [cap] next free position of each genome's range (scatter)
+    int32_t* stripe_counts; // [kStripes][cap] cells per genome in the units of each stripe
+                            // (kept current by physics and radiation)
+    int32_t* cursor;      // [kStripes][cap] next free position of each stripe's range (scatter)
     int32_t* gofs;        // [cap + 1] exclusive prefix of network units per genome
     uint8_t* slot_set;    // [cap]
     float* params;        // [cap][56]
@@ -191,6 +194,12 @@ __device__ __forceinline__ int dir_dy(int d) { return (int)((0x491001u >> (d * 3
 __device__ __forceinline__ int kernel_dir(int r, int p) {
     // offsets {0, +1, -1, +2, -2, +3, -3, +4} packed as (off & 7) in 3 bits
     return (r + (int)((0x95e5c8u >> (p * 3 - 3)) & 7)) & 7;
+}
+
+// Stripe of a cell: its bucketing unit (kBucketGroup consecutive 64 x 64
+// tiles in row-major tile order) mod kStripes.
+__device__ __forceinline__ int cell_stripe(int x, int y, int btiles_x) {
+    return ((y / kBucketTile * btiles_x + x / kBucketTile) / kBucketGroup) & (kStripes - 1);
 }
 
 __device__ __forceinline__ int wrap(int v, int n) {

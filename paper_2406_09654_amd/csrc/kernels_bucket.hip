@@ -62,7 +62,8 @@ __global__ __launch_bounds__(256) void k_prep(const BatchDev* __restrict__ b) {
     if (wi >= b->n_worlds) return;
     const auto& w = *world_at(b, wi);
     if (!w.ctl->counts_valid)
-        for (int g = blockIdx.x * 256 + threadIdx.x; g < w.cap; g += gridDim.x * 256) w.counts[g] = 0;
+        for (int g = blockIdx.x * 256 + threadIdx.x; g < kStripes * w.cap; g += gridDim.x * 256)
+            w.stripe_counts[g] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         w.ctl->acc_mass = 0;
         w.ctl->acc_mass_f64 = 0.0;
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
         const int cur = ctl_cur(w.ctl);
         const int64_t unit = u - cld(b->chunk_prefix + (wi));
         if (w.ctl->counts_valid) continue;  // block-uniform: nothing to count
+        int32_t* scount = w.stripe_counts + (int64_t)(unit & (kStripes - 1)) * w.cap;
         const int32_t* G = w.G[cur];
         for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
         __syncthreads();
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
                     const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
                     const int h = hash_find(s_key, g, true);
                     if (h >= 0) atomicAdd(&s_cnt[h], len);
-                    else atomicAdd(&w.counts[g], len);
+                    else atomicAdd(scount + g, len);
                 }
             }
         }
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
         for (int k = threadIdx.x; k < kHashSlots; k += 256) {
             const int g = s_key[k];
             if (g < 0) continue;
-            atomicAdd(&w.counts[g], s_cnt[k]);
+            atomicAdd(scount + g, s_cnt[k]);
         }
         __syncthreads();  // the table is cleared for the next unit
     }
@@ -178,12 +180,13 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
 // that finds the table full takes its run's positions straight from the
 // global cursor.  Perm entries carry the cell's rotation in the high bits.
 static_assert(kBucketGroup * kBucketTile * kBucketTile <= (1 << 14), "ranks inside a unit take 14 bits");
-__global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b) {
+__global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__ b) {
     __shared__ int s_key[kHashSlots];
     __shared__ int s_cnt[kHashSlots];
     __shared__ int s_base[kHashSlots];
     constexpr int ROWS = kBucketTile / 4;  // tile rows per wavefront
-    constexpr uint32_t kAbs = 0x80000000u;  // rank field holds an absolute position
+    constexpr uint32_t kAbs = 0x80000000u;  // bits 0..25 hold an absolute position
+    // packed per cell: rotation << 26 | (kAbs | position  or  slot << 14 | rank)
     const int n = cld(&b->n_worlds);
     if (n <= 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -195,9 +198,10 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
         const int64_t unit = u - cld(b->chunk_prefix + (wi));
         const int32_t* G = w.G[cur];
         const uint8_t* Rc = w.R[cur];
+        int32_t* scur = w.cursor + (int64_t)(unit & (kStripes - 1)) * w.cap;
         for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
         __syncthreads();
-        uint32_t pk[kBucketGroup][ROWS];  // (slot << 14 | rank) or (kAbs | position)
+        uint32_t pk[kBucketGroup][ROWS];
         int tx[kBucketGroup], ty[kBucketGroup];
         bool tile_ok[kBucketGroup];
 #pragma unroll
@@ -211,11 +215,14 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
         for (int tg = 0; tg < kBucketGroup; ++tg) {
             const int x = tx[tg] * kBucketTile + lane;
             int gv[ROWS];
+            uint32_t rv[ROWS];
 #pragma unroll
             for (int it = 0; it < ROWS; ++it) {
                 const int y = ty[tg] * kBucketTile + wv + 4 * it;
                 const bool valid = tile_ok[tg] && x < w.W && y < w.H;
-                const int g = valid ? gld(G + (int64_t)y * w.W + x) : 0;
+                const int64_t i = (int64_t)y * w.W + x;
+                const int g = valid ? gld(G + i) : 0;
+                rv[it] = valid ? (uint32_t)(gld(Rc + i) & 7) : 0u;
                 gv[it] = (g < 0 || g >= w.cap) ? 0 : g;  // ids were checked when counted
             }
 #pragma unroll
@@ -233,18 +240,19 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
                     const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
                     const int h = hash_find(s_key, g, true);
                     mine = h >= 0 ? ((uint32_t)h << 14) | (uint32_t)atomicAdd(&s_cnt[h], len)
-                                  : kAbs | (uint32_t)atomicAdd(&w.cursor[g], len);
+                                  : kAbs | (uint32_t)atomicAdd(scur + g, len);
                 }
                 const uint64_t upto = starts & ((2ull << lane) - 1ull);
                 const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
-                pk[tg][it] = __shfl(mine, rs, 64) + (uint32_t)(lane - rs);
+                pk[tg][it] = (__shfl(mine, rs, 64) + (uint32_t)(lane - rs)) | (rv[it] << kPermRotShift);
             }
+            __builtin_amdgcn_sched_barrier(0);  // one tile's loads in flight at a time (registers)
         }
         __syncthreads();
         // one global atomic per (unit, genome)
         for (int k = threadIdx.x; k < kHashSlots; k += 256) {
             const int g = s_key[k];
-            if (g >= 0) s_base[k] = atomicAdd(&w.cursor[g], s_cnt[k]);
+            if (g >= 0) s_base[k] = atomicAdd(scur + g, s_cnt[k]);
         }
         __syncthreads();
 #pragma unroll
@@ -255,9 +263,10 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
                 const int y = ty[tg] * kBucketTile + wv + 4 * it;
                 if (tile_ok[tg] && x < w.W && y < w.H) {
                     const uint32_t v = pk[tg][it];
-                    const int pos = (v & kAbs) ? (int)(v & ~kAbs) : s_base[v >> 14] + (int)(v & 0x3fffu);
+                    const int pos = (v & kAbs) ? (int)(v & (uint32_t)kPermIndexMask)
+                                               : s_base[(v >> 14) & 0x7ffu] + (int)(v & 0x3fffu);
                     const int64_t i = (int64_t)y * w.W + x;
-                    gst(w.perm + pos, (int)i | ((int)(gld(Rc + i) & 7) << kPermRotShift));
+                    gst(w.perm + pos, (int)i | (int)(v & (7u << kPermRotShift)));
                 }
             }
         }
@@ -282,7 +291,10 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict_
         for (int k = 0; k < kSlotBlock / 256; ++k) {
             const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
             if (g < w.cap) {
-                const int v = w.counts[g];
+                int v = 0;
+#pragma unroll
+                for (int q = 0; q < kStripes; ++q) v += w.stripe_counts[q * w.cap + g];
+                w.counts[g] = v;
                 c += v;
                 gsum += (v + kGroupCells - 1) / kGroupCells;
                 live += v > 0;
@@ -367,7 +379,12 @@ __global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__
             if (g >= w.cap) break;
             const int v = w.counts[g];
             w.offsets[g] = oc;
-            w.cursor[g] = oc;
+            int pos = oc;
+#pragma unroll
+            for (int q = 0; q < kStripes; ++q) {
+                w.cursor[q * w.cap + g] = pos;
+                pos += w.stripe_counts[q * w.cap + g];
+            }
             w.gofs[g] = og;
             if (v == 0) w.free_list[of++] = g;
             oc += v;
@@ -419,7 +436,7 @@ static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t
 }
 
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
-    const int cap_blocks = min(256, max(1, (ls.max_cap + 255) / 256));
+    const int cap_blocks = min(256, max(1, (kStripes * ls.max_cap + 255) / 256));
     hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
     hipLaunchKernelGGL(k_count, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
     launch_scan(bdev, ls, s);

@@ -305,8 +305,11 @@ __global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__
                 hit_parent[rank] = parent;
                 G[i] = slot;
                 w->slot_set[slot] = 1;
-                atomicAdd(w->counts + parent, -1);  // the counts stay current
-                atomicAdd(w->counts + slot, 1);
+                // the stripe counts stay current
+                const int cy = i / w->W, cx = i - cy * w->W;
+                int32_t* sc = w->stripe_counts + (int64_t)cell_stripe(cx, cy, w->btiles_x) * w->cap;
+                atomicAdd(sc + parent, -1);
+                atomicAdd(sc + slot, 1);
             }
             ++rank;
         }

@@ -20,10 +20,11 @@
 
 namespace coralai {
 
-// counts[g] += d for every lane with `on`, one atomic per distinct genome of
-// the wavefront: takeovers cluster on a few genomes (early steps from a
-// random state take over a large share of the grid), and per-lane atomics on
-// one address would serialise.  Call with the whole wavefront converged.
+// counts[g] += d for every lane with `on`, one atomic per distinct index of
+// the wavefront (index = stripe * capacity + genome): takeovers cluster on a
+// few genomes (early steps from a random state take over a large share of
+// the grid), and per-lane atomics on one address would serialise.  Call with
+// the whole wavefront converged.
 __device__ __forceinline__ void wave_count_add(int32_t* counts, int g, int d, bool on) {
     const int lane = threadIdx.x & 63;
     uint64_t pending = __ballot(on);
@@ -99,7 +100,8 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
-    int32_t* cnt = nullptr;
+    int32_t* cnt = nullptr;  // stripe counts
+    int capw = 0, btx = 1;
 
     for (; tile < tend; ++tile) {
         if (tile >= world_hi) {
@@ -115,7 +117,9 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             flow = W->flow; EI1p = W->EI1;
             Gc = W->G[cur]; Rc = W->R[cur];
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
-            cnt = W->counts;
+            cnt = W->stripe_counts;
+            capw = W->cap;
+            btx = W->btiles_x;
         }
         const int64_t lt = tile - world_lo;
         const int ty = (int)(lt / tx_n), tx = (int)(lt - (int64_t)ty * tx_n);
@@ -166,12 +170,13 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             int32_t g2 = gld(Gc + t);
             uint8_t r2 = gld(Rc + t);
             if (win >= 0 && vbest > i1) {
-                g_from = g2;
+                const int so = cell_stripe(gx, gy, btx) * capw;
+                g_from = so + g2;
                 g2 = s_g[(ly + dir_dy(win)) * LW + (lx + dir_dx(win))];
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
                 took = true;
-                g_to = g2;
+                g_to = so + g2;
             }
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
@@ -210,7 +215,8 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     Ctl* ctl = nullptr;
     int Wd = 0, Hd = 0, Nd = 0;
     __amdgpu_buffer_rsrc_t rflow[8], rout, rei1, rg, rr;
-    int32_t* cnt = nullptr;
+    int32_t* cnt = nullptr;  // stripe counts
+    int capw = 0, btx = 1;
     int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
@@ -259,7 +265,9 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             rg = buf_rsrc(W->G[cur], n4);
             rr = buf_rsrc(W->R[cur], (uint32_t)Nd);
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
-            cnt = W->counts;
+            cnt = W->stripe_counts;
+            capw = W->cap;
+            btx = W->btiles_x;
         }
         if ((Wd & 3) == 0) {
             // four consecutive cells of one row per thread.  For direction d
@@ -314,9 +322,10 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                         int nx = x + dir_dx(win);
                         nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
                         const int n = row[dir_dy(win) + 1] + nx;
-                        g_from[j] = (int32_t)gs[j];
+                        const int so = cell_stripe(x, y, btx) * capw;
+                        g_from[j] = so + (int32_t)gs[j];
                         gs[j] = __builtin_amdgcn_raw_buffer_load_b32(rg, 4 * n, 0, 0);
-                        g_to[j] = (int32_t)gs[j];
+                        g_to[j] = so + (int32_t)gs[j];
                         rs = (rs & ~(0xffu << (8 * j))) | ((uint32_t)((win + 4) & 7) << (8 * j));
                         took[j] = true;
                         acc_t += 1;
@@ -361,12 +370,13 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             }
             const int64_t i2 = i1 - (int64_t)out + in;
             if (win >= 0 && vbest > i1) {
-                g_from = g2;
+                const int so = cell_stripe(x, y, btx) * capw;
+                g_from = so + g2;
                 g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * wn, 0, 0);
                 r2 = (uint8_t)((win + 4) & 7);
                 acc_t += 1;
                 took = true;
-                g_to = g2;
+                g_to = so + g2;
             }
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);

@@ -47,7 +47,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t EI[2], C[2], G[2], R[2];
     size_t flow, EI1, out, perm;
-    size_t counts, offsets, cursor, gofs, slot_set, params, wfrag, bias;
+    size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
     size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
     int n_slot_blocks;
@@ -89,7 +89,8 @@ Layout make_layout(const coralai_world_desc* d) {
     L.perm = take(4 * N);
     L.counts = take(4 * cap);
     L.offsets = take(4 * (cap + 1));
-    L.cursor = take(4 * cap);
+    L.stripe_counts = take(4 * kStripes * cap);
+    L.cursor = take(4 * kStripes * cap);
     L.gofs = take(4 * (cap + 1));
     L.slot_set = take(cap);
     L.params = take(4 * kNParam * cap);
@@ -408,6 +409,7 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     h.perm = (int32_t*)(b + L.perm);
     h.counts = (int32_t*)(b + L.counts);
     h.offsets = (int32_t*)(b + L.offsets);
+    h.stripe_counts = (int32_t*)(b + L.stripe_counts);
     h.cursor = (int32_t*)(b + L.cursor);
     h.gofs = (int32_t*)(b + L.gofs);
     h.slot_set = (uint8_t*)(b + L.slot_set);
