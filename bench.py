@@ -60,23 +60,27 @@ def act_sources_sha256() -> str:
 def act_traffic(tuning):
     """HBM bytes per launch of the BF16 network kernel from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy
-    calibration).  None when the summary is missing, was taken for another
-    launch configuration, or the kernel's sources changed since."""
+    calibration), for the launch configuration the bench ran.  None when the
+    summary is missing, has no line for that configuration, or the kernel's
+    sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
-    fields = {}
+    want = ",".join(str(v) for v in tuning) if tuning is not None else None
+    stale = False
     with open(TRAFFIC_FILE) as f:
         for line in f:
-            if line.startswith("traffic:"):
-                for kv in line.split()[1:]:
-                    k, _, v = kv.partition("=")
-                    fields[k] = v
-    if fields.get("source_sha256") != act_sources_sha256():
-        return None, "kernel changed since the counters were taken"
-    if tuning is not None and fields.get("tuning") != ",".join(str(v) for v in tuning):
-        return None, "counters taken for tuning %s" % fields.get("tuning")
-    return int(fields["bytes_per_launch"]), "FETCH_SIZE x %s + WRITE_SIZE x %s per launch, %s" % (
-        fields.get("fetch_factor"), fields.get("write_factor"), os.path.relpath(TRAFFIC_FILE, ROOT))
+            if not line.startswith("traffic:"):
+                continue
+            fields = dict(kv.partition("=")[::2] for kv in line.split()[1:])
+            if fields.get("tuning") != want:
+                continue
+            if fields.get("source_sha256") != act_sources_sha256():
+                stale = True
+                continue
+            return int(fields["bytes_per_launch"]), "FETCH_SIZE x %s + WRITE_SIZE x %s per launch, %s" % (
+                fields.get("fetch_factor"), fields.get("write_factor"), os.path.relpath(TRAFFIC_FILE, ROOT))
+    return None, ("kernel changed since the counters were taken" if stale
+                  else "no counters for tuning %s" % want)
 
 
 def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bool, tuning=None):
