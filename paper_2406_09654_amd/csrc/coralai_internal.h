@@ -19,7 +19,7 @@ constexpr int kGroupCells = 64;   // cells per network work unit (one wavefront)
 constexpr int kBucketTile = 64;   // bucketing tile: 64 x 64 cells
 constexpr int kBucketGroup = 4;   // tiles per bucketing unit (one block)
 constexpr int kStripes = 8;       // genome counts and cursors split by bucketing unit (unit mod 8)
-constexpr int kSlotBlock = 4096;  // genome slots per scan block
+constexpr int kSlotBlock = 512;   // genome slots per scan block (<= 8192 blocks at 2^22 slots)
 constexpr int kRadBlockCells = 4096;  // cells per radiation hit block (256 x 16)
 constexpr int kPrecFP32 = 0;
 constexpr int kPrecBF16 = 1;
@@ -313,7 +313,7 @@ void launch_act_only(const BatchDev* bdev, const LaunchShape& ls, int NL, int HI
 void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
                          hipStream_t s);
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
-void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
+void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only);
 void launch_cppn(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s);
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,

@@ -327,15 +327,20 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict
     const auto& w = *world_at(b, wi);
     const int nb = w.n_slot_blocks;
     const int t = threadIdx.x;
+    // n_slot_blocks <= 8192: up to 8 consecutive partials per thread
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
     int tot[4];
-    int pre[4];
     for (int f = 0; f < 4; ++f) {
-        // n_slot_blocks <= 1024: one partial per thread
-        const int v = t < nb ? w.scan_part[t * 4 + f] : 0;
-        pre[f] = block_exclusive_scan<1024>(v, &tot[f], s_tmp);
+        int sum = 0;
+        for (int k = b0; k < b1; ++k) sum += w.scan_part[k * 4 + f];
+        int run = block_exclusive_scan<1024>(sum, &tot[f], s_tmp);
+        for (int k = b0; k < b1; ++k) {
+            const int v = w.scan_part[k * 4 + f];
+            w.scan_part[k * 4 + f] = run;
+            run += v;
+        }
     }
-    if (t < nb)
-        for (int f = 0; f < 4; ++f) w.scan_part[t * 4 + f] = pre[f];
     if (t == 0) {
         w.ctl->counts_valid = 1;
         w.offsets[w.cap] = tot[0];
@@ -349,7 +354,8 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict
 // Pass C: per 4096-slot block, the exclusive scans themselves (256 slots per
 // round, block-wide scan, running carry), the partial ranges of each genome
 // laid out one after another, plus the free-slot list.
-__global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__ b) {
+// free_only: just the free-slot list (radiation), not the step's ranges.
+__global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__ b, int free_only) {
     __shared__ int s_tmp[4];
     const int n = cld(&b->n_worlds);
     if (n <= 0) return;
@@ -378,6 +384,10 @@ __global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__
             const int g = g0 + k;
             if (g >= w.cap) break;
             const int v = w.counts[g];
+            if (free_only) {
+                if (v == 0) w.free_list[of++] = g;
+                continue;
+            }
             w.offsets[g] = oc;
             int pos = oc;
 #pragma unroll
@@ -429,21 +439,21 @@ __global__ void k_flip(const BatchDev* __restrict__ b) {
     b->worlds[wi].ctl->cur ^= 1;
 }
 
-static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
+static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(ls.misc_blocks), dim3(256), 0, s, bdev);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1, ls.max_worlds), dim3(1024), 0, s, bdev);
-    hipLaunchKernelGGL(k_scan_write, dim3(ls.misc_blocks), dim3(256), 0, s, bdev);
+    hipLaunchKernelGGL(k_scan_write, dim3(ls.misc_blocks), dim3(256), 0, s, bdev, free_only);
 }
 
-void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
+void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only) {
     const int cap_blocks = min(256, max(1, (kStripes * ls.max_cap + 255) / 256));
     hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
     hipLaunchKernelGGL(k_count, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
-    launch_scan(bdev, ls, s);
+    launch_scan(bdev, ls, s, free_only);
 }
 
 void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
-    launch_hist_only(bdev, ls, s);
+    launch_hist_only(bdev, ls, s, 0);
     hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
     hipLaunchKernelGGL(k_scatter, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
 }

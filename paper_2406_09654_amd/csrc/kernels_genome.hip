@@ -372,7 +372,7 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
     // free slots of the current state (the completed step's result), listed by
     // the slot scan; the counting pass inside runs only if the counts are not
     // current (right after a step they are)
-    launch_hist_only(bdev, ls, s);
+    launch_hist_only(bdev, ls, s, 1);
     const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
     hipLaunchKernelGGL(k_rad_hits, dim3(hb), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
