@@ -22,6 +22,7 @@
 namespace coralai {
 
 constexpr int kHashSlots = 2048;
+constexpr int kScatterStrip = 16;  // strip width of the scatter's walk over a tile
 constexpr int kHashProbes = 64;
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
@@ -171,25 +172,36 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
     }
 }
 
-// Compaction into perm in one pass over the unit.  Each run of equal
-// genomes in a tile row takes its offset inside the unit's chunk of its
-// genome with one LDS atomic (by the run's first lane, after a hash insert);
-// every cell keeps (hash slot, rank) in registers.  Then one global atomic
-// per (unit, genome) on the genome's cursor gives the chunk's base, and the
-// cells are written at base + rank with no second hash lookup.  A genome
-// that finds the table full takes its run's positions straight from the
-// global cursor.  Perm entries carry the cell's rotation in the high bits.
-static_assert(kBucketGroup * kBucketTile * kBucketTile <= (1 << 14), "ranks inside a unit take 14 bits");
+// Compaction into perm in one pass over the unit (kBucketGroup tiles, one
+// wavefront per 64 x 64 tile).  A wavefront walks its tile in SW-column
+// strips, 64/SW rows of a strip per instruction, so that a genome's cells of
+// the tile come strip by strip: with SW = 16 the network kernel's 64-cell
+// groups are compact 16 x 4 blocks of a patch, whose neighbourhoods overlap
+// (32- and 64-wide strips measured the same step time, the 16-wide walk the
+// cheapest scatter).  Each run of equal genomes in an SW-cell row segment
+// takes its rank inside the tile's
+// share of its genome with one LDS atomic on the wavefront's own counter
+// (after a hash insert); every cell keeps (slot, rank, rotation) in a
+// register.  Then per genome: the tiles' shares are laid out one after
+// another behind one global atomic on the unit's stripe cursor, and the cells
+// are written with no second lookup.  A genome that finds the table full
+// takes its run's positions straight from the cursor.  Perm entries carry
+// the cell's rotation in the high bits.
+static_assert(kBucketGroup == 4 && kBucketTile == 64, "one wavefront per 64 x 64 tile");
+template <int SW>  // strip width: 16, 32 or 64 columns
 __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__ b) {
+    constexpr int NS = 64 / SW;        // strips per tile
+    constexpr int RPI = 64 / SW;       // rows per instruction
+    constexpr int NIT = 64 / RPI;      // instructions per strip
     __shared__ int s_key[kHashSlots];
-    __shared__ int s_cnt[kHashSlots];
-    __shared__ int s_base[kHashSlots];
-    constexpr int ROWS = kBucketTile / 4;  // tile rows per wavefront
+    __shared__ int s_cnt[kBucketGroup][kHashSlots];  // per tile: cells so far, then the tile's base
     constexpr uint32_t kAbs = 0x80000000u;  // bits 0..25 hold an absolute position
-    // packed per cell: rotation << 26 | (kAbs | position  or  slot << 14 | rank)
+    // packed per cell: rotation << 26 | (kAbs | position  or  slot << 12 | rank in the tile)
     const int n = cld(&b->n_worlds);
     if (n <= 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane % SW, rsub = lane / SW;
+    const uint64_t segmask = (SW == 64 ? ~0ull : ((1ull << SW) - 1ull)) << (SW * rsub);
     const int64_t total = cld(b->chunk_prefix + (n));
     for (int64_t u = xcd_block(); u < total; u += gridDim.x) {
         const int wi = find_world(b->chunk_prefix, n, u);
@@ -199,72 +211,79 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
         const int32_t* G = w.G[cur];
         const uint8_t* Rc = w.R[cur];
         int32_t* scur = w.cursor + (int64_t)(unit & (kStripes - 1)) * w.cap;
-        for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
-        __syncthreads();
-        uint32_t pk[kBucketGroup][ROWS];
-        int tx[kBucketGroup], ty[kBucketGroup];
-        bool tile_ok[kBucketGroup];
+        for (int k = threadIdx.x; k < kHashSlots; k += 256) {
+            s_key[k] = -1;
 #pragma unroll
-        for (int tg = 0; tg < kBucketGroup; ++tg) {
-            const int tile = (int)unit * kBucketGroup + tg;
-            tile_ok[tg] = tile < w.btiles;
-            ty[tg] = tile / w.btiles_x;
-            tx[tg] = tile - ty[tg] * w.btiles_x;
+            for (int t = 0; t < kBucketGroup; ++t) s_cnt[t][k] = 0;
         }
+        __syncthreads();
+        const int tile = (int)unit * kBucketGroup + wv;
+        const bool tile_ok = tile < w.btiles;
+        const int ty = tile / w.btiles_x, tx = tile - ty * w.btiles_x;
+        uint32_t pk[NS][NIT];
 #pragma unroll
-        for (int tg = 0; tg < kBucketGroup; ++tg) {
-            const int x = tx[tg] * kBucketTile + lane;
-            int gv[ROWS];
-            uint32_t rv[ROWS];
+        for (int st = 0; st < NS; ++st) {
+            const int x = tx * kBucketTile + SW * st + col;
+            int gv[NIT];
+            uint32_t rv[NIT];
 #pragma unroll
-            for (int it = 0; it < ROWS; ++it) {
-                const int y = ty[tg] * kBucketTile + wv + 4 * it;
-                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+            for (int it = 0; it < NIT; ++it) {
+                const int y = ty * kBucketTile + RPI * it + rsub;
+                const bool valid = tile_ok && x < w.W && y < w.H;
                 const int64_t i = (int64_t)y * w.W + x;
                 const int g = valid ? gld(G + i) : 0;
                 rv[it] = valid ? (uint32_t)(gld(Rc + i) & 7) : 0u;
                 gv[it] = (g < 0 || g >= w.cap) ? 0 : g;  // ids were checked when counted
             }
 #pragma unroll
-            for (int it = 0; it < ROWS; ++it) {
-                const int y = ty[tg] * kBucketTile + wv + 4 * it;
-                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+            for (int it = 0; it < NIT; ++it) {
+                const int y = ty * kBucketTile + RPI * it + rsub;
+                const bool valid = tile_ok && x < w.W && y < w.H;
                 const int g = gv[it];
                 const int prev = __shfl_up(g, 1, 64);
-                const bool start = valid && (lane == 0 || prev != g);
+                // runs of equal genomes inside each SW-cell row segment (valid lanes are a
+                // prefix of their segment)
+                const bool start = valid && (col == 0 || prev != g);
                 const uint64_t starts = __ballot(start);
-                const int nvalid = (int)__popcll(__ballot(valid));
+                const uint64_t vmask = __ballot(valid);
                 uint32_t mine = 0;
                 if (start) {
-                    const uint64_t later = starts & ~((2ull << lane) - 1ull);
-                    const int len = (later ? __ffsll((unsigned long long)later) - 1 : nvalid) - lane;
+                    const uint64_t later = starts & ~((2ull << lane) - 1ull) & segmask;
+                    const int seg_end = SW * rsub + (int)__popcll(vmask & segmask);
+                    const int len = (later ? __ffsll((unsigned long long)later) - 1 : seg_end) - lane;
                     const int h = hash_find(s_key, g, true);
-                    mine = h >= 0 ? ((uint32_t)h << 14) | (uint32_t)atomicAdd(&s_cnt[h], len)
+                    mine = h >= 0 ? ((uint32_t)h << 12) | (uint32_t)atomicAdd(&s_cnt[wv][h], len)
                                   : kAbs | (uint32_t)atomicAdd(scur + g, len);
                 }
                 const uint64_t upto = starts & ((2ull << lane) - 1ull);
                 const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
-                pk[tg][it] = (__shfl(mine, rs, 64) + (uint32_t)(lane - rs)) | (rv[it] << kPermRotShift);
+                pk[st][it] = (__shfl(mine, rs, 64) + (uint32_t)(lane - rs)) | (rv[it] << kPermRotShift);
             }
-            __builtin_amdgcn_sched_barrier(0);  // one tile's loads in flight at a time (registers)
+            __builtin_amdgcn_sched_barrier(0);  // one strip's loads in flight at a time (registers)
         }
         __syncthreads();
-        // one global atomic per (unit, genome)
+        // per genome: one global atomic; the tiles' shares laid out in tile order
         for (int k = threadIdx.x; k < kHashSlots; k += 256) {
             const int g = s_key[k];
-            if (g >= 0) s_base[k] = atomicAdd(scur + g, s_cnt[k]);
+            if (g < 0) continue;
+            int c[kBucketGroup], tot = 0;
+#pragma unroll
+            for (int t = 0; t < kBucketGroup; ++t) { c[t] = s_cnt[t][k]; tot += c[t]; }
+            int base = atomicAdd(scur + g, tot);
+#pragma unroll
+            for (int t = 0; t < kBucketGroup; ++t) { s_cnt[t][k] = base; base += c[t]; }
         }
         __syncthreads();
 #pragma unroll
-        for (int tg = 0; tg < kBucketGroup; ++tg) {
-            const int x = tx[tg] * kBucketTile + lane;
+        for (int st = 0; st < NS; ++st) {
+            const int x = tx * kBucketTile + SW * st + col;
 #pragma unroll
-            for (int it = 0; it < ROWS; ++it) {
-                const int y = ty[tg] * kBucketTile + wv + 4 * it;
-                if (tile_ok[tg] && x < w.W && y < w.H) {
-                    const uint32_t v = pk[tg][it];
+            for (int it = 0; it < NIT; ++it) {
+                const int y = ty * kBucketTile + RPI * it + rsub;
+                if (tile_ok && x < w.W && y < w.H) {
+                    const uint32_t v = pk[st][it];
                     const int pos = (v & kAbs) ? (int)(v & (uint32_t)kPermIndexMask)
-                                               : s_base[(v >> 14) & 0x7ffu] + (int)(v & 0x3fffu);
+                                               : s_cnt[wv][(v >> 12) & 0x7ffu] + (int)(v & 0xfffu);
                     const int64_t i = (int64_t)y * w.W + x;
                     gst(w.perm + pos, (int)i | (int)(v & (7u << kPermRotShift)));
                 }
@@ -455,7 +474,7 @@ void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s
 void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
     launch_hist_only(bdev, ls, s, 0);
     hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
-    hipLaunchKernelGGL(k_scatter, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
+    hipLaunchKernelGGL(k_scatter<kScatterStrip>, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
 }
 
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
