@@ -9,8 +9,12 @@
 // its genome's weights in registers across units and reloads them only at
 // genome boundaries.  Per unit:
 //   1. every lane gathers its cell's 54 sensor values (rotation-ordered 3x3
-//      Moore kernel, periodic) straight from HBM/L2 and writes them to the
-//      wavefront's LDS stage as one row (bf16 or fp32);
+//      Moore kernel, periodic) and writes them to the wavefront's LDS stage
+//      as one row.  The FP32 form reads the ledger pairs and channels and
+//      converts them.  The BF16 form reads the 9 neighbours' 12-byte sensor
+//      records, which are already the row's bf16 values, and loads the next
+//      unit's records while this unit computes: the gather is a scattered
+//      read whose latency the network hides;
 //   2. the cells are the MFMA B operand (16 per column group), the weights
 //      the A operand; hidden layers stay in registers because the MFMA
 //      output layout is reused as the next layer's B layout (tanh in FP32,
@@ -18,8 +22,10 @@
 //   3. the 14 actuators go through LDS back to one cell per lane, and the
 //      epilogue computes the ledger conversion, the sigmoid communication,
 //      the quantised softmax flow plan and the argmax exploration, writing
-//      C' and the boundary record (E1 and I1 as one ledger pair, the 8 flows each tagged with
-//      whether it is the explored direction, the total outflow).
+//      C' and the boundary record: E1 and I1 as one ledger pair, and the 8
+//      flows, each tagged with whether it is the explored direction, as one
+//      32-byte record in direction order.  Every store of a cell is 16 or 32
+//      contiguous bytes, so a 16-cell row of a unit writes whole cache lines.
 #include <type_traits>
 
 #include "coralai_internal.h"
@@ -121,21 +127,21 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     int64_t acc_mass = 0;
     double acc_f64 = 0.0;
     uint32_t err = 0;
-    // the next unit's perm entry (cell index | rotation), loaded while this unit computes
-    bool have_pf = false;
-    int e_pf = 0;
+    // BF16 form: the next unit's sensor records and own ledger pairs, loaded
+    // while this unit computes
+    coralai_u32x3 pf_s[9];
     // Stores of a unit are issued after the next unit's loads: one counter
     // tracks vector loads and stores in issue order, so a load issued after
     // a store could not be waited for without waiting for the store too.
     bool st_pending = false;
     int st_i = 0;
-    uint32_t st_c[4], st_f[8], st_fo[8], st_used = 0;
+    uint32_t st_c[4], st_f[8];
     int64_t st_E1 = 0, st_I1 = 0;
 
     // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
-    __amdgpu_buffer_rsrc_t rEI, rC, rP, wC, wEI1, wOut, wFlow;
+    __amdgpu_buffer_rsrc_t rEI, rC, rS, rP, wC, wEI1, wFlow;
     const int32_t *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
@@ -163,10 +169,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             buf_st_f32x4(coralai_f32x4{__builtin_bit_cast(float, st_c[0]), __builtin_bit_cast(float, st_c[1]),
                                        __builtin_bit_cast(float, st_c[2]), __builtin_bit_cast(float, st_c[3])},
                          wC, 4 * ofs);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) __builtin_amdgcn_raw_buffer_store_b32(st_f[t], wFlow, st_fo[t], 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[0], st_f[1], st_f[2], st_f[3]}, wFlow, 8 * ofs, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[4], st_f[5], st_f[6], st_f[7]}, wFlow, 8 * ofs + 16, 0, 0);
             buf_st_i64x2(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
-            __builtin_amdgcn_raw_buffer_store_b32(st_used, wOut, ofs, 0, 0);
         }
         st_pending = false;
     };
@@ -189,10 +194,10 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             const uint32_t n4 = 4u * (uint32_t)Nd;
             rEI = buf_rsrc(W->EI[cur], 4u * n4);
             rC = buf_rsrc(W->C[cur], 4u * n4);
+            rS = buf_rsrc(W->S[cur], 3u * n4);
             rP = buf_rsrc(W->perm, n4);
             wC = buf_rsrc(W->C[nxt], 4u * n4);
             wEI1 = buf_rsrc(W->EI1, 4u * n4);
-            wOut = buf_rsrc(W->out, n4);
             wFlow = buf_rsrc(W->flow, 8u * n4);
             counts = W->counts; offsets = W->offsets; gofs = W->gofs;
             wfrag = W->wfrag; bias = W->bias; wstride = W->wfrag_stride; bstride = W->bias_stride;
@@ -276,24 +281,74 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         const int u_run_end = min(uend, world_lo + g_hi);
         const int gcount = cld(counts + g);
         const int goff = cld(offsets + g);
+        // perm entry (cell index | rotation) of unit uu of this run; lanes past
+        // the unit's cells read its first entry
+        auto load_entry = [&](int uu) -> int {
+            const int jj = uu - world_lo - g_lo;
+            const int cn = min(kGroupCells, gcount - jj * kGroupCells);
+            return (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rP, 4 * (goff + jj * kGroupCells + (lane < cn ? lane : 0)), 0, 0);
+        };
+        // the sensor records of cell ci (rotation cr) and its own ledger pair
+        auto gather_records = [&](int ci, int cr) {
+            const int cy = ci / Wd, cx = ci - cy * Wd;
+#pragma unroll
+            for (int p = 0; p < 9; ++p) {
+                int nidx = ci;
+                if (p > 0) {
+                    const int d = kernel_dir(cr, p);
+                    int nx = cx + dir_dx(d), ny = cy + dir_dy(d);
+                    nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
+                    ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
+                    nidx = ny * Wd + nx;
+                }
+                pf_s[p] = __builtin_amdgcn_raw_buffer_load_b96(rS, 12 * nidx, 0, 0);
+            }
+        };
+        // entries run two units ahead of the unit computed, the BF16 records one
+        int e0 = load_entry(u);
+        int e1 = u + 1 < u_run_end ? load_entry(u + 1) : 0;
+        if constexpr (NT::kBF) gather_records(e0 & kPermIndexMask, (e0 >> kPermRotShift) & 7);
         for (; u < u_run_end; ++u) {
         const int j = u - world_lo - g_lo;
-        const int cell0 = goff + j * kGroupCells;
         const int cnt = min(kGroupCells, gcount - j * kGroupCells);
         const bool valid = lane < cnt;
-        const int entry = have_pf ? e_pf
-                                  : (int)__builtin_amdgcn_raw_buffer_load_b32(
-                                        rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
+        const int entry = e0;
         const int i = entry & kPermIndexMask, r = (entry >> kPermRotShift) & 7;
-        // prefetch the next unit's cell index when it continues this genome
-        have_pf = u + 1 < u_run_end;
-        if (have_pf) {
-            const int cnt_n = min(kGroupCells, gcount - (j + 1) * kGroupCells);
-            e_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(
-                rP, 4 * (cell0 + kGroupCells + (lane < cnt_n ? lane : 0)), 0, 0);
-        }
+        int e2;
 
         // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
+        int64_t e_own, i_own;
+        if constexpr (NT::kBF) {
+            uint32_t dw[32];
+#pragma unroll
+            for (int p = 0; p < 9; ++p) {
+                dw[3 * p] = pf_s[p][0];
+                dw[3 * p + 1] = pf_s[p][1];
+                dw[3 * p + 2] = pf_s[p][2];
+            }
+#pragma unroll
+            for (int k = 3 * 9; k < 32; ++k) dw[k] = 0u;  // inputs 54..63: zero padding
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                *(coralai_u32x4*)(stage + lane * NT::STAGE_ROW + 16 * t) =
+                    coralai_u32x4{dw[4 * t], dw[4 * t + 1], dw[4 * t + 2], dw[4 * t + 3]};
+            __builtin_amdgcn_sched_barrier(0);
+            e2 = u + 2 < u_run_end ? load_entry(u + 2) : 0;  // after the wait for the records
+            if (st_pending) store_results();
+            __builtin_amdgcn_sched_barrier(0);
+            // unconditional (past the run's last unit e1 = 0: cell 0, in bounds), so
+            // the records have a single definition in the loop and no merge copy
+            // has to wait for the stores just issued
+            // issued before the prefetch: the epilogue's wait for it (one in-order
+            // vector-memory counter) then leaves the prefetch in flight
+            const i64x2 eo = buf_ld_i64x2(rEI, 16 * i);
+            e_own = eo[0];
+            i_own = eo[1];
+            __builtin_amdgcn_sched_barrier(0);
+            gather_records(e1 & kPermIndexMask, (e1 >> kPermRotShift) & 7);
+        } else {
+        e2 = u + 2 < u_run_end ? load_entry(u + 2) : 0;
         const int y = i / Wd, x = i - y * Wd;
         int64_t gE[9], gI[9];
         float gC[9][4];
@@ -317,7 +372,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         __builtin_amdgcn_sched_barrier(0);
         if (st_pending) store_results();
         __builtin_amdgcn_sched_barrier(0);
-        const int64_t e_own = gE[0], i_own = gI[0];
+        e_own = gE[0];
+        i_own = gI[0];
         float uvec[kNIn];
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
@@ -326,31 +382,19 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
             for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = gC[p][c];
         }
-        if constexpr (NT::kBF) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                bf16x8 row;
+        for (int qq = 0; qq < 4; ++qq) {
+            floatx4 v[4];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int kk = 8 * t + e;
-                    row[e] = (__bf16)(kk < kNIn ? uvec[kk] : 0.0f);
-                }
-                *(bf16x8*)(stage + lane * NT::STAGE_ROW + 16 * t) = row;
+            for (int s = 0; s < 16; ++s) {
+                const int kk = 4 * s + qq;
+                v[s >> 2][s & 3] = (s < 14 && kk < kNIn) ? uvec[kk] : 0.0f;
             }
-        } else {
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                floatx4 v[4];
-#pragma unroll
-                for (int s = 0; s < 16; ++s) {
-                    const int kk = 4 * s + qq;
-                    v[s >> 2][s & 3] = (s < 14 && kk < kNIn) ? uvec[kk] : 0.0f;
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    *(floatx4*)(stage + lane * NT::STAGE_ROW + qq * 64 + 16 * t) = v[t];
-            }
+            for (int t = 0; t < 4; ++t)
+                *(floatx4*)(stage + lane * NT::STAGE_ROW + qq * 64 + 16 * t) = v[t];
         }
+        }  // FP32 gather
         wave_lds_sync();
 
         // ---- 2. the network, CGI column groups of 16 cells at a time
@@ -530,8 +574,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             // truncating conversion of a non-negative float is its floor
             const uint32_t Fu = (uint32_t)F;
             const float per = inv * (float)Fu;  // budget per unit of softmax weight
-            const uint32_t plane = 4u * (uint32_t)Nd, own = 4u * (uint32_t)i;
-            uint32_t used = 0;
+            uint32_t used = 0, fs[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const float share = ex[t] * per;  // >= 0 and finite
@@ -539,13 +582,30 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                 const uint32_t rem = Fu - used;
                 f = f < rem ? f : rem;
                 used += f;
-                st_f[t] = (f << 1) | (uint32_t)(t == best);
-                st_fo[t] = (uint32_t)kernel_dir(r, t + 1) * plane + own;
+                fs[t] = (f << 1) | (uint32_t)(t == best);
             }
-            st_used = used;
+            // kernel position t + 1 points at direction (r + offset) & 7: put
+            // the words in offset order (fixed), then rotate by r, one
+            // conditional rotation per bit of r
+            uint32_t wd[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) wd[kernel_offset(t + 1)] = fs[t];
+#pragma unroll
+            for (int bit = 1; bit < 8; bit <<= 1) {
+                const bool on = (r & bit) != 0;
+                uint32_t nw[8];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) nw[d] = on ? wd[(d - bit) & 7] : wd[d];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) wd[d] = nw[d];
+            }
+#pragma unroll
+            for (int d = 0; d < 8; ++d) st_f[d] = wd[d];
             acc_mass += E1;
             acc_f64 += (double)E1;
         }
+        e0 = e1;
+        e1 = e2;
         }  // units of the run
     }
     if (st_pending) store_results();

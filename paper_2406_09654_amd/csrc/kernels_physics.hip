@@ -5,17 +5,20 @@
 // absorbed; among several explorers the maximal investment wins).
 //
 // Pull form on an LDS-staged halo tile: every target t reads, for each
-// direction d, the flow its neighbour n = nbr(t, d) sent toward (d+4) mod 8,
-// and n's explore direction; I2 = I1 - sum(own flows) + sum(inflows); the
+// direction d, the flow its neighbour n = nbr(t, d) sent toward (d+4) mod 8
+// (word (d+4) mod 8 of n's 8-word flow record), and n's explore direction;
+// I2 = I1 - sum(own flows) + sum(inflows); the
 // candidate explorers are the neighbours exploring toward t, the largest
 // investment wins (lowest d on ties) and takes t over when it strictly
 // exceeds I1(t).  The next state's ledger pair is (E1, I2): energy does not
 // move.  Each flow word is (amount << 1) | explored, so one read per
-// direction gives both the inflow and the candidacy.  The tile loads
-// (TW+2) x (TH+2) cells of the 8 flow planes and the genomes with coalesced
-// row loads; inflows, takeover and the block's share of the total-mass
+// direction gives both the inflow and the candidacy.  The tile loads the
+// flow records and genomes of (TW+2) x (TH+2) cells with coalesced row
+// loads; outflows, inflows, takeover and the block's share of the total-mass
 // reduction (int64 exact and FP64) follow from LDS.  Pure integer work:
-// bit-exact by construction.
+// bit-exact by construction.  In BF16 worlds every variant also writes the
+// next state's sensor record of each cell (its E and I2 with the
+// communication channels the network kernel wrote for the next state).
 #include "coralai_internal.h"
 
 namespace coralai {
@@ -100,6 +103,8 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
+    const float* Cn = nullptr;  // BF16 worlds: the next state's channels and sensor records
+    uint32_t* Sn = nullptr;
     int32_t* cnt = nullptr;  // stripe counts
     int capw = 0, btx = 1;
 
@@ -117,6 +122,7 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             flow = W->flow; EI1p = W->EI1;
             Gc = W->G[cur]; Rc = W->R[cur];
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
+            Cn = W->C[nxt]; Sn = W->S[nxt];
             cnt = W->stripe_counts;
             capw = W->cap;
             btx = W->btiles_x;
@@ -138,8 +144,13 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
                 gy = gy < 0 ? gy + Hd : (gy >= Hd ? gy - Hd : gy);
             }
             const int n = gy * Wd + gx;
+            const coralai_u32x4 fa = gld((const coralai_u32x4*)(flow + 8 * (int64_t)n));
+            const coralai_u32x4 fb = gld((const coralai_u32x4*)(flow + 8 * (int64_t)n) + 1);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) s_flow[k][idx] = gld(flow + (int64_t)k * Nd + n);
+            for (int k = 0; k < 4; ++k) {
+                s_flow[k][idx] = fa[k];
+                s_flow[4 + k][idx] = fb[k];
+            }
             s_g[idx] = gld(Gc + n);
         }
         __syncthreads();
@@ -181,6 +192,12 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);
+            if (Sn) {
+                const coralai_u32x3 rec = sense_record(e1, i2, gld((const coralai_f32x4*)Cn + t));
+                gst(Sn + 3 * (int64_t)t, rec[0]);
+                gst(Sn + 3 * (int64_t)t + 1, rec[1]);
+                gst(Sn + 3 * (int64_t)t + 2, rec[2]);
+            }
             acc_m += i2;
             acc_f += (double)i2;
         }
@@ -192,12 +209,11 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     if (wi >= 0) flush();
 }
 
-// Streaming variant: one thread per cell, no LDS.  The inflow from direction
-// d is plane (d+4) mod 8 read at the neighbour: for a wavefront of
-// consecutive cells every such read is one contiguous (shifted) segment and
-// each plane element is read by exactly one target, so nothing is re-read;
-// the cell's own outflow total comes from the record.  Buffer loads keep the
-// offsets in 32 bits (planes are < 4 GiB) and return 0 outside a plane.
+// Streaming variant, no LDS.  The inflow from direction d is word (d+4) mod 8
+// of the neighbour's flow record; each word is read by exactly one target,
+// and the cell's outflow total is the sum of its own record.  Buffer loads
+// keep the offsets in 32 bits (the records are < 2 GiB) and return 0 outside
+// a buffer.
 
 __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restrict__ b) {
     __shared__ int64_t s_red_m[4];
@@ -214,7 +230,8 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     int acc_t = 0;
     Ctl* ctl = nullptr;
     int Wd = 0, Hd = 0, Nd = 0;
-    __amdgpu_buffer_rsrc_t rflow[8], rout, rei1, rg, rr;
+    __amdgpu_buffer_rsrc_t rflow, rei1, rg, rr, rcn, wsn;
+    bool sense = false;  // BF16 world: write the next state's sensor records
     int32_t* cnt = nullptr;  // stripe counts
     int capw = 0, btx = 1;
     int64_t* EIn = nullptr;
@@ -258,23 +275,24 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             ctl = W->ctl;
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             const uint32_t n4 = 4u * (uint32_t)Nd;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) rflow[k] = buf_rsrc(W->flow + (int64_t)k * Nd, n4);
-            rout = buf_rsrc(W->out, n4);
+            rflow = buf_rsrc(W->flow, 8u * n4);
             rei1 = buf_rsrc(W->EI1, 4u * n4);
             rg = buf_rsrc(W->G[cur], n4);
             rr = buf_rsrc(W->R[cur], (uint32_t)Nd);
+            sense = W->S[nxt] != nullptr;
+            rcn = buf_rsrc(W->C[nxt], 4u * n4);
+            wsn = buf_rsrc(W->S[nxt], 3u * n4);
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
             cnt = W->stripe_counts;
             capw = W->cap;
             btx = W->btiles_x;
         }
         if ((Wd & 3) == 0) {
-            // four consecutive cells of one row per thread.  For direction d
-            // the inflow words come from plane (d+4) mod 8 at the four cells
-            // shifted by (dx, dy): the aligned 16-byte vector of the group's
-            // columns in row y+dy, plus, for dx = +-1, the one word beyond
-            // the group's edge (wrapping around the row).
+            // four consecutive cells of one row per thread: their own flow
+            // records (aligned 16-byte loads) give the outflows and, within
+            // the row, the east / west inflows; the other inflow words are
+            // single words of the records in rows y-1 and y+1 (wrapping
+            // around the row at the group's edges).
             const int t0 = (int)((unit - world_lo) * 1024) + 4 * tid;
             bool took[4] = {false, false, false, false};
             int32_t g_from[4] = {0, 0, 0, 0}, g_to[4] = {0, 0, 0, 0};
@@ -282,28 +300,48 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                 const int y = t0 / Wd, x0 = t0 - y * Wd;
                 const int row[3] = {(y == 0 ? Hd - 1 : y - 1) * Wd, y * Wd, (y == Hd - 1 ? 0 : y + 1) * Wd};
                 const int xl = x0 == 0 ? Wd - 1 : x0 - 1, xr = x0 + 4 == Wd ? 0 : x0 + 4;
+                uint32_t ow[4][8];  // own flow records
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const coralai_u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rflow, 32 * (t0 + j), 0, 0);
+                    const coralai_u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(rflow, 32 * (t0 + j) + 16, 0, 0);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) { ow[j][k] = a[k]; ow[j][4 + k] = c[k]; }
+                }
                 uint32_t fw[8][4];
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
-                    const int dx = dir_dx(d), base = row[dir_dy(d) + 1];
-                    const __amdgpu_buffer_rsrc_t rp = rflow[(d + 4) & 7];
-                    const coralai_u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rp, 4 * (base + x0), 0, 0);
-                    if (dx == 0) {
-                        fw[d][0] = a[0]; fw[d][1] = a[1]; fw[d][2] = a[2]; fw[d][3] = a[3];
-                    } else if (dx > 0) {
-                        const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rp, 4 * (base + xr), 0, 0);
-                        fw[d][0] = a[1]; fw[d][1] = a[2]; fw[d][2] = a[3]; fw[d][3] = e;
-                    } else {
-                        const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(rp, 4 * (base + xl), 0, 0);
-                        fw[d][0] = e; fw[d][1] = a[0]; fw[d][2] = a[1]; fw[d][3] = a[2];
+                    const int dx = dir_dx(d), dy = dir_dy(d), back = (d + 4) & 7, base = row[dy + 1];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int c = j + dx;  // column within the group, -1..4
+                        if (dy == 0 && c >= 0 && c < 4) {
+                            fw[d][j] = ow[c][back];
+                        } else {
+                            const int x = c < 0 ? xl : (c > 3 ? xr : x0 + c);
+                            fw[d][j] = __builtin_amdgcn_raw_buffer_load_b32(rflow, 32 * (base + x) + 4 * back, 0, 0);
+                        }
                     }
                 }
                 i64x2 ei1[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) ei1[j] = buf_ld_i64x2(rei1, 16 * (t0 + j));
-                const coralai_u32x4 outs = __builtin_amdgcn_raw_buffer_load_b128(rout, 4 * t0, 0, 0);
+                uint32_t outs[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t o = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) o += ow[j][k] >> 1;
+                    outs[j] = o;
+                }
                 coralai_u32x4 gs = __builtin_amdgcn_raw_buffer_load_b128(rg, 4 * t0, 0, 0);
                 uint32_t rs = __builtin_amdgcn_raw_buffer_load_b32(rr, t0, 0, 0);
+                coralai_f32x4 cn[4];
+                if (sense) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) cn[j] = buf_ld_f32x4(rcn, 16 * (t0 + j));
+                }
+                int64_t i2v[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     int64_t in = 0, vbest = -1;
@@ -331,11 +369,21 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                         acc_t += 1;
                     }
                     gst((i64x2*)EIn + t0 + j, i64x2{e1, i2});
+                    i2v[j] = i2;
                     acc_m += i2;
                     acc_f += (double)i2;
                 }
                 gst((coralai_u32x4*)Gn + t0 / 4, gs);
                 gst((uint32_t*)Rn + t0 / 4, rs);
+                if (sense) {  // four 12-byte records: three aligned 16-byte stores
+                    coralai_u32x3 rc[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) rc[j] = sense_record(ei1[j][0], i2v[j], cn[j]);
+                    const int so = 12 * t0;
+                    __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{rc[0][0], rc[0][1], rc[0][2], rc[1][0]}, wsn, so, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{rc[1][1], rc[1][2], rc[2][0], rc[2][1]}, wsn, so + 16, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{rc[2][2], rc[3][0], rc[3][1], rc[3][2]}, wsn, so + 32, 0, 0);
+                }
             }
             // the genome counts follow the takeovers (the next step and radiation use them)
 #pragma unroll
@@ -352,9 +400,14 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             const int y = t / Wd, x = t - y * Wd;
             const i64x2 ei1 = buf_ld_i64x2(rei1, 16 * t);
             const int64_t e1 = ei1[0], i1 = ei1[1];
-            const uint32_t out = __builtin_amdgcn_raw_buffer_load_b32(rout, 4 * t, 0, 0);
+            const coralai_u32x4 oa = __builtin_amdgcn_raw_buffer_load_b128(rflow, 32 * t, 0, 0);
+            const coralai_u32x4 ob = __builtin_amdgcn_raw_buffer_load_b128(rflow, 32 * t + 16, 0, 0);
+            uint32_t out = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out += (oa[k] >> 1) + (ob[k] >> 1);
             int32_t g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * t, 0, 0);
             uint8_t r2 = __builtin_amdgcn_raw_buffer_load_b8(rr, t, 0, 0);
+            const coralai_f32x4 cn = sense ? buf_ld_f32x4(rcn, 16 * t) : coralai_f32x4{0.f, 0.f, 0.f, 0.f};
             int64_t in = 0, vbest = -1;
             int win = -1, wn = 0;
 #pragma unroll
@@ -363,7 +416,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                 nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
                 ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
                 const int n = ny * Wd + nx;
-                const uint32_t word = __builtin_amdgcn_raw_buffer_load_b32(rflow[(d + 4) & 7], 4 * n, 0, 0);
+                const uint32_t word = __builtin_amdgcn_raw_buffer_load_b32(rflow, 32 * n + 4 * ((d + 4) & 7), 0, 0);
                 const int64_t v = word >> 1;
                 in += v;
                 if ((word & 1u) && v > vbest) { vbest = v; win = d; wn = n; }
@@ -381,6 +434,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);
+            if (sense) __builtin_amdgcn_raw_buffer_store_b96(sense_record(e1, i2, cn), wsn, 12 * t, 0, 0);
             acc_m += i2;
             acc_f += (double)i2;
         }
@@ -445,6 +499,17 @@ __global__ __launch_bounds__(256) void k_ledger_unpack(const int64_t* __restrict
     }
 }
 
+__global__ __launch_bounds__(256) void k_sense_pack(const int64_t* __restrict__ EI, const float* __restrict__ C,
+                                                    uint32_t* __restrict__ S, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const i64x2 ei = reinterpret_cast<const i64x2*>(EI)[i];
+        const coralai_u32x3 rec = sense_record(ei[0], ei[1], reinterpret_cast<const coralai_f32x4*>(C)[i]);
+        S[3 * i] = rec[0];
+        S[3 * i + 1] = rec[1];
+        S[3 * i + 2] = rec[2];
+    }
+}
+
 static int layout_blocks(int64_t n) {
     const int64_t want = (n + 255) / 256;
     return (int)(want < 4096 ? want : 4096);
@@ -459,6 +524,11 @@ void launch_ledger_pack(const int64_t* e, int e_stride, const int64_t* v, int v_
 void launch_ledger_unpack(const int64_t* src, int64_t* e, int64_t* v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_ledger_unpack, dim3(layout_blocks(n)), dim3(256), 0, s, src, e, v, n);
+}
+
+void launch_sense_pack(const int64_t* EI, const float* C, uint32_t* S, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_sense_pack, dim3(layout_blocks(n)), dim3(256), 0, s, EI, C, S, n);
 }
 
 void launch_comm_layout(const float* src, float* dst, int64_t n, int to_interleaved, hipStream_t s) {

@@ -45,8 +45,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t EI[2], C[2], G[2], R[2];
-    size_t flow, EI1, out, perm;
+    size_t EI[2], C[2], S[2], G[2], R[2];
+    size_t flow, EI1, perm;
     size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
     size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
@@ -80,12 +80,12 @@ Layout make_layout(const coralai_world_desc* d) {
     for (int k = 0; k < 2; ++k) {
         L.EI[k] = take(16 * N);
         L.C[k] = take(16 * N);
+        L.S[k] = d->precision == CORALAI_BF16 ? take(12 * N) : 0;  // BF16 only
         L.G[k] = take(4 * N);
         L.R[k] = take(N);
     }
     L.flow = take(32 * N);
     L.EI1 = take(16 * N);
-    L.out = take(4 * N);
     L.perm = take(4 * N);
     L.counts = take(4 * cap);
     L.offsets = take(4 * (cap + 1));
@@ -400,12 +400,12 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     for (int k = 0; k < 2; ++k) {
         h.EI[k] = (int64_t*)(b + L.EI[k]);
         h.C[k] = (float*)(b + L.C[k]);
+        h.S[k] = desc->precision == CORALAI_BF16 ? (uint32_t*)(b + L.S[k]) : nullptr;
         h.G[k] = (int32_t*)(b + L.G[k]);
         h.R[k] = (uint8_t*)(b + L.R[k]);
     }
     h.flow = (uint32_t*)(b + L.flow);
     h.EI1 = (int64_t*)(b + L.EI1);
-    h.out = (uint32_t*)(b + L.out);
     h.perm = (int32_t*)(b + L.perm);
     h.counts = (int32_t*)(b + L.counts);
     h.offsets = (int32_t*)(b + L.offsets);
@@ -499,6 +499,7 @@ int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, 
         csrc = (const float*)w->host.flow;
     }
     launch_comm_layout(csrc, w->host.C[cur], (int64_t)N, 1, w->stream);
+    if (w->host.S[cur]) launch_sense_pack(w->host.EI[cur], w->host.C[cur], w->host.S[cur], (int64_t)N, w->stream);
     HIP_TRY(hipMemcpyAsync(w->host.G[cur], genome, 4 * N, k, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.R[cur], rotation, N, k, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -1035,27 +1036,25 @@ int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* f
     int cur = 0, rc = current_buffer(w, &cur);
     if (rc) return rc;
     const size_t N = (size_t)w->host.N;
-    // the record as the act kernel writes it: flow words (amount << 1 |
-    // explored) per direction plane, and the outflow total
-    std::vector<uint32_t> planes(8 * N), outs(N);
+    // the record as the act kernel writes it: per cell, 8 flow words
+    // (amount << 1 | explored) in direction order
+    std::vector<uint32_t> words(8 * N);
     for (size_t i = 0; i < N; ++i) {
         uint64_t tot = 0;
         for (int k = 0; k < 8; ++k) {
             const uint32_t f = flows8[i * 8 + k];
             if (f > 0x7fffffffu) return fail(CORALAI_E_INVALID, "flow amounts must be < 2^31");
-            planes[k * N + i] = (f << 1) | (uint32_t)((explore_dir[i] & 7) == k);
+            words[i * 8 + k] = (f << 1) | (uint32_t)((explore_dir[i] & 7) == k);
             tot += f;
         }
         if (tot > 0xffffffffull) return fail(CORALAI_E_INVALID, "a cell's outflow must be < 2^32");
-        outs[i] = (uint32_t)tot;
     }
     const int nxt = cur ^ 1;
-    HIP_TRY(hipMemcpyAsync(w->host.flow, planes.data(), 4 * 8 * N, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.flow, words.data(), 4 * 8 * N, hipMemcpyHostToDevice, w->stream));
     // boundary ledger pairs: the current energy (no conversion) and the given I1,
     // staged through the next state's ledger, which physics overwrites
     HIP_TRY(hipMemcpyAsync(w->host.EI[nxt], i1, 8 * N, hipMemcpyHostToDevice, w->stream));
     launch_ledger_pack(w->host.EI[cur], 2, w->host.EI[nxt], 1, w->host.EI1, (int64_t)N, w->stream);
-    HIP_TRY(hipMemcpyAsync(w->host.out, outs.data(), 4 * N, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.C[nxt], w->host.C[cur], 16 * N, hipMemcpyDeviceToDevice, w->stream));
     launch_physics_only(w->bdev, w->ls, w->phys_tile, w->stream);
     launch_flip(w->bdev, w->stream);
