@@ -61,8 +61,6 @@ struct WorldDev {
     uint64_t seed;
     int64_t* EI[2];       // [N][2]: energy and infrastructure quanta of a cell together
     float* C[2];          // [N][4]: the 4 communication channels of a cell together
-    uint32_t* S[2];       // [N][3] BF16 worlds only (else null): the cell's 6 sensor values
-                          // E, I, C0..C3 as bf16, written by physics for the next step
     int32_t* G[2];
     uint8_t* R[2];
     uint32_t* flow;       // [N][8]: word k of a cell = (its outflow toward direction k) << 1
@@ -293,19 +291,6 @@ __device__ __forceinline__ float i64_to_f32(int64_t v) {
     return __builtin_fmaf((float)(int32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
 }
 
-// Sensor record of a cell for BF16 networks: (E, I, C0, C1, C2, C3), each
-// rounded to bf16 (RNE) from the value the FP32 form feeds its network, two
-// per word in input order.  The network kernel copies a neighbour's record
-// straight into its input row.
-typedef unsigned int coralai_u32x3 __attribute__((ext_vector_type(3)));
-__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
-    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)lo) |
-           ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)hi) << 16);
-}
-__device__ __forceinline__ coralai_u32x3 sense_record(int64_t e, int64_t i, coralai_f32x4 c) {
-    return coralai_u32x3{bf16_pair(i64_to_f32(e), i64_to_f32(i)), bf16_pair(c[0], c[1]), bf16_pair(c[2], c[3])};
-}
-
 // Host-side launch shapes ----------------------------------------------------
 
 struct LaunchShape {
@@ -344,8 +329,6 @@ void launch_ledger_pack(const int64_t* e, int e_stride, const int64_t* v, int v_
                         int64_t n, hipStream_t s);
 // and back: e[i] = src[2i], v[i] = src[2i+1] (either may be null)
 void launch_ledger_unpack(const int64_t* src, int64_t* e, int64_t* v, int64_t n, hipStream_t s);
-// sensor records (BF16 worlds) of a state: S[i] = sense_record(EI[i], C[i])
-void launch_sense_pack(const int64_t* EI, const float* C, uint32_t* S, int64_t n, hipStream_t s);
 
 int phys_tile_w(int t);
 // cells per 256-thread unit of the streaming physics: 4 per thread when the

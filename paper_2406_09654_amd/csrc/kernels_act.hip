@@ -9,12 +9,8 @@
 // its genome's weights in registers across units and reloads them only at
 // genome boundaries.  Per unit:
 //   1. every lane gathers its cell's 54 sensor values (rotation-ordered 3x3
-//      Moore kernel, periodic) and writes them to the wavefront's LDS stage
-//      as one row.  The FP32 form reads the ledger pairs and channels and
-//      converts them.  The BF16 form reads the 9 neighbours' 12-byte sensor
-//      records, which are already the row's bf16 values, and loads the next
-//      unit's records while this unit computes: the gather is a scattered
-//      read whose latency the network hides;
+//      Moore kernel, periodic) straight from HBM/L2 and writes them to the
+//      wavefront's LDS stage as one row (bf16 or fp32);
 //   2. the cells are the MFMA B operand (16 per column group), the weights
 //      the A operand; hidden layers stay in registers because the MFMA
 //      output layout is reused as the next layer's B layout (tanh in FP32,
@@ -127,9 +123,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     int64_t acc_mass = 0;
     double acc_f64 = 0.0;
     uint32_t err = 0;
-    // BF16 form: the next unit's sensor records and own ledger pairs, loaded
-    // while this unit computes
-    coralai_u32x3 pf_s[9];
+    // the next unit's perm entry (cell index | rotation), loaded while this unit computes
+    bool have_pf = false;
+    int e_pf = 0;
     // Stores of a unit are issued after the next unit's loads: one counter
     // tracks vector loads and stores in issue order, so a load issued after
     // a store could not be waited for without waiting for the store too.
@@ -141,7 +137,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
-    __amdgpu_buffer_rsrc_t rEI, rC, rS, rP, wC, wEI1, wFlow;
+    __amdgpu_buffer_rsrc_t rEI, rC, rP, wC, wEI1, wFlow;
     const int32_t *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
@@ -194,7 +190,6 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             const uint32_t n4 = 4u * (uint32_t)Nd;
             rEI = buf_rsrc(W->EI[cur], 4u * n4);
             rC = buf_rsrc(W->C[cur], 4u * n4);
-            rS = buf_rsrc(W->S[cur], 3u * n4);
             rP = buf_rsrc(W->perm, n4);
             wC = buf_rsrc(W->C[nxt], 4u * n4);
             wEI1 = buf_rsrc(W->EI1, 4u * n4);
@@ -281,74 +276,24 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         const int u_run_end = min(uend, world_lo + g_hi);
         const int gcount = cld(counts + g);
         const int goff = cld(offsets + g);
-        // perm entry (cell index | rotation) of unit uu of this run; lanes past
-        // the unit's cells read its first entry
-        auto load_entry = [&](int uu) -> int {
-            const int jj = uu - world_lo - g_lo;
-            const int cn = min(kGroupCells, gcount - jj * kGroupCells);
-            return (int)__builtin_amdgcn_raw_buffer_load_b32(
-                rP, 4 * (goff + jj * kGroupCells + (lane < cn ? lane : 0)), 0, 0);
-        };
-        // the sensor records of cell ci (rotation cr) and its own ledger pair
-        auto gather_records = [&](int ci, int cr) {
-            const int cy = ci / Wd, cx = ci - cy * Wd;
-#pragma unroll
-            for (int p = 0; p < 9; ++p) {
-                int nidx = ci;
-                if (p > 0) {
-                    const int d = kernel_dir(cr, p);
-                    int nx = cx + dir_dx(d), ny = cy + dir_dy(d);
-                    nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
-                    ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
-                    nidx = ny * Wd + nx;
-                }
-                pf_s[p] = __builtin_amdgcn_raw_buffer_load_b96(rS, 12 * nidx, 0, 0);
-            }
-        };
-        // entries run two units ahead of the unit computed, the BF16 records one
-        int e0 = load_entry(u);
-        int e1 = u + 1 < u_run_end ? load_entry(u + 1) : 0;
-        if constexpr (NT::kBF) gather_records(e0 & kPermIndexMask, (e0 >> kPermRotShift) & 7);
         for (; u < u_run_end; ++u) {
         const int j = u - world_lo - g_lo;
+        const int cell0 = goff + j * kGroupCells;
         const int cnt = min(kGroupCells, gcount - j * kGroupCells);
         const bool valid = lane < cnt;
-        const int entry = e0;
+        const int entry = have_pf ? e_pf
+                                  : (int)__builtin_amdgcn_raw_buffer_load_b32(
+                                        rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
         const int i = entry & kPermIndexMask, r = (entry >> kPermRotShift) & 7;
-        int e2;
+        // prefetch the next unit's cell index when it continues this genome
+        have_pf = u + 1 < u_run_end;
+        if (have_pf) {
+            const int cnt_n = min(kGroupCells, gcount - (j + 1) * kGroupCells);
+            e_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                rP, 4 * (cell0 + kGroupCells + (lane < cnt_n ? lane : 0)), 0, 0);
+        }
 
         // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
-        int64_t e_own, i_own;
-        if constexpr (NT::kBF) {
-            uint32_t dw[32];
-#pragma unroll
-            for (int p = 0; p < 9; ++p) {
-                dw[3 * p] = pf_s[p][0];
-                dw[3 * p + 1] = pf_s[p][1];
-                dw[3 * p + 2] = pf_s[p][2];
-            }
-#pragma unroll
-            for (int k = 3 * 9; k < 32; ++k) dw[k] = 0u;  // inputs 54..63: zero padding
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-                *(coralai_u32x4*)(stage + lane * NT::STAGE_ROW + 16 * t) =
-                    coralai_u32x4{dw[4 * t], dw[4 * t + 1], dw[4 * t + 2], dw[4 * t + 3]};
-            __builtin_amdgcn_sched_barrier(0);
-            e2 = u + 2 < u_run_end ? load_entry(u + 2) : 0;  // after the wait for the records
-            if (st_pending) store_results();
-            __builtin_amdgcn_sched_barrier(0);
-            // unconditional (past the run's last unit e1 = 0: cell 0, in bounds), so
-            // the records have a single definition in the loop and no merge copy
-            // has to wait for the stores just issued
-            // issued before the prefetch: the epilogue's wait for it (one in-order
-            // vector-memory counter) then leaves the prefetch in flight
-            const i64x2 eo = buf_ld_i64x2(rEI, 16 * i);
-            e_own = eo[0];
-            i_own = eo[1];
-            __builtin_amdgcn_sched_barrier(0);
-            gather_records(e1 & kPermIndexMask, (e1 >> kPermRotShift) & 7);
-        } else {
-        e2 = u + 2 < u_run_end ? load_entry(u + 2) : 0;
         const int y = i / Wd, x = i - y * Wd;
         int64_t gE[9], gI[9];
         float gC[9][4];
@@ -372,8 +317,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         __builtin_amdgcn_sched_barrier(0);
         if (st_pending) store_results();
         __builtin_amdgcn_sched_barrier(0);
-        e_own = gE[0];
-        i_own = gI[0];
+        const int64_t e_own = gE[0], i_own = gI[0];
         float uvec[kNIn];
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
@@ -382,19 +326,31 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
             for (int c = 0; c < 4; ++c) uvec[6 * p + 2 + c] = gC[p][c];
         }
+        if constexpr (NT::kBF) {
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-            floatx4 v[4];
+            for (int t = 0; t < 8; ++t) {
+                bf16x8 row;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int kk = 4 * s + qq;
-                v[s >> 2][s & 3] = (s < 14 && kk < kNIn) ? uvec[kk] : 0.0f;
+                for (int e = 0; e < 8; ++e) {
+                    const int kk = 8 * t + e;
+                    row[e] = (__bf16)(kk < kNIn ? uvec[kk] : 0.0f);
+                }
+                *(bf16x8*)(stage + lane * NT::STAGE_ROW + 16 * t) = row;
             }
+        } else {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                *(floatx4*)(stage + lane * NT::STAGE_ROW + qq * 64 + 16 * t) = v[t];
+            for (int qq = 0; qq < 4; ++qq) {
+                floatx4 v[4];
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const int kk = 4 * s + qq;
+                    v[s >> 2][s & 3] = (s < 14 && kk < kNIn) ? uvec[kk] : 0.0f;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    *(floatx4*)(stage + lane * NT::STAGE_ROW + qq * 64 + 16 * t) = v[t];
+            }
         }
-        }  // FP32 gather
         wave_lds_sync();
 
         // ---- 2. the network, CGI column groups of 16 cells at a time
@@ -604,8 +560,6 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             acc_mass += E1;
             acc_f64 += (double)E1;
         }
-        e0 = e1;
-        e1 = e2;
         }  // units of the run
     }
     if (st_pending) store_results();

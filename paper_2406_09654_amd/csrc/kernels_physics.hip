@@ -16,9 +16,7 @@
 // flow records and genomes of (TW+2) x (TH+2) cells with coalesced row
 // loads; outflows, inflows, takeover and the block's share of the total-mass
 // reduction (int64 exact and FP64) follow from LDS.  Pure integer work:
-// bit-exact by construction.  In BF16 worlds every variant also writes the
-// next state's sensor record of each cell (its E and I2 with the
-// communication channels the network kernel wrote for the next state).
+// bit-exact by construction.
 #include "coralai_internal.h"
 
 namespace coralai {
@@ -103,8 +101,6 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
     int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
-    const float* Cn = nullptr;  // BF16 worlds: the next state's channels and sensor records
-    uint32_t* Sn = nullptr;
     int32_t* cnt = nullptr;  // stripe counts
     int capw = 0, btx = 1;
 
@@ -122,7 +118,6 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             flow = W->flow; EI1p = W->EI1;
             Gc = W->G[cur]; Rc = W->R[cur];
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
-            Cn = W->C[nxt]; Sn = W->S[nxt];
             cnt = W->stripe_counts;
             capw = W->cap;
             btx = W->btiles_x;
@@ -192,12 +187,6 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);
-            if (Sn) {
-                const coralai_u32x3 rec = sense_record(e1, i2, gld((const coralai_f32x4*)Cn + t));
-                gst(Sn + 3 * (int64_t)t, rec[0]);
-                gst(Sn + 3 * (int64_t)t + 1, rec[1]);
-                gst(Sn + 3 * (int64_t)t + 2, rec[2]);
-            }
             acc_m += i2;
             acc_f += (double)i2;
         }
@@ -230,8 +219,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     int acc_t = 0;
     Ctl* ctl = nullptr;
     int Wd = 0, Hd = 0, Nd = 0;
-    __amdgpu_buffer_rsrc_t rflow, rei1, rg, rr, rcn, wsn;
-    bool sense = false;  // BF16 world: write the next state's sensor records
+    __amdgpu_buffer_rsrc_t rflow, rei1, rg, rr;
     int32_t* cnt = nullptr;  // stripe counts
     int capw = 0, btx = 1;
     int64_t* EIn = nullptr;
@@ -279,9 +267,6 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             rei1 = buf_rsrc(W->EI1, 4u * n4);
             rg = buf_rsrc(W->G[cur], n4);
             rr = buf_rsrc(W->R[cur], (uint32_t)Nd);
-            sense = W->S[nxt] != nullptr;
-            rcn = buf_rsrc(W->C[nxt], 4u * n4);
-            wsn = buf_rsrc(W->S[nxt], 3u * n4);
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
             cnt = W->stripe_counts;
             capw = W->cap;
@@ -336,12 +321,6 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                 }
                 coralai_u32x4 gs = __builtin_amdgcn_raw_buffer_load_b128(rg, 4 * t0, 0, 0);
                 uint32_t rs = __builtin_amdgcn_raw_buffer_load_b32(rr, t0, 0, 0);
-                coralai_f32x4 cn[4];
-                if (sense) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) cn[j] = buf_ld_f32x4(rcn, 16 * (t0 + j));
-                }
-                int64_t i2v[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     int64_t in = 0, vbest = -1;
@@ -369,21 +348,11 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                         acc_t += 1;
                     }
                     gst((i64x2*)EIn + t0 + j, i64x2{e1, i2});
-                    i2v[j] = i2;
                     acc_m += i2;
                     acc_f += (double)i2;
                 }
                 gst((coralai_u32x4*)Gn + t0 / 4, gs);
                 gst((uint32_t*)Rn + t0 / 4, rs);
-                if (sense) {  // four 12-byte records: three aligned 16-byte stores
-                    coralai_u32x3 rc[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) rc[j] = sense_record(ei1[j][0], i2v[j], cn[j]);
-                    const int so = 12 * t0;
-                    __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{rc[0][0], rc[0][1], rc[0][2], rc[1][0]}, wsn, so, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{rc[1][1], rc[1][2], rc[2][0], rc[2][1]}, wsn, so + 16, 0, 0);
-                    __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{rc[2][2], rc[3][0], rc[3][1], rc[3][2]}, wsn, so + 32, 0, 0);
-                }
             }
             // the genome counts follow the takeovers (the next step and radiation use them)
 #pragma unroll
@@ -407,7 +376,6 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             for (int k = 0; k < 4; ++k) out += (oa[k] >> 1) + (ob[k] >> 1);
             int32_t g2 = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rg, 4 * t, 0, 0);
             uint8_t r2 = __builtin_amdgcn_raw_buffer_load_b8(rr, t, 0, 0);
-            const coralai_f32x4 cn = sense ? buf_ld_f32x4(rcn, 16 * t) : coralai_f32x4{0.f, 0.f, 0.f, 0.f};
             int64_t in = 0, vbest = -1;
             int win = -1, wn = 0;
 #pragma unroll
@@ -434,7 +402,6 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             gst((i64x2*)EIn + t, i64x2{e1, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);
-            if (sense) __builtin_amdgcn_raw_buffer_store_b96(sense_record(e1, i2, cn), wsn, 12 * t, 0, 0);
             acc_m += i2;
             acc_f += (double)i2;
         }
@@ -499,17 +466,6 @@ __global__ __launch_bounds__(256) void k_ledger_unpack(const int64_t* __restrict
     }
 }
 
-__global__ __launch_bounds__(256) void k_sense_pack(const int64_t* __restrict__ EI, const float* __restrict__ C,
-                                                    uint32_t* __restrict__ S, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const i64x2 ei = reinterpret_cast<const i64x2*>(EI)[i];
-        const coralai_u32x3 rec = sense_record(ei[0], ei[1], reinterpret_cast<const coralai_f32x4*>(C)[i]);
-        S[3 * i] = rec[0];
-        S[3 * i + 1] = rec[1];
-        S[3 * i + 2] = rec[2];
-    }
-}
-
 static int layout_blocks(int64_t n) {
     const int64_t want = (n + 255) / 256;
     return (int)(want < 4096 ? want : 4096);
@@ -524,11 +480,6 @@ void launch_ledger_pack(const int64_t* e, int e_stride, const int64_t* v, int v_
 void launch_ledger_unpack(const int64_t* src, int64_t* e, int64_t* v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_ledger_unpack, dim3(layout_blocks(n)), dim3(256), 0, s, src, e, v, n);
-}
-
-void launch_sense_pack(const int64_t* EI, const float* C, uint32_t* S, int64_t n, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_sense_pack, dim3(layout_blocks(n)), dim3(256), 0, s, EI, C, S, n);
 }
 
 void launch_comm_layout(const float* src, float* dst, int64_t n, int to_interleaved, hipStream_t s) {

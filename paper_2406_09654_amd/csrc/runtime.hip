@@ -45,7 +45,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t EI[2], C[2], S[2], G[2], R[2];
+    size_t EI[2], C[2], G[2], R[2];
     size_t flow, EI1, perm;
     size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
@@ -80,7 +80,6 @@ Layout make_layout(const coralai_world_desc* d) {
     for (int k = 0; k < 2; ++k) {
         L.EI[k] = take(16 * N);
         L.C[k] = take(16 * N);
-        L.S[k] = d->precision == CORALAI_BF16 ? take(12 * N) : 0;  // BF16 only
         L.G[k] = take(4 * N);
         L.R[k] = take(N);
     }
@@ -400,7 +399,6 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     for (int k = 0; k < 2; ++k) {
         h.EI[k] = (int64_t*)(b + L.EI[k]);
         h.C[k] = (float*)(b + L.C[k]);
-        h.S[k] = desc->precision == CORALAI_BF16 ? (uint32_t*)(b + L.S[k]) : nullptr;
         h.G[k] = (int32_t*)(b + L.G[k]);
         h.R[k] = (uint8_t*)(b + L.R[k]);
     }
@@ -499,7 +497,6 @@ int coralai_set_state(coralai_world* w, const int64_t* e_q, const int64_t* i_q, 
         csrc = (const float*)w->host.flow;
     }
     launch_comm_layout(csrc, w->host.C[cur], (int64_t)N, 1, w->stream);
-    if (w->host.S[cur]) launch_sense_pack(w->host.EI[cur], w->host.C[cur], w->host.S[cur], (int64_t)N, w->stream);
     HIP_TRY(hipMemcpyAsync(w->host.G[cur], genome, 4 * N, k, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.R[cur], rotation, N, k, w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
