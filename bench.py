@@ -28,8 +28,12 @@ METRIC = "cell-updates/sec at 4096² (FP32 vs BF16); p50/p99 step latency under 
 PEAK_HBM = 8.0e12            # bytes/s
 PEAK_BF16 = 2.5e15           # dense MFMA FLOP/s
 PEAK_FP32 = 157.3e12         # FLOP/s
-# transcendental ops/s: 256 CUs x 4 SIMDs x 4 lanes/clock (quarter rate) x 2.4 GHz
-PEAK_TRANS = 256 * 4 * 4 * 2.4e9
+# transcendental ops/s: the FP32 vector peak of 157.3 TFLOP/s is 256 CUs x
+# 128 FMA lanes/clock x 2 FLOP x 2.4 GHz; exp2 / rcp / log issue at a quarter
+# of that lane rate, 32 lanes per CU per clock: 256 x 32 x 2.4 GHz
+PEAK_TRANS = 256 * 32 * 2.4e9
+ACT_BYTES_PER_CELL = 100   # reads ledger pair, comm, perm entry (36 B); writes comm, ledger pair, flows (64 B)
+PHYS_BYTES_PER_CELL = 74   # reads flow record, ledger pair, genome, rotation (53 B); writes 21 B
 RATE, SIGMA = 1e-4, 0.1
 
 
@@ -65,7 +69,8 @@ def act_traffic(tuning):
     sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
-    want = ",".join(str(v) for v in tuning) if tuning is not None else None
+    # the network kernel's traffic depends on (act_cells, act_waves), not on the physics tiling
+    want = ",".join(str(v) for v in tuning[:2]) if tuning is not None else None
     stale = False
     with open(TRAFFIC_FILE) as f:
         for line in f:
@@ -322,6 +327,7 @@ def main() -> int:
             "traffic": traffic, "traffic_note": traffic_note,
             "per_unit": "%d transcendental ops per cell (tanh, sigmoid, softmax), %d cells per launch"
                         % (trans_per_cell(hidden, layers), N),
+            "hbm_frac_algorithmic": ACT_BYTES_PER_CELL * N / (act_ms * 1e-3) / PEAK_HBM,
             "mfma_frac_bf16": flops_per_cell(hidden, layers) * N / (act_ms * 1e-3) / PEAK_BF16}
     out = {
         "metric": METRIC,
@@ -356,11 +362,12 @@ def main() -> int:
                                     "frac": fl / (fa * 1e-3) / PEAK_FP32, "traffic": None}}
         out["bf16_over_fp32"] = bf["value"] / f["value"]
     phys_ms = bf["phase_ms"]["physics"]
-    out["physics_roofline"] = {"bound": "hbm", "achieved": 78 * N / (phys_ms * 1e-3) / 1e9,
+    out["physics_roofline"] = {"bound": "hbm", "achieved": PHYS_BYTES_PER_CELL * N / (phys_ms * 1e-3) / 1e9,
                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                               "frac": 78 * N / (phys_ms * 1e-3) / PEAK_HBM,
-                               "per_unit": "78 B per cell (reads 8 flow words, outflow, boundary ledger pair, "
-                                           "genome, rotation; writes ledger pair, genome, rotation)"}
+                               "frac": PHYS_BYTES_PER_CELL * N / (phys_ms * 1e-3) / PEAK_HBM,
+                               "per_unit": "%d B per cell (reads the 32-byte flow record, boundary ledger pair, "
+                                           "genome, rotation; writes ledger pair, genome, rotation)"
+                                           % PHYS_BYTES_PER_CELL}
     if not args.no_batched:
         out["batched"] = run_batched(512, 20, 3, 3)
         print("[bench] batched: %s" % out["batched"], file=sys.stderr, flush=True)

@@ -190,9 +190,8 @@ __host__ __device__ inline FragCoord frag_coord(int nl, int hid, int prec, int e
 // Direction d points 45*d degrees counter-clockwise from +x, y pointing down.
 __device__ __forceinline__ int dir_dx(int d) { return (int)((0x440052u >> (d * 3)) & 7) - 1; }
 __device__ __forceinline__ int dir_dy(int d) { return (int)((0x491001u >> (d * 3)) & 7) - 1; }
-// Kernel position p (1..8) of rotation r: r, r+1, r-1, r+2, r-2, r+3, r-3, r+4.
-// offset of kernel position p = 1..8 from the rotation: {0, +1, -1, +2, -2,
-// +3, -3, +4}, packed as (off & 7) in 3 bits
+// Kernel position p (1..8) of rotation r points at direction r + offset(p):
+// offsets {0, +1, -1, +2, -2, +3, -3, +4}, packed as (off & 7) in 3 bits.
 __host__ __device__ constexpr int kernel_offset(int p) { return (int)((0x95e5c8u >> (p * 3 - 3)) & 7); }
 __device__ __forceinline__ int kernel_dir(int r, int p) { return (r + kernel_offset(p)) & 7; }
 
@@ -314,10 +313,11 @@ void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_t
                          hipStream_t s);
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only);
-void launch_cppn(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s);
+void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, int n_cu,
+                 hipStream_t s);
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
-void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
-                    int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s);
+void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
+                    int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s);
 void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
                          hipStream_t s);
 void launch_flip(const BatchDev* bdev, hipStream_t s);

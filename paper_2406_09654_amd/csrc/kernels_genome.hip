@@ -15,6 +15,8 @@
 // free slots (zero count) in ascending order; the new genome is the parent's
 // CPPN plus sigma * N(0,1) from Box-Muller on the Philox blocks
 // (i, step, 1 + b, 0), b = 0..13, and its network is regenerated at once.
+#include <type_traits>
+
 #include "coralai_internal.h"
 
 namespace coralai {
@@ -50,26 +52,30 @@ __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, 
     return s_out;
 }
 
-template <typename T>
-__device__ __forceinline__ T neuron_x(int j, int L) { return T(-1) + T(2) * T(j) / T(L - 1); }
-
-// Stored value of a weight / bias: the generated value times the stored
-// scale factors (stored_row_scale, stored_col_scale), then one rounding to
-// FP32 or bf16.
-template <typename T>
-__device__ __forceinline__ float cppn_weight(const float* p, int layer, int nl, int row, int lout,
-                                             int col, int lin) {
-    const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
-    const T sc = T(stored_row_scale(nl, layer, row) * stored_col_scale(layer, col));
-    return (float)(cppn_eval<T>(p, neuron_x<T>(col, lin), yi, neuron_x<T>(row, lout), yo, 0) /
-                   sqrt(T(lin)) * sc);
+// Stored value of a weight / bias of a network with NL weight layers and HID
+// hidden units: the generated value times the stored scale factors
+// (stored_row_scale, stored_col_scale), then one rounding to FP32 or bf16.
+// Neuron j of a layer of L sits at x = -1 + j * (2 / (L - 1)) and layer l at
+// y = -1 + l * (2 / NL): with the shape fixed at compile time every divisor
+// is a constant, folded into a multiplier.
+template <typename T, int NL, int HID>
+__device__ __forceinline__ float cppn_weight(const float* p, int layer, int row, int col) {
+    constexpr T dy = T(2) / T(NL);
+    const T yi = T(-1) + T(layer) * dy, yo = T(-1) + T(layer + 1) * dy;
+    const T x1 = T(-1) + T(col) * (layer == 0 ? T(2) / T(kNIn - 1) : T(2) / T(HID - 1));
+    const T x2 = T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
+    const T rs = layer == 0 ? T(1) / sqrt(T(kNIn)) : T(1) / sqrt(T(HID));  // 1 / sqrt(fan-in)
+    const T sc = T(stored_row_scale(NL, layer, row) * stored_col_scale(layer, col));
+    return (float)(cppn_eval<T>(p, x1, yi, x2, yo, 0) * rs * sc);
 }
 
-template <typename T>
-__device__ __forceinline__ float cppn_bias(const float* p, int layer, int nl, int row, int lout) {
-    const T yi = T(-1) + T(2) * T(layer) / T(nl), yo = T(-1) + T(2) * T(layer + 1) / T(nl);
-    const T sc = T(stored_row_scale(nl, layer, row));
-    return (float)(cppn_eval<T>(p, T(0), yi, neuron_x<T>(row, lout), yo, 1) * sc);
+template <typename T, int NL, int HID>
+__device__ __forceinline__ float cppn_bias(const float* p, int layer, int row) {
+    constexpr T dy = T(2) / T(NL);
+    const T yi = T(-1) + T(layer) * dy, yo = T(-1) + T(layer + 1) * dy;
+    const T x2 = T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
+    const T sc = T(stored_row_scale(NL, layer, row));
+    return (float)(cppn_eval<T>(p, T(0), yi, x2, yo, 1) * sc);
 }
 
 // Layer geometry of a bias element index.
@@ -92,40 +98,37 @@ __device__ __forceinline__ int flat_w_offset(int nl, int hid, int l) {
 
 // from_radiation = 0: the n_host slots listed by coralai_set_genomes;
 // 1: the slots the last radiation call assigned (count on the device).
+template <int NL, int HID, int PREC>
 __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, int from_radiation,
                                               int n_host) {
-    const int nl = w->NL, hid = w->HID, prec = w->prec;
+    using T = typename std::conditional<PREC == kPrecBF16, float, double>::type;
+    constexpr bool bf = PREC == kPrecBF16;
+    constexpr int ew = net_frags(NL, HID, PREC) * net_frag_elems(PREC);
+    constexpr int eb = net_bias_floats(NL, HID);
+    constexpr int per_genome = (ew + eb + 255) / 256;
     const int n = from_radiation ? w->ctl->n_new : n_host;
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
-    const int ew = net_frags(nl, hid, prec) * net_frag_elems(prec);
-    const int eb = net_bias_floats(nl, hid);
-    const int per_genome = (ew + eb + 255) / 256;
     const int64_t units = (int64_t)n * per_genome;
-    const bool bf = prec == kPrecBF16;
     for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
         const int si = (int)(unit / per_genome);
         const int e = (int)(unit - (int64_t)si * per_genome) * 256 + threadIdx.x;
         const int slot = uniform_i32(slots[si]);
         const float* p = w->params + (int64_t)slot * kNParam;
         if (e < ew) {
-            const FragCoord fc = frag_coord(nl, hid, prec, e);
-            const int lin = layer_in(nl, hid, fc.layer), lout = layer_out(nl, hid, fc.layer);
+            const FragCoord fc = frag_coord(NL, HID, PREC, e);
+            const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
             float v = 0.0f;
-            if (fc.row < lout && fc.col < lin)
-                v = bf ? cppn_weight<float>(p, fc.layer, nl, fc.row, lout, fc.col, lin)
-                       : cppn_weight<double>(p, fc.layer, nl, fc.row, lout, fc.col, lin);
+            if (fc.row < lout && fc.col < lin) v = cppn_weight<T, NL, HID>(p, fc.layer, fc.row, fc.col);
             if (!__builtin_isfinite(v)) { atomicOr(&w->ctl->err, kErrNonFinite); v = 0.0f; }
             uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
-            if (bf) ((__bf16*)dst)[e] = (__bf16)v;
+            if constexpr (bf) ((__bf16*)dst)[e] = (__bf16)v;
             else ((float*)dst)[e] = v;
         } else if (e < ew + eb) {
             int layer, row;
-            bias_coord(nl, hid, e - ew, &layer, &row);
-            const int lout = layer_out(nl, hid, layer);
+            bias_coord(NL, HID, e - ew, &layer, &row);
+            const int lout = layer == NL - 1 ? kNOut : HID;
             float v = 0.0f;
-            if (row < lout)
-                v = bf ? cppn_bias<float>(p, layer, nl, row, lout)
-                       : cppn_bias<double>(p, layer, nl, row, lout);
+            if (row < lout) v = cppn_bias<T, NL, HID>(p, layer, row);
             if (!__builtin_isfinite(v)) { atomicOr(&w->ctl->err, kErrNonFinite); v = 0.0f; }
             w->bias[(int64_t)slot * w->bias_stride + (e - ew)] = v;
         }
@@ -353,8 +356,18 @@ __global__ void k_rad_finalize(const WorldDev* __restrict__ w) {
     ctl->dropped_pub = ctl->dropped;
 }
 
-void launch_cppn(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s) {
-    hipLaunchKernelGGL(k_cppn, dim3(n_cu * 8), dim3(256), 0, s, wdev, from_radiation, n_host);
+template <int NL, int HID, int PREC>
+static void launch_cppn_t(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s) {
+    hipLaunchKernelGGL((k_cppn<NL, HID, PREC>), dim3(n_cu * 16), dim3(256), 0, s, wdev, from_radiation, n_host);
+}
+
+void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, int n_cu,
+                 hipStream_t s) {
+    const bool bf = prec == kPrecBF16;
+    if (nl == 2 && hid == 32) (bf ? launch_cppn_t<2, 32, kPrecBF16> : launch_cppn_t<2, 32, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
+    else if (nl == 2) (bf ? launch_cppn_t<2, 64, kPrecBF16> : launch_cppn_t<2, 64, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
+    else if (hid == 32) (bf ? launch_cppn_t<3, 32, kPrecBF16> : launch_cppn_t<3, 32, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
+    else (bf ? launch_cppn_t<3, 64, kPrecBF16> : launch_cppn_t<3, 64, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
 }
 
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s) {
@@ -367,8 +380,8 @@ void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int 
     hipLaunchKernelGGL(k_pack, dim3(64), dim3(256), 0, s, wdev, slot, flat, unpack, out);
 }
 
-void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls,
-                    int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s) {
+void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
+                    int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s) {
     // free slots of the current state (the completed step's result), listed by
     // the slot scan; the counting pass inside runs only if the counts are not
     // current (right after a step they are)
@@ -378,7 +391,7 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
     hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev);
     hipLaunchKernelGGL(k_rad_mutate, dim3(ls.n_cu), dim3(256), 0, s, wdev, step, sigma);
-    launch_cppn(wdev, 1, 0, ls.n_cu, s);
+    launch_cppn(wdev, nl, hid, prec, 1, 0, ls.n_cu, s);
     hipLaunchKernelGGL(k_rad_finalize, dim3(1), dim3(1), 0, s, wdev);
 }
 

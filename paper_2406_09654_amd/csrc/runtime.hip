@@ -545,7 +545,7 @@ int coralai_set_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids, co
     HIP_TRY(hipMemcpyAsync(w->host.stage_slots, slot_ids, 4 * (size_t)n, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.stage_params, cppn_params, 4 * (size_t)kNParam * n, hipMemcpyHostToDevice, w->stream));
     launch_scatter_params(w->wdev, n, w->stream);
-    launch_cppn(w->wdev, 0, n, w->ls.n_cu, w->stream);
+    launch_cppn(w->wdev, w->host.NL, w->host.HID, w->host.prec, 0, n, w->ls.n_cu, w->stream);
     int rc = check_launch();
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(w->stream));
@@ -613,7 +613,8 @@ int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_in
     else if (rate >= 1.0) T = UINT64_MAX;
     else T = (uint64_t)std::floor(rate * 18446744073709551616.0);
     int rc = timed_phase(w, 4, [&] {
-        launch_radiate(w->bdev, w->wdev, w->ls, w->L.n_rad_blocks, T, sigma, step_index, w->stream);
+        launch_radiate(w->bdev, w->wdev, w->ls, w->host.NL, w->host.HID, w->host.prec, w->L.n_rad_blocks, T, sigma,
+                       step_index, w->stream);
     });
     if (rc) return rc;
     rc = check_launch();
