@@ -98,6 +98,8 @@ __device__ __forceinline__ int flat_w_offset(int nl, int hid, int l) {
 
 // from_radiation = 0: the n_host slots listed by coralai_set_genomes;
 // 1: the slots the last radiation call assigned (count on the device).
+// One block per genome: its 56 parameters are read once into LDS, then the
+// block's threads walk the genome's weight and bias elements.
 template <int NL, int HID, int PREC>
 __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, int from_radiation,
                                               int n_host) {
@@ -105,33 +107,37 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     constexpr bool bf = PREC == kPrecBF16;
     constexpr int ew = net_frags(NL, HID, PREC) * net_frag_elems(PREC);
     constexpr int eb = net_bias_floats(NL, HID);
-    constexpr int per_genome = (ew + eb + 255) / 256;
+    __shared__ float sp[kNParam];
     const int n = from_radiation ? w->ctl->n_new : n_host;
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
-    const int64_t units = (int64_t)n * per_genome;
-    for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
-        const int si = (int)(unit / per_genome);
-        const int e = (int)(unit - (int64_t)si * per_genome) * 256 + threadIdx.x;
+    for (int si = blockIdx.x; si < n; si += gridDim.x) {
         const int slot = uniform_i32(slots[si]);
-        const float* p = w->params + (int64_t)slot * kNParam;
-        if (e < ew) {
-            const FragCoord fc = frag_coord(NL, HID, PREC, e);
-            const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
+        if (threadIdx.x < kNParam) sp[threadIdx.x] = w->params[(int64_t)slot * kNParam + threadIdx.x];
+        __syncthreads();
+        uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
+        float* bdst = w->bias + (int64_t)slot * w->bias_stride;
+        uint32_t bad = 0;
+        for (int e = threadIdx.x; e < ew + eb; e += 256) {
             float v = 0.0f;
-            if (fc.row < lout && fc.col < lin) v = cppn_weight<T, NL, HID>(p, fc.layer, fc.row, fc.col);
-            if (!__builtin_isfinite(v)) { atomicOr(&w->ctl->err, kErrNonFinite); v = 0.0f; }
-            uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
-            if constexpr (bf) ((__bf16*)dst)[e] = (__bf16)v;
-            else ((float*)dst)[e] = v;
-        } else if (e < ew + eb) {
-            int layer, row;
-            bias_coord(NL, HID, e - ew, &layer, &row);
-            const int lout = layer == NL - 1 ? kNOut : HID;
-            float v = 0.0f;
-            if (row < lout) v = cppn_bias<T, NL, HID>(p, layer, row);
-            if (!__builtin_isfinite(v)) { atomicOr(&w->ctl->err, kErrNonFinite); v = 0.0f; }
-            w->bias[(int64_t)slot * w->bias_stride + (e - ew)] = v;
+            if (e < ew) {
+                const FragCoord fc = frag_coord(NL, HID, PREC, e);
+                const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
+                if (fc.row < lout && fc.col < lin) v = cppn_weight<T, NL, HID>(sp, fc.layer, fc.row, fc.col);
+            } else {
+                int layer, row;
+                bias_coord(NL, HID, e - ew, &layer, &row);
+                if (row < (layer == NL - 1 ? kNOut : HID)) v = cppn_bias<T, NL, HID>(sp, layer, row);
+            }
+            if (!__builtin_isfinite(v)) { bad = kErrNonFinite; v = 0.0f; }
+            if (e < ew) {
+                if constexpr (bf) ((__bf16*)dst)[e] = (__bf16)v;
+                else ((float*)dst)[e] = v;
+            } else {
+                bdst[e - ew] = v;
+            }
         }
+        if (bad) atomicOr(&w->ctl->err, bad);
+        __syncthreads();  // sp is rewritten for the next genome
     }
 }
 
@@ -358,6 +364,7 @@ __global__ void k_rad_finalize(const WorldDev* __restrict__ w) {
 
 template <int NL, int HID, int PREC>
 static void launch_cppn_t(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s) {
+    // one block per genome (the count of a radiation call is known on the device only)
     hipLaunchKernelGGL((k_cppn<NL, HID, PREC>), dim3(n_cu * 16), dim3(256), 0, s, wdev, from_radiation, n_host);
 }
 
@@ -387,7 +394,9 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
     // current (right after a step they are)
     launch_hist_only(bdev, ls, s, 1);
     const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
-    hipLaunchKernelGGL(k_rad_hits, dim3(hb), dim3(256), 0, s, wdev, T, step);
+    // the hit test is a chain of 64-bit multiplies per cell: as many waves as fit
+    const int hh = max(1, min(n_rad_blocks, ls.n_cu * 32));
+    hipLaunchKernelGGL(k_rad_hits, dim3(hh), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
     hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev);
     hipLaunchKernelGGL(k_rad_mutate, dim3(ls.n_cu), dim3(256), 0, s, wdev, step, sigma);
