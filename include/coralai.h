@@ -138,9 +138,9 @@ int coralai_get_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids,
  * when out is NULL; otherwise waits and fills *out. */
 int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out);
 
-/* Radiation after step step_index (Fig. 1 C): cell i is hit when the first
- * word of Philox4x64-10(counter (i, step_index, 0, 0), key (seed, 0)) is
- * below floor(rate * 2^64); the k-th hit in ascending i takes the k-th free
+/* Radiation after step step_index (Fig. 1 C): cell i is hit when word i mod 4
+ * of Philox4x64-10(counter (floor(i / 4), step_index, 0, 0), key (seed, 0))
+ * is below floor(rate * 2^64); the k-th hit in ascending i takes the k-th free
  * slot (ascending slot ids whose genome count is zero), whose CPPN
  * parameters become the parent's plus sigma * N(0,1) (Box-Muller on Philox
  * blocks (i, step_index, 1+b, 0), b = 0..13) and whose network is

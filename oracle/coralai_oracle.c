@@ -474,15 +474,16 @@ void orc_mutation_normals(uint64_t seed, uint64_t i, uint64_t s, double* z) {
     }
 }
 
-/* Hit threshold: a cell is hit when its first draw is below floor(rate 2^64). */
+/* Hit threshold: a cell is hit when its draw is below floor(rate 2^64). */
 uint64_t orc_hit_threshold(double rate) {
     if (!(rate > 0.0)) return 0;
     if (rate >= 1.0) return UINT64_MAX;
     return (uint64_t)floor(rate * 18446744073709551616.0);
 }
 
-/* Radiation (Fig. 1 C) applied after step s: each cell i draws Philox at
- * counter (i, s, 0, 0), key (seed, 0), and is hit when o0 < T.  Free slots
+/* Radiation (Fig. 1 C) applied after step s: the Philox block at counter
+ * (floor(i / 4), s, 0, 0), key (seed, 0), gives cells 4k..4k+3 its four words;
+ * cell i is hit when word i mod 4 is below T.  Free slots
  * are the slot ids with zero count in G (ascending); the k-th hit in
  * ascending i takes free slot k, gets its parent's CPPN parameters plus
  * sigma * z, and G[i] becomes that slot; hits beyond the free slots are
@@ -502,9 +503,9 @@ int64_t orc_radiate(int64_t n, int32_t* G, int32_t cap, double* params, uint64_t
     int64_t hits = 0;
     *dropped = 0;
     for (int64_t i = 0; i < n; ++i) {
-        uint64_t ctr[4] = {(uint64_t)i, s, 0, 0}, o[4];
+        uint64_t ctr[4] = {(uint64_t)(i / 4), s, 0, 0}, o[4];
         orc_philox4x64_10(ctr, key, o);
-        if (!(o[0] < T)) continue;
+        if (!(o[i % 4] < T)) continue;
         int32_t slot = -1;
         if (hits < nfree) {
             slot = freel[hits];

@@ -10,8 +10,8 @@
 // element, written straight into the MFMA fragment order of the act kernel.
 //
 // Radiation: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
-// (seed, 0) at counter (i, step, 0, 0); a hit when the first word is below
-// floor(rate 2^64).  Hits are ranked in ascending cell order and take the
+// (seed, 0); the block at counter (k, step, 0, 0) gives cells 4k..4k+3 one
+// word each, and a cell is hit when its word is below floor(rate 2^64).  Hits are ranked in ascending cell order and take the
 // free slots (zero count) in ascending order; the new genome is the parent's
 // CPPN plus sigma * N(0,1) from Box-Muller on the Philox blocks
 // (i, step, 1 + b, 0), b = 0..13, and its network is regenerated at once.
@@ -217,13 +217,15 @@ __global__ __launch_bounds__(256) void k_rad_hits(const WorldDev* __restrict__ w
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         const int64_t base = (int64_t)blk * kRadBlockCells + 16 * threadIdx.x;
-        uint32_t bits = 0;
-        for (int j = 0; j < 16; ++j) {
-            const int64_t i = base + j;
-            if (i >= N) break;
-            uint64_t c[4] = {(uint64_t)i, step, 0ull, 0ull};
+        uint32_t bits = 0;  // base is a multiple of 16: four whole Philox blocks
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i0 = base + 4 * q;
+            if (i0 >= N) break;
+            uint64_t c[4] = {(uint64_t)(i0 >> 2), step, 0ull, 0ull};
             philox4x64_10(c, w->seed, 0ull);
-            if (c[0] < T) bits |= 1u << j;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k < N && c[k] < T) bits |= 1u << (4 * q + k);
         }
         w->hit_bits[(int64_t)blk * 256 + threadIdx.x] = (uint16_t)bits;
         if (bits) atomicAdd(&s_cnt, __popc(bits));

@@ -451,7 +451,8 @@ def test_radiate_against_bruteforce(oracle_lib):
     seed, s, rate, sigma = 42, 17, 0.02, 0.1
     G2, P2, (hc, hs), dropped = oracle_lib.radiate(G, cap, params, seed, s, rate, sigma)
     T = math.floor(rate * 2.0 ** 64)
-    hits = [i for i in range(W * H) if int(_numpy_block((i, s, 0, 0), (seed, 0))[0]) < T]
+    # cells 4k..4k+3 take the four words of the block at counter (k, s, 0, 0)
+    hits = [i for i in range(W * H) if int(_numpy_block((i // 4, s, 0, 0), (seed, 0))[i % 4]) < T]
     free = [g for g in range(cap) if g not in set(G.ravel().tolist())]
     assert hc.tolist() == hits
     assert len(hits) > len(free)        # capacity exhaustion exercised
