@@ -177,7 +177,7 @@ int coralai_batch_destroy(coralai_batch* b);
  * coralai_set_tuning forces one.  act_cells: column groups of 16 cells the
  * network kernel processes together (1, 2 or 4); act_waves: 0 = fewer
  * wavefronts per SIMD with more registers each, 1 = more wavefronts;
- * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 16x16, or 3 = streaming,
+ * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 64x8, or 3 = streaming,
  * one thread per cell without LDS.  The batch versions tune the batch's
  * single captured step over its current worlds.  Defaults before any call:
  * act_cells 2, act_waves 0, phys_tile 3. */

@@ -39,8 +39,9 @@ __device__ __forceinline__ void wave_count_add(int32_t* counts, int g, int d, bo
 }
 
 template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict__ b) {
-    constexpr int NT = TW * TH;
+__global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b) {
+    constexpr int NT = 256, CPT = TW * TH / NT;  // threads, cells per thread
+    static_assert(TW * TH % NT == 0, "a tile is a whole number of cells per thread");
     constexpr int LW = TW + 2, LH = TH + 2, LN = LW * LH;
     __shared__ uint32_t s_flow[8][LN];
     __shared__ int32_t s_g[LN];
@@ -126,6 +127,28 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
         const int ty = (int)(lt / tx_n), tx = (int)(lt - (int64_t)ty * tx_n);
         const int x0 = tx * TW, y0 = ty * TH;
 
+        // the thread's own cells (tile cells tid + NT k): their boundary
+        // ledger pairs and rotations are loaded before the halo, so their
+        // latency overlaps the staging
+        int cx[CPT], cy[CPT], ct[CPT];
+        bool mine[CPT];
+        i64x2 ei1[CPT];
+        uint8_t r_own[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int cc = tid + NT * k;
+            cx[k] = cc % TW + 1;
+            cy[k] = cc / TW + 1;
+            const int gx = x0 + cx[k] - 1, gy = y0 + cy[k] - 1;
+            mine[k] = gx < Wd && gy < Hd;
+            ct[k] = mine[k] ? gy * Wd + gx : 0;
+            ei1[k] = i64x2{0, 0};
+            r_own[k] = 0;
+            if (mine[k]) {
+                ei1[k] = gld((const i64x2*)EI1p + ct[k]);
+                r_own[k] = gld(Rc + ct[k]);
+            }
+        }
         // stage the halo tile
         const bool small = Wd < TW + 2 || Hd < TH + 2;  // tiny worlds wrap more than once
         for (int idx = tid; idx < LN; idx += NT) {
@@ -150,49 +173,51 @@ __global__ __launch_bounds__(TW * TH) void k_physics(const BatchDev* __restrict_
         }
         __syncthreads();
 
-        const int lx = tid % TW + 1, ly = tid / TW + 1;
-        const int gx = x0 + lx - 1, gy = y0 + ly - 1;
-        bool took = false;
-        int32_t g_from = 0, g_to = 0;
-        if (gx < Wd && gy < Hd) {
-            const int t = gy * Wd + gx;
-            const int own = ly * LW + lx;
-            int64_t out = 0, in = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) out += s_flow[k][own] >> 1;
-            int win = -1;
-            int64_t vbest = -1;
+        for (int k = 0; k < CPT; ++k) {
+            const int lx = cx[k], ly = cy[k];
+            bool took = false;
+            int32_t g_from = 0, g_to = 0;
+            if (mine[k]) {
+                const int t = ct[k];
+                const int own = ly * LW + lx;
+                int64_t out = 0, in = 0;
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                const int back = (d + 4) & 7;
-                const int nb = (ly + dir_dy(d)) * LW + (lx + dir_dx(d));
-                const uint32_t word = s_flow[back][nb];
-                const int64_t v = word >> 1;
-                in += v;
-                if ((word & 1u) && v > vbest) { vbest = v; win = d; }
+                for (int q = 0; q < 8; ++q) out += s_flow[q][own] >> 1;
+                int win = -1;
+                int64_t vbest = -1;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int back = (d + 4) & 7;
+                    const int nb = (ly + dir_dy(d)) * LW + (lx + dir_dx(d));
+                    const uint32_t word = s_flow[back][nb];
+                    const int64_t v = word >> 1;
+                    in += v;
+                    if ((word & 1u) && v > vbest) { vbest = v; win = d; }
+                }
+                const int64_t e1 = ei1[k][0], i1 = ei1[k][1];
+                const int64_t i2 = i1 - out + in;
+                int32_t g2 = s_g[own];
+                uint8_t r2 = r_own[k];
+                if (win >= 0 && vbest > i1) {
+                    const int so = cell_stripe(x0 + lx - 1, y0 + ly - 1, btx) * capw;
+                    g_from = so + g2;
+                    g2 = s_g[(ly + dir_dy(win)) * LW + (lx + dir_dx(win))];
+                    r2 = (uint8_t)((win + 4) & 7);
+                    acc_t += 1;
+                    took = true;
+                    g_to = so + g2;
+                }
+                gst((i64x2*)EIn + t, i64x2{e1, i2});
+                gst(Gn + t, g2);
+                gst(Rn + t, r2);
+                acc_m += i2;
+                acc_f += (double)i2;
             }
-            const int64_t e1 = gld(EI1p + 2 * (int64_t)t), i1 = gld(EI1p + 2 * (int64_t)t + 1);
-            const int64_t i2 = i1 - out + in;
-            int32_t g2 = gld(Gc + t);
-            uint8_t r2 = gld(Rc + t);
-            if (win >= 0 && vbest > i1) {
-                const int so = cell_stripe(gx, gy, btx) * capw;
-                g_from = so + g2;
-                g2 = s_g[(ly + dir_dy(win)) * LW + (lx + dir_dx(win))];
-                r2 = (uint8_t)((win + 4) & 7);
-                acc_t += 1;
-                took = true;
-                g_to = so + g2;
-            }
-            gst((i64x2*)EIn + t, i64x2{e1, i2});
-            gst(Gn + t, g2);
-            gst(Rn + t, r2);
-            acc_m += i2;
-            acc_f += (double)i2;
+            // the genome counts follow the takeovers (the next step and radiation use them)
+            wave_count_add(cnt, g_from, -1, took);
+            wave_count_add(cnt, g_to, 1, took);
         }
-        // the genome counts follow the takeovers (the next step and radiation use them)
-        wave_count_add(cnt, g_from, -1, took);
-        wave_count_add(cnt, g_to, 1, took);
         __syncthreads();  // LDS reused by the next tile
     }
     if (wi >= 0) flush();
@@ -412,15 +437,15 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     if (wi >= 0) flush();
 }
 
-int phys_tile_w(int t) { return t == 1 ? 32 : (t == 2 ? 16 : 64); }
-int phys_tile_h(int t) { return t == 1 ? 8 : (t == 2 ? 16 : 4); }
+int phys_tile_w(int t) { return t == 1 ? 32 : 64; }
+int phys_tile_h(int t) { return t == 1 ? 8 : (t == 2 ? 8 : 4); }
 
 void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
                          hipStream_t s) {
     switch (phys_tile) {
         case 3: hipLaunchKernelGGL(k_physics_stream, dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
         case 1: hipLaunchKernelGGL((k_physics<32, 8>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
-        case 2: hipLaunchKernelGGL((k_physics<16, 16>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
+        case 2: hipLaunchKernelGGL((k_physics<64, 8>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
         default: hipLaunchKernelGGL((k_physics<64, 4>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
     }
 }

@@ -257,6 +257,24 @@ def test_tuning_choices_and_graph_give_identical_results(stream, W):
             np.testing.assert_array_equal(o[ch], outs[0][ch])
 
 
+@pytest.mark.parametrize("layers,hidden", [(3, 64), (2, 32)])
+def test_bf16_tuning_choices_are_identical(stream, layers, hidden):
+    """BF16 worlds: both network forms (register budgets) at every column-group
+    width and every physics tiling step to the same state."""
+    say("bf16 tunings", layers, hidden)
+    init = gh.heterogeneous_world(150, 90, n_genomes=9, layers=layers, hidden=hidden, seed=5, precision=1)
+    outs = []
+    for act, waves, tile in [(1, 0, 0), (1, 1, 0), (2, 1, 3), (4, 0, 1), (4, 1, 3), (2, 0, 2)]:
+        w = gh.make_world(init, stream)
+        w.set_tuning(act, waves, tile)
+        w.step(3)
+        outs.append(w.get_state())
+        w.close()
+    for o in outs[1:]:
+        for ch in ("E", "I", "C", "G", "R"):
+            np.testing.assert_array_equal(o[ch], outs[0][ch])
+
+
 def test_mass_conserved_many_steps(stream):
     init = gh.heterogeneous_world(128, 96, n_genomes=8, seed=21)
     w = gh.make_world(init, stream)
