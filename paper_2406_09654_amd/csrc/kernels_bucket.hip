@@ -109,6 +109,10 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
         if (w.ctl->counts_valid) continue;  // block-uniform: nothing to count
         int32_t* scount = w.stripe_counts + (int64_t)(unit & (kStripes - 1)) * w.cap;
         const int32_t* G = w.G[cur];
+        // the world's fields in registers: the atomics below would otherwise
+        // make the compiler reload them from memory at every use
+        const int Wd = w.W, Hd = w.H, btiles = w.btiles, btiles_x = w.btiles_x, capw = w.cap;
+        const uint8_t* const slot_set = w.slot_set;
         for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
         __syncthreads();
         uint32_t bad = 0;
@@ -119,18 +123,18 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
 #pragma unroll
         for (int tg = 0; tg < kBucketGroup; ++tg) {
             const int tile = (int)unit * kBucketGroup + tg;
-            tile_ok[tg] = tile < w.btiles;
-            ty[tg] = tile / w.btiles_x;
-            tx[tg] = tile - ty[tg] * w.btiles_x;
+            tile_ok[tg] = tile < btiles;
+            ty[tg] = tile / btiles_x;
+            tx[tg] = tile - ty[tg] * btiles_x;
             const int x = tx[tg] * kBucketTile + lane;
 #pragma unroll
             for (int it = 0; it < ROWS; ++it) {
                 const int y = ty[tg] * kBucketTile + wv + 4 * it;
-                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
-                int g = valid ? gld(G + (int64_t)y * w.W + x) : 0;
+                const bool valid = tile_ok[tg] && x < Wd && y < Hd;
+                int g = valid ? gld(G + (int64_t)y * Wd + x) : 0;
                 if (valid) {
-                    if (g < 0 || g >= w.cap) { bad |= kErrGenomeRange; g = 0; }
-                    else if (!w.slot_set[g]) bad |= kErrGenomeUnset;
+                    if (g < 0 || g >= capw) { bad |= kErrGenomeRange; g = 0; }
+                    else if (!slot_set[g]) bad |= kErrGenomeUnset;
                 }
                 gv[tg][it] = g;
             }
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
 #pragma unroll
             for (int it = 0; it < ROWS; ++it) {
                 const int y = ty[tg] * kBucketTile + wv + 4 * it;
-                const bool valid = tile_ok[tg] && x < w.W && y < w.H;
+                const bool valid = tile_ok[tg] && x < Wd && y < Hd;
                 const int g = gv[tg][it];
                 const int prev = __shfl_up(g, 1, 64);
                 const bool start = valid && (lane == 0 || prev != g);
@@ -206,11 +210,15 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
     for (int64_t u = xcd_block(); u < total; u += gridDim.x) {
         const int wi = find_world(b->chunk_prefix, n, u);
         const auto& w = *world_at(b, wi);
+        // the world's fields in registers: the atomics below would otherwise
+        // make the compiler reload them from memory at every use
+        const int Wd = w.W, Hd = w.H, btiles = w.btiles, btiles_x = w.btiles_x, capw = w.cap;
+        int32_t* const permp = w.perm;
         const int cur = ctl_cur(w.ctl);
         const int64_t unit = u - cld(b->chunk_prefix + (wi));
         const int32_t* G = w.G[cur];
         const uint8_t* Rc = w.R[cur];
-        int32_t* scur = w.cursor + (int64_t)(unit & (kStripes - 1)) * w.cap;
+        int32_t* scur = w.cursor + (int64_t)(unit & (kStripes - 1)) * capw;
         for (int k = threadIdx.x; k < kHashSlots; k += 256) {
             s_key[k] = -1;
 #pragma unroll
@@ -218,8 +226,8 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
         }
         __syncthreads();
         const int tile = (int)unit * kBucketGroup + wv;
-        const bool tile_ok = tile < w.btiles;
-        const int ty = tile / w.btiles_x, tx = tile - ty * w.btiles_x;
+        const bool tile_ok = tile < btiles;
+        const int ty = tile / btiles_x, tx = tile - ty * btiles_x;
         uint32_t pk[NS][NIT];
 #pragma unroll
         for (int st = 0; st < NS; ++st) {
@@ -229,16 +237,16 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int y = ty * kBucketTile + RPI * it + rsub;
-                const bool valid = tile_ok && x < w.W && y < w.H;
-                const int64_t i = (int64_t)y * w.W + x;
+                const bool valid = tile_ok && x < Wd && y < Hd;
+                const int64_t i = (int64_t)y * Wd + x;
                 const int g = valid ? gld(G + i) : 0;
                 rv[it] = valid ? (uint32_t)(gld(Rc + i) & 7) : 0u;
-                gv[it] = (g < 0 || g >= w.cap) ? 0 : g;  // ids were checked when counted
+                gv[it] = (g < 0 || g >= capw) ? 0 : g;  // ids were checked when counted
             }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int y = ty * kBucketTile + RPI * it + rsub;
-                const bool valid = tile_ok && x < w.W && y < w.H;
+                const bool valid = tile_ok && x < Wd && y < Hd;
                 const int g = gv[it];
                 const int prev = __shfl_up(g, 1, 64);
                 // runs of equal genomes inside each SW-cell row segment (valid lanes are a
@@ -280,12 +288,12 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int y = ty * kBucketTile + RPI * it + rsub;
-                if (tile_ok && x < w.W && y < w.H) {
+                if (tile_ok && x < Wd && y < Hd) {
                     const uint32_t v = pk[st][it];
                     const int pos = (v & kAbs) ? (int)(v & (uint32_t)kPermIndexMask)
                                                : s_cnt[wv][(v >> 12) & 0x7ffu] + (int)(v & 0xfffu);
-                    const int64_t i = (int64_t)y * w.W + x;
-                    gst(w.perm + pos, (int)i | (int)(v & (7u << kPermRotShift)));
+                    const int64_t i = (int64_t)y * Wd + x;
+                    gst(permp + pos, (int)i | (int)(v & (7u << kPermRotShift)));
                 }
             }
         }
