@@ -305,19 +305,22 @@ struct LaunchShape {
 // Launchers implemented in the kernel translation units.
 void launch_step_kernels(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
                          int act_cells, int act_waves, int phys_tile, hipStream_t s,
-                         float* debug_act);
-void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
+                         float* debug_act, int recount = 1);
+// recount = 0 skips the genome histogram (k_prep, k_count): only valid when
+// every world of the launch has counts that describe its current state.
+void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int recount = 1);
 void launch_act_only(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
                      int act_cells, int act_waves, hipStream_t s, float* debug_act);
 void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
                          hipStream_t s);
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
-void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only);
+void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only, int recount = 1);
 void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, int n_cu,
                  hipStream_t s);
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
-                    int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s);
+                    int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s,
+                    int recount = 1);
 void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
                          hipStream_t s);
 void launch_flip(const BatchDev* bdev, hipStream_t s);

@@ -55,9 +55,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total, int* s_tm
     return before + x - v;
 }
 
-// Zero the step accumulators of every world, and its genome histogram
-// unless the counts already describe the current state (physics and
-// radiation keep them current; only a new state from the host does not).
+// Zero every world's genome histogram unless its counts already describe
+// the current state (physics and radiation keep them current; only a new
+// state from the host does not).  Launched, with k_count, only when the host
+// has made some world's counts stale.
 __global__ __launch_bounds__(256) void k_prep(const BatchDev* __restrict__ b) {
     const int wi = blockIdx.y;
     if (wi >= b->n_worlds) return;
@@ -65,11 +66,6 @@ __global__ __launch_bounds__(256) void k_prep(const BatchDev* __restrict__ b) {
     if (!w.ctl->counts_valid)
         for (int g = blockIdx.x * 256 + threadIdx.x; g < kStripes * w.cap; g += gridDim.x * 256)
             w.stripe_counts[g] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        w.ctl->acc_mass = 0;
-        w.ctl->acc_mass_f64 = 0.0;
-        w.ctl->acc_takeovers = 0;
-    }
 }
 
 // LDS hash of genome -> slot index; returns -1 when the table has no room.
@@ -301,9 +297,10 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
     }
 }
 
-// Scan over genome slots, pass A: per 4096-slot block, the number of cells
-// (summing the partial counters into counts), of 64-cell network units, of
-// live genomes and of free slots.
+// Scan over genome slots, pass A: per kSlotBlock-slot block, the number of
+// cells (summing the stripe counters into counts), of 64-cell network units,
+// of live genomes and of free slots.  Each world's first block also resets
+// the world's step accumulators.
 __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict__ b) {
     __shared__ int s_red[4][4];
     const int n = cld(&b->n_worlds);
@@ -314,6 +311,11 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict_
         const int wi = find_world(b->slot_prefix, n, u);
         const auto& w = *world_at(b, wi);
         const int sb = (int)(u - cld(b->slot_prefix + (wi)));
+        if (sb == 0 && threadIdx.x == 0) {  // the step accumulators start from zero
+            w.ctl->acc_mass = 0;
+            w.ctl->acc_mass_f64 = 0.0;
+            w.ctl->acc_takeovers = 0;
+        }
         int c = 0, gsum = 0, live = 0, fr = 0;
         for (int k = 0; k < kSlotBlock / 256; ++k) {
             const int g = sb * kSlotBlock + k * 256 + threadIdx.x;
@@ -472,15 +474,17 @@ static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t
     hipLaunchKernelGGL(k_scan_write, dim3(ls.misc_blocks), dim3(256), 0, s, bdev, free_only);
 }
 
-void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only) {
-    const int cap_blocks = min(256, max(1, (kStripes * ls.max_cap + 255) / 256));
-    hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
-    hipLaunchKernelGGL(k_count, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
+void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only, int recount) {
+    if (recount) {
+        const int cap_blocks = min(256, max(1, (kStripes * ls.max_cap + 255) / 256));
+        hipLaunchKernelGGL(k_prep, dim3(cap_blocks, ls.max_worlds), dim3(256), 0, s, bdev);
+        hipLaunchKernelGGL(k_count, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
+    }
     launch_scan(bdev, ls, s, free_only);
 }
 
-void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
-    launch_hist_only(bdev, ls, s, 0);
+void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int recount) {
+    launch_hist_only(bdev, ls, s, 0, recount);
     hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
     hipLaunchKernelGGL(k_scatter<kScatterStrip>, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
 }

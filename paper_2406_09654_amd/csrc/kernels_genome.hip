@@ -390,11 +390,12 @@ void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int 
 }
 
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
-                    int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s) {
+                    int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s,
+                    int recount) {
     // free slots of the current state (the completed step's result), listed by
     // the slot scan; the counting pass inside runs only if the counts are not
     // current (right after a step they are)
-    launch_hist_only(bdev, ls, s, 1);
+    launch_hist_only(bdev, ls, s, 1, recount);
     const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
     // the hit test is a chain of 64-bit multiplies per cell: as many waves as fit
     const int hh = max(1, min(n_rad_blocks, ls.n_cu * 32));

@@ -452,8 +452,8 @@ void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_t
 
 void launch_step_kernels(const BatchDev* bdev, const LaunchShape& ls, int NL, int HID, int prec,
                          int act_cells, int act_waves, int phys_tile, hipStream_t s,
-                         float* debug_act) {
-    launch_bucket_only(bdev, ls, s);
+                         float* debug_act, int recount) {
+    launch_bucket_only(bdev, ls, s, recount);
     launch_act_only(bdev, ls, NL, HID, prec, act_cells, act_waves, s, debug_act);
     launch_physics_only(bdev, ls, phys_tile, s);
     launch_finalize(bdev, ls, s);

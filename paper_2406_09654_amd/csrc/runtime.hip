@@ -164,8 +164,13 @@ struct coralai_world {
     int act_cells = 2;
     int act_waves = 0;
     int phys_tile = 3;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;     // the step
     int graph_key = -1;
+    hipGraphExec_t graph_rc = nullptr;  // the step with the genome recount first
+    int graph_rc_key = -1;
+    // the device counts may not describe the current state (a new state, the
+    // autotuner's trials, a debug hook): the next bucketing recounts
+    bool counts_stale = true;
     Ctl* pinned = nullptr;
     // live phase timing
     bool profiling = false;
@@ -193,6 +198,8 @@ struct coralai_batch {
     LaunchShape ls;
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
+    hipGraphExec_t graph_rc = nullptr;  // with the genome recount first
+    int graph_rc_key = -1;
     // orders work between the batch's stream and its worlds' own streams
     hipEvent_t ev_order = nullptr;
     std::vector<coralai_world*> worlds;
@@ -278,6 +285,7 @@ int check_launch() {
 // The device genome counts no longer describe the current state (new state
 // from the host, or trial launches that ran physics without committing it).
 int invalidate_counts(coralai_world* w) {
+    w->counts_stale = true;
     HIP_TRY(hipMemsetAsync(&w->host.ctl->counts_valid, 0, sizeof(int32_t), w->stream));
     return CORALAI_OK;
 }
@@ -344,10 +352,10 @@ int tuning_key(int act_cells, int act_waves, int phys_tile) {
 }
 
 int capture_step(hipStream_t s, const BatchDev* bdev, const LaunchShape& ls, int NL, int HID,
-                 int prec, int act_cells, int act_waves, int phys_tile, hipGraphExec_t* out) {
+                 int prec, int act_cells, int act_waves, int phys_tile, int recount, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    launch_step_kernels(bdev, ls, NL, HID, prec, act_cells, act_waves, phys_tile, s, nullptr);
+    launch_step_kernels(bdev, ls, NL, HID, prec, act_cells, act_waves, phys_tile, s, nullptr, recount);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) return fail(CORALAI_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -449,6 +457,7 @@ int coralai_world_destroy(coralai_world* w) {
     if (!g.ok) return fail(CORALAI_E_BUSY, "world is in use");
     (void)hipStreamSynchronize(w->stream);
     destroy_graph(&w->graph);
+    destroy_graph(&w->graph_rc);
     for (auto& r : w->ev_pending) { (void)hipEventDestroy(r.second.first); (void)hipEventDestroy(r.second.second); }
     for (hipEvent_t e : w->ev_pool) (void)hipEventDestroy(e);
     (void)hipHostFree(w->pinned);
@@ -570,19 +579,28 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
     if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
     const bool use_graph = w->stream != nullptr && !w->profiling;
     const int key = tuning_key(w->act_cells, w->act_waves, w->phys_tile);
+    const bool stale = w->counts_stale && n_steps > 0;  // the first step recounts
     if (use_graph && (w->graph == nullptr || w->graph_key != key)) {
         destroy_graph(&w->graph);
         int rc = capture_step(w->stream, w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec,
-                              w->act_cells, w->act_waves, w->phys_tile, &w->graph);
+                              w->act_cells, w->act_waves, w->phys_tile, 0, &w->graph);
         if (rc) return rc;
         w->graph_key = key;
     }
+    if (use_graph && stale && (w->graph_rc == nullptr || w->graph_rc_key != key)) {
+        destroy_graph(&w->graph_rc);
+        int rc = capture_step(w->stream, w->bdev, w->ls, w->host.NL, w->host.HID, w->host.prec,
+                              w->act_cells, w->act_waves, w->phys_tile, 1, &w->graph_rc);
+        if (rc) return rc;
+        w->graph_rc_key = key;
+    }
     for (int k = 0; k < n_steps; ++k) {
+        const bool recount = stale && k == 0;
         if (use_graph) {
-            HIP_TRY(hipGraphLaunch(w->graph, w->stream));
+            HIP_TRY(hipGraphLaunch(recount ? w->graph_rc : w->graph, w->stream));
         } else {
             const WorldDev& h = w->host;
-            int rc = timed_phase(w, 0, [&] { launch_bucket_only(w->bdev, w->ls, w->stream); });
+            int rc = timed_phase(w, 0, [&] { launch_bucket_only(w->bdev, w->ls, w->stream, recount); });
             if (!rc) rc = timed_phase(w, 1, [&] {
                 launch_act_only(w->bdev, w->ls, h.NL, h.HID, h.prec, w->act_cells, w->act_waves,
                                 w->stream, nullptr);
@@ -592,6 +610,7 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
             if (rc) return rc;
         }
     }
+    if (n_steps > 0) w->counts_stale = false;
     int rc = check_launch();
     if (rc) return rc;
     if (out) {
@@ -614,8 +633,9 @@ int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_in
     else T = (uint64_t)std::floor(rate * 18446744073709551616.0);
     int rc = timed_phase(w, 4, [&] {
         launch_radiate(w->bdev, w->wdev, w->ls, w->host.NL, w->host.HID, w->host.prec, w->L.n_rad_blocks, T, sigma,
-                       step_index, w->stream);
+                       step_index, w->stream, w->counts_stale ? 1 : 0);
     });
+    w->counts_stale = false;
     if (rc) return rc;
     rc = check_launch();
     if (rc) return rc;
@@ -833,8 +853,10 @@ int coralai_batch_autotune(coralai_batch* b, int32_t* act_cells_out, int32_t* ac
                           &ac, &aw, &pt);
     if (rc) return rc;
     // the trial physics launches moved the worlds' genome counts off their states
-    for (coralai_world* w : ws)
+    for (coralai_world* w : ws) {
+        w->counts_stale = true;
         HIP_TRY(hipMemsetAsync(&w->host.ctl->counts_valid, 0, sizeof(int32_t), b->stream));
+    }
     b->act_cells = ac;
     b->act_waves = aw;
     if (act_cells_out) *act_cells_out = ac;
@@ -910,18 +932,29 @@ int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
     if (b->n == 0 || n_steps == 0) return CORALAI_OK;
     const bool use_graph = b->stream != nullptr;
     const int key = tuning_key(b->act_cells, b->act_waves, b->phys_tile);
+    bool stale = false;  // some world's counts are stale: the first step recounts
+    for (coralai_world* w : b->worlds) stale = stale || w->counts_stale;
     if (use_graph && (b->graph == nullptr || b->graph_key != key)) {
         destroy_graph(&b->graph);
         int rc = capture_step(b->stream, b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells,
-                              b->act_waves, b->phys_tile, &b->graph);
+                              b->act_waves, b->phys_tile, 0, &b->graph);
         if (rc) return rc;
         b->graph_key = key;
     }
-    for (int k = 0; k < n_steps; ++k) {
-        if (use_graph) HIP_TRY(hipGraphLaunch(b->graph, b->stream));
-        else launch_step_kernels(b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells, b->act_waves,
-                                 b->phys_tile, b->stream, nullptr);
+    if (use_graph && stale && (b->graph_rc == nullptr || b->graph_rc_key != key)) {
+        destroy_graph(&b->graph_rc);
+        int rc = capture_step(b->stream, b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells,
+                              b->act_waves, b->phys_tile, 1, &b->graph_rc);
+        if (rc) return rc;
+        b->graph_rc_key = key;
     }
+    for (int k = 0; k < n_steps; ++k) {
+        const bool recount = stale && k == 0;
+        if (use_graph) HIP_TRY(hipGraphLaunch(recount ? b->graph_rc : b->graph, b->stream));
+        else launch_step_kernels(b->bdev, b->ls, b->NL, b->HID, b->prec, b->act_cells, b->act_waves,
+                                 b->phys_tile, b->stream, nullptr, recount ? 1 : 0);
+    }
+    for (coralai_world* w : b->worlds) w->counts_stale = false;
     int rc = check_launch();
     if (rc) return rc;
     // later calls on a world's own stream (get_state, step, ...) wait for these steps
@@ -945,6 +978,7 @@ int coralai_batch_destroy(coralai_batch* b) {
     if (!b) return fail(CORALAI_E_INVALID, "batch is NULL");
     (void)hipStreamSynchronize(b->stream);
     destroy_graph(&b->graph);
+    destroy_graph(&b->graph_rc);
     if (b->ev_order) (void)hipEventDestroy(b->ev_order);
     delete b;
     return CORALAI_OK;
