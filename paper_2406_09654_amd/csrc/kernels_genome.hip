@@ -33,13 +33,16 @@ __device__ __forceinline__ float node_tanh(float s) {
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * s) + 1.0f);
 }
 
+// The CPPN at (x1, y_l, x2, y_l+1): node k's input is A_k . (x1, y_l, x2,
+// y_l+1, 1) = a_k x1 + c_k x2 + base_k, where base_k = b_k y_l + d_k y_l+1 + e_k
+// depends only on the genome and the layer (precomputed per genome).
 template <typename T>
-__device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, T x2, T y2, int out) {
+__device__ __forceinline__ T cppn_eval(const float* __restrict__ p, const T* __restrict__ base, T x1, T x2,
+                                       int out) {
     T s_out = T(0);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const T s = T(p[5 * k]) * x1 + T(p[5 * k + 1]) * y1 + T(p[5 * k + 2]) * x2 +
-                    T(p[5 * k + 3]) * y2 + T(p[5 * k + 4]);
+        const T s = T(p[5 * k]) * x1 + T(p[5 * k + 2]) * x2 + base[k];
         T h;
         switch (k & 3) {
             case 0: h = node_sin(s); break;
@@ -52,30 +55,40 @@ __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, T x1, T y1, 
     return s_out;
 }
 
+// Layer heights y_l = -1 + l * (2 / NL) and the stored scale factors of
+// stored_row_scale / stored_col_scale, in T: for T = float the products are
+// the same as the FP64 ones rounded once (the factors differ by powers of 2).
+template <typename T, int NL>
+__device__ __forceinline__ T layer_y(int l) { return T(-1) + T(l) * (T(2) / T(NL)); }
+template <typename T>
+__device__ __forceinline__ T row_scale(int nl, int layer, int row) {
+    if (layer < nl - 1) return T(kTanhScale);
+    return row < 6 ? T(-kLog2e) : (row < kNOut ? T(kLog2e) : T(1));
+}
+template <typename T>
+__device__ __forceinline__ T col_scale(int layer, int col) {
+    if (layer > 0) return T(-2);
+    return col % 6 < 2 ? T(0x1p-24) : T(1);
+}
+
 // Stored value of a weight / bias of a network with NL weight layers and HID
-// hidden units: the generated value times the stored scale factors
-// (stored_row_scale, stored_col_scale), then one rounding to FP32 or bf16.
-// Neuron j of a layer of L sits at x = -1 + j * (2 / (L - 1)) and layer l at
-// y = -1 + l * (2 / NL): with the shape fixed at compile time every divisor
-// is a constant, folded into a multiplier.
+// hidden units: the generated value times the stored scale factors, then
+// one rounding to FP32 or bf16.  Neuron j of a layer of L sits at
+// x = -1 + j * (2 / (L - 1)): with the shape fixed at compile time every
+// divisor is a constant, folded into a multiplier.
 template <typename T, int NL, int HID>
-__device__ __forceinline__ float cppn_weight(const float* p, int layer, int row, int col) {
-    constexpr T dy = T(2) / T(NL);
-    const T yi = T(-1) + T(layer) * dy, yo = T(-1) + T(layer + 1) * dy;
+__device__ __forceinline__ float cppn_weight(const float* p, const T* base, int layer, int row, int col) {
     const T x1 = T(-1) + T(col) * (layer == 0 ? T(2) / T(kNIn - 1) : T(2) / T(HID - 1));
     const T x2 = T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
     const T rs = layer == 0 ? T(1) / sqrt(T(kNIn)) : T(1) / sqrt(T(HID));  // 1 / sqrt(fan-in)
-    const T sc = T(stored_row_scale(NL, layer, row) * stored_col_scale(layer, col));
-    return (float)(cppn_eval<T>(p, x1, yi, x2, yo, 0) * rs * sc);
+    const T sc = row_scale<T>(NL, layer, row) * col_scale<T>(layer, col);
+    return (float)(cppn_eval<T>(p, base, x1, x2, 0) * rs * sc);
 }
 
 template <typename T, int NL, int HID>
-__device__ __forceinline__ float cppn_bias(const float* p, int layer, int row) {
-    constexpr T dy = T(2) / T(NL);
-    const T yi = T(-1) + T(layer) * dy, yo = T(-1) + T(layer + 1) * dy;
+__device__ __forceinline__ float cppn_bias(const float* p, const T* base, int layer, int row) {
     const T x2 = T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
-    const T sc = T(stored_row_scale(NL, layer, row));
-    return (float)(cppn_eval<T>(p, T(0), yi, x2, yo, 1) * sc);
+    return (float)(cppn_eval<T>(p, base, T(0), x2, 1) * row_scale<T>(NL, layer, row));
 }
 
 // Layer geometry of a bias element index.
@@ -108,11 +121,18 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     constexpr int ew = net_frags(NL, HID, PREC) * net_frag_elems(PREC);
     constexpr int eb = net_bias_floats(NL, HID);
     __shared__ float sp[kNParam];
+    __shared__ T sbase[NL][8];  // per layer and node: b y_l + d y_l+1 + e
     const int n = from_radiation ? w->ctl->n_new : n_host;
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
     for (int si = blockIdx.x; si < n; si += gridDim.x) {
         const int slot = uniform_i32(slots[si]);
         if (threadIdx.x < kNParam) sp[threadIdx.x] = w->params[(int64_t)slot * kNParam + threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x < NL * 8) {
+            const int l = threadIdx.x >> 3, k = threadIdx.x & 7;
+            sbase[l][k] = T(sp[5 * k + 1]) * layer_y<T, NL>(l) + T(sp[5 * k + 3]) * layer_y<T, NL>(l + 1) +
+                          T(sp[5 * k + 4]);
+        }
         __syncthreads();
         uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
         float* bdst = w->bias + (int64_t)slot * w->bias_stride;
@@ -122,11 +142,12 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
             if (e < ew) {
                 const FragCoord fc = frag_coord(NL, HID, PREC, e);
                 const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
-                if (fc.row < lout && fc.col < lin) v = cppn_weight<T, NL, HID>(sp, fc.layer, fc.row, fc.col);
+                if (fc.row < lout && fc.col < lin)
+                    v = cppn_weight<T, NL, HID>(sp, sbase[fc.layer], fc.layer, fc.row, fc.col);
             } else {
                 int layer, row;
                 bias_coord(NL, HID, e - ew, &layer, &row);
-                if (row < (layer == NL - 1 ? kNOut : HID)) v = cppn_bias<T, NL, HID>(sp, layer, row);
+                if (row < (layer == NL - 1 ? kNOut : HID)) v = cppn_bias<T, NL, HID>(sp, sbase[layer], layer, row);
             }
             if (!__builtin_isfinite(v)) { bad = kErrNonFinite; v = 0.0f; }
             if (e < ew) {
