@@ -22,7 +22,6 @@
 namespace coralai {
 
 constexpr int kHashSlots = 2048;
-constexpr int kScatterStrip = 16;  // strip width of the scatter's walk over a tile
 constexpr int kHashProbes = 64;
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
@@ -68,9 +67,12 @@ __global__ __launch_bounds__(256) void k_prep(const BatchDev* __restrict__ b) {
             w.stripe_counts[g] = 0;
 }
 
-// LDS hash of genome -> slot index; returns -1 when the table has no room.
-__device__ __forceinline__ int hash_find(int* s_key, int g, bool insert) {
-    int h = (int)(((uint32_t)g * 2654435761u) >> (32 - 11));
+// LDS hash of genome -> slot index (NSLOT = 2^LOG slots); returns -1 when
+// the table has no room.
+template <int LOG>
+__device__ __forceinline__ int hash_find_n(int* s_key, int g, bool insert) {
+    constexpr int NSLOT = 1 << LOG;
+    int h = (int)(((uint32_t)g * 2654435761u) >> (32 - LOG));
     for (int p = 0; p < kHashProbes; ++p) {
         const int k = s_key[h];
         if (k == g) return h;
@@ -79,9 +81,13 @@ __device__ __forceinline__ int hash_find(int* s_key, int g, bool insert) {
             const int old = atomicCAS(&s_key[h], -1, g);
             if (old == -1 || old == g) return h;
         }
-        h = (h + 1) & (kHashSlots - 1);
+        h = (h + 1) & (NSLOT - 1);
     }
     return -1;
+}
+__device__ __forceinline__ int hash_find(int* s_key, int g, bool insert) {
+    static_assert(kHashSlots == 2048, "hash_find indexes 2^11 slots");
+    return hash_find_n<11>(s_key, g, insert);
 }
 
 // Genome histogram.  A block takes a unit of kBucketGroup consecutive tiles
@@ -172,38 +178,37 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
     }
 }
 
-// Compaction into perm in one pass over the unit (kBucketGroup tiles, one
-// wavefront per 64 x 64 tile).  A wavefront walks its tile in SW-column
-// strips, 64/SW rows of a strip per instruction, so that a genome's cells of
-// the tile come strip by strip: with SW = 16 the network kernel's 64-cell
-// groups are compact 16 x 4 blocks of a patch, whose neighbourhoods overlap
-// (32- and 64-wide strips measured the same step time, the 16-wide walk the
-// cheapest scatter).  Each run of equal genomes in an SW-cell row segment
-// takes its rank inside the tile's
-// share of its genome with one LDS atomic on the wavefront's own counter
-// (after a hash insert); every cell keeps (slot, rank, rotation) in a
-// register.  Then per genome: the tiles' shares are laid out one after
-// another behind one global atomic on the unit's stripe cursor, and the cells
-// are written with no second lookup.  A genome that finds the table full
-// takes its run's positions straight from the cursor.  Perm entries carry
-// the cell's rotation in the high bits.
-static_assert(kBucketGroup == 4 && kBucketTile == 64, "one wavefront per 64 x 64 tile");
-template <int SW>  // strip width: 16, 32 or 64 columns
-__global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__ b) {
-    constexpr int NS = 64 / SW;        // strips per tile
-    constexpr int RPI = 64 / SW;       // rows per instruction
-    constexpr int NIT = 64 / RPI;      // instructions per strip
-    __shared__ int s_key[kHashSlots];
-    __shared__ int s_cnt[kBucketGroup][kHashSlots];  // per tile: cells so far, then the tile's base
+// Compaction into perm, one 64 x 64 tile per block and one wavefront per
+// 16-column strip of it.  A wavefront walks its strip four rows per
+// instruction, so that a genome's cells of the tile come strip by strip: the
+// network kernel's 64-cell groups are then compact 16 x 4 blocks of a patch,
+// whose neighbourhoods overlap.  Each run of equal genomes in a 16-cell row
+// segment takes its rank inside the strip's share of its genome with one LDS
+// atomic on the wavefront's own counter (after a hash insert); every cell
+// keeps (slot, rank, rotation) in a register.  Then per genome: the strips'
+// shares are laid out one after another behind one global atomic on the
+// unit's stripe cursor, and the cells are written with no second lookup.  A
+// genome that finds the table full takes its run's positions straight from
+// the cursor.  Perm entries carry the cell's rotation in the high bits.
+// (Sixteen dependent steps per wavefront and a small register and LDS
+// footprint keep many tiles in flight.)
+constexpr int kScatterHashLog = 10;
+constexpr int kScatterHash = 1 << kScatterHashLog;
+static_assert(kBucketTile == 64, "four 16-column strips per tile");
+__global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b) {
+    constexpr int SW = 16, RPI = 4, NIT = 16;  // strip width, rows per instruction, instructions
+    __shared__ int s_key[kScatterHash];
+    __shared__ int s_cnt[4][kScatterHash];  // per strip: cells so far, then the strip's base
     constexpr uint32_t kAbs = 0x80000000u;  // bits 0..25 hold an absolute position
-    // packed per cell: rotation << 26 | (kAbs | position  or  slot << 12 | rank in the tile)
+    // packed per cell: rotation << 26 | (kAbs | position  or  slot << 12 | rank in the strip)
     const int n = cld(&b->n_worlds);
     if (n <= 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane % SW, rsub = lane / SW;
-    const uint64_t segmask = (SW == 64 ? ~0ull : ((1ull << SW) - 1ull)) << (SW * rsub);
-    const int64_t total = cld(b->chunk_prefix + (n));
-    for (int64_t u = xcd_block(); u < total; u += gridDim.x) {
+    const uint64_t segmask = ((1ull << SW) - 1ull) << (SW * rsub);
+    const int64_t total = cld(b->chunk_prefix + (n)) * kBucketGroup;  // tiles
+    for (int64_t tt = xcd_block(); tt < total; tt += gridDim.x) {
+        const int64_t u = tt / kBucketGroup;
         const int wi = find_world(b->chunk_prefix, n, u);
         const auto& w = *world_at(b, wi);
         // the world's fields in registers: the atomics below would otherwise
@@ -215,19 +220,18 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
         const int32_t* G = w.G[cur];
         const uint8_t* Rc = w.R[cur];
         int32_t* scur = w.cursor + (int64_t)(unit & (kStripes - 1)) * capw;
-        for (int k = threadIdx.x; k < kHashSlots; k += 256) {
+        for (int k = threadIdx.x; k < kScatterHash; k += 256) {
             s_key[k] = -1;
 #pragma unroll
-            for (int t = 0; t < kBucketGroup; ++t) s_cnt[t][k] = 0;
+            for (int t = 0; t < 4; ++t) s_cnt[t][k] = 0;
         }
         __syncthreads();
-        const int tile = (int)unit * kBucketGroup + wv;
+        const int tile = (int)unit * kBucketGroup + (int)(tt - u * kBucketGroup);
         const bool tile_ok = tile < btiles;
         const int ty = tile / btiles_x, tx = tile - ty * btiles_x;
-        uint32_t pk[NS][NIT];
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int x = tx * kBucketTile + SW * st + col;
+        const int x = tx * kBucketTile + SW * wv + col;  // this wavefront's strip
+        uint32_t pk[NIT];
+        {
             int gv[NIT];
             uint32_t rv[NIT];
 #pragma unroll
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
                 const bool valid = tile_ok && x < Wd && y < Hd;
                 const int g = gv[it];
                 const int prev = __shfl_up(g, 1, 64);
-                // runs of equal genomes inside each SW-cell row segment (valid lanes are a
+                // runs of equal genomes inside each 16-cell row segment (valid lanes are a
                 // prefix of their segment)
                 const bool start = valid && (col == 0 || prev != g);
                 const uint64_t starts = __ballot(start);
@@ -255,45 +259,40 @@ __global__ __launch_bounds__(256, 2) void k_scatter(const BatchDev* __restrict__
                     const uint64_t later = starts & ~((2ull << lane) - 1ull) & segmask;
                     const int seg_end = SW * rsub + (int)__popcll(vmask & segmask);
                     const int len = (later ? __ffsll((unsigned long long)later) - 1 : seg_end) - lane;
-                    const int h = hash_find(s_key, g, true);
+                    const int h = hash_find_n<kScatterHashLog>(s_key, g, true);
                     mine = h >= 0 ? ((uint32_t)h << 12) | (uint32_t)atomicAdd(&s_cnt[wv][h], len)
                                   : kAbs | (uint32_t)atomicAdd(scur + g, len);
                 }
                 const uint64_t upto = starts & ((2ull << lane) - 1ull);
                 const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
-                pk[st][it] = (__shfl(mine, rs, 64) + (uint32_t)(lane - rs)) | (rv[it] << kPermRotShift);
+                pk[it] = (__shfl(mine, rs, 64) + (uint32_t)(lane - rs)) | (rv[it] << kPermRotShift);
             }
-            __builtin_amdgcn_sched_barrier(0);  // one strip's loads in flight at a time (registers)
         }
         __syncthreads();
-        // per genome: one global atomic; the tiles' shares laid out in tile order
-        for (int k = threadIdx.x; k < kHashSlots; k += 256) {
+        // per genome: one global atomic; the strips' shares laid out in strip order
+        for (int k = threadIdx.x; k < kScatterHash; k += 256) {
             const int g = s_key[k];
             if (g < 0) continue;
-            int c[kBucketGroup], tot = 0;
+            int c[4], tot = 0;
 #pragma unroll
-            for (int t = 0; t < kBucketGroup; ++t) { c[t] = s_cnt[t][k]; tot += c[t]; }
+            for (int t = 0; t < 4; ++t) { c[t] = s_cnt[t][k]; tot += c[t]; }
             int base = atomicAdd(scur + g, tot);
 #pragma unroll
-            for (int t = 0; t < kBucketGroup; ++t) { s_cnt[t][k] = base; base += c[t]; }
+            for (int t = 0; t < 4; ++t) { s_cnt[t][k] = base; base += c[t]; }
         }
         __syncthreads();
 #pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            const int x = tx * kBucketTile + SW * st + col;
-#pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const int y = ty * kBucketTile + RPI * it + rsub;
-                if (tile_ok && x < Wd && y < Hd) {
-                    const uint32_t v = pk[st][it];
-                    const int pos = (v & kAbs) ? (int)(v & (uint32_t)kPermIndexMask)
-                                               : s_cnt[wv][(v >> 12) & 0x7ffu] + (int)(v & 0xfffu);
-                    const int64_t i = (int64_t)y * Wd + x;
-                    gst(permp + pos, (int)i | (int)(v & (7u << kPermRotShift)));
-                }
+        for (int it = 0; it < NIT; ++it) {
+            const int y = ty * kBucketTile + RPI * it + rsub;
+            if (tile_ok && x < Wd && y < Hd) {
+                const uint32_t v = pk[it];
+                const int pos = (v & kAbs) ? (int)(v & (uint32_t)kPermIndexMask)
+                                           : s_cnt[wv][(v >> 12) & 0x3ffu] + (int)(v & 0xfffu);
+                const int64_t i = (int64_t)y * Wd + x;
+                gst(permp + pos, (int)i | (int)(v & (7u << kPermRotShift)));
             }
         }
-        __syncthreads();  // the table is cleared for the next unit
+        __syncthreads();  // the table is cleared for the next tile
     }
 }
 
@@ -486,7 +485,7 @@ void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s
 void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int recount) {
     launch_hist_only(bdev, ls, s, 0, recount);
     hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
-    hipLaunchKernelGGL(k_scatter<kScatterStrip>, dim3(ls.chunk_blocks), dim3(256), 0, s, bdev);
+    hipLaunchKernelGGL(k_scatter, dim3(ls.n_cu * 16), dim3(256), 0, s, bdev);
 }
 
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s) {
