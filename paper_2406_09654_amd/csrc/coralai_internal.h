@@ -315,8 +315,8 @@ void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_t
                          hipStream_t s);
 void launch_finalize(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s);
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only, int recount = 1);
-void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, int n_cu,
-                 hipStream_t s);
+void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, uint64_t step,
+                 float sigma, int n_cu, hipStream_t s);
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
                     int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s,

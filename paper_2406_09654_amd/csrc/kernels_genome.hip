@@ -109,13 +109,37 @@ __device__ __forceinline__ int flat_w_offset(int nl, int hid, int l) {
     return o;
 }
 
-// from_radiation = 0: the n_host slots listed by coralai_set_genomes;
-// 1: the slots the last radiation call assigned (count on the device).
+// ------------------------------------------------------------------ Philox
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+}
+
+// Odd multiple of 2^-24 from the top 23 bits: exact in FP32, inside (0, 1).
+__device__ __forceinline__ float philox_uniform(uint64_t o) {
+    return (float)(2u * (uint32_t)(o >> 41) + 1u) * 0x1p-24f;
+}
+
 // One block per genome: its 56 parameters are read once into LDS, then the
 // block's threads walk the genome's weight and bias elements.
+// from_radiation = 0: the n_host slots listed by coralai_set_genomes;
+// 1: the slots the last radiation call assigned (count on the device).  A
+// radiation genome is first mutated here: its parameters are the parent's
+// plus sigma * N(0, 1), four normals per lane 0..13 from Box-Muller on the
+// Philox block (cell, step, 1 + lane, 0); they are stored and go straight
+// to the block's LDS.
 template <int NL, int HID, int PREC>
 __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, int from_radiation,
-                                              int n_host) {
+                                              int n_host, uint64_t step, float sigma) {
     using T = typename std::conditional<PREC == kPrecBF16, float, double>::type;
     constexpr bool bf = PREC == kPrecBF16;
     constexpr int ew = net_frags(NL, HID, PREC) * net_frag_elems(PREC);
@@ -126,7 +150,32 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
     for (int si = blockIdx.x; si < n; si += gridDim.x) {
         const int slot = uniform_i32(slots[si]);
-        if (threadIdx.x < kNParam) sp[threadIdx.x] = w->params[(int64_t)slot * kNParam + threadIdx.x];
+        const int parent = from_radiation ? uniform_i32(((const int32_t*)w->stage_params)[si]) : -1;
+        if (parent >= 0) {  // radiation: hit list (cell, parent) in the staging buffers
+            if (threadIdx.x < 14) {
+                const int lane = threadIdx.x;
+                const int i = w->stage_slots[si];
+                const float* pp = w->params + (int64_t)parent * kNParam;
+                float* np = w->params + (int64_t)slot * kNParam;
+                uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(1 + lane), 0ull};
+                philox4x64_10(c, w->seed, 0ull);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
+                    const float rr = sqrtf(-2.0f * logf(u1));
+                    float sn, cs;
+                    sincospif(2.0f * u2, &sn, &cs);
+                    const int m = 4 * lane + 2 * h;
+                    const float v0 = pp[m] + sigma * (rr * cs), v1 = pp[m + 1] + sigma * (rr * sn);
+                    np[m] = v0;
+                    np[m + 1] = v1;
+                    sp[m] = v0;
+                    sp[m + 1] = v1;
+                }
+            }
+        } else if (threadIdx.x < kNParam) {
+            sp[threadIdx.x] = w->params[(int64_t)slot * kNParam + threadIdx.x];
+        }
         __syncthreads();
         if (threadIdx.x < NL * 8) {
             const int l = threadIdx.x >> 3, k = threadIdx.x & 7;
@@ -210,25 +259,7 @@ __global__ __launch_bounds__(256) void k_scatter_params(const WorldDev* __restri
     }
 }
 
-// ------------------------------------------------------------------ Philox
-
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-        k0 += 0x9E3779B97F4A7C15ull;
-        k1 += 0xBB67AE8584CAA73Bull;
-    }
-}
-
-// Odd multiple of 2^-24 from the top 23 bits: exact in FP32, inside (0, 1).
-__device__ __forceinline__ float philox_uniform(uint64_t o) {
-    return (float)(2u * (uint32_t)(o >> 41) + 1u) * 0x1p-24f;
-}
+// ------------------------------------------------------------------ radiation
 
 __global__ __launch_bounds__(256) void k_rad_hits(const WorldDev* __restrict__ w, uint64_t T,
                                                   uint64_t step) {
@@ -304,6 +335,8 @@ __global__ __launch_bounds__(1024) void k_rad_scan(const WorldDev* __restrict__ 
         ctl->hits = tot;
         ctl->n_new = nn;
         ctl->dropped = tot - nn;
+        ctl->hits_pub = tot;  // the call's published statistics
+        ctl->dropped_pub = tot - nn;
     }
 }
 
@@ -348,56 +381,23 @@ __global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__
     }
 }
 
-// New parameters of every assigned hit: parent + sigma * N(0, 1), one
-// wavefront per hit, lane b < 14 drawing Philox block (i, step, 1 + b, 0)
-// whose two pairs of uniforms give normals 4b .. 4b+3 by Box-Muller.
-__global__ __launch_bounds__(256) void k_rad_mutate(const WorldDev* __restrict__ w, uint64_t step,
-                                                    float sigma) {
-    const int n_new = w->ctl->n_new;
-    const int lane = threadIdx.x & 63;
-    const int32_t* hit_cell = w->stage_slots;
-    const int32_t* hit_parent = (const int32_t*)w->stage_params;
-    for (int r = blockIdx.x * 4 + (threadIdx.x >> 6); r < n_new; r += gridDim.x * 4) {
-        const int parent = hit_parent[r];
-        if (parent < 0 || lane >= 14) continue;
-        const int i = hit_cell[r];
-        const int slot = w->new_slots[r];
-        const float* pp = w->params + (int64_t)parent * kNParam;
-        float* np = w->params + (int64_t)slot * kNParam;
-        uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(1 + lane), 0ull};
-        philox4x64_10(c, w->seed, 0ull);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
-            const float rr = sqrtf(-2.0f * logf(u1));
-            float sn, cs;
-            sincospif(2.0f * u2, &sn, &cs);
-            const int m = 4 * lane + 2 * h;
-            np[m] = pp[m] + sigma * (rr * cs);
-            np[m + 1] = pp[m + 1] + sigma * (rr * sn);
-        }
-    }
-}
-
-__global__ void k_rad_finalize(const WorldDev* __restrict__ w) {
-    Ctl* ctl = w->ctl;
-    ctl->hits_pub = ctl->hits;
-    ctl->dropped_pub = ctl->dropped;
-}
 
 template <int NL, int HID, int PREC>
-static void launch_cppn_t(const WorldDev* wdev, int from_radiation, int n_host, int n_cu, hipStream_t s) {
+static void launch_cppn_t(const WorldDev* wdev, int from_radiation, int n_host, uint64_t step, float sigma,
+                          int n_cu, hipStream_t s) {
     // one block per genome (the count of a radiation call is known on the device only)
-    hipLaunchKernelGGL((k_cppn<NL, HID, PREC>), dim3(n_cu * 16), dim3(256), 0, s, wdev, from_radiation, n_host);
+    hipLaunchKernelGGL((k_cppn<NL, HID, PREC>), dim3(n_cu * 16), dim3(256), 0, s, wdev, from_radiation, n_host,
+                       step, sigma);
 }
 
-void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, int n_cu,
-                 hipStream_t s) {
+void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, uint64_t step,
+                 float sigma, int n_cu, hipStream_t s) {
     const bool bf = prec == kPrecBF16;
-    if (nl == 2 && hid == 32) (bf ? launch_cppn_t<2, 32, kPrecBF16> : launch_cppn_t<2, 32, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
-    else if (nl == 2) (bf ? launch_cppn_t<2, 64, kPrecBF16> : launch_cppn_t<2, 64, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
-    else if (hid == 32) (bf ? launch_cppn_t<3, 32, kPrecBF16> : launch_cppn_t<3, 32, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
-    else (bf ? launch_cppn_t<3, 64, kPrecBF16> : launch_cppn_t<3, 64, kPrecFP32>)(wdev, from_radiation, n_host, n_cu, s);
+    auto go = [&](auto fn) { fn(wdev, from_radiation, n_host, step, sigma, n_cu, s); };
+    if (nl == 2 && hid == 32) bf ? go(launch_cppn_t<2, 32, kPrecBF16>) : go(launch_cppn_t<2, 32, kPrecFP32>);
+    else if (nl == 2) bf ? go(launch_cppn_t<2, 64, kPrecBF16>) : go(launch_cppn_t<2, 64, kPrecFP32>);
+    else if (hid == 32) bf ? go(launch_cppn_t<3, 32, kPrecBF16>) : go(launch_cppn_t<3, 32, kPrecFP32>);
+    else bf ? go(launch_cppn_t<3, 64, kPrecBF16>) : go(launch_cppn_t<3, 64, kPrecFP32>);
 }
 
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s) {
@@ -423,9 +423,7 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
     hipLaunchKernelGGL(k_rad_hits, dim3(hh), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
     hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev);
-    hipLaunchKernelGGL(k_rad_mutate, dim3(ls.n_cu), dim3(256), 0, s, wdev, step, sigma);
-    launch_cppn(wdev, nl, hid, prec, 1, 0, ls.n_cu, s);
-    hipLaunchKernelGGL(k_rad_finalize, dim3(1), dim3(1), 0, s, wdev);
+    launch_cppn(wdev, nl, hid, prec, 1, 0, step, sigma, ls.n_cu, s);  // mutation, then the networks
 }
 
 }  // namespace coralai

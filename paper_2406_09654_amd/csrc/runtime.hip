@@ -554,7 +554,7 @@ int coralai_set_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids, co
     HIP_TRY(hipMemcpyAsync(w->host.stage_slots, slot_ids, 4 * (size_t)n, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(w->host.stage_params, cppn_params, 4 * (size_t)kNParam * n, hipMemcpyHostToDevice, w->stream));
     launch_scatter_params(w->wdev, n, w->stream);
-    launch_cppn(w->wdev, w->host.NL, w->host.HID, w->host.prec, 0, n, w->ls.n_cu, w->stream);
+    launch_cppn(w->wdev, w->host.NL, w->host.HID, w->host.prec, 0, n, 0, 0.0f, w->ls.n_cu, w->stream);
     int rc = check_launch();
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(w->stream));
