@@ -270,9 +270,9 @@ __global__ __launch_bounds__(256) void k_rad_hits(const WorldDev* __restrict__ w
         __syncthreads();
         const int64_t base = (int64_t)blk * kRadBlockCells + 16 * threadIdx.x;
         uint32_t bits = 0;  // base is a multiple of 16: four whole Philox blocks
-        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {  // four independent multiply chains interleave
             const int64_t i0 = base + 4 * q;
-            if (i0 >= N) break;
             uint64_t c[4] = {(uint64_t)(i0 >> 2), step, 0ull, 0ull};
             philox4x64_10(c, w->seed, 0ull);
 #pragma unroll
