@@ -209,10 +209,18 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                     if (cld(gofs + t + 1) > k0) { gn = t; break; }
             }
             if (gn < 0) {
+                // the largest g with gofs[g] <= k0, by a 64-way search: each lane
+                // probes one of 64 evenly spaced slots of [lo, hi], and the
+                // probes at or below k0 are a prefix (gofs does not decrease)
                 int lo = 0, hi = cap - 1;
                 while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (cld(gofs + mid) <= k0) lo = mid; else hi = mid - 1;
+                    const int step = (hi - lo + 63) / 64;
+                    const int pos = min(hi, lo + (lane + 1) * step);
+                    const int nle = (int)__popcll(__ballot(cld(gofs + pos) <= k0));
+                    const int nlo = nle > 0 ? min(hi, lo + nle * step) : lo;
+                    hi = nle < 64 ? min(hi, lo + (nle + 1) * step) - 1 : hi;
+                    lo = uniform_i32(nlo);
+                    hi = uniform_i32(hi);
                 }
                 gn = lo;
             }
