@@ -180,7 +180,7 @@ int coralai_batch_destroy(coralai_batch* b);
  * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 64x8, or 3 = streaming,
  * one thread per cell without LDS.  The batch versions tune the batch's
  * single captured step over its current worlds.  Defaults before any call:
- * act_cells 2, act_waves 0, phys_tile 3. */
+ * act_cells 2, act_waves 0, phys_tile 2. */
 int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* act_waves_out,
                      int32_t* phys_tile_out);
 int coralai_set_tuning(coralai_world* w, int32_t act_cells, int32_t act_waves, int32_t phys_tile);

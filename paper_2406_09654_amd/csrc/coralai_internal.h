@@ -215,6 +215,23 @@ __device__ __forceinline__ int xcd_block() {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Contiguous share [begin, end) of `total` items for logical part `part` of
+// `parts`: every part gets floor or ceil of total / parts.  With fewer items
+// than parts the non-empty shares are spread evenly over the part ids, so a
+// small job still reaches every XCD.
+__device__ __forceinline__ void balanced_share(int64_t total, int64_t part, int64_t parts, int64_t* begin,
+                                               int64_t* end) {
+    *begin = part * total / parts;
+    *end = (part + 1) * total / parts;
+}
+
+// First item of a block's strided loop over `total` items: XCD-contiguous
+// when the job fills the grid, else the hardware order (round robin over
+// the XCDs).
+__device__ __forceinline__ int64_t spread_block(int64_t total) {
+    return total >= (int64_t)gridDim.x ? (int64_t)xcd_block() : (int64_t)blockIdx.x;
+}
+
 // Scalar (constant address space) load of data that is invariant while the
 // kernel runs: prefix tables, counters written by earlier kernels.
 template <typename T>

@@ -107,6 +107,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     const int nworlds = cld(&b->n_worlds);
     if (nworlds <= 0) return;
     const int total = cld(b->group_prefix + (nworlds));
+    // chunks of ceil(total / waves) units: a small job keeps fewer waves busy,
+    // each with more units, which pays each wave's run setup (genome lookup,
+    // weights, biases) fewer times than one unit per wave would
     const int nwaves = gridDim.x * 4;
     const int per = (total + nwaves - 1) / nwaves;
     int u = uniform_i32((xcd_block() * 4 + wv) * per);

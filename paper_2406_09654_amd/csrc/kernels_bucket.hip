@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
     if (n <= 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t total = cld(b->chunk_prefix + (n));
-    for (int64_t u = xcd_block(); u < total; u += gridDim.x) {
+    for (int64_t u = spread_block(total); u < total; u += gridDim.x) {
         const int wi = find_world(b->chunk_prefix, n, u);
         const auto& w = *world_at(b, wi);
         const int cur = ctl_cur(w.ctl);
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
     const int col = lane % SW, rsub = lane / SW;
     const uint64_t segmask = ((1ull << SW) - 1ull) << (SW * rsub);
     const int64_t total = cld(b->chunk_prefix + (n)) * kBucketGroup;  // tiles
-    for (int64_t tt = xcd_block(); tt < total; tt += gridDim.x) {
+    for (int64_t tt = spread_block(total); tt < total; tt += gridDim.x) {
         const int64_t u = tt / kBucketGroup;
         const int wi = find_world(b->chunk_prefix, n, u);
         const auto& w = *world_at(b, wi);

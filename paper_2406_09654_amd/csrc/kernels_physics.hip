@@ -53,10 +53,8 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
     if (nworlds <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t total = cld(b->tile_prefix + (nworlds));
-    const int blk = xcd_block();
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    int64_t tile = (int64_t)blk * per;
-    const int64_t tend = min(total, tile + per);
+    int64_t tile, tend;
+    balanced_share(total, xcd_block(), gridDim.x, &tile, &tend);
 
     int wi = -1;
     int64_t world_hi = -1;
@@ -274,9 +272,8 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
         acc_f = 0.0;
         acc_t = 0;
     };
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    int64_t unit = (int64_t)xcd_block() * per;
-    const int64_t uend = min(total, unit + per);
+    int64_t unit, uend;
+    balanced_share(total, xcd_block(), gridDim.x, &unit, &uend);
     for (; unit < uend; ++unit) {
         if (unit >= world_hi) {
             if (wi >= 0) flush();

@@ -163,7 +163,7 @@ struct coralai_world {
     LaunchShape ls;
     int act_cells = 2;
     int act_waves = 0;
-    int phys_tile = 3;
+    int phys_tile = 2;
     hipGraphExec_t graph = nullptr;     // the step
     int graph_key = -1;
     hipGraphExec_t graph_rc = nullptr;  // the step with the genome recount first
@@ -194,7 +194,7 @@ struct coralai_batch {
     int32_t* tiles_x;
     int n = 0;
     int NL = 0, HID = 0, prec = 0;
-    int act_cells = 2, act_waves = 0, phys_tile = 3;
+    int act_cells = 2, act_waves = 0, phys_tile = 2;
     LaunchShape ls;
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
