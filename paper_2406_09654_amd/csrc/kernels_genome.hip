@@ -24,9 +24,95 @@ namespace coralai {
 // T = double for FP32 worlds (weights then rounded once to FP32), float for
 // BF16 worlds (whose weights are rounded to bf16, 2^-9 relative, so the
 // hardware sin / exp / reciprocal, accurate to ~1e-6 here, suffice).
-__device__ __forceinline__ double node_sin(double s) { return sin(s); }
-__device__ __forceinline__ double node_gauss(double s) { return exp(-s * s); }
-__device__ __forceinline__ double node_tanh(double s) { return tanh(s); }
+//
+// The FP64 node functions are written for the arguments a CPPN produces
+// (a x1 + c x2 + base with |x| <= 1): Cody-Waite reduction by pi/2 or ln 2,
+// split into parts that are each the double nearest to what the previous
+// parts leave of the constant, then the Taylor series of sin, cos or exp on
+// the reduced interval (|r| <= pi/4: the first omitted sin term is below
+// 1e-19; |r| <= ln2/2: the first omitted exp term is below 5e-18).  Each
+// result is within a few 2^-53 of its own scale, against the 2^-24 of the
+// rounding to FP32 that follows.  sin falls back to the library beyond
+// |s| = 2^20, where the three-part pi/2 would no longer suffice.
+template <int N>
+__device__ __forceinline__ constexpr double inv_factorial() {
+    double f = 1.0;
+    for (int k = 2; k <= N; ++k) f *= k;
+    return 1.0 / f;
+}
+
+// e^x = 2^k (1 + r q(r)), q(r) = 1 + r/2! + r^2/3! + ...; returns r q(r) and k
+__device__ __forceinline__ double exp_reduced(double x, int* k_out) {  // x in [-746, 60]
+    const double k = rint(x * 0x1.71547652b82fep+0);                     // x / ln 2
+    double r = fma(-k, 0x1.62e42fefa39efp-1, x);                         // ln 2, first part
+    r = fma(-k, 0x1.abc9e3b39803fp-56, r);                                // ln 2, second part
+    double q = inv_factorial<13>();
+    q = fma(q, r, inv_factorial<12>());
+    q = fma(q, r, inv_factorial<11>());
+    q = fma(q, r, inv_factorial<10>());
+    q = fma(q, r, inv_factorial<9>());
+    q = fma(q, r, inv_factorial<8>());
+    q = fma(q, r, inv_factorial<7>());
+    q = fma(q, r, inv_factorial<6>());
+    q = fma(q, r, inv_factorial<5>());
+    q = fma(q, r, inv_factorial<4>());
+    q = fma(q, r, inv_factorial<3>());
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    *k_out = (int)k;
+    return r * q;
+}
+
+__device__ __forceinline__ double node_sin(double s) {
+    if (!(fabs(s) < 0x1p20)) return sin(s);
+    const double k = rint(s * 0x1.45f306dc9c883p-1);  // s / (pi / 2)
+    double r = fma(-k, 0x1.921fb54442d18p+0, s);     // pi / 2, three parts
+    r = fma(-k, 0x1.1a62633145c07p-54, r);
+    r = fma(-k, -0x1.f1976b7ed8fbcp-110, r);
+    const double z = r * r;
+    double ps = -inv_factorial<17>();
+    ps = fma(ps, -z, inv_factorial<15>());
+    ps = fma(ps, -z, inv_factorial<13>());
+    ps = fma(ps, -z, inv_factorial<11>());
+    ps = fma(ps, -z, inv_factorial<9>());
+    ps = fma(ps, -z, inv_factorial<7>());
+    ps = fma(ps, -z, inv_factorial<5>());
+    ps = fma(ps, -z, inv_factorial<3>());
+    ps = fma(ps, -z, 1.0);
+    const double sn = ps * r;
+    double pc = inv_factorial<18>();
+    pc = fma(pc, -z, inv_factorial<16>());
+    pc = fma(pc, -z, inv_factorial<14>());
+    pc = fma(pc, -z, inv_factorial<12>());
+    pc = fma(pc, -z, inv_factorial<10>());
+    pc = fma(pc, -z, inv_factorial<8>());
+    pc = fma(pc, -z, inv_factorial<6>());
+    pc = fma(pc, -z, inv_factorial<4>());
+    pc = fma(pc, -z, 0.5);
+    const double cs = fma(pc, -z, 1.0);
+    const int qd = (int)(int64_t)k & 3;  // quadrant: sin(r + q pi/2)
+    const double v = (qd & 1) ? cs : sn;
+    return (qd & 2) ? -v : v;
+}
+
+__device__ __forceinline__ double node_gauss(double s) {
+    const double x = -s * s;
+    if (x < -746.0) return 0.0;  // NaN passes through
+    int k;
+    const double rq = exp_reduced(x, &k);
+    return ldexp(1.0 + rq, k);
+}
+
+__device__ __forceinline__ double node_tanh(double s) {
+    // tanh a = t / (t + 2) with t = e^2a - 1, which keeps its relative
+    // accuracy for small a (k = 0: t = r q(r)); beyond a = 20 tanh is 1 in FP64
+    const double a = fabs(s);
+    int k;
+    const double rq = exp_reduced(2.0 * (a > 20.0 ? 20.0 : a), &k);  // NaN passes through
+    const double t = k == 0 ? rq : ldexp(1.0 + rq, k) - 1.0;
+    return copysign(a > 20.0 ? 1.0 : t / (t + 2.0), s);
+}
+
 __device__ __forceinline__ float node_sin(float s) { return __sinf(s); }
 __device__ __forceinline__ float node_gauss(float s) { return __expf(-s * s); }
 __device__ __forceinline__ float node_tanh(float s) {

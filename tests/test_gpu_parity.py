@@ -46,6 +46,29 @@ def test_cppn_weights_match_oracle(stream, layers, hidden, prec):
     w.close()
 
 
+@pytest.mark.parametrize("layers,scale", [(2, 1.0), (3, 1.0), (3, 4.0)])
+def test_fp32_cppn_weights_within_two_roundings(stream, layers, scale):
+    """FP32 networks: each weight is the FP64 CPPN value rounded to FP32 when
+    stored and again when the debug hook divides out the stored scale factor
+    (not a power of 2 for most rows), so each element is within two FP32
+    roundings of the oracle's FP64 value.  A parameter scale of 4 takes the
+    sin arguments over many quadrants, the gaussians to underflow and the
+    tanh nodes into saturation."""
+    say("cppn fp32 elementwise", layers, scale)
+    init = gh.heterogeneous_world(8, 8, n_genomes=6, layers=layers, hidden=64, precision=0, seed=11,
+                                  scale=scale)
+    w = gh.make_world(init, stream)
+    d = gh.oracle_desc(init.spec)
+    size = oracle.net_size(d)
+    for s in range(6):
+        got = w.debug_get_weights(s, size).astype(np.float64)
+        ref = oracle.cppn_to_net(d, init.params[s].astype(np.float64))
+        bound = 2.0 ** -22 * np.abs(ref) + 1e-12 * np.abs(ref).max()
+        bad = np.flatnonzero(np.abs(got - ref) > bound)
+        assert bad.size == 0, (s, bad[:5], got[bad[:5]], ref[bad[:5]])
+    w.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_debug_weights_roundtrip(stream, prec):
     """Flat weights in, flat weights out: exact up to the one rounding of the
