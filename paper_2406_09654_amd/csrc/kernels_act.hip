@@ -364,36 +364,37 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         }
         wave_lds_sync();
 
-        // ---- 2. the network, CGI column groups of 16 cells at a time
+        // ---- 2. the network, G column groups of 16 cells per pass (pass cb
+        // covers groups cb G .. cb G + G - 1)
         floatx4 outv[4];
-#pragma unroll
-        for (int cb = 0; cb < 4 / CGI; ++cb) {
-            floatx4 acc[CGI][MT];
+        auto pass = [&](auto g_const, int cb) __attribute__((always_inline)) {
+            constexpr int G = decltype(g_const)::value;
+            floatx4 acc[G][MT];
             floatx4 bv0[MT];  // the biases enter as the first MFMA's accumulator
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) bv0[mt] = *(const floatx4*)(gbias + 16 * mt);
             if constexpr (NT::kBF) {
-                bf16x8 xin[CGI][KS0];
+                bf16x8 xin[G][KS0];
 #pragma unroll
-                for (int cc = 0; cc < CGI; ++cc)
+                for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                     for (int s = 0; s < KS0; ++s)
-                        xin[cc][s] = *(const bf16x8*)(stage + (16 * (cb * CGI + cc) + n16) * NT::STAGE_ROW +
+                        xin[cc][s] = *(const bf16x8*)(stage + (16 * (cb * G + cc) + n16) * NT::STAGE_ROW +
                                                       (16 * q + 8 * s) * 2);
 #pragma unroll
                 for (int s = 0; s < KS0; ++s)
 #pragma unroll
-                    for (int cc = 0; cc < CGI; ++cc)
+                    for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
                             acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], s == 0 ? bv0[mt] : acc[cc][mt]);
             } else {
-                float xin[CGI][16];
+                float xin[G][16];
 #pragma unroll
-                for (int cc = 0; cc < CGI; ++cc)
+                for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        const floatx4 v = *(const floatx4*)(stage + (16 * (cb * CGI + cc) + n16) * NT::STAGE_ROW +
+                        const floatx4 v = *(const floatx4*)(stage + (16 * (cb * G + cc) + n16) * NT::STAGE_ROW +
                                                             q * 64 + 16 * t);
                         xin[cc][4 * t + 0] = v[0]; xin[cc][4 * t + 1] = v[1];
                         xin[cc][4 * t + 2] = v[2]; xin[cc][4 * t + 3] = v[3];
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
                 for (int s = 0; s < KS0; ++s)
 #pragma unroll
-                    for (int cc = 0; cc < CGI; ++cc)
+                    for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
                             acc[cc][mt] = mfma(w0[mt][s], xin[cc][s], s == 0 ? bv0[mt] : acc[cc][mt]);
@@ -412,9 +413,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                 const bool last = layer == NL - 1;
                 const float* lb = gbias + (last ? (NL == 3 ? 2 * HID : HID) : HID);
                 if constexpr (NT::kBF) {
-                    bf16x8 h[CGI][KSH];
+                    bf16x8 h[G][KSH];
 #pragma unroll
-                    for (int cc = 0; cc < CGI; ++cc)
+                    for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
@@ -425,11 +426,11 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                     if (last) {
                         const floatx4 bv = *(const floatx4*)lb;
 #pragma unroll
-                        for (int cc = 0; cc < CGI; ++cc) {
+                        for (int cc = 0; cc < G; ++cc) {
                             floatx4 o = mfma(wo[0], h[cc][0], bv);
 #pragma unroll
                             for (int s = 1; s < KSH; ++s) o = mfma(wo[s], h[cc][s], o);
-                            outv[cb * CGI + cc] = o;
+                            outv[cb * G + cc] = o;
                         }
                     } else {
                         floatx4 bvh[MT];
@@ -438,15 +439,15 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
-                            for (int cc = 0; cc < CGI; ++cc)
+                            for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                                 for (int mt = 0; mt < MT; ++mt)
                                     acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s], s == 0 ? bvh[mt] : acc[cc][mt]);
                     }
                 } else {
-                    float h[CGI][MT][4];
+                    float h[G][MT][4];
 #pragma unroll
-                    for (int cc = 0; cc < CGI; ++cc)
+                    for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -454,11 +455,11 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                     if (last) {
                         const floatx4 bv = *(const floatx4*)lb;
 #pragma unroll
-                        for (int cc = 0; cc < CGI; ++cc) {
+                        for (int cc = 0; cc < G; ++cc) {
                             floatx4 o = mfma(wo[0], h[cc][0][0], bv);
 #pragma unroll
                             for (int s = 1; s < KSH; ++s) o = mfma(wo[s], h[cc][s >> 2][s & 3], o);
-                            outv[cb * CGI + cc] = o;
+                            outv[cb * G + cc] = o;
                         }
                     } else {
                         floatx4 bvh[MT];
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
-                            for (int cc = 0; cc < CGI; ++cc)
+                            for (int cc = 0; cc < G; ++cc)
 #pragma unroll
                                 for (int mt = 0; mt < MT; ++mt)
                                     acc[cc][mt] = mfma(w1[mt % MT1][s], h[cc][s >> 2][s & 3],
@@ -475,7 +476,14 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                     }
                 }
             }
-        }
+        };
+        // passes whose groups hold no valid cell are skipped (only invalid
+        // lanes read their actuator rows): with one group per pass, a unit of
+        // at most 16 cells, such as the one-cell genomes radiation creates,
+        // takes a quarter of the network work
+#pragma unroll
+        for (int cb = 0; cb < 4 / CGI; ++cb)
+            if (16 * CGI * cb < cnt) pass(std::integral_constant<int, CGI>{}, cb);
         wave_lds_sync();  // all stage reads done before the actuator rows overwrite them
 #pragma unroll
         for (int c = 0; c < 4; ++c)
