@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     // tracks vector loads and stores in issue order, so a load issued after
     // a store could not be waited for without waiting for the store too.
     bool st_pending = false;
-    int st_i = 0;
+    int st_i = -1;
     uint32_t st_c[4], st_f[8];
     int64_t st_E1 = 0, st_I1 = 0;
 
@@ -162,21 +162,28 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         err = 0;
     };
 
+    // A lane with nothing to store (st_i < 0) stores at the end of each
+    // buffer, where a raw buffer store is discarded: the stores are issued by
+    // every lane of every unit, so the wait counts around them are exact.
     auto store_results = [&]() {
-        const uint32_t ofs = 4u * (uint32_t)st_i;
-        if (st_i >= 0) {
-            buf_st_f32x4(coralai_f32x4{__builtin_bit_cast(float, st_c[0]), __builtin_bit_cast(float, st_c[1]),
-                                       __builtin_bit_cast(float, st_c[2]), __builtin_bit_cast(float, st_c[3])},
-                         wC, 4 * ofs);
-            __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[0], st_f[1], st_f[2], st_f[3]}, wFlow, 8 * ofs, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[4], st_f[5], st_f[6], st_f[7]}, wFlow, 8 * ofs + 16, 0, 0);
-            buf_st_i64x2(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
-        }
+        const uint32_t ofs = st_i >= 0 ? 4u * (uint32_t)st_i : 4u * (uint32_t)Nd;
+        buf_st_f32x4(coralai_f32x4{__builtin_bit_cast(float, st_c[0]), __builtin_bit_cast(float, st_c[1]),
+                                   __builtin_bit_cast(float, st_c[2]), __builtin_bit_cast(float, st_c[3])},
+                     wC, 4 * ofs);
+        __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[0], st_f[1], st_f[2], st_f[3]}, wFlow, 8 * ofs, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[4], st_f[5], st_f[6], st_f[7]}, wFlow, 8 * ofs + 16, 0, 0);
+        buf_st_i64x2(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
+        st_i = -1;
         st_pending = false;
     };
 
-    // Outer loop: one run of units of a single genome (weights loaded once,
-    // loop-invariant in the inner loop); inner loop: the run's units.
+    // One loop over the wave's units.  A unit that starts a run of a new
+    // genome first looks the genome up and issues its weight loads; the
+    // bias and row-sum set-up then runs while the unit's gather is in
+    // flight.  Weights stay in registers for the rest of the run.
+    int run_end = -1;  // first unit past the current run
+    int gcount = 0, goff = 0;
+    floatx4 bias_ld = {0.f, 0.f, 0.f, 0.f};
     while (u < uend) {
         if (u >= world_hi) {
             if (st_pending) store_results();  // the buffers below change with the world
@@ -200,9 +207,11 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             counts = W->counts; offsets = W->offsets; gofs = W->gofs;
             wfrag = W->wfrag; bias = W->bias; wstride = W->wfrag_stride; bstride = W->bias_stride;
             g = -1;
-            g_hi = -1;
+            run_end = -1;
+            have_pf = false;
         }
-        {
+        const bool new_run = u >= run_end;
+        if (new_run) {
             const int k0 = u - world_lo;
             // the run's genome: short linear probe, else binary search over gofs
             int gn = -1;
@@ -230,6 +239,57 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             g = uniform_i32(gn);
             g_lo = cld(gofs + g);
             g_hi = cld(gofs + g + 1);
+            run_end = min(uend, world_lo + g_hi);
+            gcount = cld(counts + g);
+            goff = cld(offsets + g);
+        }
+        const int j = u - world_lo - g_lo;
+        const int cell0 = goff + j * kGroupCells;
+        const int cnt = min(kGroupCells, gcount - j * kGroupCells);
+        const bool valid = lane < cnt;
+        // a prefetched entry of a lane past the unit's cells is replaced by
+        // lane 0's, so that such lanes gather the addresses lane 0 gathers.
+        // Each branch waits for its own load (the empty asm uses the value),
+        // so the prefetched path does not wait for the stores issued after it.
+        int entry;
+        if (have_pf) {
+            const int e0 = __builtin_amdgcn_readfirstlane(e_pf);
+            entry = valid ? e_pf : e0;
+        } else {
+            entry = (int)__builtin_amdgcn_raw_buffer_load_b32(rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
+            asm volatile("" : "+v"(entry));
+        }
+        const int i = entry & kPermIndexMask, r = (entry >> kPermRotShift) & 7;
+        // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
+        const int y = i / Wd, x = i - y * Wd;
+        int nidx[9];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            nidx[p] = i;
+            if (p > 0) {
+                const int d = kernel_dir(r, p);
+                int nx = x + dir_dx(d), ny = y + dir_dy(d);
+                nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
+                ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
+                nidx[p] = ny * Wd + nx;
+            }
+        }
+        int64_t gE[9], gI[9];
+        float gC[9][4];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const i64x2 ei = buf_ld_i64x2(rEI, 16 * nidx[p]);
+            gE[p] = ei[0];
+            gI[p] = ei[1];
+            const coralai_f32x4 cv = buf_ld_f32x4(rC, 16 * nidx[p]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) gC[p][c] = cv[c];
+        }
+        // Loads in issue order: the gather, a new run's weights, the next
+        // unit's cell indices; then the previous unit's stores.  One counter
+        // covers them all and they complete in order, so each wait below
+        // leaves what was issued after its operand in flight.
+        if (new_run) {
             // weights of genome g -> registers
             const uint8_t* wb = wfrag + (int64_t)g * wstride + lane * (NT::FRAG_BYTES / 64);
 #pragma unroll
@@ -247,86 +307,23 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
             for (int s = 0; s < KSH; ++s)
                 wo[s] = gld((const frag_t*)(wb + (NT::F0 + NT::F1 + s) * NT::FRAG_BYTES));
-            const float* gb = bias + (int64_t)g * bstride;
-            for (int t = lane; t < net_bias_floats(NL, HID) / 4; t += 64)
-                *(floatx4*)(sbias + 4 * t) = gld((const floatx4*)(gb + 4 * t));
-            wave_lds_sync();
-            // layers after a hidden layer read r = (1 - tanh) / 2 through
-            // weights stored times -2: their biases gain -1/2 of the stored
-            // row sums (an MFMA against a ones operand)
-            {
-                frag_t ones;
-                if constexpr (NT::kBF) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
-                } else {
-                    ones = 1.0f;
-                }
-                if constexpr (NL == 3) {
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) {
-                        floatx4 rs = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int s = 0; s < KSH; ++s) rs = mfma(w1[mt][s], ones, rs);
-                        if (n16 == 0) {
-                            floatx4* bp = (floatx4*)(sbias + HID + 16 * mt + 4 * q);
-                            *bp = *bp - 0.5f * rs;
-                        }
-                    }
-                }
-                floatx4 rs = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < KSH; ++s) rs = mfma(wo[s], ones, rs);
-                if (n16 == 0) {
-                    floatx4* bp = (floatx4*)(sbias + (NL == 3 ? 2 * HID : HID) + 4 * q);
-                    *bp = *bp - 0.5f * rs;
-                }
-                wave_lds_sync();
-            }
+            static_assert(net_bias_floats(NL, HID) / 4 <= 64, "one bias load per lane");
+            if (lane < net_bias_floats(NL, HID) / 4)
+                bias_ld = gld((const floatx4*)(bias + (int64_t)g * bstride + 4 * lane));
         }
-        const int u_run_end = min(uend, world_lo + g_hi);
-        const int gcount = cld(counts + g);
-        const int goff = cld(offsets + g);
-        for (; u < u_run_end; ++u) {
-        const int j = u - world_lo - g_lo;
-        const int cell0 = goff + j * kGroupCells;
-        const int cnt = min(kGroupCells, gcount - j * kGroupCells);
-        const bool valid = lane < cnt;
-        const int entry = have_pf ? e_pf
-                                  : (int)__builtin_amdgcn_raw_buffer_load_b32(
-                                        rP, 4 * (cell0 + (valid ? lane : 0)), 0, 0);
-        const int i = entry & kPermIndexMask, r = (entry >> kPermRotShift) & 7;
-        // prefetch the next unit's cell index when it continues this genome
-        have_pf = u + 1 < u_run_end;
-        if (have_pf) {
-            const int cnt_n = min(kGroupCells, gcount - (j + 1) * kGroupCells);
-            e_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(
-                rP, 4 * (cell0 + kGroupCells + (lane < cnt_n ? lane : 0)), 0, 0);
-        }
-
-        // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
-        const int y = i / Wd, x = i - y * Wd;
-        int64_t gE[9], gI[9];
-        float gC[9][4];
-#pragma unroll
-        for (int p = 0; p < 9; ++p) {
-            int nidx = i;
-            if (p > 0) {
-                const int d = kernel_dir(r, p);
-                int nx = x + dir_dx(d), ny = y + dir_dy(d);
-                nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
-                ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
-                nidx = ny * Wd + nx;
-            }
-            const i64x2 ei = buf_ld_i64x2(rEI, 16 * nidx);
-            gE[p] = ei[0];
-            gI[p] = ei[1];
-            const coralai_f32x4 cv = buf_ld_f32x4(rC, 16 * nidx);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) gC[p][c] = cv[c];
+        // the next unit's cell indices: within the run, or the first unit of
+        // the next run, whose genome's cells follow this genome's in the
+        // world's perm (reads past the buffer return 0)
+        // (issued by every unit, used only when have_pf)
+        have_pf = u + 1 < uend && u + 1 < world_hi;
+        {
+            const bool same = u + 1 < run_end;
+            const int next0 = same ? cell0 + kGroupCells : goff + gcount;
+            const int cnt_n = same ? min(kGroupCells, gcount - (j + 1) * kGroupCells) : kGroupCells;
+            e_pf = (int)__builtin_amdgcn_raw_buffer_load_b32(rP, 4 * (next0 + (lane < cnt_n ? lane : 0)), 0, 0);
         }
         __builtin_amdgcn_sched_barrier(0);
-        if (st_pending) store_results();
+        store_results();  // the previous unit's results (past the buffers if none)
         __builtin_amdgcn_sched_barrier(0);
         const int64_t e_own = gE[0], i_own = gI[0];
         float uvec[kNIn];
@@ -364,6 +361,42 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         }
         wave_lds_sync();
 
+        if (new_run) {
+            if (lane < net_bias_floats(NL, HID) / 4) *(floatx4*)(sbias + 4 * lane) = bias_ld;
+            wave_lds_sync();
+            // layers after a hidden layer read r = (1 - tanh) / 2 through
+            // weights stored times -2: their biases gain -1/2 of the stored
+            // row sums (an MFMA against a ones operand)
+            {
+                frag_t ones;
+                if constexpr (NT::kBF) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+                } else {
+                    ones = 1.0f;
+                }
+                if constexpr (NL == 3) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        floatx4 rs = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int s = 0; s < KSH; ++s) rs = mfma(w1[mt][s], ones, rs);
+                        if (n16 == 0) {
+                            floatx4* bp = (floatx4*)(sbias + HID + 16 * mt + 4 * q);
+                            *bp = *bp - 0.5f * rs;
+                        }
+                    }
+                }
+                floatx4 rs = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KSH; ++s) rs = mfma(wo[s], ones, rs);
+                if (n16 == 0) {
+                    floatx4* bp = (floatx4*)(sbias + (NL == 3 ? 2 * HID : HID) + 4 * q);
+                    *bp = *bp - 0.5f * rs;
+                }
+                wave_lds_sync();
+            }
+        }
         // ---- 2. the network, G column groups of 16 cells per pass (pass cb
         // covers groups cb G .. cb G + G - 1)
         floatx4 outv[4];
@@ -579,7 +612,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             acc_mass += E1;
             acc_f64 += (double)E1;
         }
-        }  // units of the run
+        ++u;
     }
     if (st_pending) store_results();
     flush();
