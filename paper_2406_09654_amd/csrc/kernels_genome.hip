@@ -7,7 +7,9 @@
 // outputs (weight, bias) = B h, evaluated in FP64 for FP32 networks.  Neuron j of layer l sits at
 // (-1 + 2j/(L_l - 1), -1 + 2l/n); W_l[o][j] = CPPN_w(x_j, y_l, x_o, y_{l+1}) /
 // sqrt(L_l) and b_l[o] = CPPN_b(0, y_l, x_o, y_{l+1}).  One thread per weight
-// element, written straight into the MFMA fragment order of the act kernel.
+// element, combining a per-column and a per-row table of node-input parts
+// (built once per genome), written straight into the MFMA fragment order of
+// the act kernel.
 //
 // Radiation: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
 // (seed, 0); the block at counter (k, step, 0, 0) gives cells 4k..4k+3 one
@@ -63,8 +65,12 @@ __device__ __forceinline__ double exp_reduced(double x, int* k_out) {  // x in [
     return r * q;
 }
 
-__device__ __forceinline__ double node_sin(double s) {
-    if (!(fabs(s) < 0x1p20)) return sin(s);
+__device__ __forceinline__ void node_sincos(double s, double* sn_out, double* cs_out) {
+    if (!(fabs(s) < 0x1p20)) {
+        *sn_out = sin(s);
+        *cs_out = cos(s);
+        return;
+    }
     const double k = rint(s * 0x1.45f306dc9c883p-1);  // s / (pi / 2)
     double r = fma(-k, 0x1.921fb54442d18p+0, s);     // pi / 2, three parts
     r = fma(-k, 0x1.1a62633145c07p-54, r);
@@ -90,9 +96,14 @@ __device__ __forceinline__ double node_sin(double s) {
     pc = fma(pc, -z, inv_factorial<4>());
     pc = fma(pc, -z, 0.5);
     const double cs = fma(pc, -z, 1.0);
-    const int qd = (int)(int64_t)k & 3;  // quadrant: sin(r + q pi/2)
-    const double v = (qd & 1) ? cs : sn;
-    return (qd & 2) ? -v : v;
+    const int qd = (int)(int64_t)k & 3;  // quadrant: (sin, cos)(r + q pi/2)
+    double so = (qd & 1) ? cs : sn, co = (qd & 1) ? -sn : cs;
+    if (qd & 2) {
+        so = -so;
+        co = -co;
+    }
+    *sn_out = so;
+    *cs_out = co;
 }
 
 __device__ __forceinline__ double node_gauss(double s) {
@@ -113,32 +124,78 @@ __device__ __forceinline__ double node_tanh(double s) {
     return copysign(a > 20.0 ? 1.0 : t / (t + 2.0), s);
 }
 
-__device__ __forceinline__ float node_sin(float s) { return __sinf(s); }
+__device__ __forceinline__ void node_sincos(float s, float* sn, float* cs) {
+    *sn = __sinf(s);
+    *cs = __cosf(s);
+}
 __device__ __forceinline__ float node_gauss(float s) { return __expf(-s * s); }
 __device__ __forceinline__ float node_tanh(float s) {
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * s) + 1.0f);
 }
 
 // The CPPN at (x1, y_l, x2, y_l+1): node k's input is A_k . (x1, y_l, x2,
-// y_l+1, 1) = a_k x1 + c_k x2 + base_k, where base_k = b_k y_l + d_k y_l+1 + e_k
-// depends only on the genome and the layer (precomputed per genome).
+// y_l+1, 1) = (a_k x1 + base_k) + c_k x2, a column part plus a row part, where
+// base_k = b_k y_l + d_k y_l+1 + e_k depends only on the genome and the layer.
+// Per genome, each layer's columns and rows get a table entry; with
+// sin(A + B) = sin A cos B + cos A sin B and
+// tanh(A + B) = 1 - 2 / (e^2A e^2B + 1), a weight then costs two FMAs per sin
+// node, one exponential per gaussian and one reciprocal per tanh node.
+// Entry of a column (A_k) or row (B_k) part:
+enum : int { kTA1, kTA3, kTA5, kTA7, kTS0, kTC0, kTS4, kTC4, kTE2, kTE6, kTA2, kTA6, kTab };
+
+// e^2v, or -1 where the product of a column and a row value could leave the
+// finite range (|v| above 40 in FP32, 300 in FP64): tanh is then evaluated
+// directly on A + B
+__device__ __forceinline__ float exp2v_guarded(float v) { return fabsf(v) <= 40.0f ? __expf(2.0f * v) : -1.0f; }
+__device__ __forceinline__ double exp2v_guarded(double v) {
+    if (!(fabs(v) <= 300.0)) return -1.0;
+    int k;
+    const double rq = exp_reduced(2.0 * v, &k);
+    return ldexp(1.0 + rq, k);
+}
+
+// off = 0: column part a_k x + base_k; off = 2 (base null): row part c_k x
 template <typename T>
-__device__ __forceinline__ T cppn_eval(const float* __restrict__ p, const T* __restrict__ base, T x1, T x2,
-                                       int out) {
-    T s_out = T(0);
+__device__ __forceinline__ void fill_entry(T* e, const float* p, int off, const T* base, T x) {
+    T v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const T s = T(p[5 * k]) * x1 + T(p[5 * k + 2]) * x2 + base[k];
-        T h;
-        switch (k & 3) {
-            case 0: h = node_sin(s); break;
-            case 1: h = node_gauss(s); break;
-            case 2: h = node_tanh(s); break;
-            default: h = s; break;
-        }
-        s_out += T(p[40 + 8 * out + k]) * h;
-    }
-    return s_out;
+    for (int k = 0; k < 8; ++k) v[k] = T(p[5 * k + off]) * x + (base ? base[k] : T(0));
+    e[kTA1] = v[1];
+    e[kTA3] = v[3];
+    e[kTA5] = v[5];
+    e[kTA7] = v[7];
+    e[kTA2] = v[2];
+    e[kTA6] = v[6];
+    node_sincos(v[0], &e[kTS0], &e[kTC0]);
+    node_sincos(v[4], &e[kTS4], &e[kTC4]);
+    e[kTE2] = exp2v_guarded(v[2]);
+    e[kTE6] = exp2v_guarded(v[6]);
+}
+
+__device__ __forceinline__ float tanh_sum(float e, float f, float a, float b) {
+    if (e < 0.0f || f < 0.0f) return node_tanh(a + b);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e * f + 1.0f);
+}
+__device__ __forceinline__ double tanh_sum(double e, double f, double a, double b) {
+    if (e < 0.0 || f < 0.0) return node_tanh(a + b);
+    return 1.0 - 2.0 / (e * f + 1.0);
+}
+
+// Output `out` (0 weight, 1 bias) of the CPPN at a column entry c and a row
+// entry r: sum over the nodes of B_out,k phi_k(A_k + B_k), in node order.
+template <typename T>
+__device__ __forceinline__ T cppn_eval(const float* __restrict__ p, const T* __restrict__ c, const T* __restrict__ r,
+                                       int out) {
+    const float* po = p + 40 + 8 * out;
+    T s = T(po[0]) * (c[kTS0] * r[kTC0] + c[kTC0] * r[kTS0]);
+    s += T(po[1]) * node_gauss(c[kTA1] + r[kTA1]);
+    s += T(po[2]) * tanh_sum(c[kTE2], r[kTE2], c[kTA2], r[kTA2]);
+    s += T(po[3]) * (c[kTA3] + r[kTA3]);
+    s += T(po[4]) * (c[kTS4] * r[kTC4] + c[kTC4] * r[kTS4]);
+    s += T(po[5]) * node_gauss(c[kTA5] + r[kTA5]);
+    s += T(po[6]) * tanh_sum(c[kTE6], r[kTE6], c[kTA6], r[kTA6]);
+    s += T(po[7]) * (c[kTA7] + r[kTA7]);
+    return s;
 }
 
 // Layer heights y_l = -1 + l * (2 / NL) and the stored scale factors of
@@ -163,18 +220,25 @@ __device__ __forceinline__ T col_scale(int layer, int col) {
 // x = -1 + j * (2 / (L - 1)): with the shape fixed at compile time every
 // divisor is a constant, folded into a multiplier.
 template <typename T, int NL, int HID>
-__device__ __forceinline__ float cppn_weight(const float* p, const T* base, int layer, int row, int col) {
-    const T x1 = T(-1) + T(col) * (layer == 0 ? T(2) / T(kNIn - 1) : T(2) / T(HID - 1));
-    const T x2 = T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
-    const T rs = layer == 0 ? T(1) / sqrt(T(kNIn)) : T(1) / sqrt(T(HID));  // 1 / sqrt(fan-in)
-    const T sc = row_scale<T>(NL, layer, row) * col_scale<T>(layer, col);
-    return (float)(cppn_eval<T>(p, base, x1, x2, 0) * rs * sc);
+__device__ __forceinline__ T col_x(int layer, int col) {
+    return T(-1) + T(col) * (layer == 0 ? T(2) / T(kNIn - 1) : T(2) / T(HID - 1));
+}
+template <typename T, int NL, int HID>
+__device__ __forceinline__ T row_x(int layer, int row) {
+    return T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
 }
 
 template <typename T, int NL, int HID>
-__device__ __forceinline__ float cppn_bias(const float* p, const T* base, int layer, int row) {
-    const T x2 = T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
-    return (float)(cppn_eval<T>(p, base, T(0), x2, 1) * row_scale<T>(NL, layer, row));
+__device__ __forceinline__ float cppn_weight(const float* p, const T* ce, const T* re, int layer, int row, int col) {
+    const T rs = layer == 0 ? T(1) / sqrt(T(kNIn)) : T(1) / sqrt(T(HID));  // 1 / sqrt(fan-in)
+    const T sc = row_scale<T>(NL, layer, row) * col_scale<T>(layer, col);
+    return (float)(cppn_eval<T>(p, ce, re, 0) * rs * sc);
+}
+
+// biases: the CPPN at x1 = 0, second output
+template <typename T, int NL, int HID>
+__device__ __forceinline__ float cppn_bias(const float* p, const T* ce0, const T* re, int layer, int row) {
+    return (float)(cppn_eval<T>(p, ce0, re, 1) * row_scale<T>(NL, layer, row));
 }
 
 // Layer geometry of a bias element index.
@@ -232,6 +296,11 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     constexpr int eb = net_bias_floats(NL, HID);
     __shared__ float sp[kNParam];
     __shared__ T sbase[NL][8];  // per layer and node: b y_l + d y_l+1 + e
+    // per layer: column entries of the 64 columns and of x1 = 0 (biases, index
+    // 64), row entries of the 64 rows
+    __shared__ T stc[NL][65][kTab];
+    __shared__ T str[NL][64][kTab];
+    static_assert(HID <= 64 && kNIn <= 64, "one table entry per column and row");
     const int n = from_radiation ? w->ctl->n_new : n_host;
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
     for (int si = blockIdx.x; si < n; si += gridDim.x) {
@@ -269,6 +338,16 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
                           T(sp[5 * k + 4]);
         }
         __syncthreads();
+        for (int t = threadIdx.x; t < NL * (65 + 64); t += 256) {
+            if (t < NL * 65) {
+                const int l = t / 65, c = t - 65 * l;
+                fill_entry<T>(stc[l][c], sp, 0, sbase[l], c == 64 ? T(0) : col_x<T, NL, HID>(l, c));
+            } else {
+                const int l = (t - NL * 65) / 64, r = (t - NL * 65) - 64 * l;
+                fill_entry<T>(str[l][r], sp, 2, nullptr, row_x<T, NL, HID>(l, r));
+            }
+        }
+        __syncthreads();
         uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
         float* bdst = w->bias + (int64_t)slot * w->bias_stride;
         uint32_t bad = 0;
@@ -278,11 +357,13 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
                 const FragCoord fc = frag_coord(NL, HID, PREC, e);
                 const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
                 if (fc.row < lout && fc.col < lin)
-                    v = cppn_weight<T, NL, HID>(sp, sbase[fc.layer], fc.layer, fc.row, fc.col);
+                    v = cppn_weight<T, NL, HID>(sp, stc[fc.layer][fc.col], str[fc.layer][fc.row], fc.layer, fc.row,
+                                               fc.col);
             } else {
                 int layer, row;
                 bias_coord(NL, HID, e - ew, &layer, &row);
-                if (row < (layer == NL - 1 ? kNOut : HID)) v = cppn_bias<T, NL, HID>(sp, sbase[layer], layer, row);
+                if (row < (layer == NL - 1 ? kNOut : HID))
+                    v = cppn_bias<T, NL, HID>(sp, stc[layer][64], str[layer][row], layer, row);
             }
             if (!__builtin_isfinite(v)) { bad = kErrNonFinite; v = 0.0f; }
             if (e < ew) {
