@@ -167,6 +167,38 @@ def test_single_step_matches_oracle_fp32(stream, W, H, layers, hidden):
     w.close()
 
 
+def test_small_genomes_step_matches_oracle_every_tuning(stream):
+    """400 genomes drawn per cell on 48x40 (about 5 cells each, some empty),
+    as radiation leaves them: nearly every unit starts a run of a new genome
+    (prefetched cell indices across runs, weights loaded behind the gather)
+    and holds at most 16 cells (one network pass; the other column groups
+    are skipped).  Each tuning matches the oracle, and all give identical
+    results."""
+    say("small genomes")
+    init = gh.heterogeneous_world(48, 40, n_genomes=400, capacity=512, layers=3, hidden=64, seed=17)
+    d = gh.oracle_desc(init.spec)
+    ref, info = oracle.step(d, oracle.State.from_init(init), oracle.nets_for(d, init.params),
+                            want_margins=True)
+    counts = np.bincount(init.G.ravel(), minlength=512)
+    assert counts.max() <= 16 and (counts[:400] == 0).any()
+    first = None
+    for tuning in [(1, 0, 2), (2, 0, 0), (4, 0, 1), (1, 1, 3), (4, 1, 2)]:
+        say("  tuning", tuning)
+        w = gh.make_world(init, stream)
+        w.set_tuning(*tuning)
+        st = w.step(1, stats=True)
+        out = w.get_state()
+        gh.compare_step(out, ref, info["margins"], max_band_frac=0.05)
+        assert st["error_word"] == 0
+        assert int(out["E"].sum() + out["I"].sum()) == int(init.E.sum() + init.I.sum())
+        if first is None:
+            first = out
+        else:
+            for k in ("E", "I", "C", "G", "R"):
+                np.testing.assert_array_equal(out[k], first[k])
+        w.close()
+
+
 def test_plain_64_trajectory_snapshots(stream):
     """The 64x64 plain-method workload: single steps from GPU states taken
     along a 100-step GPU trajectory (steps 0, 10, 50, 99)."""
