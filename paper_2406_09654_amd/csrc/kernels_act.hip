@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     // a store could not be waited for without waiting for the store too.
     bool st_pending = false;
     int st_i = -1;
-    uint32_t st_c[4], st_f[8];
+    uint32_t st_c[4] = {0u, 0u, 0u, 0u}, st_f[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     int64_t st_E1 = 0, st_I1 = 0;
 
     // world fields kept in scalar registers
@@ -178,9 +178,9 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     };
 
     // One loop over the wave's units.  A unit that starts a run of a new
-    // genome first looks the genome up and issues its weight loads; the
-    // bias and row-sum set-up then runs while the unit's gather is in
-    // flight.  Weights stay in registers for the rest of the run.
+    // genome looks the genome up, issues its gather and then the genome's
+    // weight loads; the bias and row-sum set-up follows the conversion of the
+    // gathered values.  Weights stay in registers for the rest of the run.
     int run_end = -1;  // first unit past the current run
     int gcount = 0, goff = 0;
     floatx4 bias_ld = {0.f, 0.f, 0.f, 0.f};

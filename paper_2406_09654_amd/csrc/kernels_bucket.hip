@@ -269,16 +269,29 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
             }
         }
         __syncthreads();
-        // per genome: one global atomic; the strips' shares laid out in strip order
-        for (int k = threadIdx.x; k < kScatterHash; k += 256) {
-            const int g = s_key[k];
-            if (g < 0) continue;
-            int c[4], tot = 0;
+        // per genome: one global atomic; the strips' shares laid out in strip
+        // order.  A thread's atomics are issued together, then their results
+        // used, so their latencies overlap.
+        {
+            constexpr int KP = kScatterHash / 256;
+            int gk[KP], base[KP], c[KP][4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) { c[t] = s_cnt[t][k]; tot += c[t]; }
-            int base = atomicAdd(scur + g, tot);
+            for (int j = 0; j < KP; ++j) {
+                const int k = threadIdx.x + 256 * j;
+                gk[j] = s_key[k];
+                int tot = 0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) { s_cnt[t][k] = base; base += c[t]; }
+                for (int t = 0; t < 4; ++t) { c[j][t] = s_cnt[t][k]; tot += c[j][t]; }
+                base[j] = gk[j] >= 0 ? atomicAdd(scur + gk[j], tot) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                if (gk[j] < 0) continue;
+                const int k = threadIdx.x + 256 * j;
+                int bj = base[j];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) { s_cnt[t][k] = bj; bj += c[j][t]; }
+            }
         }
         __syncthreads();
 #pragma unroll
