@@ -154,9 +154,10 @@ __device__ __forceinline__ double exp2v_guarded(double v) {
     return ldexp(1.0 + rq, k);
 }
 
-// off = 0: column part a_k x + base_k; off = 2 (base null): row part c_k x
+// off = 0: column part a_k x + base_k; off = 2 (base null): row part c_k x.
+// Returns whether a tanh part is out of the exponential's range.
 template <typename T>
-__device__ __forceinline__ void fill_entry(T* e, const float* p, int off, const T* base, T x) {
+__device__ __forceinline__ bool fill_entry(T* e, const float* p, int off, const T* base, T x) {
     T v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = T(p[5 * k + off]) * x + (base ? base[k] : T(0));
@@ -170,30 +171,34 @@ __device__ __forceinline__ void fill_entry(T* e, const float* p, int off, const 
     node_sincos(v[4], &e[kTS4], &e[kTC4]);
     e[kTE2] = exp2v_guarded(v[2]);
     e[kTE6] = exp2v_guarded(v[6]);
+    return e[kTE2] < T(0) || e[kTE6] < T(0);
 }
 
+// GUARD: some part of this genome's tables is out of the exponential's range
+template <bool GUARD>
 __device__ __forceinline__ float tanh_sum(float e, float f, float a, float b) {
-    if (e < 0.0f || f < 0.0f) return node_tanh(a + b);
+    if (GUARD && (e < 0.0f || f < 0.0f)) return node_tanh(a + b);
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e * f + 1.0f);
 }
+template <bool GUARD>
 __device__ __forceinline__ double tanh_sum(double e, double f, double a, double b) {
-    if (e < 0.0 || f < 0.0) return node_tanh(a + b);
+    if (GUARD && (e < 0.0 || f < 0.0)) return node_tanh(a + b);
     return 1.0 - 2.0 / (e * f + 1.0);
 }
 
 // Output `out` (0 weight, 1 bias) of the CPPN at a column entry c and a row
 // entry r: sum over the nodes of B_out,k phi_k(A_k + B_k), in node order.
-template <typename T>
+template <typename T, bool GUARD>
 __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, const T* __restrict__ c, const T* __restrict__ r,
                                        int out) {
     const float* po = p + 40 + 8 * out;
     T s = T(po[0]) * (c[kTS0] * r[kTC0] + c[kTC0] * r[kTS0]);
     s += T(po[1]) * node_gauss(c[kTA1] + r[kTA1]);
-    s += T(po[2]) * tanh_sum(c[kTE2], r[kTE2], c[kTA2], r[kTA2]);
+    s += T(po[2]) * tanh_sum<GUARD>(c[kTE2], r[kTE2], c[kTA2], r[kTA2]);
     s += T(po[3]) * (c[kTA3] + r[kTA3]);
     s += T(po[4]) * (c[kTS4] * r[kTC4] + c[kTC4] * r[kTS4]);
     s += T(po[5]) * node_gauss(c[kTA5] + r[kTA5]);
-    s += T(po[6]) * tanh_sum(c[kTE6], r[kTE6], c[kTA6], r[kTA6]);
+    s += T(po[6]) * tanh_sum<GUARD>(c[kTE6], r[kTE6], c[kTA6], r[kTA6]);
     s += T(po[7]) * (c[kTA7] + r[kTA7]);
     return s;
 }
@@ -228,17 +233,17 @@ __device__ __forceinline__ T row_x(int layer, int row) {
     return T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
 }
 
-template <typename T, int NL, int HID>
+template <typename T, int NL, int HID, bool GUARD>
 __device__ __forceinline__ float cppn_weight(const float* p, const T* ce, const T* re, int layer, int row, int col) {
     const T rs = layer == 0 ? T(1) / sqrt(T(kNIn)) : T(1) / sqrt(T(HID));  // 1 / sqrt(fan-in)
     const T sc = row_scale<T>(NL, layer, row) * col_scale<T>(layer, col);
-    return (float)(cppn_eval<T>(p, ce, re, 0) * rs * sc);
+    return (float)(cppn_eval<T, GUARD>(p, ce, re, 0) * rs * sc);
 }
 
 // biases: the CPPN at x1 = 0, second output
-template <typename T, int NL, int HID>
+template <typename T, int NL, int HID, bool GUARD>
 __device__ __forceinline__ float cppn_bias(const float* p, const T* ce0, const T* re, int layer, int row) {
-    return (float)(cppn_eval<T>(p, ce0, re, 1) * row_scale<T>(NL, layer, row));
+    return (float)(cppn_eval<T, GUARD>(p, ce0, re, 1) * row_scale<T>(NL, layer, row));
 }
 
 // Layer geometry of a bias element index.
@@ -338,41 +343,49 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
                           T(sp[5 * k + 4]);
         }
         __syncthreads();
+        bool out_of_range = false;
         for (int t = threadIdx.x; t < NL * (65 + 64); t += 256) {
             if (t < NL * 65) {
                 const int l = t / 65, c = t - 65 * l;
-                fill_entry<T>(stc[l][c], sp, 0, sbase[l], c == 64 ? T(0) : col_x<T, NL, HID>(l, c));
+                out_of_range |= fill_entry<T>(stc[l][c], sp, 0, sbase[l], c == 64 ? T(0) : col_x<T, NL, HID>(l, c));
             } else {
                 const int l = (t - NL * 65) / 64, r = (t - NL * 65) - 64 * l;
-                fill_entry<T>(str[l][r], sp, 2, nullptr, row_x<T, NL, HID>(l, r));
+                out_of_range |= fill_entry<T>(str[l][r], sp, 2, nullptr, row_x<T, NL, HID>(l, r));
             }
         }
-        __syncthreads();
+        // block-uniform: only a genome with a part out of range takes the
+        // element loop with the direct tanh fallback
+        const bool guard = __syncthreads_or(out_of_range);
         uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
         float* bdst = w->bias + (int64_t)slot * w->bias_stride;
         uint32_t bad = 0;
-        for (int e = threadIdx.x; e < ew + eb; e += 256) {
-            float v = 0.0f;
-            if (e < ew) {
-                const FragCoord fc = frag_coord(NL, HID, PREC, e);
-                const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
-                if (fc.row < lout && fc.col < lin)
-                    v = cppn_weight<T, NL, HID>(sp, stc[fc.layer][fc.col], str[fc.layer][fc.row], fc.layer, fc.row,
-                                               fc.col);
-            } else {
-                int layer, row;
-                bias_coord(NL, HID, e - ew, &layer, &row);
-                if (row < (layer == NL - 1 ? kNOut : HID))
-                    v = cppn_bias<T, NL, HID>(sp, stc[layer][64], str[layer][row], layer, row);
+        auto elements = [&](auto guard_c) {
+            constexpr bool GUARD = decltype(guard_c)::value;
+            for (int e = threadIdx.x; e < ew + eb; e += 256) {
+                float v = 0.0f;
+                if (e < ew) {
+                    const FragCoord fc = frag_coord(NL, HID, PREC, e);
+                    const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
+                    if (fc.row < lout && fc.col < lin)
+                        v = cppn_weight<T, NL, HID, GUARD>(sp, stc[fc.layer][fc.col], str[fc.layer][fc.row],
+                                                           fc.layer, fc.row, fc.col);
+                } else {
+                    int layer, row;
+                    bias_coord(NL, HID, e - ew, &layer, &row);
+                    if (row < (layer == NL - 1 ? kNOut : HID))
+                        v = cppn_bias<T, NL, HID, GUARD>(sp, stc[layer][64], str[layer][row], layer, row);
+                }
+                if (!__builtin_isfinite(v)) { bad = kErrNonFinite; v = 0.0f; }
+                if (e < ew) {
+                    if constexpr (bf) ((__bf16*)dst)[e] = (__bf16)v;
+                    else ((float*)dst)[e] = v;
+                } else {
+                    bdst[e - ew] = v;
+                }
             }
-            if (!__builtin_isfinite(v)) { bad = kErrNonFinite; v = 0.0f; }
-            if (e < ew) {
-                if constexpr (bf) ((__bf16*)dst)[e] = (__bf16)v;
-                else ((float*)dst)[e] = v;
-            } else {
-                bdst[e - ew] = v;
-            }
-        }
+        };
+        if (guard) elements(std::integral_constant<bool, true>{});
+        else elements(std::integral_constant<bool, false>{});
         if (bad) atomicOr(&w->ctl->err, bad);
         __syncthreads();  // sp is rewritten for the next genome
     }

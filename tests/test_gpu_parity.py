@@ -69,6 +69,43 @@ def test_fp32_cppn_weights_within_two_roundings(stream, layers, scale):
     w.close()
 
 
+def _tanh_part_max(params, layers):
+    """Largest |column part| or |row part| of the tanh nodes (k = 2, 6) over
+    the layers: a_k x1 + b_k y_l + d_k y_l+1 + e_k and c_k x2, |x| <= 1."""
+    p = params.astype(np.float64).reshape(len(params), 56)
+    m = 0.0
+    for k in (2, 6):
+        a, b, c, d, e = (p[:, 5 * k + j] for j in range(5))
+        for l in range(layers):
+            y0, y1 = -1 + 2 * l / layers, -1 + 2 * (l + 1) / layers
+            m = max(m, float(np.max(np.abs(a) + np.abs(b * y0 + d * y1 + e))), float(np.max(np.abs(c))))
+    return m
+
+
+@pytest.mark.parametrize("prec,scale,limit", [(1, 16.0, 40.0), (0, 160.0, 300.0)])
+def test_cppn_weights_large_parameters(stream, prec, scale, limit):
+    """Parameters large enough that some tanh node's column or row part
+    leaves the range of the tabulated exponentials (40 in FP32, 300 in FP64):
+    those genomes evaluate tanh of the sum directly, and still match the
+    oracle (BF16 normwise, FP32 within two roundings per element)."""
+    say("cppn large parameters", prec, scale)
+    init = gh.heterogeneous_world(8, 8, n_genomes=6, layers=3, hidden=64, precision=prec, seed=23, scale=scale)
+    assert _tanh_part_max(init.params, 3) > limit
+    w = gh.make_world(init, stream)
+    d = gh.oracle_desc(init.spec)
+    size = oracle.net_size(d)
+    for s in range(6):
+        got = w.debug_get_weights(s, size).astype(np.float64)
+        ref = oracle.cppn_to_net(d, init.params[s].astype(np.float64))
+        if prec == 1:
+            assert gh.normwise(got, ref) <= 4e-3, (s, gh.normwise(got, ref))
+        else:
+            bound = 2.0 ** -22 * np.abs(ref) + 1e-12 * np.abs(ref).max()
+            bad = np.flatnonzero(np.abs(got - ref) > bound)
+            assert bad.size == 0, (s, bad[:5], got[bad[:5]], ref[bad[:5]])
+    w.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_debug_weights_roundtrip(stream, prec):
     """Flat weights in, flat weights out: exact up to the one rounding of the
