@@ -266,12 +266,24 @@ __device__ __forceinline__ int flat_w_offset(int nl, int hid, int l) {
 
 // ------------------------------------------------------------------ Philox
 
+// 64 x 64 -> 128-bit product from four 32 x 32 -> 64-bit multiply-adds
+// (none of the partial sums can overflow 64 bits)
+__device__ __forceinline__ void mul_128(uint64_t a, uint64_t b, uint64_t* lo, uint64_t* hi) {
+    const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+    const uint64_t p00 = a0 * b0;
+    const uint64_t t = a0 * b1 + (p00 >> 32);
+    const uint64_t u = a1 * b0 + (uint32_t)t;
+    *lo = (u << 32) | (uint32_t)p00;
+    *hi = a1 * b1 + (t >> 32) + (u >> 32);
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
     const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        uint64_t lo0, hi0, lo1, hi1;
+        mul_128(M0, c[0], &lo0, &hi0);
+        mul_128(M1, c[2], &lo1, &hi1);
         const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
         k0 += 0x9E3779B97F4A7C15ull;
