@@ -175,10 +175,12 @@ int coralai_batch_destroy(coralai_batch* b);
 /* Launch tuning.  coralai_autotune times the candidate configurations on the
  * world's current state (without advancing it) and keeps the fastest;
  * coralai_set_tuning forces one.  act_cells: column groups of 16 cells the
- * network kernel processes together (1, 2 or 4); act_waves: 0 = fewer
+ * network kernel processes together in one pass (1, 2 or 4; a pass holding
+ * none of a 64-cell unit's cells is skipped); act_waves: 0 = fewer
  * wavefronts per SIMD with more registers each, 1 = more wavefronts;
- * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 64x8, or 3 = streaming,
- * one thread per cell without LDS.  The batch versions tune the batch's
+ * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 64x8, or 3 = streaming
+ * without LDS (one thread per four cells of a row when the width is a
+ * multiple of 4, else per cell).  The batch versions tune the batch's
  * single captured step over its current worlds.  Defaults before any call:
  * act_cells 2, act_waves 0, phys_tile 2. */
 int coralai_autotune(coralai_world* w, int32_t* act_cells_out, int32_t* act_waves_out,
