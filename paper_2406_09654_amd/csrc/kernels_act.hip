@@ -109,11 +109,28 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     const int total = cld(b->group_prefix + (nworlds));
     // chunks of ceil(total / waves) units: a small job keeps fewer waves busy,
     // each with more units, which pays each wave's run setup (genome lookup,
-    // weights, biases) fewer times than one unit per wave would
+    // weights, biases) fewer times than one unit per wave would.  A large job
+    // is cut into nseg equal segments and a wave takes one chunk from each:
+    // the units of one-cell genomes (which radiation puts in the lowest free
+    // slots, mostly past the initial genomes) then spread over all waves
+    // instead of loading the waves at the end of the list.  (FP32 networks,
+    // with twice the weight bytes per run start, keep one segment.)
     const int nwaves = gridDim.x * 4;
-    const int per = (total + nwaves - 1) / nwaves;
-    int u = uniform_i32((xcd_block() * 4 + wv) * per);
-    const int uend = min(total, u + per);
+    const int nseg = NT::kBF && total >= 64 * nwaves ? 4 : 1;
+    const int seglen = (total + nseg - 1) / nseg;
+    const int per = (seglen + nwaves - 1) / nwaves;
+    const int wid = xcd_block() * 4 + wv;
+    int seg = 0;
+    int u = 0, uend = 0;
+    auto enter_segment = [&]() {
+        u = uniform_i32(min(total, seg * seglen + wid * per));
+        uend = uniform_i32(min(min(total, (seg + 1) * seglen), u + per));
+    };
+    enter_segment();
+    while (u >= uend && seg + 1 < nseg) {
+        ++seg;
+        enter_segment();
+    }
     if (u >= uend) return;  // no block-wide barriers below: waves are independent
 
     frag_t w0[MT][KS0];
@@ -613,6 +630,14 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             acc_f64 += (double)E1;
         }
         ++u;
+        // the next segment's chunk starts a new run
+        while (u >= uend && seg + 1 < nseg) {
+            ++seg;
+            enter_segment();
+            run_end = -1;
+            g = -1;
+            have_pf = false;
+        }
     }
     if (st_pending) store_results();
     flush();
