@@ -389,6 +389,10 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict
         w.ctl->total_groups = tot[1];
         w.ctl->live = tot[2];
         w.ctl->n_free = tot[3];
+        if (b->n_worlds == 1) {  // the prefix over worlds (k_world_prefix) of a lone world
+            b->group_prefix[0] = 0;
+            b->group_prefix[1] = tot[1];
+        }
     }
 }
 
@@ -497,7 +501,8 @@ void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s
 
 void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int recount) {
     launch_hist_only(bdev, ls, s, 0, recount);
-    hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
+    // a single world's prefix is written by k_scan_blocks
+    if (ls.max_worlds > 1) hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
     hipLaunchKernelGGL(k_scatter, dim3(ls.n_cu * 16), dim3(256), 0, s, bdev);
 }
 
