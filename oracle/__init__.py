@@ -20,6 +20,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 N_PARAM = 56
 N_IN = 54
 N_OUT = 14
+# near-tie report per target: logit gap, |v - I1|, v_win - v_second, magnitude, decided flag
+N_MARGIN = 5
 
 
 def build(force: bool = True) -> str:
@@ -42,13 +44,13 @@ class _Desc(ct.Structure):
 class Record(ct.Structure):
     _fields_ = [("e1", ct.c_int64), ("i1", ct.c_int64), ("flow", ct.c_int64 * 8),
                 ("explore_dir", ct.c_int32), ("explore_pos", ct.c_int32),
-                ("logit_gap", ct.c_double), ("runner_dir", ct.c_int32), ("pad", ct.c_int32)]
+                ("logit_gap", ct.c_double), ("runner_dir", ct.c_int32), ("exact", ct.c_int32)]
 
 
 RECORD_DTYPE = np.dtype([("e1", np.int64), ("i1", np.int64), ("flow", np.int64, (8,)),
                          ("explore_dir", np.int32), ("explore_pos", np.int32),
                          ("logit_gap", np.float64), ("runner_dir", np.int32),
-                         ("pad", np.int32)])
+                         ("exact", np.int32)])
 assert RECORD_DTYPE.itemsize == ct.sizeof(Record)
 
 _lib = None
@@ -222,7 +224,7 @@ def step(d: Desc, s: State, nets: np.ndarray, rows: tuple[int, int] | None = Non
     R2 = R.copy()
     act = np.full((N, N_OUT), np.nan) if want_act else None
     rec = np.zeros(N, dtype=RECORD_DTYPE) if want_records else None
-    mar = np.full((N, 4), np.nan) if want_margins else None
+    mar = np.full((N, N_MARGIN), np.nan) if want_margins else None
     nul = ct.c_void_p(0)
     tk = lib().orc_step_rows(ct.byref(d.c()), _p(E), _p(I), _p(C), _p(G), _p(R), _p(nets),
                              int(nets.shape[0]), int(y0), int(y1), _p(E2), _p(I2), _p(C2),
@@ -237,7 +239,7 @@ def step(d: Desc, s: State, nets: np.ndarray, rows: tuple[int, int] | None = Non
     if rec is not None:
         info["records"] = rec.reshape(H, W)
     if mar is not None:
-        info["margins"] = mar.reshape(H, W, 4)
+        info["margins"] = mar.reshape(H, W, N_MARGIN)
     return State(E2, I2, C2, G2, R2), info
 
 

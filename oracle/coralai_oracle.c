@@ -55,7 +55,7 @@ typedef struct {
     int32_t explore_pos;   /* kernel position p* in 1..8 */
     double logit_gap;      /* top-1 minus top-2 flow logit (FP64) */
     int32_t runner_dir;    /* absolute direction of the second-largest logit */
-    int32_t pad;
+    int32_t exact;         /* 1: every integer above is decided with margin (see floor_decided) */
 } orc_record;
 
 /* Directions: d at 45*d degrees counter-clockwise from +x, y pointing down. */
@@ -192,6 +192,22 @@ void orc_forward(const orc_desc* d, const double* net, const double* u, double* 
 
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
+/* Relative perturbation of a floored argument that an FP32 evaluation of the
+ * same step may make: the network outputs may differ by up to 1e-5 of their
+ * largest magnitude, which moves a sigmoid or a softmax weight by well under
+ * 1e-3 of its value; a factor 10 on top. */
+#define ORC_FLOOR_REL 1e-2
+
+/* floor(x) of a non-negative argument is decided when every value within
+ * ORC_FLOOR_REL * x of x has the same floor, or when x is exactly zero (one
+ * factor of the product is an exact zero, which any precision reproduces).
+ * Used only for the near-tie report of the parity tests, never for the
+ * step's results. */
+static int floor_decided(double x) {
+    if (x == 0.0) return 1;
+    return floor(x * (1.0 - ORC_FLOOR_REL)) == floor(x * (1.0 + ORC_FLOOR_REL));
+}
+
 /* Actuators -> local part of the physics (Experiment):
  *   invest / liquidate: x_inv = min(E, floor(rho_inv * sig(a0) * E)),
  *                       x_liq = min(I, floor(rho_liq * sig(a1) * I)),
@@ -206,8 +222,10 @@ static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 void orc_actuate(const orc_desc* d, int64_t e, int64_t i, int r, const double* a,
                  orc_record* rec, double* comm_out) {
     double se = sigmoid(a[0]), sl = sigmoid(a[1]);
-    int64_t xi = (int64_t)floor(d->rho_invest * se * (double)e);
-    int64_t xl = (int64_t)floor(d->rho_liquidate * sl * (double)i);
+    const double arg_inv = d->rho_invest * se * (double)e, arg_liq = d->rho_liquidate * sl * (double)i;
+    int64_t xi = (int64_t)floor(arg_inv);
+    int64_t xl = (int64_t)floor(arg_liq);
+    int exact = floor_decided(arg_inv) && floor_decided(arg_liq);
     if (xi > e) xi = e;
     if (xl > i) xl = i;
     if (xi < 0) xi = 0;
@@ -227,14 +245,17 @@ void orc_actuate(const orc_desc* d, int64_t e, int64_t i, int r, const double* a
         if (k != best && lg[k] > second) { second = lg[k]; runner = k; }
     rec->logit_gap = m - second;
     rec->runner_dir = orc_kernel_dir(r, runner + 1);
-    rec->pad = 0;
     double ex[8], s = 0.0;
     for (int k = 0; k < 8; ++k) { ex[k] = exp(lg[k] - m); s += ex[k]; }
-    int64_t F = (int64_t)floor(d->kappa_flow * (double)rec->i1);
+    const double arg_F = d->kappa_flow * (double)rec->i1;
+    int64_t F = (int64_t)floor(arg_F);
     if (F < 0) F = 0;
+    exact = exact && floor_decided(arg_F);
     int64_t used = 0;
     for (int k = 0; k < 8; ++k) {
-        int64_t f = (int64_t)floor((ex[k] / s) * (double)F);
+        const double arg_f = (ex[k] / s) * (double)F;
+        exact = exact && floor_decided(arg_f);
+        int64_t f = (int64_t)floor(arg_f);
         if (f > F - used) f = F - used;
         if (f < 0) f = 0;
         used += f;
@@ -242,6 +263,7 @@ void orc_actuate(const orc_desc* d, int64_t e, int64_t i, int r, const double* a
     }
     rec->explore_pos = best + 1;
     rec->explore_dir = orc_kernel_dir(r, best + 1);
+    rec->exact = exact;
 }
 
 /* Whole per-cell act: sense, network of the cell's genome, actuate. */
@@ -314,9 +336,17 @@ static int cell_physics(const orc_desc* d, const orc_record* rec_t, const orc_re
  *   E2, I2 (int64), C2 (4 planes, double), G2, R2;
  *   act (N x 14, nullable): raw network outputs of the rows;
  *   rec_out (N, nullable): per-cell records of the rows;
- *   margins (N x 4, nullable): per target (smallest flow-logit gap among the
- *   neighbours whose top two explore directions include t, |v_win - I1|,
- *   v_win - v_second when the winner takes over, max(v_win, I1)).
+ *   margins (N x 5, nullable): per target t, the decision margins of the
+ *   near-tie report:
+ *     0: smallest flow-logit gap (top-1 minus top-2) among the neighbours
+ *        whose two leading explore directions include t and that could
+ *        invest in t at all (some flow not decided to be exactly zero);
+ *     1: |v_win - I1(t)|, infinity without a candidate explorer;
+ *     2: v_win - v_second when the winner takes over, else infinity;
+ *     3: max(v_win, I1(t)) with a candidate, else 0;
+ *     4: 1 when I1(t) and every candidate's flows are decided integers
+ *        (floor_decided), so that the takeover and ranking decisions are
+ *        exact comparisons of exactly known integers; else 0.
  * Returns the number of takeovers in the rows, or -1 on a bad genome id. */
 int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, const double* C,
                       const int32_t* G, const uint8_t* R, const double* nets, int32_t n_genomes,
@@ -349,13 +379,19 @@ int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, con
         /* a neighbour's near-tied argmax matters to t only if one of its two
          * leading explore directions points at t */
         double gap = INFINITY;
+        int decided = rec[t].exact;
         for (int dd = 0; dd < 8; ++dd) {
             nidx[dd] = nbr(d, t, dd);
             nrec[dd] = &rec[nidx[dd]];
+            const orc_record* rn = nrec[dd];
             const int back = (dd + 4) & 7;
-            if ((nrec[dd]->explore_dir == back || nrec[dd]->runner_dir == back) &&
-                nrec[dd]->logit_gap < gap)
-                gap = nrec[dd]->logit_gap;
+            int64_t fsum = 0;
+            for (int k = 0; k < 8; ++k) fsum += rn->flow[k];
+            /* flows all exactly zero: it invests nothing in any direction */
+            const int idle = rn->exact && fsum == 0;
+            if ((rn->explore_dir == back || rn->runner_dir == back) && !idle && rn->logit_gap < gap)
+                gap = rn->logit_gap;
+            if (rn->explore_dir == back) decided = decided && rn->exact;
         }
         double mt, mr, mg;
         takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt,
@@ -364,10 +400,11 @@ int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, con
         for (int c = 0; c < 4; ++c) C2[c * N + t] = cn[c * N + t];
         if (rec_out) rec_out[t] = rec[t];
         if (margins) {
-            margins[t * 4 + 0] = gap;
-            margins[t * 4 + 1] = mt;
-            margins[t * 4 + 2] = mr;
-            margins[t * 4 + 3] = mg;
+            margins[t * 5 + 0] = gap;
+            margins[t * 5 + 1] = mt;
+            margins[t * 5 + 2] = mr;
+            margins[t * 5 + 3] = mg;
+            margins[t * 5 + 4] = decided ? 1.0 : 0.0;
         }
     }
     free(rec);
@@ -390,7 +427,7 @@ int64_t orc_physics_from_records(const orc_desc* d, const int64_t* i1, const int
         rec[i].explore_pos = 0;
         rec[i].logit_gap = 0;
         rec[i].runner_dir = 0;
-        rec[i].pad = 0;
+        rec[i].exact = 0;
     }
     int64_t takeovers = 0;
     for (int64_t t = 0; t < N; ++t) {

@@ -83,6 +83,17 @@ def sig(x):
     return 1.0 / (1.0 + math.exp(-x))
 
 
+# Relative perturbation of a floored argument within which an FP32 evaluation
+# of the same step may move it (the near-tie report of the parity tests).
+FLOOR_REL = 1e-2
+
+
+def floor_decided(x):
+    """Every value within FLOOR_REL * x of x has the same floor, or x is an
+    exact zero."""
+    return x == 0.0 or math.floor(x * (1.0 - FLOOR_REL)) == math.floor(x * (1.0 + FLOOR_REL))
+
+
 class World:
     def __init__(self, W, H, E, I, C, G, R, nets, rho_i, rho_l, kappa):
         self.W, self.H = W, H
@@ -106,8 +117,9 @@ class World:
             u += [self.E[c] * Q, self.I[c] * Q] + [self.C[k][c] for k in range(4)]
         a = run_net(self.nets[self.G[i]], u)
         e, inf = self.E[i], self.I[i]
-        x_inv = min(e, math.floor(self.rho_i * sig(a[0]) * e))
-        x_liq = min(inf, math.floor(self.rho_l * sig(a[1]) * inf))
+        args = [self.rho_i * sig(a[0]) * e, self.rho_l * sig(a[1]) * inf]
+        x_inv = min(e, math.floor(args[0]))
+        x_liq = min(inf, math.floor(args[1]))
         e1, i1 = e - x_inv + x_liq, inf + x_inv - x_liq
         comm = [sig(a[2 + k]) for k in range(4)]
         logits = a[6:14]
@@ -116,14 +128,54 @@ class World:
         tot = 0.0
         for v in ex:
             tot += v
-        F = math.floor(self.kappa * i1)
+        args.append(self.kappa * i1)
+        F = math.floor(args[-1])
         flows, used = {}, 0
         for p in range(8):
-            f = min(math.floor((ex[p] / tot) * F), F - used)
+            args.append((ex[p] / tot) * F)
+            f = min(math.floor(args[-1]), F - used)
             used += f
             flows[order[p]] = f
         best = logits.index(m)
-        return dict(e1=e1, i1=i1, comm=comm, flows=flows, explore=order[best], act=a)
+        return dict(e1=e1, i1=i1, comm=comm, flows=flows, explore=order[best], act=a,
+                    order=order, logits=logits, exact=all(floor_decided(x) for x in args))
+
+    def margins(self, plans, t):
+        """The near-tie report of target t, from the plans of its neighbours:
+        (smallest top-1 minus top-2 flow-logit gap of a neighbour whose two
+        leading explore directions include t and whose flows are not all
+        decided zeros; |v_win - I1(t)|; v_win - v_second on a takeover;
+        max(v_win, I1(t)); 1.0 when I1(t) and every explorer's flows are
+        decided integers)."""
+        pt = plans[t]
+        gap = math.inf
+        cands = []
+        for d in range(8):
+            n = self.neighbour(t, d)
+            pn = plans[n]
+            back = (d + 4) % 8
+            lg = pn["logits"]
+            top1 = max(range(8), key=lambda k: (lg[k], -k))
+            top2 = max((k for k in range(8) if k != top1), key=lambda k: (lg[k], -k))
+            idle = pn["exact"] and all(v == 0 for v in pn["flows"].values())
+            if back in (pn["order"][top1], pn["order"][top2]) and not idle:
+                gap = min(gap, lg[top1] - lg[top2])
+            if pn["explore"] == back:
+                cands.append((pn["flows"][back], d, pn["exact"]))
+        if not cands:
+            return [gap, math.inf, math.inf, 0.0, 1.0 if pt["exact"] else 0.0]
+        win = cands[0]
+        for c in cands[1:]:
+            if c[0] > win[0]:
+                win = c
+        take = float(abs(win[0] - pt["i1"]))
+        mag = float(max(win[0], pt["i1"]))
+        rank = math.inf
+        others = [c[0] for c in cands if c is not win]
+        if win[0] > pt["i1"] and others:
+            rank = float(win[0] - max(others))
+        decided = pt["exact"] and all(c[2] for c in cands)
+        return [gap, take, rank, mag, 1.0 if decided else 0.0]
 
     def step(self):
         N = self.W * self.H

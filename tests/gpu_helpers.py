@@ -7,9 +7,14 @@ outside the near-tie band):
   * G, R:      bit-exact wherever the oracle's FP64 decision margins are
                outside the near-tie band -- the flow-logit gap of every
                neighbour whose top two explore directions include the cell
-               is >= 1e-4, |v_win - I1| >= 1e-5 * max(v_win, I1) + 64 quanta,
-               and, when the winner takes over, v_win - v_second is as large;
-               cells inside the band are counted and must be rare;
+               (and that can invest at all) is >= 1e-4, and either
+               |v_win - I1| >= 1e-5 * max(v_win, I1) + 64 quanta and, when
+               the winner takes over, v_win - v_second is as large, or all
+               the integers those comparisons read are decided (every floor
+               behind them is away from an integer by more than 1% of its
+               argument, or is an exact zero), so that the comparison is
+               exact however close; cells inside the band are counted and
+               must be rare;
   * mass:      exact (int64 sum of the GPU state == the input's sum; the GPU's
                FP64 reduction equals it exactly).
 """
@@ -41,7 +46,8 @@ def oracle_state_from(st: dict) -> "oracle.State":
 
 def band_mask(margins: np.ndarray) -> np.ndarray:
     thr = 1e-5 * margins[..., 3] + 64.0
-    return (margins[..., 0] < GAP_BAND) | (margins[..., 1] < thr) | (margins[..., 2] < thr)
+    close = (margins[..., 1] < thr) | (margins[..., 2] < thr)
+    return (margins[..., 0] < GAP_BAND) | (close & (margins[..., 4] == 0))
 
 
 def normwise(gpu: np.ndarray, ref: np.ndarray) -> float:

@@ -195,7 +195,7 @@ def test_single_step_matches_oracle_fp32(stream, W, H, layers, hidden):
     d = gh.oracle_desc(init.spec)
     ref, info = oracle.step(d, oracle.State.from_init(init), oracle.nets_for(d, init.params),
                             want_margins=True)
-    rep = gh.compare_step(out, ref, info["margins"], max_band_frac=0.05)
+    rep = gh.compare_step(out, ref, info["margins"], max_band_frac=1e-2)
     m0 = int(init.E.sum() + init.I.sum())
     assert int(out["E"].sum() + out["I"].sum()) == m0
     assert st["mass_quanta"] == m0 and st["mass_fp64"] == float(m0)
@@ -225,7 +225,7 @@ def test_small_genomes_step_matches_oracle_every_tuning(stream):
         w.set_tuning(*tuning)
         st = w.step(1, stats=True)
         out = w.get_state()
-        gh.compare_step(out, ref, info["margins"], max_band_frac=0.05)
+        gh.compare_step(out, ref, info["margins"], max_band_frac=1e-2)
         assert st["error_word"] == 0
         assert int(out["E"].sum() + out["I"].sum()) == int(init.E.sum() + init.I.sum())
         if first is None:

@@ -158,6 +158,34 @@ def test_step_matches_bruteforce(oracle_lib, W, H, layers, hidden):
         np.testing.assert_allclose(info["act"].reshape(-1, 14), act, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("W,H,layers,hidden", [(5, 7, 2, 8), (8, 8, 2, 16), (6, 4, 3, 8),
+                                               (1, 5, 2, 8), (2, 2, 2, 8)])
+def test_near_tie_margins_match_bruteforce(oracle_lib, W, H, layers, hidden):
+    """The oracle's near-tie report (the margins that decide which cells the
+    GPU parity tests excuse from the exact G/R comparison) equals the same
+    five numbers recomputed target by target from the brute-force plans:
+    the neighbours' logit gaps toward the target, |v_win - I1|, the ranking
+    margin, the magnitude and the decided flag.  A third of the cells carry
+    no mass, so exact-zero budgets, idle neighbours and decided ties occur."""
+    seen = np.zeros(5, bool)
+    for seed in range(4):
+        d, s, params = tiny_world(oracle_lib, W, H, hidden=hidden, layers=layers, seed=seed,
+                                  scale=2.0)
+        empty = np.random.default_rng(100 + seed).random((H, W)) < 0.35
+        s.E[empty] = 0
+        s.I[empty] = 0
+        _, info = oracle_lib.step(d, s, oracle_lib.nets_for(d, params), want_margins=True)
+        bw = bf_world(d, s, params, oracle_lib)
+        plans = [bw.plan(i) for i in range(W * H)]
+        ref = np.array([bw.margins(plans, t) for t in range(W * H)])
+        got = info["margins"].reshape(-1, 5)
+        np.testing.assert_array_equal(got, ref)
+        seen |= [np.isfinite(ref[:, 0]).any(), np.isfinite(ref[:, 1]).any(),
+                 np.isfinite(ref[:, 2]).any(), (ref[:, 4] == 1).any(), (ref[:, 4] == 0).any()]
+    if W * H >= 20:
+        assert seen.all(), seen
+
+
 def test_bruteforce_exercises_takeovers(oracle_lib):
     """The brute-force cases above include takeovers (else they would not pin the rule)."""
     total = 0
