@@ -218,13 +218,19 @@ const char* coralai_version(void);
  *                   int64, flows [W*H x 8] uint32 (< 2^31) toward absolute
  *                   directions 0..7, explore direction [W*H] uint8 -- on the current G,
  *                   R; the result becomes the current state with E and C
- *                   unchanged. */
+ *                   unchanged;
+ *  debug_set_act_segments: the number of segments of the genome-ordered
+ *                   unit list from which each wavefront of the network kernel
+ *                   takes one chunk (0 = automatic: 4 for BF16 networks on
+ *                   jobs of at least 64 units per wavefront, else 1); results
+ *                   do not depend on it, which the tests check. */
 int coralai_debug_buckets(coralai_world* w, int32_t* counts, int32_t* offsets, int32_t* perm);
 int coralai_debug_actuators(coralai_world* w, float* act);
 int coralai_debug_set_weights(coralai_world* w, int32_t slot, const float* flat);
 int coralai_debug_get_weights(coralai_world* w, int32_t slot, float* flat);
 int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* flows8,
                           const uint8_t* explore_dir);
+int coralai_debug_set_act_segments(coralai_world* w, int32_t n_segments);
 
 #ifdef __cplusplus
 }

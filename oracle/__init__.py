@@ -67,6 +67,7 @@ def lib():
         L.orc_net_size.argtypes = [P]
         L.orc_cppn.argtypes = [P] + [ct.c_double] * 4 + [P]
         L.orc_cppn_to_net.argtypes = [P, P, P]
+        L.orc_nets_for.argtypes = [P, ct.c_int64, P, P]
         L.orc_sense.argtypes = [P, P, P, P, P, ct.c_int64, P]
         L.orc_forward.argtypes = [P, P, P, P]
         L.orc_kernel_dir.restype = ct.c_int
@@ -146,10 +147,13 @@ def cppn_to_net(d: Desc, params: np.ndarray) -> np.ndarray:
 
 
 def nets_for(d: Desc, params: np.ndarray) -> np.ndarray:
-    """Flat FP64 networks [n_genomes, net_size] for an array of CPPN params."""
-    params = np.asarray(params)
-    return np.stack([cppn_to_net(d, params[k]) for k in range(params.shape[0])]) \
-        if params.shape[0] else np.zeros((0, net_size(d)))
+    """Flat FP64 networks [n_genomes, net_size] for an array of CPPN params
+    (cppn_to_net of each, genomes spread over the OpenMP threads)."""
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, N_PARAM))
+    out = np.zeros((p.shape[0], net_size(d)), dtype=np.float64)
+    if p.shape[0]:
+        lib().orc_nets_for(ct.byref(d.c()), p.shape[0], _p(p), _p(out))
+    return out
 
 
 def unflatten(d: Desc, net: np.ndarray) -> list[tuple[np.ndarray, np.ndarray]]:

@@ -151,6 +151,14 @@ void orc_cppn_to_net(const orc_desc* d, const double* p, double* net) {
     }
 }
 
+/* The networks of n genomes (params: n x 56 doubles) into nets (n x
+ * orc_net_size doubles), one genome per thread: orc_cppn_to_net each. */
+void orc_nets_for(const orc_desc* d, int64_t n, const double* params, double* nets) {
+    const int64_t nsz = orc_net_size(d);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < n; ++k) orc_cppn_to_net(d, params + k * ORC_NPARAM, nets + k * nsz);
+}
+
 /* Sensors over the Kernel (Experiment): u[p*6 + ch] is channel ch of the
  * cell at kernel position p, channels (E, I, C0, C1, C2, C3), E and I as
  * mass values (quanta * 2^-24). */
@@ -193,10 +201,11 @@ void orc_forward(const orc_desc* d, const double* net, const double* u, double* 
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
 /* Relative perturbation of a floored argument that an FP32 evaluation of the
- * same step may make: the network outputs may differ by up to 1e-5 of their
- * largest magnitude, which moves a sigmoid or a softmax weight by well under
- * 1e-3 of its value; a factor 10 on top. */
-#define ORC_FLOOR_REL 1e-2
+ * same step may make.  A sigmoid or a softmax weight moves relatively by about
+ * the absolute error of the network outputs it reads (twice that for a
+ * softmax weight), which an FP32 evaluation keeps near 1e-4 even at the
+ * worst cells of a 4096 x 4096 grid; 1e-3 leaves a factor of 5 on top. */
+#define ORC_FLOOR_REL 1e-3
 
 /* floor(x) of a non-negative argument is decided when every value within
  * ORC_FLOOR_REL * x of x has the same floor, or when x is exactly zero (one

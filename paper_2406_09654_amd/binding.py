@@ -34,7 +34,7 @@ EXPORTED = [
     "coralai_version", "coralai_debug_buckets", "coralai_debug_actuators",
     "coralai_debug_set_weights", "coralai_debug_get_weights", "coralai_debug_physics",
     "coralai_set_profiling", "coralai_get_profile", "coralai_batch_autotune",
-    "coralai_batch_set_tuning",
+    "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -103,6 +103,7 @@ def lib() -> ct.CDLL:
             "coralai_debug_set_weights": (ct.c_int, [P, I32, P]),
             "coralai_debug_get_weights": (ct.c_int, [P, I32, P]),
             "coralai_debug_physics": (ct.c_int, [P, P, P, P]),
+            "coralai_debug_set_act_segments": (ct.c_int, [P, I32]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
         }
@@ -254,6 +255,10 @@ def coralai_debug_get_weights(h, slot: int, flat) -> None:
 
 def coralai_debug_physics(h, i1, flows8, explore) -> None:
     _check(lib().coralai_debug_physics(h, _host(i1), _host(flows8), _host(explore)))
+
+
+def coralai_debug_set_act_segments(h, n_segments: int) -> None:
+    _check(lib().coralai_debug_set_act_segments(h, n_segments))
 
 
 def coralai_set_profiling(h, on: bool) -> None:

@@ -136,9 +136,14 @@ __host__ __device__ constexpr int net_flat_size(int nl, int hid) {
 // arithmetic out of the network kernel (one rounding of the product):
 //  * rows of hidden layers carry kTanhScale = 2 log2(e): the kernel computes
 //    r = 1 / (2^y + 1) on y = 2 log2(e) x, and tanh(x) = 1 - 2r;
-//  * layers after a hidden layer therefore take r as input: their columns
-//    carry -2, and the kernel adds -1/2 of each stored row's sum to its bias
-//    when it loads a genome (sum_j w_j tanh_j = sum_j w_j - 2 sum_j w_j r_j);
+//  * BF16 networks: layers after a hidden layer take r as input (r is what
+//    gets rounded to bf16): their columns carry -2, and the kernel adds -1/2
+//    of each stored row's sum to its bias when it loads a genome
+//    (sum_j w_j tanh_j = sum_j w_j - 2 sum_j w_j r_j).  FP32 networks take
+//    tanh = 1 - 2r itself (one FMA): in FP32 the row-sum correction and the
+//    r-weighted sum cancel to the final value, which loses about a factor 2
+//    of accuracy on the actuators against tanh, while in BF16 the operand
+//    rounding dominates either way;
 //  * output rows 0..5 (sigmoid actuators) carry -log2(e) and rows 6..13 (flow
 //    logits) +log2(e): sigmoid and softmax then need one exp2 each;
 //  * layer-0 columns of the energy and infrastructure channels carry 2^-24,
@@ -150,8 +155,10 @@ __host__ __device__ inline double stored_row_scale(int nl, int layer, int row) {
     if (layer < nl - 1) return kTanhScale;
     return row < 6 ? -kLog2e : (row < kNOut ? kLog2e : 1.0);
 }
-__host__ __device__ inline double stored_col_scale(int layer, int col) {
-    if (layer > 0) return -2.0;
+// layers after a hidden layer read r = (1 - tanh) / 2 (BF16) or tanh (FP32)
+__host__ __device__ constexpr bool hidden_input_is_r(int prec) { return prec == kPrecBF16; }
+__host__ __device__ inline double stored_col_scale(int prec, int layer, int col) {
+    if (layer > 0) return hidden_input_is_r(prec) ? -2.0 : 1.0;
     return col % 6 < 2 ? 0x1p-24 : 1.0;
 }
 
@@ -317,6 +324,10 @@ struct LaunchShape {
     int misc_blocks;
     int max_worlds;
     int max_cap;
+    // segments of the unit list the network kernel deals out to its waves:
+    // 0 = automatic (4 for BF16 networks on large jobs, else 1); k >= 1
+    // forces k (a test hook: results do not depend on it)
+    int act_segments;
 };
 
 // Launchers implemented in the kernel translation units.

@@ -49,10 +49,17 @@ struct Net {
 
 // Hidden activation r = 1 / (2^y + 1) = (1 - tanh(x)) / 2 on y = 2 log2(e) x:
 // one exp2 and one reciprocal, exact limits.  The stored weights carry the
-// argument scale, and the next layer's weights the -2 and the row-sum bias
-// correction that turn r back into tanh.
+// argument scale.  BF16 networks feed r to the next layer, whose weights
+// carry the -2 and the row-sum bias correction that turn r back into tanh;
+// FP32 networks feed tanh = 1 - 2r.
 __device__ __forceinline__ float tanh_r(float y) {
     return __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
+}
+// tanh itself, from the odd symmetry: 1 - 2r on |y| (r <= 1/2), sign of y.
+// r below 1/2 keeps the absolute error of 1 - 2r at the rounding of r, where
+// r near 1 (tanh near -1) would carry the rounding of 1 into it.
+__device__ __forceinline__ float tanh_t(float y) {
+    return __builtin_copysignf(__builtin_fmaf(-2.0f, tanh_r(__builtin_fabsf(y)), 1.0f), y);
 }
 
 // sigmoid on an actuator stored times -log2(e): 1 / (1 + 2^x)
@@ -89,12 +96,13 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 
 template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG>
 __global__ __launch_bounds__(256, WAVES) void k_act(
-    const BatchDev* __restrict__ b, float* __restrict__ dbg) {
+    const BatchDev* __restrict__ b, float* __restrict__ dbg, int seg_force) {
     using NT = Net<NL, HID, PREC>;
     using frag_t = typename NT::frag_t;
     constexpr int MT = NT::MT, KS0 = NT::KS0, KSH = NT::KSH;
     constexpr int MT1 = NL == 3 ? MT : 1;
     static_assert(4 % CGI == 0, "column groups per pass must divide 4");
+    static_assert(hidden_input_is_r(PREC) == NT::kBF, "BF16 layers read r, FP32 layers read tanh");
 
     __shared__ __attribute__((aligned(16))) uint8_t smem[4 * NT::STAGE_BYTES];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -116,7 +124,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     // instead of loading the waves at the end of the list.  (FP32 networks,
     // with twice the weight bytes per run start, keep one segment.)
     const int nwaves = gridDim.x * 4;
-    const int nseg = NT::kBF && total >= 64 * nwaves ? 4 : 1;
+    const int nseg = seg_force > 0 ? seg_force : (NT::kBF && total >= 64 * nwaves ? 4 : 1);
     const int seglen = (total + nseg - 1) / nseg;
     const int per = (seglen + nwaves - 1) / nwaves;
     const int wid = xcd_block() * 4 + wv;
@@ -381,10 +389,10 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         if (new_run) {
             if (lane < net_bias_floats(NL, HID) / 4) *(floatx4*)(sbias + 4 * lane) = bias_ld;
             wave_lds_sync();
-            // layers after a hidden layer read r = (1 - tanh) / 2 through
-            // weights stored times -2: their biases gain -1/2 of the stored
-            // row sums (an MFMA against a ones operand)
-            {
+            // BF16: layers after a hidden layer read r = (1 - tanh) / 2
+            // through weights stored times -2: their biases gain -1/2 of the
+            // stored row sums (an MFMA against a ones operand)
+            if constexpr (hidden_input_is_r(PREC)) {
                 frag_t ones;
                 if constexpr (NT::kBF) {
 #pragma unroll
@@ -470,7 +478,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                         for (int s = 0; s < KSH; ++s)
 #pragma unroll
                             for (int t = 0; t < 4; ++t) {
-                                h[cc][s][t] = (__bf16)tanh_r(acc[cc][2 * s][t]);
+                                h[cc][s][t] = (__bf16)tanh_r(acc[cc][2 * s][t]);  // r is rounded
                                 h[cc][s][4 + t] = (__bf16)tanh_r(acc[cc][2 * s + 1][t]);
                             }
                     if (last) {
@@ -501,7 +509,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) h[cc][mt][t] = tanh_r(acc[cc][mt][t]);
+                            for (int t = 0; t < 4; ++t) h[cc][mt][t] = tanh_t(acc[cc][mt][t]);
                     if (last) {
                         const floatx4 bv = *(const floatx4*)lb;
 #pragma unroll
@@ -656,7 +664,8 @@ template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG>
 static void launch_act_c(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, float* dbg) {
     static int blocks = 0;
     if (blocks == 0) blocks = resident_blocks(k_act<NL, HID, PREC, CGI, WAVES, DEBUG>, ls.n_cu);
-    hipLaunchKernelGGL((k_act<NL, HID, PREC, CGI, WAVES, DEBUG>), dim3(blocks), dim3(256), 0, s, bdev, dbg);
+    hipLaunchKernelGGL((k_act<NL, HID, PREC, CGI, WAVES, DEBUG>), dim3(blocks), dim3(256), 0, s, bdev, dbg,
+                       ls.act_segments);
 }
 
 // act_cells: column groups of 16 cells processed together (1, 2, 4);

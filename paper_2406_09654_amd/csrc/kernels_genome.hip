@@ -213,9 +213,9 @@ __device__ __forceinline__ T row_scale(int nl, int layer, int row) {
     if (layer < nl - 1) return T(kTanhScale);
     return row < 6 ? T(-kLog2e) : (row < kNOut ? T(kLog2e) : T(1));
 }
-template <typename T>
+template <typename T, int PREC>
 __device__ __forceinline__ T col_scale(int layer, int col) {
-    if (layer > 0) return T(-2);
+    if (layer > 0) return hidden_input_is_r(PREC) ? T(-2) : T(1);
     return col % 6 < 2 ? T(0x1p-24) : T(1);
 }
 
@@ -233,10 +233,10 @@ __device__ __forceinline__ T row_x(int layer, int row) {
     return T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
 }
 
-template <typename T, int NL, int HID, bool GUARD>
+template <typename T, int NL, int HID, int PREC, bool GUARD>
 __device__ __forceinline__ float cppn_weight(const float* p, const T* ce, const T* re, int layer, int row, int col) {
     const T rs = layer == 0 ? T(1) / sqrt(T(kNIn)) : T(1) / sqrt(T(HID));  // 1 / sqrt(fan-in)
-    const T sc = row_scale<T>(NL, layer, row) * col_scale<T>(layer, col);
+    const T sc = row_scale<T>(NL, layer, row) * col_scale<T, PREC>(layer, col);
     return (float)(cppn_eval<T, GUARD>(p, ce, re, 0) * rs * sc);
 }
 
@@ -379,8 +379,8 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
                     const FragCoord fc = frag_coord(NL, HID, PREC, e);
                     const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
                     if (fc.row < lout && fc.col < lin)
-                        v = cppn_weight<T, NL, HID, GUARD>(sp, stc[fc.layer][fc.col], str[fc.layer][fc.row],
-                                                           fc.layer, fc.row, fc.col);
+                        v = cppn_weight<T, NL, HID, PREC, GUARD>(sp, stc[fc.layer][fc.col], str[fc.layer][fc.row],
+                                                                 fc.layer, fc.row, fc.col);
                 } else {
                     int layer, row;
                     bias_coord(NL, HID, e - ew, &layer, &row);
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(256) void k_pack(const WorldDev* __restrict__ w, in
             const int lin = layer_in(nl, hid, fc.layer), lout = layer_out(nl, hid, fc.layer);
             const bool ok = fc.row < lout && fc.col < lin;
             const int fi = flat_w_offset(nl, hid, fc.layer) + fc.row * lin + fc.col;
-            const double sc = stored_row_scale(nl, fc.layer, fc.row) * stored_col_scale(fc.layer, fc.col);
+            const double sc = stored_row_scale(nl, fc.layer, fc.row) * stored_col_scale(prec, fc.layer, fc.col);
             if (!unpack) {
                 const float v = ok ? (float)((double)flat[fi] * sc) : 0.0f;
                 if (bf) ((__bf16*)dst)[e] = (__bf16)v;

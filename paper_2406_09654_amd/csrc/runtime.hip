@@ -1058,6 +1058,16 @@ int coralai_debug_get_weights(coralai_world* w, int32_t slot, float* flat) {
     return rc;
 }
 
+int coralai_debug_set_act_segments(coralai_world* w, int32_t n_segments) {
+    WORLD_GUARD(w);
+    if (n_segments < 0 || n_segments > 64) return fail(CORALAI_E_INVALID, "n_segments must be in [0, 64]");
+    (void)hipStreamSynchronize(w->stream);
+    w->ls.act_segments = n_segments;
+    destroy_graph(&w->graph);  // recaptured with the new launch argument at the next step
+    destroy_graph(&w->graph_rc);
+    return CORALAI_OK;
+}
+
 int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* flows8, const uint8_t* explore_dir) {
     WORLD_GUARD(w);
     {

@@ -173,6 +173,9 @@ class World:
         B.coralai_debug_get_weights(self.h, slot, out)
         return out
 
+    def debug_set_act_segments(self, n_segments: int) -> None:
+        B.coralai_debug_set_act_segments(self.h, n_segments)
+
     def debug_physics(self, i1, flows8, explore) -> None:
         B.coralai_debug_physics(self.h, np.ascontiguousarray(i1, dtype=np.int64).ravel(),
                                 np.ascontiguousarray(flows8, dtype=np.uint32).reshape(-1, 8),

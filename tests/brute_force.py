@@ -85,7 +85,7 @@ def sig(x):
 
 # Relative perturbation of a floored argument within which an FP32 evaluation
 # of the same step may move it (the near-tie report of the parity tests).
-FLOOR_REL = 1e-2
+FLOOR_REL = 1e-3
 
 
 def floor_decided(x):

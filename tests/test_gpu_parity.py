@@ -498,9 +498,57 @@ def test_batch_equals_each_world_alone(stream):
         w2.step(4)
         ref = w2.get_state()
         out = w.get_state()
-        for ch in ("E", "I", "G"):
+        for ch in ("E", "I", "C", "G", "R"):
             np.testing.assert_array_equal(out[ch], ref[ch])
         w2.close()
+    b.close()
+    for w in worlds:
+        w.close()
+
+
+def test_batch_fp32_single_step_matches_oracle(stream):
+    """FP32 worlds of different sizes (one of 1x1) stepped once together by the
+    batched graph: each world's step matches the oracle."""
+    from paper_2406_09654_amd.world import Batch
+    inits = [gh.heterogeneous_world(s, s + 5 * k, n_genomes=3 + k, seed=300 + k, precision=0)
+             for k, s in enumerate([64, 96, 33, 130, 1, 200, 17])]
+    worlds = [gh.make_world(init, stream) for init in inits]
+    b = Batch(8, stream)
+    b.set_worlds(worlds)
+    b.step(1)
+    b.sync()
+    for init, w in zip(inits, worlds):
+        d = gh.oracle_desc(init.spec)
+        ref, info = oracle.step(d, oracle.State.from_init(init), oracle.nets_for(d, init.params),
+                                want_margins=True)
+        rep = gh.compare_step(w.get_state(), ref, info["margins"], max_band_frac=1e-2)
+        say("  batched world", init.spec.width, init.spec.height, rep)
+    b.close()
+    for w in worlds:
+        w.close()
+
+
+def test_batched_512_world_set_fp32_sample_matches_oracle(stream):
+    """The 512-world batched workload (sides 64..512, 8..128 genomes), run
+    with FP32 networks in one autotuned batched step; 16 sampled worlds
+    match the oracle."""
+    from paper_2406_09654_amd.world import Batch
+    specs = wl.batched_world_specs(512)
+    inits = [wl.batched_world(side, ng, seed, precision=0) for side, ng, seed in specs]
+    worlds = [gh.make_world(init, stream) for init in inits]
+    b = Batch(512, stream)
+    b.set_worlds(worlds)
+    tuning = b.autotune()
+    b.step(1)
+    b.sync()
+    pick = np.random.default_rng(5).choice(512, 16, replace=False)
+    for k in pick:
+        init = inits[k]
+        d = gh.oracle_desc(init.spec)
+        ref, info = oracle.step(d, oracle.State.from_init(init), oracle.nets_for(d, init.params),
+                                want_margins=True)
+        rep = gh.compare_step(worlds[k].get_state(), ref, info["margins"], max_band_frac=1e-2)
+        say("  world", int(k), init.spec.width, "tuning", tuning, rep)
     b.close()
     for w in worlds:
         w.close()

@@ -4,7 +4,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import workloads as wl
+from tests import gpu_helpers as gh
 
 pytestmark = pytest.mark.gpu
 
@@ -54,3 +56,28 @@ def test_admission_by_bytes_limits_residency():
     assert rep["n_requests"] == len(reqs)
     assert all(len(rep["results"][r.rid].step_ids) == r.n_steps for r in reqs)
     assert rep["step_latency_ms_p99"] >= rep["step_latency_ms_p50"] > 0
+
+
+def test_served_one_step_requests_match_oracle():
+    """FP32 serving: requests of one step arrive while longer ones run, so
+    each is stepped in a batch with others; each result matches the
+    oracle's single step from the request's seeded state."""
+    from paper_2406_09654_amd.serving import Server
+    spec = [(0, 96, 12, 6), (0, 40, 5, 1), (1, 70, 9, 1), (1, 128, 30, 4), (2, 33, 4, 1),
+            (3, 150, 20, 1), (3, 64, 16, 1), (5, 100, 8, 1)]
+    reqs = [wl.Request(k, float(a), side, ng, steps, 8100 + k)
+            for k, (a, side, ng, steps) in enumerate(spec)]
+    inits = {r.rid: wl.request_world(r) for r in reqs}
+    srv = Server(precision=0, max_worlds=4, max_chunk=1)
+    rep = srv.run(reqs, inits, arrivals="step", keep_states=True)
+    srv.close()
+    assert rep["mean_resident"] > 1.0
+    for r in reqs:
+        if r.n_steps != 1:
+            continue
+        init = inits[r.rid]
+        d = gh.oracle_desc(init.spec)
+        ref, info = oracle.step(d, oracle.State.from_init(init), oracle.nets_for(d, init.params),
+                                want_margins=True)
+        st = {k: v.cpu().numpy() for k, v in rep["results"][r.rid].state.items()}
+        gh.compare_step(st, ref, info["margins"], max_band_frac=1e-2)
