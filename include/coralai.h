@@ -232,6 +232,18 @@ int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* f
                           const uint8_t* explore_dir);
 int coralai_debug_set_act_segments(coralai_world* w, int32_t n_segments);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as coralai_debug_set_weights, staged through a fixed 64 KiB
+ * buffer in the library's device data (one per device, kept until the
+ * process ends) instead of a buffer allocated per call.  Calls no hipMalloc
+ * or hipFree.  Networks larger than 16384 floats are rejected with
+ * CORALAI_E_INVALID (every shape the world description allows fits: the
+ * largest, 54-64-64-14, has 8590).  Waits for the world's stream before it
+ * returns; calls that overlap on one device (from several threads) race on
+ * the shared buffer. */
+int coralai_debug_set_weights_noalloc(coralai_world* w, int32_t slot, const float* flat);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,7 @@ EXPORTED = [
     "coralai_debug_set_weights", "coralai_debug_get_weights", "coralai_debug_physics",
     "coralai_set_profiling", "coralai_get_profile", "coralai_batch_autotune",
     "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
+    "coralai_debug_set_weights_noalloc",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -104,6 +105,7 @@ def lib() -> ct.CDLL:
             "coralai_debug_get_weights": (ct.c_int, [P, I32, P]),
             "coralai_debug_physics": (ct.c_int, [P, P, P, P]),
             "coralai_debug_set_act_segments": (ct.c_int, [P, I32]),
+            "coralai_debug_set_weights_noalloc": (ct.c_int, [P, I32, P]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
         }
@@ -247,6 +249,10 @@ def coralai_debug_actuators(h, act) -> None:
 
 def coralai_debug_set_weights(h, slot: int, flat) -> None:
     _check(lib().coralai_debug_set_weights(h, slot, _host(flat)))
+
+
+def coralai_debug_set_weights_noalloc(h, slot: int, flat) -> None:
+    _check(lib().coralai_debug_set_weights_noalloc(h, slot, _host(flat)))
 
 
 def coralai_debug_get_weights(h, slot: int, flat) -> None:

@@ -11,7 +11,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/coralai.h"
@@ -155,6 +157,7 @@ struct BusyGuard {
 struct coralai_world {
     coralai_world_desc desc;
     Layout L;
+    int device = 0;      // current device at creation: the arena's and the stream's
     hipStream_t stream;
     uint8_t* base;
     WorldDev host;       // the device table entry, host copy
@@ -386,7 +389,10 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     const size_t need = coralai_world_bytes(desc);
     if (arena_bytes < need)
         return fail(CORALAI_E_NOMEM, "arena of %zu bytes is smaller than the %zu bytes the world needs", arena_bytes, need);
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(CORALAI_E_HIP, "hipGetDevice failed");
     coralai_world* w = new coralai_world();
+    w->device = device;
     w->desc = *desc;
     w->L = make_layout(desc);
     w->stream = (hipStream_t)hip_stream;
@@ -1056,6 +1062,67 @@ int coralai_debug_get_weights(coralai_world* w, int32_t slot, float* flat) {
     if (!rc && hipStreamSynchronize(w->stream) != hipSuccess) rc = fail(CORALAI_E_HIP, "sync failed");
     (void)hipFree(d);
     return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Staging buffer of coralai_debug_set_weights_noalloc, one copy per device,
+// held until the process ends.  In host code the array's name is only a
+// host-side stand-in: kernels get the device address that
+// hipGetSymbolAddress returns for the device (noalloc_scratch), never the
+// name.  Every call on a device shares that device's copy.
+constexpr int kNoAllocScratchFloats = 16384;  // 64 KiB; the largest network (54-64-64-14) has 8590 floats
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+
+// The device address of this device's scratch, looked up once per device
+// with that device current.
+int noalloc_scratch(int device, float** out) {
+    static std::mutex mu;
+    static std::unordered_map<int, float*> ptrs;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = ptrs.find(device);
+    if (it != ptrs.end()) {
+        *out = it->second;
+        return CORALAI_OK;
+    }
+    int prev = -1;
+    HIP_TRY(hipGetDevice(&prev));
+    if (prev != device) HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || p == nullptr)
+        return fail(CORALAI_E_HIP, "hipGetSymbolAddress of the staging buffer failed on device %d: %s", device,
+                    hipGetErrorString(e));
+    ptrs[device] = (float*)p;
+    *out = (float*)p;
+    return CORALAI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int coralai_debug_set_weights_noalloc(coralai_world* w, int32_t slot, const float* flat) {
+    WORLD_GUARD(w);
+    if (slot < 0 || slot >= w->host.cap || !flat) return fail(CORALAI_E_INVALID, "bad slot or NULL weights");
+    const size_t n = (size_t)net_flat_size(w->host.NL, w->host.HID);
+    if (n > (size_t)kNoAllocScratchFloats)
+        return fail(CORALAI_E_INVALID, "a network of %zu floats exceeds the %d-float staging buffer", n,
+                    kNoAllocScratchFloats);
+    float* d = nullptr;
+    int rc = noalloc_scratch(w->device, &d);
+    if (rc) return rc;
+    // every one of the n staged floats is written before the kernel reads it
+    HIP_TRY(hipMemcpyAsync(d, flat, 4 * n, hipMemcpyHostToDevice, w->stream));
+    launch_pack_weights(w->wdev, slot, d, 0, nullptr, w->stream);
+    rc = check_launch();
+    if (rc) return rc;
+    // the next call on this device may overwrite the staging buffer
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
 }
 
 int coralai_debug_set_act_segments(coralai_world* w, int32_t n_segments) {

@@ -168,6 +168,9 @@ class World:
     def debug_set_weights(self, slot: int, flat) -> None:
         B.coralai_debug_set_weights(self.h, slot, np.ascontiguousarray(flat, dtype=np.float32))
 
+    def debug_set_weights_noalloc(self, slot: int, flat) -> None:
+        B.coralai_debug_set_weights_noalloc(self.h, slot, np.ascontiguousarray(flat, dtype=np.float32))
+
     def debug_get_weights(self, slot: int, size: int) -> np.ndarray:
         out = np.zeros(size, np.float32)
         B.coralai_debug_get_weights(self.h, slot, out)
