@@ -35,6 +35,12 @@ PEAK_TRANS = 256 * 32 * 2.4e9
 ACT_BYTES_PER_CELL = 100   # reads ledger pair, comm, perm entry (36 B); writes comm, ledger pair, flows (64 B)
 PHYS_BYTES_PER_CELL = 74   # reads flow record, ledger pair, genome, rotation (53 B); writes 21 B
 RATE, SIGMA = 1e-4, 0.1
+BYTES_PER_CELL_STEP = 190  # two-pass design: act (100 B) + physics (74 B) + bucketing (~12 B) + finalize
+# Serving request rate: 0.8 x the 512-world batched capacity measured when
+# the rate was frozen (1.55e10 cell-updates/s) divided by the mean request
+# work, E[side^2] E[steps] for log-uniform side 128..2048 and steps 10..1000:
+# (2048^2 - 128^2) / (2 ln 16) x (1000 - 10) / ln 100 = 7.53e5 x 215 = 1.62e8
+SERVING_RATE = 77.0
 
 
 def flops_per_cell(hidden: int, layers: int) -> int:
@@ -49,16 +55,39 @@ def trans_per_cell(hidden: int, layers: int) -> int:
 
 
 ACT_SOURCES = ["paper_2406_09654_amd/csrc/kernels_act.hip", "paper_2406_09654_amd/csrc/coralai_internal.h"]
+NET_SOURCES = ACT_SOURCES + ["paper_2406_09654_amd/csrc/kernels_genome.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_act_bf16_4096_hbm_traffic.md")
+BF16_ERROR_FILE = os.path.join(ROOT, "profiles", "bf16_error_vs_oracle.md")
 
 
-def act_sources_sha256() -> str:
+def sources_sha256(paths) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in ACT_SOURCES:
+    for rel in paths:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def act_sources_sha256() -> str:
+    return sources_sha256(ACT_SOURCES)
+
+
+def bf16_error_statement():
+    """The BF16 form's error against the FP64 oracle, as the GPU parity tests
+    measured it (committed summary); None when the network or weight kernels
+    changed since."""
+    if not os.path.exists(BF16_ERROR_FILE):
+        return None
+    with open(BF16_ERROR_FILE) as f:
+        for line in f:
+            if line.startswith("bf16_error_json: "):
+                rec = json.loads(line[len("bf16_error_json: "):])
+                if rec.get("source_sha256") != sources_sha256(NET_SOURCES):
+                    return {"stale": "network or weight kernels changed since the measurement"}
+                rec["source"] = os.path.relpath(BF16_ERROR_FILE, ROOT)
+                return rec
+    return None
 
 
 def act_traffic(tuning):
@@ -89,6 +118,12 @@ def act_traffic(tuning):
 
 
 def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bool, tuning=None):
+    """One form on the 4096^2 trajectory: warmup steps, the autotuner, two
+    more steps, then `steps` steps on the production path (each step one
+    captured graph replay, radiation after it; no profiling); then the same
+    steps of the same trajectory with live phase timing (direct launches
+    with HIP events between the phases on the world's stream), whose
+    network-kernel time gives the roofline."""
     import torch
 
     from paper_2406_09654_amd.world import World
@@ -112,16 +147,29 @@ def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bo
         tuning = w.autotune()
         advance(2)
     w.sync()
+    torch.cuda.synchronize()
+    first = step_index + 1
+    t0 = time.perf_counter()
+    advance(steps)
+    w.sync()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    w.close()
+    # the same steps again on a second world with the same tuning (the
+    # trajectory does not depend on the launch configuration), now with the
+    # phases timed
+    w = World.from_init(init, stream=stream, precision=precision)
+    w.set_tuning(*tuning)
+    step_index = 0
+    advance(first - 1)
+    w.sync()
     w.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        w.step(1)
-        step_index += 1
-        w.radiate(RATE, SIGMA, step_index, stats=False)
+    advance(steps)
     w.sync()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t_phase = time.perf_counter() - t0
     prof = w.profile()
     st = w.stats()
     w.set_profiling(False)
@@ -129,14 +177,59 @@ def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bo
     del w
     torch.cuda.empty_cache()
     N = init.spec.width * init.spec.height
-    elapsed = t1 - t0
     return {
-        "value": N * steps / elapsed,
-        "ms_per_step": 1e3 * elapsed / steps,
+        "value": N * steps / t_graph,
+        "ms_per_step": 1e3 * t_graph / steps,
+        "timed_steps": [first, first + steps - 1],
+        "phase_timed": {"value": N * steps / t_phase, "ms_per_step": 1e3 * t_phase / steps,
+                        "timed_steps": [first, first + steps - 1]},
         "phase_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
         "stats": st,
         "tuning": tuning,
     }
+
+
+def run_long(init, precision: int, n_steps: int, tuning, stream, block: int = 100):
+    """The 4096^2 workload run as configured: n_steps steps, each followed by
+    radiation at 1e-4, in blocks of `block` steps (queued without waiting;
+    the block's end waits and reads the statistics of its last step and
+    radiation call)."""
+    import torch
+
+    from paper_2406_09654_amd.world import World
+
+    w = World.from_init(init, stream=stream, precision=precision)
+    w.set_tuning(*tuning)
+    N = init.spec.width * init.spec.height
+    blocks = []
+    k = 0
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    while k < n_steps:
+        n = min(block, n_steps - k)
+        t0 = time.perf_counter()
+        for _ in range(n - 1):
+            w.step(1)
+            k += 1
+            w.radiate(RATE, SIGMA, k, stats=False)
+        st_step = w.step(1, stats=True)
+        k += 1
+        st = w.radiate(RATE, SIGMA, k, stats=True)
+        dt = time.perf_counter() - t0
+        blocks.append({"steps": [k - n + 1, k], "ms_per_step": 1e3 * dt / n,
+                       "live_genomes": st_step["live_genomes"], "takeovers_last_step": st_step["takeovers"],
+                       "hits_last_call": st["hits"], "dropped_hits_last_call": st["dropped_hits"]})
+        assert st["error_word"] == 0 and st_step["mass_quanta"] == int(init.E.sum() + init.I.sum())
+    total = time.perf_counter() - t_all
+    w.close()
+    del w
+    torch.cuda.empty_cache()
+    last = [b for b in blocks if b["steps"][0] > n_steps - block]
+    return {"steps": n_steps, "value": N * n_steps / total, "ms_per_step_mean": 1e3 * total / n_steps,
+            "ms_per_step_last_block": last[-1]["ms_per_step"] if last else None,
+            "live_genomes_end": blocks[-1]["live_genomes"], "genome_capacity": init.spec.genome_capacity,
+            "dropped_hits_last_call": blocks[-1]["dropped_hits_last_call"],
+            "hits_last_call": blocks[-1]["hits_last_call"], "blocks": blocks, "tuning": tuning}
 
 
 def run_batched(n_worlds: int, steps: int, warmup: int, alone_steps: int):
@@ -215,10 +308,40 @@ def run_serving(n_requests: int, rate: float):
     return out
 
 
-def cpu_baseline(init, target_s: float = 12.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n: int) -> None:
+    """Set the OpenMP thread count of the runtime the oracle is linked with."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def cpu_baseline(init, target_s: float = 12.0, one_thread_s: float = 5.0):
     """The FP64 oracle (as it stands, OpenMP over cells) on a band of rows of
     the same state, widened to the whole grid and then repeated until about
-    target_s seconds of CPU work have been timed."""
+    target_s seconds of CPU work have been timed; then on one thread."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = _cpu_baseline(init, target_s, threads)
+    _omp_threads(1)
+    try:
+        one = _cpu_baseline(init, one_thread_s, 1)
+    finally:
+        _omp_threads(threads)
+    out["one_thread"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    out["cpu_model"] = cpu_model()
+    return out
+
+
+def _cpu_baseline(init, target_s: float, threads: int):
     import numpy as np
 
     import oracle
@@ -251,7 +374,6 @@ def cpu_baseline(init, target_s: float = 12.0):
         oracle.step(d, s, nets)
         total += time.perf_counter() - t0
         reps += 1
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": cells * reps / total, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "FP64 oracle step (sense, network, actuation, physics) on %d full rows "
@@ -275,8 +397,13 @@ def main() -> int:
                     help="act_cells,act_waves,phys_tile for the FP32 form instead of autotuning")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-world batched form")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving form")
-    ap.add_argument("--serving-requests", type=int, default=32)
-    ap.add_argument("--serving-rate", type=float, default=20.0, help="Poisson arrivals per second")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
+                    help="Poisson arrivals per second (default: 0.8 x the batched capacity / mean request work)")
+    ap.add_argument("--long-steps", type=int, default=1000,
+                    help="steps of the as-configured 4096^2 run per form (0 skips it)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="profiling aid: run only the 512-world batched form and print its block")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -297,6 +424,11 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.batched_only:
+        b = run_batched(512, args.steps, 3, 3)
+        print(json.dumps({"metric": "batched cell-updates/s (512 worlds, profiling run)", "value": b["value"],
+                          "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "batched": b}), flush=True)
+        return 0
     side = args.size
     patches = max(1, 65536 * side * side // (4096 * 4096))
     print("[bench] generating %dx%d workload" % (side, side), file=sys.stderr, flush=True)
@@ -316,6 +448,16 @@ def main() -> int:
         print("[bench] %s: %.3e cell-updates/s, %.3f ms/step, phases %s" % (
             name, forms[name]["value"], forms[name]["ms_per_step"], forms[name]["phase_ms"]),
             file=sys.stderr, flush=True)
+
+    long_runs = {}
+    if args.long_steps > 0 and side == 4096:
+        for prec, name in ([(1, "bf16")] if args.bf16_only else [(1, "bf16"), (0, "fp32")]):
+            print("[bench] %s: %d steps as configured" % (name, args.long_steps), file=sys.stderr, flush=True)
+            long_runs[name] = run_long(init, prec, args.long_steps, forms[name]["tuning"], stream)
+            print("[bench] %s long run: %.3f ms/step mean, %.3f last block, live genomes %d, dropped %d"
+                  % (name, long_runs[name]["ms_per_step_mean"], long_runs[name]["ms_per_step_last_block"],
+                     long_runs[name]["live_genomes_end"], long_runs[name]["dropped_hits_last_call"]),
+                  file=sys.stderr, flush=True)
 
     bf = forms["bf16"]
     act_ms = bf["phase_ms"]["act"]
@@ -348,14 +490,19 @@ def main() -> int:
                                % (side, side, patches),
                    "cells": N, "genomes": 4096, "network": "54-64-64-14"},
         "roofline": roof,
+        "timed_steps": bf["timed_steps"],
+        "path": "captured step graph per step, radiation after each step, no profiling",
+        "phase_timed": bf["phase_timed"],
         "phase_ms_per_step": bf["phase_ms"],
         "tuning": bf["tuning"],
+        "bf16_error": bf16_error_statement(),
     }
     if "fp32" in forms:
         f = forms["fp32"]
         fa = f["phase_ms"]["act"]
         fl = flops_per_cell(hidden, layers) * N
         out["fp32"] = {"value": f["value"], "ms_per_step": f["ms_per_step"],
+                       "timed_steps": f["timed_steps"], "phase_timed": f["phase_timed"],
                        "phase_ms_per_step": f["phase_ms"], "tuning": f["tuning"],
                        "roofline": {"kernel": "k_act", "bound": "mfma", "achieved": fl / (fa * 1e-3) / 1e12,
                                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
@@ -368,8 +515,16 @@ def main() -> int:
                                "per_unit": "%d B per cell (reads the 32-byte flow record, boundary ledger pair, "
                                            "genome, rotation; writes ledger pair, genome, rotation)"
                                            % PHYS_BYTES_PER_CELL}
+    if long_runs:
+        out["long_run"] = long_runs
     if not args.no_batched:
         out["batched"] = run_batched(512, 20, 3, 3)
+        b = out["batched"]
+        b["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM / 1e9,
+                         "achieved": b["value"] * BYTES_PER_CELL_STEP / 1e9,
+                         "frac": b["value"] * BYTES_PER_CELL_STEP / PEAK_HBM,
+                         "per_unit": "%d B per cell-update (the two-pass design's act, physics and "
+                                     "bucketing bytes), whole batched step" % BYTES_PER_CELL_STEP}
         print("[bench] batched: %s" % out["batched"], file=sys.stderr, flush=True)
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_requests, args.serving_rate)
