@@ -65,7 +65,9 @@ enum {
     CORALAI_ERR_GENOME_RANGE = 1u,
     CORALAI_ERR_GENOME_UNSET = 2u,
     CORALAI_ERR_LEDGER = 4u,    /* negative stock or a flow budget >= 2^31 quanta */
-    CORALAI_ERR_NONFINITE = 8u  /* network output or CPPN weight not finite */
+    CORALAI_ERR_NONFINITE = 8u, /* network output or CPPN weight not finite */
+    CORALAI_ERR_MASS = 16u      /* a step changed the total mass by other than the
+                                   day / night cycle's injected minus removed quanta */
 };
 
 /* World description.  The physics constants are the recorded readings of
@@ -148,6 +150,30 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out);
  * dropped and counted.  rate in [0, 1], sigma >= 0.  Waits when out != NULL. */
 int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_index,
                     coralai_stats* out);
+
+/* Day / night cycle (Experiment: energy is added to and removed from the
+ * substrate in a day / night cycle).  period = 0 switches it off (the
+ * default); otherwise, for the step s (steps completed before it, as in
+ * coralai_stats.steps) and q = s mod period, the daylight is the triangle
+ * wave L = period - 4 min(q, period - q) (period at noon, -period at
+ * midnight), and the physics pass sets every cell's energy to
+ *   E2 = E1 + floor(inject_quanta * max(L, 0) / period)
+ *           - floor(floor(E1 * remove_num / 65536) * max(-L, 0) / period)
+ * in exact int64 arithmetic: inject_quanta in [0, 2^40) quanta per cell per
+ * step at noon, remove_num in [0, 65536] (the fraction of a cell's energy
+ * removed per step at midnight, over 65536).  A cell's energy must stay below
+ * 2^40 quanta (else CORALAI_ERR_LEDGER).  Each step then checks on the device
+ * that the total mass moved by exactly the injected minus the removed quanta
+ * (CORALAI_ERR_MASS otherwise).  Takes effect from the next step of the
+ * world; a world that is in a batch takes it at the batch's next
+ * coralai_batch_set_worlds. */
+int coralai_set_daylight(coralai_world* w, int32_t period, int64_t inject_quanta, int32_t remove_num);
+
+/* The cycle's energy ledger in quanta: injected and removed by the last step,
+ * and in total since the world was created.  Waits for the stream; any
+ * pointer may be NULL. */
+int coralai_get_energy_ledger(coralai_world* w, int64_t* injected_last, int64_t* removed_last,
+                              int64_t* injected_total, int64_t* removed_total);
 
 /* Wait for the world's stream; report (and clear) device error bits. */
 int coralai_sync(coralai_world* w);

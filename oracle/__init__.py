@@ -38,7 +38,9 @@ class _Desc(ct.Structure):
     _fields_ = [("width", ct.c_int32), ("height", ct.c_int32),
                 ("n_weight_layers", ct.c_int32), ("hidden", ct.c_int32),
                 ("rho_invest", ct.c_double), ("rho_liquidate", ct.c_double),
-                ("kappa_flow", ct.c_double)]
+                ("kappa_flow", ct.c_double), ("day_period", ct.c_int32),
+                ("night_num", ct.c_int32), ("day_inject", ct.c_int64),
+                ("cycle_step", ct.c_int64)]
 
 
 class Record(ct.Structure):
@@ -74,7 +76,7 @@ def lib():
         L.orc_kernel_dir.argtypes = [ct.c_int, ct.c_int]
         L.orc_step_rows.restype = ct.c_int64
         L.orc_step_rows.argtypes = [P, P, P, P, P, P, P, ct.c_int32, ct.c_int32, ct.c_int32,
-                                    P, P, P, P, P, P, P, P]
+                                    P, P, P, P, P, P, P, P, P]
         L.orc_physics_from_records.restype = ct.c_int64
         L.orc_physics_from_records.argtypes = [P] * 9
         L.orc_buckets.restype = ct.c_int
@@ -107,6 +109,10 @@ class Desc:
     rho_invest: float = 0.1
     rho_liquidate: float = 0.1
     kappa_flow: float = 0.25
+    day_period: int = 0          # day / night cycle: 0 = none
+    night_num: int = 0
+    day_inject: int = 0
+    cycle_step: int = 0          # steps completed before the step
 
     @classmethod
     def from_spec(cls, spec) -> "Desc":
@@ -118,7 +124,8 @@ class Desc:
 
     def c(self) -> _Desc:
         return _Desc(self.width, self.height, self.n_weight_layers, self.hidden,
-                     self.rho_invest, self.rho_liquidate, self.kappa_flow)
+                     self.rho_invest, self.rho_liquidate, self.kappa_flow, self.day_period,
+                     self.night_num, self.day_inject, self.cycle_step)
 
     @property
     def n(self) -> int:
@@ -230,14 +237,15 @@ def step(d: Desc, s: State, nets: np.ndarray, rows: tuple[int, int] | None = Non
     rec = np.zeros(N, dtype=RECORD_DTYPE) if want_records else None
     mar = np.full((N, N_MARGIN), np.nan) if want_margins else None
     nul = ct.c_void_p(0)
+    eio = np.zeros(2, np.int64)
     tk = lib().orc_step_rows(ct.byref(d.c()), _p(E), _p(I), _p(C), _p(G), _p(R), _p(nets),
                              int(nets.shape[0]), int(y0), int(y1), _p(E2), _p(I2), _p(C2),
                              _p(G2), _p(R2), _p(act) if act is not None else nul,
                              _p(rec) if rec is not None else nul,
-                             _p(mar) if mar is not None else nul)
+                             _p(mar) if mar is not None else nul, _p(eio))
     if tk < 0:
         raise ValueError("genome id outside the network table")
-    info = {"takeovers": int(tk)}
+    info = {"takeovers": int(tk), "injected": int(eio[0]), "removed": int(eio[1])}
     if act is not None:
         info["act"] = act.reshape(H, W, N_OUT)
     if rec is not None:

@@ -44,6 +44,13 @@ typedef struct {
     int32_t n_weight_layers; /* 2: 54-h-14, 3: 54-h-h-14 */
     int32_t hidden;
     double rho_invest, rho_liquidate, kappa_flow;
+    /* day / night cycle (0 = none): period in steps, energy quanta added per
+     * cell per step at noon, fraction (over 65536) of a cell's energy removed
+     * per step at midnight, and the number of steps completed before this one */
+    int32_t day_period;
+    int32_t night_num;
+    int64_t day_inject;
+    int64_t cycle_step;
 } orc_desc;
 
 /* Per-cell result of sense -> act -> local conversion (the "record" that the
@@ -287,6 +294,30 @@ static void cell_record(const orc_desc* d, const int64_t* E, const int64_t* I, c
     orc_actuate(d, E[i], I[i], R[i] & 7, a, rec, comm);
 }
 
+/* Day / night cycle (Experiment: energy is added to and removed from the
+ * substrate in a day / night cycle; the shape is a reading).  The daylight of
+ * the step is a triangle wave over the period P: with q = cycle_step mod P
+ * the cycle has run q steps since noon, min(q, P - q) is the distance to the
+ * nearest noon, and the daylight is L = P - 4 min(q, P - q), so L = P at
+ * noon, 0 a quarter period away, -P at midnight.  By day (L > 0) every cell
+ * gains floor(A L / P) quanta of energy; by night (L < 0) it loses
+ * floor(floor(E1 num / 65536) (-L) / P) quanta of its energy E1 (never more
+ * than E1).  Integers throughout.  Returns the cell's energy after the cycle
+ * and adds the cell's gain and loss to io[0] and io[1]. */
+static int64_t cycle_energy(const orc_desc* d, int64_t e1, int64_t io[2]) {
+    if (d->day_period <= 0) return e1;
+    const int64_t P = d->day_period;
+    const int64_t q = d->cycle_step % P;
+    const int64_t to_noon = q < P - q ? q : P - q;
+    const int64_t L = P - 4 * to_noon;
+    int64_t gain = 0, loss = 0;
+    if (L > 0) gain = d->day_inject * L / P;
+    if (L < 0) loss = ((e1 * (int64_t)d->night_num) / 65536) * (-L) / P;
+    io[0] += gain;
+    io[1] += loss;
+    return e1 + gain - loss;
+}
+
 /* Physics (Experiment, exploration and takeover), pulled at target t: every
  * neighbour n = nbr(t, d) sends t its flow toward direction (d+4) mod 8;
  * neighbours whose explore direction is (d+4) mod 8 are candidates; the
@@ -355,12 +386,16 @@ static int cell_physics(const orc_desc* d, const orc_record* rec_t, const orc_re
  *     3: max(v_win, I1(t)) with a candidate, else 0;
  *     4: 1 when I1(t) and every candidate's flows are decided integers
  *        (floor_decided), so that the takeover and ranking decisions are
- *        exact comparisons of exactly known integers; else 0.
+ *        exact comparisons of exactly known integers; else 0;
+ *   energy_io (2, nullable): the day / night cycle's injected and removed
+ *   quanta over the rows.
+ * E2 = the cycle applied to E1 (cycle_energy; E1 itself without a cycle).
  * Returns the number of takeovers in the rows, or -1 on a bad genome id. */
 int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, const double* C,
                       const int32_t* G, const uint8_t* R, const double* nets, int32_t n_genomes,
                       int32_t y0, int32_t y1, int64_t* E2, int64_t* I2, double* C2, int32_t* G2,
-                      uint8_t* R2, double* act, orc_record* rec_out, double* margins) {
+                      uint8_t* R2, double* act, orc_record* rec_out, double* margins,
+                      int64_t* energy_io) {
     const int64_t W = d->width, H = d->height, N = W * H;
     const int64_t nsz = orc_net_size(d);
     for (int64_t i = 0; i < N; ++i)
@@ -379,8 +414,8 @@ int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, con
                     (act && in_rows) ? act + i * ORC_NOUT : NULL);
         for (int c = 0; c < 4; ++c) cn[c * N + i] = comm[c];
     }
-    int64_t takeovers = 0;
-#pragma omp parallel for schedule(static) reduction(+ : takeovers)
+    int64_t takeovers = 0, gained = 0, lost = 0;
+#pragma omp parallel for schedule(static) reduction(+ : takeovers, gained, lost)
     for (int64_t k = 0; k < (int64_t)rows * W; ++k) {
         int64_t y = (y0 + k / W) % H, x = k % W, t = y * W + x;
         int64_t nidx[8];
@@ -405,7 +440,10 @@ int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, con
         double mt, mr, mg;
         takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt,
                                   &mr, &mg);
-        E2[t] = rec[t].e1;
+        int64_t io[2] = {0, 0};
+        E2[t] = cycle_energy(d, rec[t].e1, io);
+        gained += io[0];
+        lost += io[1];
         for (int c = 0; c < 4; ++c) C2[c * N + t] = cn[c * N + t];
         if (rec_out) rec_out[t] = rec[t];
         if (margins) {
@@ -418,6 +456,10 @@ int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, con
     }
     free(rec);
     free(cn);
+    if (energy_io) {
+        energy_io[0] = gained;
+        energy_io[1] = lost;
+    }
     return takeovers;
 }
 

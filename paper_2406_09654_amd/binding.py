@@ -23,7 +23,7 @@ CORALAI_E_GENOME = -3
 CORALAI_E_NUMERIC = -4
 CORALAI_E_HIP = -5
 CORALAI_E_BUSY = -6
-ERR_GENOME_RANGE, ERR_GENOME_UNSET, ERR_LEDGER, ERR_NONFINITE = 1, 2, 4, 8
+ERR_GENOME_RANGE, ERR_GENOME_UNSET, ERR_LEDGER, ERR_NONFINITE, ERR_MASS = 1, 2, 4, 8, 16
 
 EXPORTED = [
     "coralai_world_bytes", "coralai_world_create", "coralai_world_destroy", "coralai_set_state",
@@ -35,7 +35,7 @@ EXPORTED = [
     "coralai_debug_set_weights", "coralai_debug_get_weights", "coralai_debug_physics",
     "coralai_set_profiling", "coralai_get_profile", "coralai_batch_autotune",
     "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
-    "coralai_debug_set_weights_noalloc",
+    "coralai_debug_set_weights_noalloc", "coralai_set_daylight", "coralai_get_energy_ledger",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -106,6 +106,8 @@ def lib() -> ct.CDLL:
             "coralai_debug_physics": (ct.c_int, [P, P, P, P]),
             "coralai_debug_set_act_segments": (ct.c_int, [P, I32]),
             "coralai_debug_set_weights_noalloc": (ct.c_int, [P, I32, P]),
+            "coralai_set_daylight": (ct.c_int, [P, I32, ct.c_int64, I32]),
+            "coralai_get_energy_ledger": (ct.c_int, [P, P, P, P, P]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
         }
@@ -181,6 +183,18 @@ def coralai_radiate(h, rate: float, sigma: float, step_index: int,
                     stats: coralai_stats | None = None) -> None:
     _check(lib().coralai_radiate(h, rate, sigma, step_index,
                                  ct.byref(stats) if stats is not None else None))
+
+
+def coralai_set_daylight(h, period: int, inject_quanta: int, remove_num: int) -> None:
+    _check(lib().coralai_set_daylight(h, period, inject_quanta, remove_num))
+
+
+def coralai_get_energy_ledger(h) -> dict:
+    v = np.zeros(4, np.int64)
+    p = [ct.c_void_p(v.ctypes.data + 8 * k) for k in range(4)]
+    _check(lib().coralai_get_energy_ledger(h, *p))
+    return {"injected_last": int(v[0]), "removed_last": int(v[1]),
+            "injected_total": int(v[2]), "removed_total": int(v[3])}
 
 
 def coralai_sync(h) -> None:

@@ -25,7 +25,7 @@ constexpr int kPrecFP32 = 0;
 constexpr int kPrecBF16 = 1;
 
 constexpr uint32_t kErrGenomeRange = 1u, kErrGenomeUnset = 2u, kErrLedger = 4u,
-                   kErrNonFinite = 8u;
+                   kErrNonFinite = 8u, kErrMass = 16u;
 
 // Per-world control block (device memory, inside the world's arena).
 struct Ctl {
@@ -49,6 +49,16 @@ struct Ctl {
     int32_t live_pub;
     int32_t hits_pub;
     int32_t dropped_pub;
+    // day / night energy ledger: this step's accumulators, the last step's
+    // totals and the running totals since creation (quanta)
+    int64_t acc_injected;
+    int64_t acc_removed;
+    int64_t injected_pub;
+    int64_t removed_pub;
+    int64_t injected_total;
+    int64_t removed_total;
+    int32_t mass_valid;     // `mass` is the sum of the current state (the next step checks against it)
+    int32_t pad_ctl2;
 };
 
 // One world as the kernels see it (device memory).  All planes are
@@ -57,8 +67,11 @@ struct WorldDev {
     int32_t W, H, N, cap;
     int32_t NL, HID, prec, n_rad_blocks;
     float rho_i, rho_l, kappa;
-    int32_t pad0;
+    int32_t day_period;   // day / night cycle length in steps (0 = no cycle)
     uint64_t seed;
+    int64_t day_inject;   // energy quanta a cell receives per step at noon
+    int32_t night_num;    // at midnight a cell loses night_num / 65536 of its energy per step
+    int32_t pad_dn;
     int64_t* EI[2];       // [N][2]: energy and infrastructure quanta of a cell together
     float* C[2];          // [N][4]: the 4 communication channels of a cell together
     int32_t* G[2];
@@ -312,6 +325,48 @@ __device__ __forceinline__ void buf_st_f32x4(coralai_f32x4 v, __amdgpu_buffer_rs
 // conversion for the common |v| < 2^24, correctly rounded below 2^32).
 __device__ __forceinline__ float i64_to_f32(int64_t v) {
     return __builtin_fmaf((float)(int32_t)(v >> 32), 4294967296.0f, (float)(uint32_t)v);
+}
+
+// Day / night cycle (Experiment: energy is added to and removed from the
+// substrate in a day / night cycle).  With period P and q = s mod P for the
+// step s (steps completed before it), the daylight is the triangle wave
+// L = P - 4 min(q, P - q) in [-P, P] (P at noon, q = 0; -P at midnight,
+// q = P / 2).  In the physics pass every cell's energy becomes
+//   E2 = E1 + floor(A max(L, 0) / P) - floor(floor(E1 num / 2^16) max(-L, 0) / P),
+// all in int64 (E1 < 2^40 quanta, A < 2^40), so every side of the
+// computation gets the same integers and the mass ledger moves by exactly
+// the injected minus the removed quanta.
+struct DayNight {
+    int64_t inject;  // quanta per cell this step
+    int64_t night;   // max(-L, 0)
+    int64_t period;
+    int64_t num;
+};
+__device__ __forceinline__ DayNight day_night(int32_t period, int64_t day_inject, int32_t night_num,
+                                               int64_t steps_done) {
+    DayNight dn{0, 0, 1, 0};
+    if (period <= 0) return dn;
+    const int64_t P = period, q = steps_done % P;
+    const int64_t L = P - 4 * (q < P - q ? q : P - q);
+    dn.period = P;
+    dn.inject = L > 0 ? day_inject * L / P : 0;
+    dn.night = L < 0 ? -L : 0;
+    dn.num = night_num;
+    return dn;
+}
+// Energy after the cycle's source and sink; adds this cell's injected and
+// removed quanta to the accumulators.
+__device__ __forceinline__ int64_t day_night_energy(int64_t e1, const DayNight& dn, int64_t& inj,
+                                                    int64_t& rem, uint32_t& err) {
+    int64_t ec = e1;
+    if (ec >= (1ll << 40)) {
+        err |= kErrLedger;
+        ec = (1ll << 40) - 1;
+    }
+    const int64_t r = dn.night > 0 ? ((ec * dn.num) >> 16) * dn.night / dn.period : 0;
+    inj += dn.inject;
+    rem += r;
+    return e1 + dn.inject - r;
 }
 
 // Host-side launch shapes ----------------------------------------------------

@@ -327,6 +327,8 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict_
             w.ctl->acc_mass = 0;
             w.ctl->acc_mass_f64 = 0.0;
             w.ctl->acc_takeovers = 0;
+            w.ctl->acc_injected = 0;
+            w.ctl->acc_removed = 0;
         }
         int c = 0, gsum = 0, live = 0, fr = 0;
         for (int k = 0; k < kSlotBlock / 256; ++k) {
@@ -470,8 +472,16 @@ __global__ void k_finalize(const BatchDev* __restrict__ b) {
     const int wi = blockIdx.y * blockDim.x + threadIdx.x;
     if (wi >= b->n_worlds) return;
     Ctl* c = b->worlds[wi].ctl;
+    // conservation check against the previous step: the sum moves by exactly
+    // the cycle's injected minus removed quanta (zero without the cycle)
+    if (c->mass_valid && c->acc_mass != c->mass + c->acc_injected - c->acc_removed) c->err |= kErrMass;
     c->mass = c->acc_mass;
     c->mass_f64 = c->acc_mass_f64;
+    c->mass_valid = 1;
+    c->injected_pub = c->acc_injected;
+    c->removed_pub = c->acc_removed;
+    c->injected_total += c->acc_injected;
+    c->removed_total += c->acc_removed;
     c->takeovers = (int32_t)c->acc_takeovers;
     c->live_pub = c->live;
     c->steps += 1;

@@ -10,8 +10,9 @@
 // I2 = I1 - sum(own flows) + sum(inflows); the
 // candidate explorers are the neighbours exploring toward t, the largest
 // investment wins (lowest d on ties) and takes t over when it strictly
-// exceeds I1(t).  The next state's ledger pair is (E1, I2): energy does not
-// move.  Each flow word is (amount << 1) | explored, so one read per
+// exceeds I1(t).  The next state's ledger pair is (E2, I2): energy does not
+// move between cells, and E2 = E1 plus the day / night cycle's source and
+// sink (exact integers, see day_night).  Each flow word is (amount << 1) | explored, so one read per
 // direction gives both the inflow and the candidacy.  The tile loads the
 // flow records and genomes of (TW+2) x (TH+2) cells with coalesced row
 // loads; outflows, inflows, takeover and the block's share of the total-mass
@@ -38,6 +39,23 @@ __device__ __forceinline__ void wave_count_add(int32_t* counts, int g, int d, bo
     }
 }
 
+// Adds a wavefront's injected and removed quanta and error bits to the
+// world's step accumulators (one atomic each from the first lane holding a
+// nonzero sum; the cycle is off in most worlds).
+__device__ __forceinline__ void day_night_flush(Ctl* ctl, int64_t inj, int64_t rem, uint32_t err, int lane) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        inj += __shfl_xor(inj, o, 64);
+        rem += __shfl_xor(rem, o, 64);
+        err |= __shfl_xor(err, o, 64);
+    }
+    if (lane == 0 && ctl != nullptr) {
+        if (inj) atomicAdd((unsigned long long*)&ctl->acc_injected, (unsigned long long)inj);
+        if (rem) atomicAdd((unsigned long long*)&ctl->acc_removed, (unsigned long long)rem);
+        if (err) atomicOr(&ctl->err, err);
+    }
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b) {
     constexpr int NT = 256, CPT = TW * TH / NT;  // threads, cells per thread
@@ -58,10 +76,12 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
 
     int wi = -1;
     int64_t world_hi = -1;
-    int64_t acc_m = 0;
+    int64_t acc_m = 0, acc_inj = 0, acc_rem = 0;
     double acc_f = 0.0;
     int acc_t = 0;
+    uint32_t err = 0;
     Ctl* ctl = nullptr;
+    DayNight dn{0, 0, 1, 0};
 
     auto flush = [&]() {
         // block-wide: every thread of the block walks the same tiles
@@ -86,9 +106,13 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
             atomicAdd((unsigned long long*)&ctl->acc_takeovers, (unsigned long long)(int64_t)st);
         }
         __syncthreads();
+        day_night_flush(ctl, acc_inj, acc_rem, err, lane);
         acc_m = 0;
         acc_f = 0.0;
         acc_t = 0;
+        acc_inj = 0;
+        acc_rem = 0;
+        err = 0;
     };
 
     int Wd = 0, Hd = 0, Nd = 0, tx_n = 1;
@@ -113,6 +137,7 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
             Wd = W->W; Hd = W->H; Nd = W->N;
             tx_n = cld(b->tiles_x + (wi));
             ctl = W->ctl;
+            dn = day_night(W->day_period, W->day_inject, W->night_num, cld(&ctl->steps));
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             flow = W->flow; EI1p = W->EI1;
             Gc = W->G[cur]; Rc = W->R[cur];
@@ -206,11 +231,13 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
                     took = true;
                     g_to = so + g2;
                 }
-                gst((i64x2*)EIn + t, i64x2{e1, i2});
+                const int64_t e2 = day_night_energy(e1, dn, acc_inj, acc_rem, err);
+                gst((i64x2*)EIn + t, i64x2{e2, i2});
                 gst(Gn + t, g2);
                 gst(Rn + t, r2);
-                acc_m += i2;
-                acc_f += (double)i2;
+                // the network kernel added E1; the cycle's change and I2 complete the sum
+                acc_m += i2 + (e2 - e1);
+                acc_f += (double)(i2 + (e2 - e1));
             }
             // the genome counts follow the takeovers (the next step and radiation use them)
             wave_count_add(cnt, g_from, -1, took);
@@ -237,10 +264,12 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     const int64_t total = cld(b->tile_prefix + (nworlds));
     int wi = -1;
     int64_t world_hi = -1, world_lo = 0;
-    int64_t acc_m = 0;
+    int64_t acc_m = 0, acc_inj = 0, acc_rem = 0;
     double acc_f = 0.0;
     int acc_t = 0;
+    uint32_t err = 0;
     Ctl* ctl = nullptr;
+    DayNight dn{0, 0, 1, 0};
     int Wd = 0, Hd = 0, Nd = 0;
     __amdgpu_buffer_rsrc_t rflow, rei1, rg, rr;
     int32_t* cnt = nullptr;  // stripe counts
@@ -268,9 +297,13 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                       (unsigned long long)(int64_t)(s_red_t[0] + s_red_t[1] + s_red_t[2] + s_red_t[3]));
         }
         __syncthreads();
+        day_night_flush(ctl, acc_inj, acc_rem, err, lane);
         acc_m = 0;
         acc_f = 0.0;
         acc_t = 0;
+        acc_inj = 0;
+        acc_rem = 0;
+        err = 0;
     };
     int64_t unit, uend;
     balanced_share(total, xcd_block(), gridDim.x, &unit, &uend);
@@ -283,6 +316,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             const auto* W = world_at(b, wi);
             Wd = W->W; Hd = W->H; Nd = W->N;
             ctl = W->ctl;
+            dn = day_night(W->day_period, W->day_inject, W->night_num, cld(&ctl->steps));
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             const uint32_t n4 = 4u * (uint32_t)Nd;
             rflow = buf_rsrc(W->flow, 8u * n4);
@@ -369,9 +403,10 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                         took[j] = true;
                         acc_t += 1;
                     }
-                    gst((i64x2*)EIn + t0 + j, i64x2{e1, i2});
-                    acc_m += i2;
-                    acc_f += (double)i2;
+                    const int64_t e2 = day_night_energy(e1, dn, acc_inj, acc_rem, err);
+                    gst((i64x2*)EIn + t0 + j, i64x2{e2, i2});
+                    acc_m += i2 + (e2 - e1);
+                    acc_f += (double)(i2 + (e2 - e1));
                 }
                 gst((coralai_u32x4*)Gn + t0 / 4, gs);
                 gst((uint32_t*)Rn + t0 / 4, rs);
@@ -421,11 +456,12 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                 took = true;
                 g_to = so + g2;
             }
-            gst((i64x2*)EIn + t, i64x2{e1, i2});
+            const int64_t e2 = day_night_energy(e1, dn, acc_inj, acc_rem, err);
+            gst((i64x2*)EIn + t, i64x2{e2, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);
-            acc_m += i2;
-            acc_f += (double)i2;
+            acc_m += i2 + (e2 - e1);
+            acc_f += (double)(i2 + (e2 - e1));
         }
         // the genome counts follow the takeovers (the next step and radiation use them)
         wave_count_add(cnt, g_from, -1, took);

@@ -262,6 +262,8 @@ int report_errors(coralai_world* w, uint32_t* word_out) {
         HIP_TRY(hipStreamSynchronize(w->stream));
         if (e & (CORALAI_ERR_GENOME_RANGE | CORALAI_ERR_GENOME_UNSET))
             return fail(CORALAI_E_GENOME, "a cell names a genome slot outside [0, capacity) or without parameters (error word 0x%x)", e);
+        if (e & CORALAI_ERR_MASS)
+            return fail(CORALAI_E_NUMERIC, "the total mass changed by other than the injected minus the removed quanta (error word 0x%x)", e);
         return fail(CORALAI_E_NUMERIC, "non-finite network output / CPPN weight or ledger overflow (error word 0x%x)", e);
     }
     return CORALAI_OK;
@@ -287,9 +289,13 @@ int check_launch() {
 
 // The device genome counts no longer describe the current state (new state
 // from the host, or trial launches that ran physics without committing it).
+// The state changed outside a step (new state, a debug hook, the
+// autotuner's trials): the genome counts must be recounted, and the next
+// step has no previous total mass to check against.
 int invalidate_counts(coralai_world* w) {
     w->counts_stale = true;
     HIP_TRY(hipMemsetAsync(&w->host.ctl->counts_valid, 0, sizeof(int32_t), w->stream));
+    HIP_TRY(hipMemsetAsync(&w->host.ctl->mass_valid, 0, sizeof(int32_t), w->stream));
     return CORALAI_OK;
 }
 
@@ -1122,6 +1128,31 @@ int coralai_debug_set_weights_noalloc(coralai_world* w, int32_t slot, const floa
     if (rc) return rc;
     // the next call on this device may overwrite the staging buffer
     HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int coralai_set_daylight(coralai_world* w, int32_t period, int64_t inject_quanta, int32_t remove_num) {
+    WORLD_GUARD(w);
+    if (period != 0 && period < 2) return fail(CORALAI_E_INVALID, "period must be 0 (no cycle) or >= 2 steps");
+    if (inject_quanta < 0 || inject_quanta >= (1ll << 40)) return fail(CORALAI_E_INVALID, "inject_quanta must be in [0, 2^40)");
+    if (remove_num < 0 || remove_num > 65536) return fail(CORALAI_E_INVALID, "remove_num must be in [0, 65536]");
+    (void)hipStreamSynchronize(w->stream);
+    w->host.day_period = period;
+    w->host.day_inject = period ? inject_quanta : 0;
+    w->host.night_num = period ? remove_num : 0;
+    return write_world_tables(w);
+}
+
+int coralai_get_energy_ledger(coralai_world* w, int64_t* injected_last, int64_t* removed_last,
+                              int64_t* injected_total, int64_t* removed_total) {
+    WORLD_GUARD(w);
+    const int rc = read_ctl(w);
+    if (rc) return rc;
+    const Ctl& c = *w->pinned;
+    if (injected_last) *injected_last = c.injected_pub;
+    if (removed_last) *removed_last = c.removed_pub;
+    if (injected_total) *injected_total = c.injected_total;
+    if (removed_total) *removed_total = c.removed_total;
     return CORALAI_OK;
 }
 

@@ -128,6 +128,15 @@ class World:
         B.coralai_radiate(self.h, rate, sigma, step_index, None)
         return None
 
+    def set_daylight(self, period: int, inject_quanta: int, remove_num: int) -> None:
+        """Day / night cycle: period in steps (0 = off), energy quanta added per
+        cell per step at noon, fraction (over 65536) of a cell's energy removed
+        per step at midnight."""
+        B.coralai_set_daylight(self.h, period, inject_quanta, remove_num)
+
+    def energy_ledger(self) -> dict:
+        return B.coralai_get_energy_ledger(self.h)
+
     def sync(self) -> None:
         B.coralai_sync(self.h)
 

@@ -94,12 +94,23 @@ def floor_decided(x):
     return x == 0.0 or math.floor(x * (1.0 - FLOOR_REL)) == math.floor(x * (1.0 + FLOOR_REL))
 
 
+def daylight(step, period):
+    """Daylight of a step in a cycle of `period` steps, as an integer in
+    [-period, period]: period at noon (step 0 of the cycle), falling linearly
+    to 0 a quarter cycle later and to -period at midnight, then back."""
+    hours_since_noon = step % period
+    hours_to_noon = min(hours_since_noon, period - hours_since_noon)
+    return period - 4 * hours_to_noon
+
+
 class World:
-    def __init__(self, W, H, E, I, C, G, R, nets, rho_i, rho_l, kappa):
+    def __init__(self, W, H, E, I, C, G, R, nets, rho_i, rho_l, kappa, cycle=None):
         self.W, self.H = W, H
         self.E, self.I, self.C, self.G, self.R = E, I, C, G, R   # flat lists; C = 4 lists
         self.nets = nets
         self.rho_i, self.rho_l, self.kappa = rho_i, rho_l, kappa
+        # day / night cycle: (period, quanta per cell at noon, removal over 65536, step)
+        self.cycle = cycle
 
     def at(self, x, y):
         return (y % self.H) * self.W + (x % self.W)
@@ -196,6 +207,13 @@ class World:
                     best = (amount, d, n)
             I2[t] = pt["i1"] - sum(pt["flows"].values()) + inflow
             E2[t] = pt["e1"]
+            if self.cycle is not None:
+                period, noon_quanta, removal, step = self.cycle
+                light = daylight(step, period)
+                if light > 0:
+                    E2[t] += noon_quanta * light // period
+                elif light < 0:
+                    E2[t] -= (pt["e1"] * removal // 65536) * (-light) // period
             for k in range(4):
                 C2[k][t] = pt["comm"][k]
             G2[t], R2[t] = self.G[t], self.R[t]

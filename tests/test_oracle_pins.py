@@ -32,10 +32,11 @@ def tiny_world(oracle, W, H, n_genomes=3, hidden=8, layers=2, seed=1, scale=1.0,
 def bf_world(d, s, params, oracle):
     widths = d.widths()
     nets = [bf.build_net(list(map(float, p)), widths) for p in params]
+    cycle = (d.day_period, d.day_inject, d.night_num, d.cycle_step) if d.day_period else None
     return bf.World(d.width, d.height, [int(v) for v in s.E.ravel()], [int(v) for v in s.I.ravel()],
                     [list(map(float, s.C[k].ravel())) for k in range(4)],
                     [int(v) for v in s.G.ravel()], [int(v) for v in s.R.ravel()], nets,
-                    d.rho_invest, d.rho_liquidate, d.kappa_flow)
+                    d.rho_invest, d.rho_liquidate, d.kappa_flow, cycle)
 
 
 # ---------------------------------------------------------------- geometry
@@ -508,3 +509,83 @@ def test_hit_counts_binomial(oracle_lib):
     n, p = W * H, 0.01
     mean = np.mean(counts)
     assert abs(mean - n * p) < 4 * math.sqrt(n * p * (1 - p) / len(counts))
+
+
+# ---------------------------------------------------------------- day / night cycle
+
+@pytest.mark.parametrize("period,q", [(8, 0), (8, 1), (8, 3), (8, 4), (8, 6), (10, 5), (7, 3)])
+def test_day_night_step_matches_bruteforce(oracle_lib, period, q):
+    """With the cycle on, every phase (noon, morning, dusk, midnight, and odd
+    periods whose midnight falls between steps) matches the brute force."""
+    for seed in range(2):
+        d, s, params = tiny_world(oracle_lib, 6, 5, hidden=8, seed=seed, scale=2.0)
+        d.day_period, d.day_inject, d.night_num, d.cycle_step = period, 3_000_017, 40_000, 3 * period + q
+        s2, info = oracle_lib.step(d, s, oracle_lib.nets_for(d, params))
+        E2, I2, C2, G2, R2, tk, _ = bf_world(d, s, params, oracle_lib).step()
+        assert s2.E.ravel().tolist() == E2
+        assert s2.I.ravel().tolist() == I2
+        assert s2.G.ravel().tolist() == G2 and s2.R.ravel().tolist() == R2
+
+
+def test_day_night_uniform_world_closed_form(oracle_lib):
+    """A uniform world under a genome whose CPPN output layer is zero (a = 0:
+    sigmoid 1/2, softmax 1/8): every cell's E1 = E - floor(E/20) + floor(I/20)
+    and the cycle adds floor(A L / P) by day or removes
+    floor(floor(E1 num / 65536) (-L) / P) by night, with L = P at noon, P/2 an
+    eighth of a period later, 0 at a quarter, -P at midnight."""
+    W = H = 6
+    e, i = 5_000_000, 3_000_000
+    E = np.full((H, W), e, np.int64)
+    I = np.full((H, W), i, np.int64)
+    C = np.zeros((4, H, W))
+    G = np.zeros((H, W), np.int32)
+    R = np.zeros((H, W), np.uint8)
+    p = np.random.default_rng(1).standard_normal(56)
+    p[40:] = 0.0
+    e1 = e - e // 20 + i // 20
+    A, num, P = 1_000_003, 30_000, 16
+    for q, L in [(0, 16), (2, 8), (4, 0), (6, -8), (8, -16), (12, 0), (14, 8)]:
+        d = oracle_lib.Desc(W, H, 2, 8, day_period=P, day_inject=A, night_num=num, cycle_step=5 * P + q)
+        s2, info = oracle_lib.step(d, oracle_lib.State(E, I, C, G, R), oracle_lib.nets_for(d, p[None]))
+        gain = A * L // P if L > 0 else 0
+        loss = (e1 * num // 65536) * (-L) // P if L < 0 else 0
+        assert (s2.E == e1 + gain - loss).all(), (q, int(s2.E[0, 0]), e1, gain, loss)
+        assert info["injected"] == gain * W * H and info["removed"] == loss * W * H
+    # midnight with the whole fraction removes all the energy
+    d = oracle_lib.Desc(W, H, 2, 8, day_period=P, day_inject=A, night_num=65536, cycle_step=P // 2)
+    s2, _ = oracle_lib.step(d, oracle_lib.State(E, I, C, G, R), oracle_lib.nets_for(d, p[None]))
+    assert (s2.E == 0).all()
+
+
+def test_day_night_ledger_balance_over_cycles(oracle_lib):
+    """Over two periods of the 64x64 workload the total mass moves by exactly
+    the injected minus the removed quanta at every step, and a full period's
+    injection with P = 4 is one noon's worth (A per cell)."""
+    init = wl.config_plain_64()
+    d = oracle_lib.Desc.from_spec(init.spec)
+    nets = oracle_lib.nets_for(d, init.params)
+    s = oracle_lib.State.from_init(init)
+    d.day_period, d.day_inject, d.night_num = 4, 2_000_000, 20_000
+    m = oracle_lib.mass(s.E, s.I)
+    inj_total = 0
+    for k in range(8):
+        d.cycle_step = k
+        s, info = oracle_lib.step(d, s, nets)
+        m2 = oracle_lib.mass(s.E, s.I)
+        assert m2 == m + info["injected"] - info["removed"]
+        assert (info["removed"] > 0) == (k % 4 == 2)
+        m = m2
+        inj_total += info["injected"]
+    assert inj_total == 2 * 2_000_000 * 64 * 64
+
+
+def test_day_night_off_is_the_plain_step(oracle_lib):
+    d, s, params = tiny_world(oracle_lib, 9, 7, hidden=8, seed=3)
+    nets = oracle_lib.nets_for(d, params)
+    a, ia = oracle_lib.step(d, s, nets, want_records=True)
+    d.day_inject, d.night_num, d.cycle_step = 123456, 4000, 17   # period 0: no cycle
+    b, ib = oracle_lib.step(d, s, nets)
+    for x, y in [(a.E, b.E), (a.I, b.I), (a.G, b.G), (a.R, b.R)]:
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a.E, ia["records"]["e1"])
+    assert ib["injected"] == 0 and ib["removed"] == 0
