@@ -84,8 +84,12 @@ typedef struct {
     float rho_invest;         /* default 0.1 */
     float rho_liquidate;      /* default 0.1 */
     float kappa_flow;         /* default 0.25 */
-    int32_t reserved;         /* must be 0 */
+    int32_t flags;            /* CORALAI_WORLD_* bits, 0 by default */
 } coralai_world_desc;
+
+/* coralai_world_desc.flags: reserve the 32-byte-per-cell energy flow records
+ * that energy transport (coralai_set_physics_variant) needs. */
+enum { CORALAI_WORLD_ENERGY_FLOWS = 1 };
 
 /* Per-world statistics, as of the last completed step or radiation call. */
 typedef struct {
@@ -169,6 +173,20 @@ int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_in
  * coralai_batch_set_worlds. */
 int coralai_set_daylight(coralai_world* w, int32_t period, int64_t inject_quanta, int32_t remove_num);
 
+/* Physics variants (Experiment: an explore actuator spreads infrastructure
+ * to the neighbour of the maximal actuator; which quantity moves is a
+ * reading).  explore_mode 0 (default): the exploration budget
+ * floor(kappa_flow * I1) is split over the 8 neighbours by the softmax of
+ * the explore actuators; 1 (hard max): all of it goes to the neighbour of the
+ * maximal explore actuator (lowest kernel position on ties).
+ * kappa_energy > 0: a cell also sends floor(kappa_energy * E1) of its energy
+ * along the same directions in the same proportions, so energy moves with
+ * the infrastructure; 0 (default): energy stays.  kappa_energy > 0 needs a
+ * world created with CORALAI_WORLD_ENERGY_FLOWS.  Per-cell budgets must stay
+ * below 2^31 quanta (else CORALAI_ERR_LEDGER).  Takes effect from the next
+ * step (a world in a batch: at the batch's next coralai_batch_set_worlds). */
+int coralai_set_physics_variant(coralai_world* w, int32_t explore_mode, float kappa_energy);
+
 /* The cycle's energy ledger in quanta: injected and removed by the last step,
  * and in total since the world was created.  Waits for the stream; any
  * pointer may be NULL. */
@@ -244,7 +262,8 @@ const char* coralai_version(void);
  *                   int64, flows [W*H x 8] uint32 (< 2^31) toward absolute
  *                   directions 0..7, explore direction [W*H] uint8 -- on the current G,
  *                   R; the result becomes the current state with E and C
- *                   unchanged;
+ *                   unchanged (infrastructure flows only: an error while
+ *                   energy transport is on);
  *  debug_set_act_segments: the number of segments of the genome-ordered
  *                   unit list from which each wavefront of the network kernel
  *                   takes one chunk (0 = automatic: 4 for BF16 networks on

@@ -40,19 +40,21 @@ class _Desc(ct.Structure):
                 ("rho_invest", ct.c_double), ("rho_liquidate", ct.c_double),
                 ("kappa_flow", ct.c_double), ("day_period", ct.c_int32),
                 ("night_num", ct.c_int32), ("day_inject", ct.c_int64),
-                ("cycle_step", ct.c_int64)]
+                ("cycle_step", ct.c_int64), ("explore_mode", ct.c_int32),
+                ("pad_desc", ct.c_int32), ("kappa_energy", ct.c_double)]
 
 
 class Record(ct.Structure):
     _fields_ = [("e1", ct.c_int64), ("i1", ct.c_int64), ("flow", ct.c_int64 * 8),
                 ("explore_dir", ct.c_int32), ("explore_pos", ct.c_int32),
-                ("logit_gap", ct.c_double), ("runner_dir", ct.c_int32), ("exact", ct.c_int32)]
+                ("logit_gap", ct.c_double), ("runner_dir", ct.c_int32), ("exact", ct.c_int32),
+                ("eflow", ct.c_int64 * 8)]
 
 
 RECORD_DTYPE = np.dtype([("e1", np.int64), ("i1", np.int64), ("flow", np.int64, (8,)),
                          ("explore_dir", np.int32), ("explore_pos", np.int32),
                          ("logit_gap", np.float64), ("runner_dir", np.int32),
-                         ("exact", np.int32)])
+                         ("exact", np.int32), ("eflow", np.int64, (8,))])
 assert RECORD_DTYPE.itemsize == ct.sizeof(Record)
 
 _lib = None
@@ -113,6 +115,8 @@ class Desc:
     night_num: int = 0
     day_inject: int = 0
     cycle_step: int = 0          # steps completed before the step
+    explore_mode: int = 0        # 0: softmax split of the exploration budget, 1: all to the maximal
+    kappa_energy: float = 0.0    # > 0: energy moves along the flow directions
 
     @classmethod
     def from_spec(cls, spec) -> "Desc":
@@ -125,7 +129,8 @@ class Desc:
     def c(self) -> _Desc:
         return _Desc(self.width, self.height, self.n_weight_layers, self.hidden,
                      self.rho_invest, self.rho_liquidate, self.kappa_flow, self.day_period,
-                     self.night_num, self.day_inject, self.cycle_step)
+                     self.night_num, self.day_inject, self.cycle_step, self.explore_mode, 0,
+                     self.kappa_energy)
 
     @property
     def n(self) -> int:

@@ -51,6 +51,13 @@ typedef struct {
     int32_t night_num;
     int64_t day_inject;
     int64_t cycle_step;
+    /* physics variants: explore_mode 0 splits the exploration budget by the
+     * softmax of the explore actuators, 1 sends all of it to the maximal
+     * one; kappa_energy > 0 also moves floor(kappa_energy E1) of a cell's
+     * energy along the same directions in the same proportions */
+    int32_t explore_mode;
+    int32_t pad_desc;
+    double kappa_energy;
 } orc_desc;
 
 /* Per-cell result of sense -> act -> local conversion (the "record" that the
@@ -63,6 +70,7 @@ typedef struct {
     double logit_gap;      /* top-1 minus top-2 flow logit (FP64) */
     int32_t runner_dir;    /* absolute direction of the second-largest logit */
     int32_t exact;         /* 1: every integer above is decided with margin (see floor_decided) */
+    int64_t eflow[8];      /* energy sent toward absolute direction d (energy transport) */
 } orc_record;
 
 /* Directions: d at 45*d degrees counter-clockwise from +x, y pointing down. */
@@ -234,6 +242,11 @@ static int floor_decided(double x) {
  *                       f_p = min(floor(w_p F), F - sum_{q<p} f_q);
  *                       the explored neighbour is the argmax position (lowest
  *                       on ties) and its investment is that position's flow.
+ *                       Hard-max variant (explore_mode 1): the maximal
+ *                       explore actuator takes the whole budget, f_p* = F.
+ *   energy transport:   with kappa_energy > 0 the budget floor(kappa_energy
+ *                       E1) is split the same way (softmax weights with the
+ *                       running clamp, or all to p*).
  * All in FP64, quanta as integers. */
 void orc_actuate(const orc_desc* d, int64_t e, int64_t i, int r, const double* a,
                  orc_record* rec, double* comm_out) {
@@ -269,13 +282,36 @@ void orc_actuate(const orc_desc* d, int64_t e, int64_t i, int r, const double* a
     exact = exact && floor_decided(arg_F);
     int64_t used = 0;
     for (int k = 0; k < 8; ++k) {
-        const double arg_f = (ex[k] / s) * (double)F;
-        exact = exact && floor_decided(arg_f);
-        int64_t f = (int64_t)floor(arg_f);
-        if (f > F - used) f = F - used;
-        if (f < 0) f = 0;
+        int64_t f;
+        if (d->explore_mode == 1) {
+            f = k == best ? F : 0;
+        } else {
+            const double arg_f = (ex[k] / s) * (double)F;
+            exact = exact && floor_decided(arg_f);
+            f = (int64_t)floor(arg_f);
+            if (f > F - used) f = F - used;
+            if (f < 0) f = 0;
+        }
         used += f;
         rec->flow[orc_kernel_dir(r, k + 1)] = f;
+    }
+    for (int k = 0; k < 8; ++k) rec->eflow[k] = 0;
+    if (d->kappa_energy > 0.0) {
+        int64_t FE = (int64_t)floor(d->kappa_energy * (double)rec->e1);
+        if (FE < 0) FE = 0;
+        int64_t eused = 0;
+        for (int k = 0; k < 8; ++k) {
+            int64_t g;
+            if (d->explore_mode == 1) {
+                g = k == best ? FE : 0;
+            } else {
+                g = (int64_t)floor((ex[k] / s) * (double)FE);
+                if (g > FE - eused) g = FE - eused;
+                if (g < 0) g = 0;
+            }
+            eused += g;
+            rec->eflow[orc_kernel_dir(r, k + 1)] = g;
+        }
     }
     rec->explore_pos = best + 1;
     rec->explore_dir = orc_kernel_dir(r, best + 1);
@@ -440,8 +476,14 @@ int64_t orc_step_rows(const orc_desc* d, const int64_t* E, const int64_t* I, con
         double mt, mr, mg;
         takeovers += cell_physics(d, &rec[t], nrec, G, R, nidx, t, &I2[t], &G2[t], &R2[t], &mt,
                                   &mr, &mg);
+        /* energy transport: E1 minus the cell's own energy flows plus the
+         * flows its neighbours send toward it (direction d's neighbour sends
+         * its flow toward (d+4) mod 8) */
+        int64_t e_mid = rec[t].e1;
+        for (int k = 0; k < 8; ++k) e_mid -= rec[t].eflow[k];
+        for (int dd = 0; dd < 8; ++dd) e_mid += nrec[dd]->eflow[(dd + 4) & 7];
         int64_t io[2] = {0, 0};
-        E2[t] = cycle_energy(d, rec[t].e1, io);
+        E2[t] = cycle_energy(d, e_mid, io);
         gained += io[0];
         lost += io[1];
         for (int c = 0; c < 4; ++c) C2[c * N + t] = cn[c * N + t];
@@ -479,6 +521,7 @@ int64_t orc_physics_from_records(const orc_desc* d, const int64_t* i1, const int
         rec[i].logit_gap = 0;
         rec[i].runner_dir = 0;
         rec[i].exact = 0;
+        for (int k = 0; k < 8; ++k) rec[i].eflow[k] = 0;
     }
     int64_t takeovers = 0;
     for (int64_t t = 0; t < N; ++t) {

@@ -24,6 +24,7 @@ CORALAI_E_NUMERIC = -4
 CORALAI_E_HIP = -5
 CORALAI_E_BUSY = -6
 ERR_GENOME_RANGE, ERR_GENOME_UNSET, ERR_LEDGER, ERR_NONFINITE, ERR_MASS = 1, 2, 4, 8, 16
+WORLD_ENERGY_FLOWS = 1
 
 EXPORTED = [
     "coralai_world_bytes", "coralai_world_create", "coralai_world_destroy", "coralai_set_state",
@@ -36,6 +37,7 @@ EXPORTED = [
     "coralai_set_profiling", "coralai_get_profile", "coralai_batch_autotune",
     "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
     "coralai_debug_set_weights_noalloc", "coralai_set_daylight", "coralai_get_energy_ledger",
+    "coralai_set_physics_variant",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -44,7 +46,7 @@ class coralai_world_desc(ct.Structure):
     _fields_ = [("width", ct.c_int32), ("height", ct.c_int32), ("n_weight_layers", ct.c_int32),
                 ("hidden", ct.c_int32), ("genome_capacity", ct.c_int32), ("precision", ct.c_int32),
                 ("seed", ct.c_uint64), ("rho_invest", ct.c_float), ("rho_liquidate", ct.c_float),
-                ("kappa_flow", ct.c_float), ("reserved", ct.c_int32)]
+                ("kappa_flow", ct.c_float), ("flags", ct.c_int32)]
 
 
 class coralai_stats(ct.Structure):
@@ -108,6 +110,7 @@ def lib() -> ct.CDLL:
             "coralai_debug_set_weights_noalloc": (ct.c_int, [P, I32, P]),
             "coralai_set_daylight": (ct.c_int, [P, I32, ct.c_int64, I32]),
             "coralai_get_energy_ledger": (ct.c_int, [P, P, P, P, P]),
+            "coralai_set_physics_variant": (ct.c_int, [P, I32, ct.c_float]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
         }
@@ -187,6 +190,10 @@ def coralai_radiate(h, rate: float, sigma: float, step_index: int,
 
 def coralai_set_daylight(h, period: int, inject_quanta: int, remove_num: int) -> None:
     _check(lib().coralai_set_daylight(h, period, inject_quanta, remove_num))
+
+
+def coralai_set_physics_variant(h, explore_mode: int, kappa_energy: float) -> None:
+    _check(lib().coralai_set_physics_variant(h, explore_mode, kappa_energy))
 
 
 def coralai_get_energy_ledger(h) -> dict:

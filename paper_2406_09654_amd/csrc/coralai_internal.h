@@ -71,7 +71,10 @@ struct WorldDev {
     uint64_t seed;
     int64_t day_inject;   // energy quanta a cell receives per step at noon
     int32_t night_num;    // at midnight a cell loses night_num / 65536 of its energy per step
-    int32_t pad_dn;
+    int32_t explore_mode; // 0: softmax split of the exploration budget, 1: all to the maximal actuator
+    float kappa_e;        // > 0: floor(kappa_e E1) of a cell's energy moves along its flow directions
+    int32_t pad_pv;
+    uint32_t* eflow;      // [N][8] energy flow words (amount << 1), only with CORALAI_WORLD_ENERGY_FLOWS
     int64_t* EI[2];       // [N][2]: energy and infrastructure quanta of a cell together
     float* C[2];          // [N][4]: the 4 communication channels of a cell together
     int32_t* G[2];

@@ -160,12 +160,16 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     bool st_pending = false;
     int st_i = -1;
     uint32_t st_c[4] = {0u, 0u, 0u, 0u}, st_f[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t st_e[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     int64_t st_E1 = 0, st_I1 = 0;
 
     // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
-    __amdgpu_buffer_rsrc_t rEI, rC, rP, wC, wEI1, wFlow;
+    // physics variants: hard-max exploration, energy transport budget
+    bool hard_max = false;
+    float kappa_e = 0.f;
+    __amdgpu_buffer_rsrc_t rEI, rC, rP, wC, wEI1, wFlow, wEflow;
     const int32_t *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
@@ -198,6 +202,10 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[0], st_f[1], st_f[2], st_f[3]}, wFlow, 8 * ofs, 0, 0);
         __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[4], st_f[5], st_f[6], st_f[7]}, wFlow, 8 * ofs + 16, 0, 0);
         buf_st_i64x2(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
+        if (kappa_e > 0.f) {  // world-uniform: energy transport records
+            __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_e[0], st_e[1], st_e[2], st_e[3]}, wEflow, 8 * ofs, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_e[4], st_e[5], st_e[6], st_e[7]}, wEflow, 8 * ofs + 16, 0, 0);
+        }
         st_i = -1;
         st_pending = false;
     };
@@ -220,6 +228,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             const auto* W = world_at(b, wi);
             Wd = W->W; Hd = W->H; Nd = W->N; cap = W->cap;
             rho_i = W->rho_i; rho_l = W->rho_l; kappa = W->kappa;
+            hard_max = W->explore_mode == 1;
+            kappa_e = W->eflow != nullptr ? W->kappa_e : 0.f;
             ctl = W->ctl;
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             const uint32_t n4 = 4u * (uint32_t)Nd;
@@ -229,6 +239,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             wC = buf_rsrc(W->C[nxt], 4u * n4);
             wEI1 = buf_rsrc(W->EI1, 4u * n4);
             wFlow = buf_rsrc(W->flow, 8u * n4);
+            wEflow = buf_rsrc(W->eflow != nullptr ? W->eflow : W->flow, 8u * n4);
             counts = W->counts; offsets = W->offsets; gofs = W->gofs;
             wfrag = W->wfrag; bias = W->bias; wstride = W->wfrag_stride; bstride = W->bias_stride;
             g = -1;
@@ -606,34 +617,57 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             // all amounts are below 2^31: 32-bit integers suffice, and the
             // truncating conversion of a non-negative float is its floor
             const uint32_t Fu = (uint32_t)F;
-            const float per = inv * (float)Fu;  // budget per unit of softmax weight
-            uint32_t used = 0, fs[8];
+            // the budget's split: softmax shares with a running clamp, or (hard
+            // max) all to the maximal explore actuator
+            auto split = [&](uint32_t budget, uint32_t* out) __attribute__((always_inline)) {
+                const float per = inv * (float)budget;  // budget per unit of softmax weight
+                uint32_t used = 0;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float share = ex[t] * per;  // >= 0 and finite
-                uint32_t f = (uint32_t)share;
-                const uint32_t rem = Fu - used;
-                f = f < rem ? f : rem;
-                used += f;
-                fs[t] = (f << 1) | (uint32_t)(t == best);
-            }
+                for (int t = 0; t < 8; ++t) {
+                    const float share = ex[t] * per;  // >= 0 and finite
+                    uint32_t f = (uint32_t)share;
+                    const uint32_t rem = budget - used;
+                    f = f < rem ? f : rem;
+                    if (hard_max) f = t == best ? budget : 0u;
+                    used += f;
+                    out[t] = f;
+                }
+            };
             // kernel position t + 1 points at direction (r + offset) & 7: put
             // the words in offset order (fixed), then rotate by r, one
             // conditional rotation per bit of r
-            uint32_t wd[8];
+            auto to_directions = [&](const uint32_t* fs, uint32_t* dst) __attribute__((always_inline)) {
+                uint32_t wd[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) wd[kernel_offset(t + 1)] = fs[t];
+                for (int t = 0; t < 8; ++t) wd[kernel_offset(t + 1)] = fs[t];
 #pragma unroll
-            for (int bit = 1; bit < 8; bit <<= 1) {
-                const bool on = (r & bit) != 0;
-                uint32_t nw[8];
+                for (int bit = 1; bit < 8; bit <<= 1) {
+                    const bool on = (r & bit) != 0;
+                    uint32_t nw[8];
 #pragma unroll
-                for (int d = 0; d < 8; ++d) nw[d] = on ? wd[(d - bit) & 7] : wd[d];
+                    for (int d = 0; d < 8; ++d) nw[d] = on ? wd[(d - bit) & 7] : wd[d];
 #pragma unroll
-                for (int d = 0; d < 8; ++d) wd[d] = nw[d];
+                    for (int d = 0; d < 8; ++d) wd[d] = nw[d];
+                }
+#pragma unroll
+                for (int d = 0; d < 8; ++d) dst[d] = wd[d];
+            };
+            uint32_t fs[8];
+            split(Fu, fs);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) fs[t] = (fs[t] << 1) | (uint32_t)(t == best);
+            to_directions(fs, st_f);
+            if (kappa_e > 0.f) {
+                // energy transport: floor(kappa_e E1) along the same directions
+                int64_t FE = (int64_t)floorf(kappa_e * i64_to_f32(E1));
+                if (FE < 0) FE = 0;
+                if (FE > 0x7fffffffll) { err |= kErrLedger; FE = 0x7fffffffll; }
+                uint32_t es[8];
+                split((uint32_t)FE, es);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) es[t] <<= 1;
+                to_directions(es, st_e);
             }
-#pragma unroll
-            for (int d = 0; d < 8; ++d) st_f[d] = wd[d];
             acc_mass += E1;
             acc_f64 += (double)E1;
         }

@@ -39,6 +39,27 @@ __device__ __forceinline__ void wave_count_add(int32_t* counts, int g, int d, bo
     }
 }
 
+// Energy transport (physics variant): the net energy a cell gains, the words
+// (d+4) mod 8 of its 8 neighbours' energy records (what each sends toward it)
+// minus the sum of its own record, read through the caches.  Each word is
+// (amount << 1).
+__device__ __forceinline__ int64_t energy_moved(const uint32_t* __restrict__ eflow, int x, int y, int W, int H) {
+    const int64_t t = (int64_t)y * W + x;
+    const coralai_u32x4 a = gld((const coralai_u32x4*)(eflow + 8 * t));
+    const coralai_u32x4 c = gld((const coralai_u32x4*)(eflow + 8 * t) + 1);
+    int64_t net = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) net -= (int64_t)(a[k] >> 1) + (int64_t)(c[k] >> 1);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        int nx = x + dir_dx(d), ny = y + dir_dy(d);
+        nx = nx < 0 ? nx + W : (nx >= W ? nx - W : nx);
+        ny = ny < 0 ? ny + H : (ny >= H ? ny - H : ny);
+        net += (int64_t)(gld(eflow + 8 * ((int64_t)ny * W + nx) + ((d + 4) & 7)) >> 1);
+    }
+    return net;
+}
+
 // Adds a wavefront's injected and removed quanta and error bits to the
 // world's step accumulators (one atomic each from the first lane holding a
 // nonzero sum; the cycle is off in most worlds).
@@ -118,6 +139,7 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
     int Wd = 0, Hd = 0, Nd = 0, tx_n = 1;
     int64_t world_lo = 0;
     const uint32_t* flow = nullptr;
+    const uint32_t* eflow = nullptr;  // non-null: energy transport
     const int64_t* EI1p = nullptr;
     const int32_t* Gc = nullptr;
     const uint8_t* Rc = nullptr;
@@ -140,6 +162,7 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
             dn = day_night(W->day_period, W->day_inject, W->night_num, cld(&ctl->steps));
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             flow = W->flow; EI1p = W->EI1;
+            eflow = W->kappa_e > 0.f ? W->eflow : nullptr;
             Gc = W->G[cur]; Rc = W->R[cur];
             EIn = W->EI[nxt]; Gn = W->G[nxt]; Rn = W->R[nxt];
             cnt = W->stripe_counts;
@@ -231,11 +254,12 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
                     took = true;
                     g_to = so + g2;
                 }
-                const int64_t e2 = day_night_energy(e1, dn, acc_inj, acc_rem, err);
+                const int64_t em = eflow ? e1 + energy_moved(eflow, x0 + lx - 1, y0 + ly - 1, Wd, Hd) : e1;
+                const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
                 gst((i64x2*)EIn + t, i64x2{e2, i2});
                 gst(Gn + t, g2);
                 gst(Rn + t, r2);
-                // the network kernel added E1; the cycle's change and I2 complete the sum
+                // the network kernel added E1; the energy moved, the cycle's change and I2 complete the sum
                 acc_m += i2 + (e2 - e1);
                 acc_f += (double)(i2 + (e2 - e1));
             }
@@ -277,6 +301,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
     int64_t* EIn = nullptr;
     int32_t* Gn = nullptr;
     uint8_t* Rn = nullptr;
+    const uint32_t* eflow = nullptr;  // non-null: energy transport
     auto flush = [&]() {
         int64_t m = acc_m;
         double f = acc_f;
@@ -327,6 +352,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             cnt = W->stripe_counts;
             capw = W->cap;
             btx = W->btiles_x;
+            eflow = W->kappa_e > 0.f ? W->eflow : nullptr;
         }
         if ((Wd & 3) == 0) {
             // four consecutive cells of one row per thread: their own flow
@@ -403,7 +429,8 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                         took[j] = true;
                         acc_t += 1;
                     }
-                    const int64_t e2 = day_night_energy(e1, dn, acc_inj, acc_rem, err);
+                    const int64_t em = eflow ? e1 + energy_moved(eflow, x0 + j, y, Wd, Hd) : e1;
+                    const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
                     gst((i64x2*)EIn + t0 + j, i64x2{e2, i2});
                     acc_m += i2 + (e2 - e1);
                     acc_f += (double)(i2 + (e2 - e1));
@@ -456,7 +483,8 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                 took = true;
                 g_to = so + g2;
             }
-            const int64_t e2 = day_night_energy(e1, dn, acc_inj, acc_rem, err);
+            const int64_t em = eflow ? e1 + energy_moved(eflow, x, y, Wd, Hd) : e1;
+            const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
             gst((i64x2*)EIn + t, i64x2{e2, i2});
             gst(Gn + t, g2);
             gst(Rn + t, r2);

@@ -51,6 +51,7 @@ struct Layout {
     size_t flow, EI1, perm;
     size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
+    size_t eflow;  // 0: not reserved
     size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
     int n_slot_blocks;
     size_t total;
@@ -68,7 +69,7 @@ bool desc_valid(const coralai_world_desc* d, std::string* why) {
     if (d->hidden != 32 && d->hidden != 64) return bad("hidden must be 32 or 64");
     if (d->genome_capacity < 1 || d->genome_capacity > (1 << 22)) return bad("genome_capacity must be in [1, 2^22]");
     if (d->precision != CORALAI_FP32 && d->precision != CORALAI_BF16) return bad("precision must be CORALAI_FP32 or CORALAI_BF16");
-    if (d->reserved != 0) return bad("reserved must be 0");
+    if (d->flags & ~CORALAI_WORLD_ENERGY_FLOWS) return bad("unknown flags");
     for (float v : {d->rho_invest, d->rho_liquidate, d->kappa_flow})
         if (!(v >= 0.0f && v <= 1.0f)) return bad("rho_invest, rho_liquidate, kappa_flow must be in [0, 1]");
     return true;
@@ -86,6 +87,7 @@ Layout make_layout(const coralai_world_desc* d) {
         L.R[k] = take(N);
     }
     L.flow = take(32 * N);
+    L.eflow = (d->flags & CORALAI_WORLD_ENERGY_FLOWS) ? take(32 * N) : 0;
     L.EI1 = take(16 * N);
     L.perm = take(4 * N);
     L.counts = take(4 * cap);
@@ -423,6 +425,7 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
         h.R[k] = (uint8_t*)(b + L.R[k]);
     }
     h.flow = (uint32_t*)(b + L.flow);
+    h.eflow = L.eflow ? (uint32_t*)(b + L.eflow) : nullptr;
     h.EI1 = (int64_t*)(b + L.EI1);
     h.perm = (int32_t*)(b + L.perm);
     h.counts = (int32_t*)(b + L.counts);
@@ -1143,6 +1146,18 @@ int coralai_set_daylight(coralai_world* w, int32_t period, int64_t inject_quanta
     return write_world_tables(w);
 }
 
+int coralai_set_physics_variant(coralai_world* w, int32_t explore_mode, float kappa_energy) {
+    WORLD_GUARD(w);
+    if (explore_mode != 0 && explore_mode != 1) return fail(CORALAI_E_INVALID, "explore_mode must be 0 or 1");
+    if (!(kappa_energy >= 0.0f && kappa_energy <= 1.0f)) return fail(CORALAI_E_INVALID, "kappa_energy must be in [0, 1]");
+    if (kappa_energy > 0.0f && w->host.eflow == nullptr)
+        return fail(CORALAI_E_INVALID, "energy transport needs a world created with CORALAI_WORLD_ENERGY_FLOWS");
+    (void)hipStreamSynchronize(w->stream);
+    w->host.explore_mode = explore_mode;
+    w->host.kappa_e = kappa_energy;
+    return write_world_tables(w);
+}
+
 int coralai_get_energy_ledger(coralai_world* w, int64_t* injected_last, int64_t* removed_last,
                               int64_t* injected_total, int64_t* removed_total) {
     WORLD_GUARD(w);
@@ -1173,6 +1188,7 @@ int coralai_debug_physics(coralai_world* w, const int64_t* i1, const uint32_t* f
         if (irc) return irc;
     }
     if (!i1 || !flows8 || !explore_dir) return fail(CORALAI_E_INVALID, "a record array is NULL");
+    if (w->host.kappa_e > 0.0f) return fail(CORALAI_E_INVALID, "debug_physics takes infrastructure flows only (energy transport is on)");
     int cur = 0, rc = current_buffer(w, &cur);
     if (rc) return rc;
     const size_t N = (size_t)w->host.N;

@@ -20,9 +20,9 @@ class _nullctx:
 def make_desc(width: int, height: int, n_weight_layers: int = 2, hidden: int = 32,
               genome_capacity: int = 16, precision: int = 0, seed: int = 0,
               rho_invest: float = 0.1, rho_liquidate: float = 0.1,
-              kappa_flow: float = 0.25) -> B.coralai_world_desc:
+              kappa_flow: float = 0.25, flags: int = 0) -> B.coralai_world_desc:
     return B.coralai_world_desc(width, height, n_weight_layers, hidden, genome_capacity,
-                                precision, seed, rho_invest, rho_liquidate, kappa_flow, 0)
+                                precision, seed, rho_invest, rho_liquidate, kappa_flow, flags)
 
 
 def desc_from_spec(spec) -> B.coralai_world_desc:
@@ -54,8 +54,9 @@ class World:
 
     @classmethod
     def from_init(cls, init, stream=None, precision: int | None = None,
-                  sync: bool = True) -> "World":
+                  sync: bool = True, flags: int = 0) -> "World":
         d = desc_from_spec(init.spec)
+        d.flags = flags
         if precision is not None:
             d.precision = precision
         w = cls(d, stream, sync=sync)
@@ -133,6 +134,13 @@ class World:
         cell per step at noon, fraction (over 65536) of a cell's energy removed
         per step at midnight."""
         B.coralai_set_daylight(self.h, period, inject_quanta, remove_num)
+
+    def set_physics_variant(self, explore_mode: int, kappa_energy: float) -> None:
+        """explore_mode 0: softmax split of the exploration budget, 1: all to
+        the maximal explore actuator; kappa_energy > 0: that fraction of a
+        cell's energy moves along the same directions (needs the world created
+        with flags=WORLD_ENERGY_FLOWS)."""
+        B.coralai_set_physics_variant(self.h, explore_mode, kappa_energy)
 
     def energy_ledger(self) -> dict:
         return B.coralai_get_energy_ledger(self.h)

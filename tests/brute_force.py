@@ -104,13 +104,18 @@ def daylight(step, period):
 
 
 class World:
-    def __init__(self, W, H, E, I, C, G, R, nets, rho_i, rho_l, kappa, cycle=None):
+    def __init__(self, W, H, E, I, C, G, R, nets, rho_i, rho_l, kappa, cycle=None,
+                 hard_max=False, kappa_energy=0.0):
         self.W, self.H = W, H
         self.E, self.I, self.C, self.G, self.R = E, I, C, G, R   # flat lists; C = 4 lists
         self.nets = nets
         self.rho_i, self.rho_l, self.kappa = rho_i, rho_l, kappa
         # day / night cycle: (period, quanta per cell at noon, removal over 65536, step)
         self.cycle = cycle
+        # physics variants: the whole exploration budget to the maximal
+        # explore actuator; energy moving along the same directions
+        self.hard_max = hard_max
+        self.kappa_energy = kappa_energy
 
     def at(self, x, y):
         return (y % self.H) * self.W + (x % self.W)
@@ -141,14 +146,27 @@ class World:
             tot += v
         args.append(self.kappa * i1)
         F = math.floor(args[-1])
-        flows, used = {}, 0
-        for p in range(8):
-            args.append((ex[p] / tot) * F)
-            f = min(math.floor(args[-1]), F - used)
-            used += f
-            flows[order[p]] = f
         best = logits.index(m)
-        return dict(e1=e1, i1=i1, comm=comm, flows=flows, explore=order[best], act=a,
+
+        def split(budget, record):
+            out, used = {}, 0
+            for p in range(8):
+                if self.hard_max:
+                    amount = budget if p == best else 0
+                else:
+                    share = (ex[p] / tot) * budget
+                    if record:
+                        args.append(share)
+                    amount = min(math.floor(share), budget - used)
+                used += amount
+                out[order[p]] = amount
+            return out
+
+        flows = split(F, True)
+        eflows = {d: 0 for d in range(8)}
+        if self.kappa_energy > 0:
+            eflows = split(math.floor(self.kappa_energy * e1), False)
+        return dict(e1=e1, i1=i1, comm=comm, flows=flows, eflows=eflows, explore=order[best], act=a,
                     order=order, logits=logits, exact=all(floor_decided(x) for x in args))
 
     def margins(self, plans, t):
@@ -206,14 +224,17 @@ class World:
                 if plans[n]["explore"] == back and (best is None or amount > best[0]):
                     best = (amount, d, n)
             I2[t] = pt["i1"] - sum(pt["flows"].values()) + inflow
-            E2[t] = pt["e1"]
+            energy = pt["e1"] - sum(pt["eflows"].values())
+            for d in range(8):
+                energy += plans[self.neighbour(t, d)]["eflows"][(d + 4) % 8]
+            E2[t] = energy
             if self.cycle is not None:
                 period, noon_quanta, removal, step = self.cycle
                 light = daylight(step, period)
                 if light > 0:
                     E2[t] += noon_quanta * light // period
                 elif light < 0:
-                    E2[t] -= (pt["e1"] * removal // 65536) * (-light) // period
+                    E2[t] -= (energy * removal // 65536) * (-light) // period
             for k in range(4):
                 C2[k][t] = pt["comm"][k]
             G2[t], R2[t] = self.G[t], self.R[t]

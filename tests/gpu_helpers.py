@@ -63,12 +63,16 @@ def normwise(gpu: np.ndarray, ref: np.ndarray) -> float:
 
 
 def compare_step(gpu_out: dict, ref: "oracle.State", margins: np.ndarray, rows=None,
-                 tol: float = TOL, max_band_frac: float = 1e-3, act_ref: np.ndarray | None = None):
-    """Assert one step's parity; returns a report dict."""
+                 tol: float = TOL, max_band_frac: float = 1e-3, act_ref: np.ndarray | None = None,
+                 ledger_outside_band: bool = False):
+    """Assert one step's parity; returns a report dict.  ledger_outside_band:
+    compare E and I only outside the near-tie band (hard-max exploration,
+    where a near-tied argmax moves the whole budget between two cells)."""
     sl = slice(None) if rows is None else slice(rows[0], rows[1])
     rep = {}
+    keep = ~band_mask(margins[sl]) if ledger_outside_band else np.ones(gpu_out["E"][sl].shape, bool)
     for ch in ("E", "I"):
-        rep[ch] = normwise(gpu_out[ch][sl], getattr(ref, ch)[sl])
+        rep[ch] = normwise(gpu_out[ch][sl][keep], getattr(ref, ch)[sl][keep])
     rep["C"] = max(normwise(gpu_out["C"][c][sl], ref.C[c][sl]) for c in range(4))
     tol_c = tol
     if act_ref is not None:

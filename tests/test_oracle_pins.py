@@ -36,7 +36,8 @@ def bf_world(d, s, params, oracle):
     return bf.World(d.width, d.height, [int(v) for v in s.E.ravel()], [int(v) for v in s.I.ravel()],
                     [list(map(float, s.C[k].ravel())) for k in range(4)],
                     [int(v) for v in s.G.ravel()], [int(v) for v in s.R.ravel()], nets,
-                    d.rho_invest, d.rho_liquidate, d.kappa_flow, cycle)
+                    d.rho_invest, d.rho_liquidate, d.kappa_flow, cycle,
+                    hard_max=d.explore_mode == 1, kappa_energy=d.kappa_energy)
 
 
 # ---------------------------------------------------------------- geometry
@@ -589,3 +590,75 @@ def test_day_night_off_is_the_plain_step(oracle_lib):
         np.testing.assert_array_equal(x, y)
     np.testing.assert_array_equal(a.E, ia["records"]["e1"])
     assert ib["injected"] == 0 and ib["removed"] == 0
+
+
+# ---------------------------------------------------------------- physics variants
+
+@pytest.mark.parametrize("hard,kappa_e,cycle", [(True, 0.0, False), (False, 0.3, False), (True, 0.25, False),
+                                                 (True, 0.2, True)])
+def test_physics_variants_match_bruteforce(oracle_lib, hard, kappa_e, cycle):
+    """Hard-max exploration (the whole budget to the maximal explore
+    actuator) and energy transport along the flow directions, alone, together
+    and with the day / night cycle, against the brute force on tiny grids
+    (including 1x1 and 2x2, where directions alias)."""
+    for (W, H) in [(1, 1), (2, 2), (5, 7), (6, 4)]:
+        for seed in range(2):
+            d, s, params = tiny_world(oracle_lib, W, H, hidden=8, seed=seed, scale=2.0)
+            d.explore_mode, d.kappa_energy = (1 if hard else 0), kappa_e
+            if cycle:
+                d.day_period, d.day_inject, d.night_num, d.cycle_step = 6, 1_000_003, 50_000, 4
+            s2, info = oracle_lib.step(d, s, oracle_lib.nets_for(d, params))
+            E2, I2, C2, G2, R2, tk, _ = bf_world(d, s, params, oracle_lib).step()
+            assert s2.E.ravel().tolist() == E2, (W, H, seed)
+            assert s2.I.ravel().tolist() == I2
+            assert s2.G.ravel().tolist() == G2 and s2.R.ravel().tolist() == R2
+            assert info["takeovers"] == tk
+
+
+def test_physics_variants_conserve_mass(oracle_lib):
+    init = wl.config_plain_64()
+    d = oracle_lib.Desc.from_spec(init.spec)
+    d.explore_mode, d.kappa_energy = 1, 0.25
+    nets = oracle_lib.nets_for(d, init.params)
+    s = oracle_lib.State.from_init(init)
+    m0 = oracle_lib.mass(s.E, s.I)
+    e0 = int(s.E.sum())
+    moved = 0
+    for _ in range(10):
+        s2, _ = oracle_lib.step(d, s, nets)
+        assert oracle_lib.mass(s2.E, s2.I) == m0
+        assert (s2.E >= 0).all() and (s2.I >= 0).all()
+        moved += int(np.abs(s2.E - s.E).sum())
+        s = s2
+    assert moved > 0
+
+
+def test_hard_max_uniform_logit_closed_form(oracle_lib):
+    """Zero output layer (a = 0): the maximal explore actuator is position 1,
+    the cell's own rotation, so under hard max every cell sends its whole
+    budget F = floor(I1 / 4) to the neighbour its rotation points at, and its
+    energy budget floor(kappa_E E1) the same way: two np.roll sums."""
+    rng = np.random.default_rng(4)
+    W, H = 7, 5
+    E = wl.to_ledger(rng.random((H, W)))
+    I = wl.to_ledger(rng.random((H, W)))
+    C = rng.random((4, H, W))
+    G = np.zeros((H, W), np.int32)
+    R = rng.integers(0, 8, (H, W)).astype(np.uint8)
+    p = rng.standard_normal(56)
+    p[40:] = 0.0
+    d = oracle_lib.Desc(W, H, 2, 8, explore_mode=1, kappa_energy=0.5)
+    s2, _ = oracle_lib.step(d, oracle_lib.State(E, I, C, G, R), oracle_lib.nets_for(d, p[None]))
+    e1 = E - E // 20 + I // 20
+    i1 = I + E // 20 - I // 20
+    F = i1 // 4
+    FE = np.floor(0.5 * e1.astype(np.float64)).astype(np.int64)
+    i2 = i1 - F
+    e2 = e1 - FE
+    dirs = [(1, 0), (1, -1), (0, -1), (-1, -1), (-1, 0), (-1, 1), (0, 1), (1, 1)]
+    for r, (dx, dy) in enumerate(dirs):
+        on = R == r
+        i2 = i2 + np.roll(np.where(on, F, 0), (dy, dx), axis=(0, 1))
+        e2 = e2 + np.roll(np.where(on, FE, 0), (dy, dx), axis=(0, 1))
+    np.testing.assert_array_equal(s2.I, i2)
+    np.testing.assert_array_equal(s2.E, e2)
