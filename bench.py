@@ -189,6 +189,57 @@ def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bo
     }
 
 
+VARIANTS = [
+    ("day_night", "day/night cycle, period 100 steps, 2^-6 mass units per cell at noon, 1/64 of a cell's energy per step at midnight",
+     dict(daylight=(100, 1 << 18, 1024))),
+    ("hard_max", "hard-max exploration (the whole budget to the maximal explore actuator)", dict(variant=(1, 0.0))),
+    ("energy_transport", "energy transport: 1/4 of a cell's energy along the flow directions", dict(variant=(0, 0.25))),
+]
+
+
+def run_variants(init, precision: int, steps: int, warmup: int, tuning, stream):
+    """The 4096^2 step with each physics option on, on the production path
+    (graph replay + radiation), same tuning as the plain form."""
+    import torch
+
+    from paper_2406_09654_amd.binding import WORLD_ENERGY_FLOWS
+    from paper_2406_09654_amd.world import World
+
+    out = {}
+    N = init.spec.width * init.spec.height
+    for name, what, opts in VARIANTS:
+        flags = WORLD_ENERGY_FLOWS if "variant" in opts and opts["variant"][1] > 0 else 0
+        w = World.from_init(init, stream=stream, precision=precision, flags=flags)
+        w.set_tuning(*tuning)
+        if "daylight" in opts:
+            w.set_daylight(*opts["daylight"])
+        if "variant" in opts:
+            w.set_physics_variant(*opts["variant"])
+        k = 0
+        for _ in range(warmup):
+            w.step(1)
+            k += 1
+            w.radiate(RATE, SIGMA, k, stats=False)
+        w.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            w.step(1)
+            k += 1
+            w.radiate(RATE, SIGMA, k, stats=False)
+        w.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = w.stats()
+        assert st["error_word"] == 0
+        out[name] = {"what": what, "value": N * steps / dt, "ms_per_step": 1e3 * dt / steps,
+                     "timed_steps": [warmup + 1, warmup + steps]}
+        w.close()
+        del w
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_long(init, precision: int, n_steps: int, tuning, stream, block: int = 100):
     """The 4096^2 workload run as configured: n_steps steps, each followed by
     radiation at 1e-4, in blocks of `block` steps (queued without waiting;
@@ -402,6 +453,8 @@ def main() -> int:
                     help="Poisson arrivals per second (default: 0.8 x the batched capacity / mean request work)")
     ap.add_argument("--long-steps", type=int, default=1000,
                     help="steps of the as-configured 4096^2 run per form (0 skips it)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the 4096^2 step with the day/night cycle, hard max and energy transport")
     ap.add_argument("--batched-only", action="store_true",
                     help="profiling aid: run only the 512-world batched form and print its block")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -448,6 +501,13 @@ def main() -> int:
         print("[bench] %s: %.3e cell-updates/s, %.3f ms/step, phases %s" % (
             name, forms[name]["value"], forms[name]["ms_per_step"], forms[name]["phase_ms"]),
             file=sys.stderr, flush=True)
+
+    variants = None
+    if not args.no_variants:
+        print("[bench] bf16 physics options", file=sys.stderr, flush=True)
+        variants = run_variants(init, 1, args.steps, args.warmup + 2, forms["bf16"]["tuning"], stream)
+        print("[bench] options: %s" % {k: round(v["ms_per_step"], 3) for k, v in variants.items()},
+              file=sys.stderr, flush=True)
 
     long_runs = {}
     if args.long_steps > 0 and side == 4096:
@@ -515,6 +575,8 @@ def main() -> int:
                                "per_unit": "%d B per cell (reads the 32-byte flow record, boundary ledger pair, "
                                            "genome, rotation; writes ledger pair, genome, rotation)"
                                            % PHYS_BYTES_PER_CELL}
+    if variants:
+        out["physics_options_bf16"] = variants
     if long_runs:
         out["long_run"] = long_runs
     if not args.no_batched:

@@ -386,6 +386,10 @@ struct LaunchShape {
     // 0 = automatic (4 for BF16 networks on large jobs, else 1); k >= 1
     // forces k (a test hook: results do not depend on it)
     int act_segments;
+    // 1: some world of the launch uses a physics variant (hard-max
+    // exploration or energy transport), so the network kernel compiled with
+    // the variants' code runs; 0: the kernel without it
+    int act_variants;
 };
 
 // Launchers implemented in the kernel translation units.

@@ -83,6 +83,44 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Flow plan helpers of the physics variants.  A budget split by the softmax
+// weights ex / sum (inv = 1 / sum) with a running clamp, in kernel-position
+// order; or all of it to the maximal position.
+__device__ __forceinline__ void split_soft(uint32_t budget, const float (&ex)[8], float inv, uint32_t (&out)[8]) {
+    const float per = inv * (float)budget;
+    uint32_t used = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        uint32_t f = (uint32_t)(ex[t] * per);  // >= 0 and finite: truncation is the floor
+        const uint32_t rem = budget - used;
+        f = f < rem ? f : rem;
+        used += f;
+        out[t] = f;
+    }
+}
+__device__ __forceinline__ void split_hard(uint32_t budget, int best, uint32_t (&out)[8]) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) out[t] = t == best ? budget : 0u;
+}
+// Kernel position t + 1 points at direction (r + offset) & 7: the words in
+// offset order, then rotated by r, one conditional rotation per bit of r.
+__device__ __forceinline__ void to_directions(const uint32_t (&fs)[8], int r, uint32_t (&dst)[8]) {
+    uint32_t wd[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) wd[kernel_offset(t + 1)] = fs[t];
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1) {
+        const bool on = (r & bit) != 0;
+        uint32_t nw[8];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) nw[d] = on ? wd[(d - bit) & 7] : wd[d];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) wd[d] = nw[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 8; ++d) dst[d] = wd[d];
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -94,7 +132,7 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG>
+template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG, bool VARIANTS>
 __global__ __launch_bounds__(256, WAVES) void k_act(
     const BatchDev* __restrict__ b, float* __restrict__ dbg, int seg_force) {
     using NT = Net<NL, HID, PREC>;
@@ -166,10 +204,11 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
-    // physics variants: hard-max exploration, energy transport budget
-    bool hard_max = false;
-    float kappa_e = 0.f;
-    __amdgpu_buffer_rsrc_t rEI, rC, rP, wC, wEI1, wFlow, wEflow;
+    // physics variants in one scalar (bit 0: hard-max exploration, bit 1:
+    // energy transport), in the kernel compiled with VARIANTS only; their
+    // parameters are read from the world's table where used
+    int variant = 0;
+    __amdgpu_buffer_rsrc_t rEI, rC, rP, wC, wEI1, wFlow;
     const int32_t *counts = nullptr, *offsets = nullptr, *gofs = nullptr;
     const uint8_t* wfrag = nullptr;
     const float* bias = nullptr;
@@ -202,7 +241,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[0], st_f[1], st_f[2], st_f[3]}, wFlow, 8 * ofs, 0, 0);
         __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[4], st_f[5], st_f[6], st_f[7]}, wFlow, 8 * ofs + 16, 0, 0);
         buf_st_i64x2(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
-        if (kappa_e > 0.f) {  // world-uniform: energy transport records
+        if (VARIANTS && (variant & 2)) {  // world-uniform: energy transport records
+            const __amdgpu_buffer_rsrc_t wEflow = buf_rsrc(world_at(b, wi)->eflow, 32u * (uint32_t)Nd);
             __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_e[0], st_e[1], st_e[2], st_e[3]}, wEflow, 8 * ofs, 0, 0);
             __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_e[4], st_e[5], st_e[6], st_e[7]}, wEflow, 8 * ofs + 16, 0, 0);
         }
@@ -228,8 +268,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             const auto* W = world_at(b, wi);
             Wd = W->W; Hd = W->H; Nd = W->N; cap = W->cap;
             rho_i = W->rho_i; rho_l = W->rho_l; kappa = W->kappa;
-            hard_max = W->explore_mode == 1;
-            kappa_e = W->eflow != nullptr ? W->kappa_e : 0.f;
+            if constexpr (VARIANTS)
+                variant = (W->explore_mode == 1 ? 1 : 0) | (W->eflow != nullptr && W->kappa_e > 0.f ? 2 : 0);
             ctl = W->ctl;
             const int cur = ctl_cur(ctl), nxt = cur ^ 1;
             const uint32_t n4 = 4u * (uint32_t)Nd;
@@ -239,7 +279,6 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             wC = buf_rsrc(W->C[nxt], 4u * n4);
             wEI1 = buf_rsrc(W->EI1, 4u * n4);
             wFlow = buf_rsrc(W->flow, 8u * n4);
-            wEflow = buf_rsrc(W->eflow != nullptr ? W->eflow : W->flow, 8u * n4);
             counts = W->counts; offsets = W->offsets; gofs = W->gofs;
             wfrag = W->wfrag; bias = W->bias; wstride = W->wfrag_stride; bstride = W->bias_stride;
             g = -1;
@@ -617,26 +656,21 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             // all amounts are below 2^31: 32-bit integers suffice, and the
             // truncating conversion of a non-negative float is its floor
             const uint32_t Fu = (uint32_t)F;
-            // the budget's split: softmax shares with a running clamp, or (hard
-            // max) all to the maximal explore actuator
-            auto split = [&](uint32_t budget, uint32_t* out) __attribute__((always_inline)) {
-                const float per = inv * (float)budget;  // budget per unit of softmax weight
-                uint32_t used = 0;
+            if constexpr (!VARIANTS) {
+                const float per = inv * (float)Fu;  // budget per unit of softmax weight
+                uint32_t used = 0, fs[8];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     const float share = ex[t] * per;  // >= 0 and finite
                     uint32_t f = (uint32_t)share;
-                    const uint32_t rem = budget - used;
+                    const uint32_t rem = Fu - used;
                     f = f < rem ? f : rem;
-                    if (hard_max) f = t == best ? budget : 0u;
                     used += f;
-                    out[t] = f;
+                    fs[t] = (f << 1) | (uint32_t)(t == best);
                 }
-            };
-            // kernel position t + 1 points at direction (r + offset) & 7: put
-            // the words in offset order (fixed), then rotate by r, one
-            // conditional rotation per bit of r
-            auto to_directions = [&](const uint32_t* fs, uint32_t* dst) __attribute__((always_inline)) {
+                // kernel position t + 1 points at direction (r + offset) & 7: put
+                // the words in offset order (fixed), then rotate by r, one
+                // conditional rotation per bit of r
                 uint32_t wd[8];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) wd[kernel_offset(t + 1)] = fs[t];
@@ -650,23 +684,30 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                     for (int d = 0; d < 8; ++d) wd[d] = nw[d];
                 }
 #pragma unroll
-                for (int d = 0; d < 8; ++d) dst[d] = wd[d];
-            };
-            uint32_t fs[8];
-            split(Fu, fs);
+                for (int d = 0; d < 8; ++d) st_f[d] = wd[d];
+            } else {
+                // physics variants: the budget's split (softmax shares with a
+                // running clamp, or with hard max all to the maximal explore
+                // actuator), then the same for the energy budget
+                uint32_t fs[8];
+                if (variant & 1) split_hard(Fu, best, fs);
+                else split_soft(Fu, ex, inv, fs);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) fs[t] = (fs[t] << 1) | (uint32_t)(t == best);
-            to_directions(fs, st_f);
-            if (kappa_e > 0.f) {
-                // energy transport: floor(kappa_e E1) along the same directions
-                int64_t FE = (int64_t)floorf(kappa_e * i64_to_f32(E1));
-                if (FE < 0) FE = 0;
-                if (FE > 0x7fffffffll) { err |= kErrLedger; FE = 0x7fffffffll; }
-                uint32_t es[8];
-                split((uint32_t)FE, es);
+                for (int t = 0; t < 8; ++t) fs[t] = (fs[t] << 1) | (uint32_t)(t == best);
+                to_directions(fs, r, st_f);
+                if (variant & 2) {
+                    // energy transport: floor(kappa_e E1) along the same directions
+                    const float kappa_e = cld(&world_at(b, wi)->kappa_e);
+                    int64_t FE = (int64_t)floorf(kappa_e * i64_to_f32(E1));
+                    if (FE < 0) FE = 0;
+                    if (FE > 0x7fffffffll) { err |= kErrLedger; FE = 0x7fffffffll; }
+                    uint32_t es[8];
+                    if (variant & 1) split_hard((uint32_t)FE, best, es);
+                    else split_soft((uint32_t)FE, ex, inv, es);
 #pragma unroll
-                for (int t = 0; t < 8; ++t) es[t] <<= 1;
-                to_directions(es, st_e);
+                    for (int t = 0; t < 8; ++t) es[t] <<= 1;
+                    to_directions(es, r, st_e);
+                }
             }
             acc_mass += E1;
             acc_f64 += (double)E1;
@@ -694,12 +735,18 @@ static int resident_blocks(K kernel, int n_cu) {
     return n_cu * per_cu;
 }
 
+template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG, bool VARIANTS>
+static void launch_act_v(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, float* dbg) {
+    static int blocks = 0;
+    if (blocks == 0) blocks = resident_blocks(k_act<NL, HID, PREC, CGI, WAVES, DEBUG, VARIANTS>, ls.n_cu);
+    hipLaunchKernelGGL((k_act<NL, HID, PREC, CGI, WAVES, DEBUG, VARIANTS>), dim3(blocks), dim3(256), 0, s, bdev,
+                       dbg, ls.act_segments);
+}
+
 template <int NL, int HID, int PREC, int CGI, int WAVES, bool DEBUG>
 static void launch_act_c(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, float* dbg) {
-    static int blocks = 0;
-    if (blocks == 0) blocks = resident_blocks(k_act<NL, HID, PREC, CGI, WAVES, DEBUG>, ls.n_cu);
-    hipLaunchKernelGGL((k_act<NL, HID, PREC, CGI, WAVES, DEBUG>), dim3(blocks), dim3(256), 0, s, bdev, dbg,
-                       ls.act_segments);
+    if (ls.act_variants) launch_act_v<NL, HID, PREC, CGI, WAVES, DEBUG, true>(bdev, ls, s, dbg);
+    else launch_act_v<NL, HID, PREC, CGI, WAVES, DEBUG, false>(bdev, ls, s, dbg);
 }
 
 // act_cells: column groups of 16 cells processed together (1, 2, 4);

@@ -358,8 +358,8 @@ void destroy_graph(hipGraphExec_t* g) {
 }
 
 // Capture the step sequence once; every size it needs is read on the device.
-int tuning_key(int act_cells, int act_waves, int phys_tile) {
-    return act_cells * 100 + act_waves * 10 + phys_tile;
+int tuning_key(int act_cells, int act_waves, int phys_tile, int act_variants) {
+    return act_variants * 1000 + act_cells * 100 + act_waves * 10 + phys_tile;
 }
 
 int capture_step(hipStream_t s, const BatchDev* bdev, const LaunchShape& ls, int NL, int HID,
@@ -593,7 +593,7 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
     WORLD_GUARD(w);
     if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
     const bool use_graph = w->stream != nullptr && !w->profiling;
-    const int key = tuning_key(w->act_cells, w->act_waves, w->phys_tile);
+    const int key = tuning_key(w->act_cells, w->act_waves, w->phys_tile, w->ls.act_variants);
     const bool stale = w->counts_stale && n_steps > 0;  // the first step recounts
     if (use_graph && (w->graph == nullptr || w->graph_key != key)) {
         destroy_graph(&w->graph);
@@ -902,9 +902,11 @@ int batch_upload(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
     std::vector<WorldDev> tab(n);
     std::vector<int64_t> cp(n + 1, 0), tp(n + 1, 0), sp(n + 1, 0);
     std::vector<int32_t> tx(std::max(n, 1), 0);
+    int variants = 0;
     for (int k = 0; k < n; ++k) {
         coralai_world* w = worlds[k];
         if (!w) return fail(CORALAI_E_INVALID, "world %d is NULL", k);
+        variants |= w->ls.act_variants;
         if (k == 0) { b->NL = w->host.NL; b->HID = w->host.HID; b->prec = w->host.prec; }
         if (w->host.NL != b->NL || w->host.HID != b->HID || w->host.prec != b->prec)
             return fail(CORALAI_E_INVALID, "world %d: a batch needs one network shape and precision", k);
@@ -934,6 +936,7 @@ int batch_upload(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->n = n;
     b->worlds.assign(worlds, worlds + n);
+    b->ls.act_variants = variants;  // part of the graph key: the step is recaptured when it changes
     return CORALAI_OK;
 }
 }  // namespace
@@ -946,7 +949,7 @@ int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
     if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
     if (b->n == 0 || n_steps == 0) return CORALAI_OK;
     const bool use_graph = b->stream != nullptr;
-    const int key = tuning_key(b->act_cells, b->act_waves, b->phys_tile);
+    const int key = tuning_key(b->act_cells, b->act_waves, b->phys_tile, b->ls.act_variants);
     bool stale = false;  // some world's counts are stale: the first step recounts
     for (coralai_world* w : b->worlds) stale = stale || w->counts_stale;
     if (use_graph && (b->graph == nullptr || b->graph_key != key)) {
@@ -1155,6 +1158,8 @@ int coralai_set_physics_variant(coralai_world* w, int32_t explore_mode, float ka
     (void)hipStreamSynchronize(w->stream);
     w->host.explore_mode = explore_mode;
     w->host.kappa_e = kappa_energy;
+    // the network kernel with the variants' code runs only while one is on
+    w->ls.act_variants = (explore_mode != 0 || kappa_energy > 0.0f) ? 1 : 0;
     return write_world_tables(w);
 }
 
