@@ -187,6 +187,36 @@ int coralai_set_daylight(coralai_world* w, int32_t period, int64_t inject_quanta
  * step (a world in a batch: at the batch's next coralai_batch_set_worlds). */
 int coralai_set_physics_variant(coralai_world* w, int32_t explore_mode, float kappa_energy);
 
+/* Phylogeny (Discussion: the framework tracks phylogeny).  Every genome slot
+ * records the slot it was mutated from (-1 for a genome set by
+ * coralai_set_genomes) and the number of steps completed when it was created
+ * (the step_index of its radiation call).  A slot that becomes free and is
+ * reused records its new genome; coralai_get_births returns the birth events
+ * of the last radiation call, so a caller that reads them after each call
+ * keeps the whole tree.
+ * coralai_get_lineage: parents and birth steps of n slots (host arrays, any
+ * may be NULL).
+ * coralai_get_births: the last radiation call's births in the order of their
+ * cells: cell index, parent slot, new slot (host arrays of max_births, any
+ * may be NULL); *n_births receives the number of births (which may exceed
+ * max_births: the first max_births are copied).  Valid until the next
+ * radiation call, coralai_set_genomes or coralai_genetic_distance. */
+int coralai_get_lineage(coralai_world* w, int32_t n, const int32_t* slot_ids, int32_t* parents,
+                        int64_t* birth_steps);
+int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int32_t* parents, int32_t* slots,
+                       int32_t* n_births);
+
+/* NEAT's measure of genetic similarity (Discussion; Stanley and Miikkulainen's
+ * compatibility distance c1 E / N + c2 D / N + c3 W): every CPPN here has the
+ * same fixed topology, so all genes match (no excess E or disjoint D genes)
+ * and the distance of genomes a and b is c3 times the mean absolute
+ * difference of their 56 parameters.  Computes the na x nb matrix
+ * out_device[i * nb + j] = distance(slots_a[i], slots_b[j]) on the GPU into a
+ * caller-owned device buffer of na * nb floats (host slot lists,
+ * na + nb <= 56 x genome_capacity).  Waits for the stream. */
+int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_a, int32_t nb,
+                             const int32_t* slots_b, float c3, float* out_device);
+
 /* The cycle's energy ledger in quanta: injected and removed by the last step,
  * and in total since the world was created.  Waits for the stream; any
  * pointer may be NULL. */

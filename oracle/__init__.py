@@ -92,6 +92,8 @@ def lib():
         L.orc_radiate.restype = ct.c_int64
         L.orc_radiate.argtypes = [ct.c_int64, P, ct.c_int32, P, ct.c_uint64, ct.c_uint64,
                                   ct.c_uint64, ct.c_double, P, P, ct.c_int64, P]
+        L.orc_genetic_distance.restype = ct.c_double
+        L.orc_genetic_distance.argtypes = [P, P, ct.c_double]
         L.orc_mass.restype = ct.c_int64
         L.orc_mass.argtypes = [ct.c_int64, P, P]
         _lib = L
@@ -331,3 +333,20 @@ def mass(E: np.ndarray, I: np.ndarray) -> int:
     E = np.ascontiguousarray(E, dtype=np.int64).ravel()
     I = np.ascontiguousarray(I, dtype=np.int64).ravel()
     return int(lib().orc_mass(E.size, _p(E), _p(I)))
+
+
+def genetic_distance(a: np.ndarray, b: np.ndarray, c3: float = 1.0) -> float:
+    """NEAT compatibility distance of two genomes' CPPN parameters."""
+    pa = np.ascontiguousarray(a, dtype=np.float64)
+    pb = np.ascontiguousarray(b, dtype=np.float64)
+    return float(lib().orc_genetic_distance(_p(pa), _p(pb), float(c3)))
+
+
+def births(G_before: np.ndarray, hits) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """The phylogeny's new edges of one radiation call: (cell, parent slot,
+    new slot) of every hit that received a slot, from the genome map before
+    the call and radiate()'s hit list."""
+    cells, slots = hits
+    took = slots >= 0
+    cells = cells[took].astype(np.int64)
+    return cells, np.asarray(G_before).ravel()[cells].astype(np.int32), slots[took].astype(np.int32)

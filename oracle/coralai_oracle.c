@@ -539,6 +539,17 @@ int64_t orc_physics_from_records(const orc_desc* d, const int64_t* i1, const int
     return takeovers;
 }
 
+/* NEAT's compatibility distance of two genomes (Discussion: NEAT's measure
+ * of genetic similarity; the measure of Stanley and Miikkulainen,
+ * c1 E / N + c2 D / N + c3 W).  The CPPNs share one fixed topology, so all
+ * 56 genes match: no excess (E) or disjoint (D) genes, and W is the mean
+ * absolute difference of the matching genes' weights. */
+double orc_genetic_distance(const double* a, const double* b, double c3) {
+    double w = 0.0;
+    for (int m = 0; m < ORC_NPARAM; ++m) w += fabs(a[m] - b[m]);
+    return c3 * (w / ORC_NPARAM);
+}
+
 /* Buckets: counts = histogram of G over [0, cap), offsets = exclusive prefix
  * sum, perm = cells ordered by genome, ascending cell index within a genome
  * (a stable counting sort).  Returns -1 on an id outside [0, cap). */

@@ -37,7 +37,8 @@ EXPORTED = [
     "coralai_set_profiling", "coralai_get_profile", "coralai_batch_autotune",
     "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
     "coralai_debug_set_weights_noalloc", "coralai_set_daylight", "coralai_get_energy_ledger",
-    "coralai_set_physics_variant",
+    "coralai_set_physics_variant", "coralai_get_lineage", "coralai_get_births",
+    "coralai_genetic_distance",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -111,6 +112,9 @@ def lib() -> ct.CDLL:
             "coralai_set_daylight": (ct.c_int, [P, I32, ct.c_int64, I32]),
             "coralai_get_energy_ledger": (ct.c_int, [P, P, P, P, P]),
             "coralai_set_physics_variant": (ct.c_int, [P, I32, ct.c_float]),
+            "coralai_get_lineage": (ct.c_int, [P, I32, P, P, P]),
+            "coralai_get_births": (ct.c_int, [P, I32, P, P, P, P]),
+            "coralai_genetic_distance": (ct.c_int, [P, I32, P, I32, P, ct.c_float, P]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
         }
@@ -194,6 +198,21 @@ def coralai_set_daylight(h, period: int, inject_quanta: int, remove_num: int) ->
 
 def coralai_set_physics_variant(h, explore_mode: int, kappa_energy: float) -> None:
     _check(lib().coralai_set_physics_variant(h, explore_mode, kappa_energy))
+
+
+def coralai_get_lineage(h, slots: np.ndarray, parents: np.ndarray, births: np.ndarray) -> None:
+    _check(lib().coralai_get_lineage(h, int(slots.size), _host(slots), _host(parents), _host(births)))
+
+
+def coralai_get_births(h, max_births: int, cells, parents, slots) -> int:
+    n = ct.c_int32(0)
+    _check(lib().coralai_get_births(h, max_births, _host(cells), _host(parents), _host(slots), ct.byref(n)))
+    return int(n.value)
+
+
+def coralai_genetic_distance(h, slots_a: np.ndarray, slots_b: np.ndarray, c3: float, out_ptr: int) -> None:
+    _check(lib().coralai_genetic_distance(h, int(slots_a.size), _host(slots_a), int(slots_b.size),
+                                          _host(slots_b), c3, ct.c_void_p(out_ptr)))
 
 
 def coralai_get_energy_ledger(h) -> dict:

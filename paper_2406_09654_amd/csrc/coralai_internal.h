@@ -91,6 +91,8 @@ struct WorldDev {
     int32_t* gofs;        // [cap + 1] exclusive prefix of network units per genome
     uint8_t* slot_set;    // [cap]
     float* params;        // [cap][56]
+    int32_t* lineage_parent;  // [cap] slot the genome was mutated from (-1: set by the caller)
+    int64_t* lineage_birth;   // [cap] steps completed when the genome was created
     uint8_t* wfrag;       // [cap][wfrag_stride] weights in MFMA fragment order
     float* bias;          // [cap][bias_stride]
     int64_t wfrag_stride;
@@ -408,6 +410,10 @@ void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s
 void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radiation, int n_host, uint64_t step,
                  float sigma, int n_cu, hipStream_t s);
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
+// NEAT compatibility distance of genome pairs (slots: device list of the na
+// slots of A, then the nb of B) into out[na][nb] (device).
+void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na, int nb, float c3, float* out,
+                             int n_cu, hipStream_t s);
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
                     int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s,
                     int recount = 1);

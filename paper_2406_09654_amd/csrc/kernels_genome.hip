@@ -19,6 +19,8 @@
 // (i, step, 1 + b, 0), b = 0..13, and its network is regenerated at once.
 #include <type_traits>
 
+#include <algorithm>
+
 #include "coralai_internal.h"
 
 namespace coralai {
@@ -447,8 +449,41 @@ __global__ __launch_bounds__(256) void k_scatter_params(const WorldDev* __restri
         const int k = e / kNParam, m = e - k * kNParam;
         const int slot = w->stage_slots[k];
         w->params[(int64_t)slot * kNParam + m] = w->stage_params[e];
-        if (m == 0) w->slot_set[slot] = 1;
+        if (m == 0) {
+            w->slot_set[slot] = 1;
+            // a genome the caller sets is a root of the phylogeny
+            w->lineage_parent[slot] = -1;
+            w->lineage_birth[slot] = w->ctl->steps;
+        }
     }
+}
+
+// NEAT's compatibility distance (genetic similarity) of two genomes:
+// c1 E / N + c2 D / N + c3 W, with E / D the excess / disjoint genes and W
+// the mean weight difference of the matching genes.  Every CPPN here has the
+// same fixed topology, so all 56 genes match (E = D = 0) and the distance is
+// c3 times the mean absolute difference of the parameters.
+__global__ __launch_bounds__(256) void k_genetic_distance(const WorldDev* __restrict__ w,
+                                                          const int32_t* __restrict__ slots, int na, int nb,
+                                                          float c3, float* __restrict__ out) {
+    const int64_t total = (int64_t)na * nb;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e / nb), j = (int)(e - (int64_t)i * nb);
+        const float* pa = w->params + (int64_t)slots[i] * kNParam;
+        const float* pb = w->params + (int64_t)slots[na + j] * kNParam;
+        float acc = 0.0f;
+#pragma unroll 8
+        for (int m = 0; m < kNParam; ++m) acc += fabsf(pa[m] - pb[m]);
+        out[e] = c3 * (acc * (1.0f / kNParam));
+    }
+}
+
+void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na, int nb, float c3, float* out,
+                             int n_cu, hipStream_t s) {
+    const int64_t total = (int64_t)na * nb;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, (int64_t)n_cu * 8);
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_genetic_distance, dim3(blocks), dim3(256), 0, s, wdev, slots, na, nb, c3, out);
 }
 
 // ------------------------------------------------------------------ radiation
@@ -535,7 +570,7 @@ __global__ __launch_bounds__(1024) void k_rad_scan(const WorldDev* __restrict__ 
 // The k-th hit (cells in ascending order) takes the k-th free slot: the
 // cell's genome becomes the slot, and the hit's cell and parent are listed
 // for the mutation kernel.
-__global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__ w) {
+__global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__ w, uint64_t step) {
     __shared__ int s_tmp[4];
     const Ctl* ctl = w->ctl;
     const int cur = ctl->cur;
@@ -562,6 +597,8 @@ __global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__
                 hit_parent[rank] = parent;
                 G[i] = slot;
                 w->slot_set[slot] = 1;
+                w->lineage_parent[slot] = parent;  // the phylogeny's edge
+                w->lineage_birth[slot] = (int64_t)step;
                 // the stripe counts stay current
                 const int cy = i / w->W, cx = i - cy * w->W;
                 int32_t* sc = w->stripe_counts + (int64_t)cell_stripe(cx, cy, w->btiles_x) * w->cap;
@@ -614,7 +651,7 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
     const int hh = max(1, min(n_rad_blocks, ls.n_cu * 32));
     hipLaunchKernelGGL(k_rad_hits, dim3(hh), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
-    hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev);
+    hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev, step);
     launch_cppn(wdev, nl, hid, prec, 1, 0, step, sigma, ls.n_cu, s);  // mutation, then the networks
 }
 

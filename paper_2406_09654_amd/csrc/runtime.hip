@@ -52,6 +52,7 @@ struct Layout {
     size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
     size_t eflow;  // 0: not reserved
+    size_t lineage_parent, lineage_birth;
     size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
     int n_slot_blocks;
     size_t total;
@@ -97,6 +98,8 @@ Layout make_layout(const coralai_world_desc* d) {
     L.gofs = take(4 * (cap + 1));
     L.slot_set = take(cap);
     L.params = take(4 * kNParam * cap);
+    L.lineage_parent = take(4 * cap);
+    L.lineage_birth = take(8 * cap);
     L.wfrag_stride = (int64_t)net_frags(d->n_weight_layers, d->hidden, d->precision) *
                      net_frag_bytes(d->precision);
     L.wfrag = take((size_t)L.wfrag_stride * cap);
@@ -435,6 +438,8 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     h.gofs = (int32_t*)(b + L.gofs);
     h.slot_set = (uint8_t*)(b + L.slot_set);
     h.params = (float*)(b + L.params);
+    h.lineage_parent = (int32_t*)(b + L.lineage_parent);
+    h.lineage_birth = (int64_t*)(b + L.lineage_birth);
     h.wfrag = (uint8_t*)(b + L.wfrag);
     h.bias = (float*)(b + L.bias);
     h.wfrag_stride = L.wfrag_stride;
@@ -1173,6 +1178,63 @@ int coralai_get_energy_ledger(coralai_world* w, int64_t* injected_last, int64_t*
     if (removed_last) *removed_last = c.removed_pub;
     if (injected_total) *injected_total = c.injected_total;
     if (removed_total) *removed_total = c.removed_total;
+    return CORALAI_OK;
+}
+
+int coralai_get_lineage(coralai_world* w, int32_t n, const int32_t* slot_ids, int32_t* parents,
+                        int64_t* birth_steps) {
+    WORLD_GUARD(w);
+    if (n < 0 || (n > 0 && !slot_ids)) return fail(CORALAI_E_INVALID, "bad slot list");
+    for (int k = 0; k < n; ++k) {
+        if (slot_ids[k] < 0 || slot_ids[k] >= w->host.cap)
+            return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", slot_ids[k], w->host.cap);
+        if (parents)
+            HIP_TRY(hipMemcpyAsync(parents + k, w->host.lineage_parent + slot_ids[k], 4, hipMemcpyDeviceToHost, w->stream));
+        if (birth_steps)
+            HIP_TRY(hipMemcpyAsync(birth_steps + k, w->host.lineage_birth + slot_ids[k], 8, hipMemcpyDeviceToHost, w->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int32_t* parents, int32_t* slots,
+                       int32_t* n_births) {
+    WORLD_GUARD(w);
+    if (max_births < 0 || !n_births) return fail(CORALAI_E_INVALID, "bad arguments");
+    int rc = read_ctl(w);
+    if (rc) return rc;
+    const int n = std::min(max_births, std::max(0, w->pinned->n_new));
+    *n_births = std::max(0, w->pinned->n_new);
+    if (n > 0) {
+        if (cells) HIP_TRY(hipMemcpyAsync(cells, w->host.stage_slots, 4 * (size_t)n, hipMemcpyDeviceToHost, w->stream));
+        if (parents) HIP_TRY(hipMemcpyAsync(parents, w->host.stage_params, 4 * (size_t)n, hipMemcpyDeviceToHost, w->stream));
+        if (slots) HIP_TRY(hipMemcpyAsync(slots, w->host.new_slots, 4 * (size_t)n, hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipStreamSynchronize(w->stream));
+    }
+    return CORALAI_OK;
+}
+
+int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_a, int32_t nb,
+                             const int32_t* slots_b, float c3, float* out_device) {
+    WORLD_GUARD(w);
+    if (na < 0 || nb < 0 || (na > 0 && !slots_a) || (nb > 0 && !slots_b)) return fail(CORALAI_E_INVALID, "bad slot lists");
+    if ((int64_t)na + nb > (int64_t)kNParam * w->host.cap)
+        return fail(CORALAI_E_INVALID, "na + nb must be <= 56 x the genome capacity");
+    if (na == 0 || nb == 0) return CORALAI_OK;
+    if (!out_device) return fail(CORALAI_E_INVALID, "out_device is NULL");
+    for (int k = 0; k < na + nb; ++k) {
+        const int sl = k < na ? slots_a[k] : slots_b[k - na];
+        if (sl < 0 || sl >= w->host.cap) return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", sl, w->host.cap);
+    }
+    // the slot lists go through the parameter staging area of set_genomes
+    // (56 x capacity words, free between calls)
+    int32_t* staged = (int32_t*)w->host.stage_params;
+    HIP_TRY(hipMemcpyAsync(staged, slots_a, 4 * (size_t)na, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(staged + na, slots_b, 4 * (size_t)nb, hipMemcpyHostToDevice, w->stream));
+    launch_genetic_distance(w->wdev, staged, na, nb, c3, out_device, w->ls.n_cu, w->stream);
+    int rc = check_launch();
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(w->stream));
     return CORALAI_OK;
 }
 

@@ -142,6 +142,32 @@ class World:
         with flags=WORLD_ENERGY_FLOWS)."""
         B.coralai_set_physics_variant(self.h, explore_mode, kappa_energy)
 
+    def lineage(self, slots) -> tuple[np.ndarray, np.ndarray]:
+        """(parent slot, birth step) of each slot; parent -1 for genomes the caller set."""
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        parents = np.empty(s.size, np.int32)
+        births = np.empty(s.size, np.int64)
+        B.coralai_get_lineage(self.h, s, parents, births)
+        return parents, births
+
+    def births(self) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """(cell, parent slot, new slot) of each birth of the last radiation call."""
+        n = B.coralai_get_births(self.h, 0, np.empty(1, np.int32), np.empty(1, np.int32), np.empty(1, np.int32))
+        cells, parents, slots = (np.empty(max(n, 1), np.int32) for _ in range(3))
+        B.coralai_get_births(self.h, n, cells, parents, slots)
+        return cells[:n], parents[:n], slots[:n]
+
+    def genetic_distance(self, slots_a, slots_b, c3: float = 1.0) -> np.ndarray:
+        """NEAT compatibility distance matrix [len(a), len(b)], computed on the GPU."""
+        a = np.ascontiguousarray(slots_a, dtype=np.int32)
+        b = np.ascontiguousarray(slots_b, dtype=np.int32)
+        out = torch.empty((a.size, b.size), dtype=torch.float32, device="cuda")
+        ctx = torch.cuda.stream(self.stream) if self.stream is not None else _nullctx()
+        with ctx:
+            torch.cuda.current_stream().synchronize()
+        B.coralai_genetic_distance(self.h, a, b, c3, out.data_ptr())
+        return out.cpu().numpy()
+
     def energy_ledger(self) -> dict:
         return B.coralai_get_energy_ledger(self.h)
 

@@ -662,3 +662,43 @@ def test_hard_max_uniform_logit_closed_form(oracle_lib):
         e2 = e2 + np.roll(np.where(on, FE, 0), (dy, dx), axis=(0, 1))
     np.testing.assert_array_equal(s2.I, i2)
     np.testing.assert_array_equal(s2.E, e2)
+
+
+# ---------------------------------------------------------------- genetic distance, phylogeny
+
+def test_genetic_distance_properties(oracle_lib):
+    """NEAT compatibility distance with all genes matching: zero for a genome
+    and itself, c3 |t| for a uniform shift by t, symmetric, the triangle
+    inequality, and numpy's mean absolute difference."""
+    rng = np.random.default_rng(12)
+    P = rng.standard_normal((6, 56))
+    assert oracle_lib.genetic_distance(P[0], P[0], 0.4) == 0.0
+    assert abs(oracle_lib.genetic_distance(P[1], P[1] + 0.375, 2.0) - 0.75) < 1e-15
+    for i in range(6):
+        for j in range(6):
+            dij = oracle_lib.genetic_distance(P[i], P[j], 1.5)
+            assert dij == oracle_lib.genetic_distance(P[j], P[i], 1.5)
+            assert abs(dij - 1.5 * np.mean(np.abs(P[i] - P[j]))) < 1e-14
+            for k in range(6):
+                assert dij <= oracle_lib.genetic_distance(P[i], P[k], 1.5) + \
+                    oracle_lib.genetic_distance(P[k], P[j], 1.5) + 1e-14
+
+
+def test_births_follow_the_radiated_cells(oracle_lib):
+    """A radiation call's births: the parent of each new slot is the genome its
+    cell held before the call, and the new slot is the one the cell holds
+    after it."""
+    rng = np.random.default_rng(3)
+    G = rng.integers(0, 5, (30, 40)).astype(np.int32)
+    cap = 64
+    P = np.zeros((cap, 56))
+    P[:5] = rng.standard_normal((5, 56))
+    G2, P2, hits, dropped = oracle_lib.radiate(G, cap, P, 7, 3, 0.02, 0.1)
+    cells, parents, slots = oracle_lib.births(G, hits)
+    assert len(cells) > 10 and dropped == 0
+    np.testing.assert_array_equal(G.ravel()[cells], parents)
+    np.testing.assert_array_equal(G2.ravel()[cells], slots)
+    assert np.all(np.diff(cells) > 0) and len(np.unique(slots)) == len(slots)
+    # each child is its parent plus the mutation: genetic distance sigma E|z| on average
+    d = np.array([oracle_lib.genetic_distance(P2[s], P[p]) for s, p in zip(slots, parents)])
+    assert 0.05 < d.mean() < 0.11
