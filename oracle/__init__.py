@@ -92,6 +92,9 @@ def lib():
         L.orc_radiate.restype = ct.c_int64
         L.orc_radiate.argtypes = [ct.c_int64, P, ct.c_int32, P, ct.c_uint64, ct.c_uint64,
                                   ct.c_uint64, ct.c_double, P, P, ct.c_int64, P]
+        L.orc_merge.restype = ct.c_int64
+        L.orc_merge.argtypes = [ct.POINTER(_Desc), P, P, ct.c_int32, P, ct.c_uint64, ct.c_uint64,
+                                ct.c_uint64, P, P, P, P, ct.c_int64, P]
         L.orc_genetic_distance.restype = ct.c_double
         L.orc_genetic_distance.argtypes = [P, P, ct.c_double]
         L.orc_mass.restype = ct.c_int64
@@ -327,6 +330,30 @@ def radiate(G: np.ndarray, cap: int, params: np.ndarray, seed: int, step_index: 
                            float(sigma), _p(hc), _p(hs), max_hits, ct.byref(dropped))
     k = min(nh, max_hits)
     return G2.reshape(shp), P, (hc[:k].copy(), hs[:k].copy()), int(dropped.value)
+
+
+def merge(d: Desc, G: np.ndarray, R: np.ndarray, cap: int, params: np.ndarray, seed: int,
+          step_index: int, rate: float, max_hits: int = 1 << 20):
+    """Merging (NEAT crossover) after step ``step_index``: returns
+    (G', params', (cells, slots, a, b), dropped)."""
+    shp = G.shape
+    G2 = np.ascontiguousarray(G, dtype=np.int32).ravel().copy()
+    R2 = np.ascontiguousarray(R, dtype=np.uint8).ravel()
+    assert G2.size == R2.size == d.width * d.height
+    P = np.ascontiguousarray(params, dtype=np.float64).copy()
+    assert P.shape == (cap, N_PARAM)
+    hc = np.zeros(max_hits, np.int64)
+    hs = np.zeros(max_hits, np.int32)
+    ha = np.zeros(max_hits, np.int32)
+    hb = np.zeros(max_hits, np.int32)
+    dropped = ct.c_int64(0)
+    dc = d.c()
+    nh = lib().orc_merge(ct.byref(dc), _p(G2), _p(R2), cap, _p(P), int(seed), int(step_index),
+                         hit_threshold(rate), _p(hc), _p(hs), _p(ha), _p(hb), max_hits,
+                         ct.byref(dropped))
+    k = min(nh, max_hits)
+    return (G2.reshape(shp), P, (hc[:k].copy(), hs[:k].copy(), ha[:k].copy(), hb[:k].copy()),
+            int(dropped.value))
 
 
 def mass(E: np.ndarray, I: np.ndarray) -> int:

@@ -18,6 +18,8 @@
  *     angular distance to the cell's Rotation; Explore actuators, one per
  *     offset, spread infrastructure; takeover rule with maximal investment.
  *   - Fig. 1 (C): radiation mutates CPPN genomes and regenerates weights.
+ *   - Abstract and System Design: merging, NEAT's crossover of two genomes,
+ *     applied through the physics where two organisms meet.
  * Every constant the paper leaves open is a recorded reading (directions,
  * kernel order, ledger quanta, rates, flow budget, CPPN geometry, Philox
  * layout); each function names the reading it uses.
@@ -670,6 +672,69 @@ int64_t orc_radiate(int64_t n, int32_t* G, int32_t cap, double* params, uint64_t
     free(counts);
     free(freel);
     return hits;
+}
+
+/* Merging (abstract: survival, merging and mutation; System Design: NEAT's
+ * crossover operator applied through the physics), after step s.  A cell is
+ * a merge candidate when word i mod 4 of the Philox block at counter
+ * (floor(i / 4), s, 0, 1), key (seed, 0), is below T; its partner is the
+ * neighbour it faces (direction R[i]).  The merge takes place when the two
+ * cells hold different genomes in the map as it was before the call (G0).
+ * The k-th merge in ascending i takes the k-th free slot (zero count in G0,
+ * ascending) and becomes the crossover of its own genome a = G0[i] and its
+ * partner's b = G0[partner]: every CPPN here has the same genes, so all
+ * genes match and gene m is inherited from b when bit m of word 0 of the
+ * Philox block (i, s, 0, 2) is set, from a otherwise.  G[i] becomes the new
+ * slot; merges beyond the free slots are dropped.  hit_* (nullable,
+ * capacity max_hits) list the merges in order: cell, new slot (-1 when
+ * dropped), a, b.  Returns the number of merges; *dropped counts the
+ * dropped ones. */
+int64_t orc_merge(const orc_desc* d, int32_t* G, const uint8_t* R, int32_t cap, double* params,
+                  uint64_t seed, uint64_t s, uint64_t T, int64_t* hit_cells, int32_t* hit_slots,
+                  int32_t* hit_a, int32_t* hit_b, int64_t max_hits, int64_t* dropped) {
+    const int64_t n = (int64_t)d->width * d->height;
+    int32_t* G0 = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* counts = (int32_t*)calloc((size_t)cap, sizeof(int32_t));
+    int32_t* freel = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+    memcpy(G0, G, sizeof(int32_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) counts[G0[i]]++;
+    int32_t nfree = 0;
+    for (int32_t g = 0; g < cap; ++g)
+        if (counts[g] == 0) freel[nfree++] = g;
+    uint64_t key[2] = {seed, 0};
+    int64_t merges = 0;
+    *dropped = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t ctr[4] = {(uint64_t)(i / 4), s, 0, 1}, o[4];
+        orc_philox4x64_10(ctr, key, o);
+        if (!(o[i % 4] < T)) continue;
+        const int32_t a = G0[i], b = G0[nbr(d, i, R[i] & 7)];
+        if (a == b) continue;
+        int32_t slot = -1;
+        if (merges < nfree) {
+            slot = freel[merges];
+            uint64_t mc[4] = {(uint64_t)i, s, 0, 2}, mo[4];
+            orc_philox4x64_10(mc, key, mo);
+            for (int m = 0; m < ORC_NPARAM; ++m) {
+                const int32_t src = ((mo[0] >> m) & 1) ? b : a;
+                params[(int64_t)slot * ORC_NPARAM + m] = params[(int64_t)src * ORC_NPARAM + m];
+            }
+            G[i] = slot;
+        } else {
+            (*dropped)++;
+        }
+        if (hit_cells && merges < max_hits) {
+            hit_cells[merges] = i;
+            hit_slots[merges] = slot;
+            hit_a[merges] = a;
+            hit_b[merges] = b;
+        }
+        merges++;
+    }
+    free(G0);
+    free(counts);
+    free(freel);
+    return merges;
 }
 
 /* Exact and FP64 total mass sum(E + I). */

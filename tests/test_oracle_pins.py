@@ -702,3 +702,119 @@ def test_births_follow_the_radiated_cells(oracle_lib):
     # each child is its parent plus the mutation: genetic distance sigma E|z| on average
     d = np.array([oracle_lib.genetic_distance(P2[s], P[p]) for s, p in zip(slots, parents)])
     assert 0.05 < d.mean() < 0.11
+
+
+# ---------------------------------------------------------------- merging (NEAT crossover)
+
+def _facing(i, r, W, H):
+    """The neighbour cell i faces: direction r points 45 r degrees
+    counter-clockwise from +x with y pointing down, so its unit step is
+    (round(cos), -round(sin)) of that angle."""
+    ang = math.radians(45 * int(r))
+    dx, dy = int(round(math.cos(ang))), -int(round(math.sin(ang)))
+    x, y = i % W, i // W
+    return ((y + dy) % H) * W + (x + dx) % W
+
+
+def _merge_world(seed, W=40, H=30, n_genomes=6, cap=24):
+    rng = np.random.default_rng(seed)
+    G = rng.integers(0, n_genomes, (H, W)).astype(np.int32)
+    G[G == 3] = 2                        # leave a hole below the highest id
+    R = rng.integers(0, 8, (H, W)).astype(np.uint8)
+    P = np.zeros((cap, 56))
+    P[:n_genomes] = rng.standard_normal((n_genomes, 56))
+    return G, R, P
+
+
+def test_merge_against_bruteforce(oracle_lib):
+    """Candidates from numpy Philox, partner from the trigonometric direction,
+    the snapshot rule (a partner's genome as it was before the call), slot
+    assignment in cell order, capacity exhaustion and the gene-wise crossover
+    re-derived from the mask block."""
+    W, H, cap = 40, 30, 150
+    G, R, P = _merge_world(5, W, H, cap=cap)
+    seed, s, rate = 99, 12, 0.2
+    d = oracle_lib.Desc(W, H)
+    G2, P2, (hc, hs, ha, hb), dropped = oracle_lib.merge(d, G, R, cap, P, seed, s, rate)
+    T = math.floor(rate * 2.0 ** 64)
+    Gf = G.ravel()
+    cand = [i for i in range(W * H) if int(_numpy_block((i // 4, s, 0, 1), (seed, 0))[i % 4]) < T]
+    merges = [i for i in cand if Gf[_facing(i, R.ravel()[i], W, H)] != Gf[i]]
+    assert len(cand) > len(merges) > 0  # same-genome partners are skipped
+    free = [g for g in range(cap) if g not in set(Gf.tolist())]
+    assert len(merges) > len(free)      # capacity exhaustion exercised
+    assert hc.tolist() == merges and dropped == len(merges) - len(free)
+    # some partner is itself an earlier merge: the snapshot rule matters
+    assert set(_facing(i, R.ravel()[i], W, H) for i in merges[:len(free)]) & set(merges[:len(free)])
+    Gexp = Gf.copy()
+    for k, i in enumerate(merges):
+        a, b = Gf[i], Gf[_facing(i, R.ravel()[i], W, H)]
+        assert (ha[k], hb[k]) == (a, b)
+        if k >= len(free):
+            assert hs[k] == -1
+            continue
+        assert hs[k] == free[k]
+        mask = int(_numpy_block((i, s, 0, 2), (seed, 0))[0])
+        child = np.array([P[b, m] if (mask >> m) & 1 else P[a, m] for m in range(56)])
+        np.testing.assert_array_equal(P2[free[k]], child)
+        Gexp[i] = free[k]
+    np.testing.assert_array_equal(G2.ravel(), Gexp)
+    # the parents' parameters are untouched
+    used = np.unique(Gf)
+    np.testing.assert_array_equal(P2[used], P[used])
+
+
+def test_merge_degenerate_cases(oracle_lib):
+    """Rate 0 merges nothing; a world of one genome never merges at any rate;
+    rate 1 makes every cell with a foreign partner a candidate."""
+    W, H, cap = 16, 12, 400
+    G, R, P = _merge_world(8, W, H, cap=cap)
+    d = oracle_lib.Desc(W, H)
+    G2, P2, hits, dropped = oracle_lib.merge(d, G, R, cap, P, 1, 2, 0.0)
+    assert len(hits[0]) == 0 and dropped == 0
+    np.testing.assert_array_equal(G2, G)
+    np.testing.assert_array_equal(P2, P)
+    Gu = np.full_like(G, 4)
+    G2, _, hits, _ = oracle_lib.merge(d, Gu, R, cap, P, 1, 2, 1.0)
+    assert len(hits[0]) == 0
+    np.testing.assert_array_equal(G2, Gu)
+    G2, P2, (hc, hs, ha, hb), dropped = oracle_lib.merge(d, G, R, cap, P, 1, 2, 1.0)
+    Gf = G.ravel()
+    expect = [i for i in range(W * H) if Gf[_facing(i, R.ravel()[i], W, H)] != Gf[i]]
+    assert hc.tolist() == expect and dropped == 0
+    free = [g for g in range(cap) if g not in set(Gf.tolist())]
+    np.testing.assert_array_equal(G2.ravel()[expect], free[:len(expect)])
+
+
+def test_merge_crossover_is_gene_wise_and_fair(oracle_lib):
+    """Every child gene equals one parent's gene at that position, and over
+    many merges each parent supplies half of the genes (binomial bound)."""
+    W, H, cap = 64, 64, 4096
+    G, R, P = _merge_world(21, W, H, n_genomes=6, cap=cap)
+    d = oracle_lib.Desc(W, H)
+    G2, P2, (hc, hs, ha, hb), dropped = oracle_lib.merge(d, G, R, cap, P, 4, 40, 0.2)
+    took = hs >= 0
+    assert took.sum() > 300 and dropped == 0
+    child, A, B = P2[hs[took]], P[ha[took]], P[hb[took]]
+    from_a, from_b = child == A, child == B
+    assert np.all(from_a | from_b)
+    n = from_b.size
+    k = from_b.sum()
+    assert abs(k - n / 2) < 5 * math.sqrt(n / 4)
+
+
+def test_merge_births_record_both_parents(oracle_lib):
+    """The merges' new slots are distinct, listed in cell order, and each new
+    genome sits at distance at most that of its parents from either parent
+    (a crossover never leaves the box the parents span)."""
+    W, H, cap = 40, 30, 128
+    G, R, P = _merge_world(30, W, H, cap=cap)
+    d = oracle_lib.Desc(W, H)
+    G2, P2, (hc, hs, ha, hb), dropped = oracle_lib.merge(d, G, R, cap, P, 3, 9, 0.05)
+    assert dropped == 0 and len(hc) > 10
+    assert np.all(np.diff(hc) > 0) and len(np.unique(hs)) == len(hs)
+    np.testing.assert_array_equal(G2.ravel()[hc], hs)
+    for s_, a, b in zip(hs, ha, hb):
+        dab = oracle_lib.genetic_distance(P[a], P[b])
+        assert oracle_lib.genetic_distance(P2[s_], P[a]) + oracle_lib.genetic_distance(P2[s_], P[b]) \
+            == pytest.approx(dab, rel=1e-12)
