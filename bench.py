@@ -194,12 +194,15 @@ VARIANTS = [
      dict(daylight=(100, 1 << 18, 1024))),
     ("hard_max", "hard-max exploration (the whole budget to the maximal explore actuator)", dict(variant=(1, 0.0))),
     ("energy_transport", "energy transport: 1/4 of a cell's energy along the flow directions", dict(variant=(0, 0.25))),
+    ("merging", "merging (NEAT crossover with the faced neighbour's genome) at 1e-4 per cell per step, after radiation",
+     dict(merge=RATE)),
 ]
 
 
 def run_variants(init, precision: int, steps: int, warmup: int, tuning, stream):
     """The 4096^2 step with each physics option on, on the production path
-    (graph replay + radiation), same tuning as the plain form."""
+    (graph replay + radiation), same tuning as the plain form; merging adds a
+    merging call after each radiation call."""
     import torch
 
     from paper_2406_09654_amd.binding import WORLD_ENERGY_FLOWS
@@ -220,6 +223,8 @@ def run_variants(init, precision: int, steps: int, warmup: int, tuning, stream):
             w.step(1)
             k += 1
             w.radiate(RATE, SIGMA, k, stats=False)
+            if "merge" in opts:
+                w.merge(opts["merge"], k, stats=False)
         w.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -227,6 +232,8 @@ def run_variants(init, precision: int, steps: int, warmup: int, tuning, stream):
             w.step(1)
             k += 1
             w.radiate(RATE, SIGMA, k, stats=False)
+            if "merge" in opts:
+                w.merge(opts["merge"], k, stats=False)
         w.sync()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0

@@ -155,6 +155,23 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out);
 int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_index,
                     coralai_stats* out);
 
+/* Merging after step step_index (Abstract: organisms evolve through
+ * survival, merging and mutation; System Design: NEAT's crossover operator,
+ * applied through the physics).  Cell i is a candidate when word i mod 4 of
+ * Philox4x64-10(counter (floor(i / 4), step_index, 0, 1), key (seed, 0)) is
+ * below floor(rate * 2^64); it merges with the neighbour it faces (direction
+ * R[i]) when the two cells hold different genomes a = G[i] and
+ * b = G[neighbour], both read from the map as it was before the call.  The
+ * k-th merge in ascending i takes the k-th free slot (ascending slot ids
+ * whose genome count is zero); the new genome is the NEAT crossover of a and
+ * b: every CPPN here has the same genes, so all of them match, and gene m
+ * (of the 56 parameters) comes from b when bit m of word 0 of the Philox
+ * block (i, step_index, 0, 2) is set, from a otherwise.  Its network is
+ * regenerated and G[i] becomes the slot.  Merges beyond the free slots are
+ * dropped.  The stats count merges as hits (stats.hits, stats.dropped).
+ * rate in [0, 1].  Waits when out != NULL. */
+int coralai_merge(coralai_world* w, double rate, uint64_t step_index, coralai_stats* out);
+
 /* Day / night cycle (Experiment: energy is added to and removed from the
  * substrate in a day / night cycle).  period = 0 switches it off (the
  * default); otherwise, for the step s (steps completed before it, as in
@@ -188,23 +205,26 @@ int coralai_set_daylight(coralai_world* w, int32_t period, int64_t inject_quanta
 int coralai_set_physics_variant(coralai_world* w, int32_t explore_mode, float kappa_energy);
 
 /* Phylogeny (Discussion: the framework tracks phylogeny).  Every genome slot
- * records the slot it was mutated from (-1 for a genome set by
- * coralai_set_genomes) and the number of steps completed when it was created
- * (the step_index of its radiation call).  A slot that becomes free and is
- * reused records its new genome; coralai_get_births returns the birth events
- * of the last radiation call, so a caller that reads them after each call
- * keeps the whole tree.
- * coralai_get_lineage: parents and birth steps of n slots (host arrays, any
- * may be NULL).
- * coralai_get_births: the last radiation call's births in the order of their
- * cells: cell index, parent slot, new slot (host arrays of max_births, any
- * may be NULL); *n_births receives the number of births (which may exceed
- * max_births: the first max_births are copied).  Valid until the next
- * radiation call, coralai_set_genomes or coralai_genetic_distance. */
+ * records the slot it was mutated from, or for a merge its own genome a and
+ * its partner's b (parent -1 for a genome set by coralai_set_genomes; second
+ * parent -1 unless the slot was born by merging), and the number of steps
+ * completed when it was created (the step_index of its radiation or merging
+ * call).  A slot that becomes free and is reused records its new genome;
+ * coralai_get_births returns the birth events of the last radiation or
+ * merging call, so a caller that reads them after each call keeps the whole
+ * tree.
+ * coralai_get_lineage: parents, second parents and birth steps of n slots
+ * (host arrays, any may be NULL).
+ * coralai_get_births: the last radiation or merging call's births in the
+ * order of their cells: cell index, parent slot, second parent slot (-1
+ * after radiation), new slot (host arrays of max_births, any may be NULL);
+ * *n_births receives the number of births (which may exceed max_births: the
+ * first max_births are copied).  Valid until the next radiation or merging
+ * call or coralai_set_genomes (after which there are none). */
 int coralai_get_lineage(coralai_world* w, int32_t n, const int32_t* slot_ids, int32_t* parents,
-                        int64_t* birth_steps);
-int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int32_t* parents, int32_t* slots,
-                       int32_t* n_births);
+                        int32_t* parents2, int64_t* birth_steps);
+int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int32_t* parents,
+                       int32_t* parents2, int32_t* slots, int32_t* n_births);
 
 /* NEAT's measure of genetic similarity (Discussion; Stanley and Miikkulainen's
  * compatibility distance c1 E / N + c2 D / N + c3 W): every CPPN here has the
@@ -213,7 +233,7 @@ int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int
  * difference of their 56 parameters.  Computes the na x nb matrix
  * out_device[i * nb + j] = distance(slots_a[i], slots_b[j]) on the GPU into a
  * caller-owned device buffer of na * nb floats (host slot lists,
- * na + nb <= 56 x genome_capacity).  Waits for the stream. */
+ * na + nb <= 54 x genome_capacity).  Waits for the stream. */
 int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_a, int32_t nb,
                              const int32_t* slots_b, float c3, float* out_device);
 
@@ -265,13 +285,14 @@ int coralai_batch_autotune(coralai_batch* b, int32_t* act_cells_out, int32_t* ac
 int coralai_batch_set_tuning(coralai_batch* b, int32_t act_cells, int32_t act_waves,
                              int32_t phys_tile);
 
-/* Live phase timing.  While profiling is on, coralai_step and coralai_radiate
+/* Live phase timing.  While profiling is on, coralai_step, coralai_radiate and coralai_merge
  * launch their kernels directly (no graph) with HIP events recorded on the
  * world's stream between the phases; coralai_get_profile waits for the
  * stream and returns, per phase, the summed milliseconds and the number of
  * timed launches since profiling was switched on.  Phases:
  * 0 bucketing (histogram, scans, compaction), 1 sense+act (network),
- * 2 physics, 3 step finalisation, 4 radiation (incl. weight regeneration). */
+ * 2 physics, 3 step finalisation, 4 radiation or merging (incl. weight
+ * regeneration). */
 enum { CORALAI_PHASES = 5 };
 int coralai_set_profiling(coralai_world* w, int on);
 int coralai_get_profile(coralai_world* w, double* ms_sum, int64_t* launches);

@@ -38,7 +38,7 @@ EXPORTED = [
     "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
     "coralai_debug_set_weights_noalloc", "coralai_set_daylight", "coralai_get_energy_ledger",
     "coralai_set_physics_variant", "coralai_get_lineage", "coralai_get_births",
-    "coralai_genetic_distance",
+    "coralai_genetic_distance", "coralai_merge",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -112,8 +112,9 @@ def lib() -> ct.CDLL:
             "coralai_set_daylight": (ct.c_int, [P, I32, ct.c_int64, I32]),
             "coralai_get_energy_ledger": (ct.c_int, [P, P, P, P, P]),
             "coralai_set_physics_variant": (ct.c_int, [P, I32, ct.c_float]),
-            "coralai_get_lineage": (ct.c_int, [P, I32, P, P, P]),
-            "coralai_get_births": (ct.c_int, [P, I32, P, P, P, P]),
+            "coralai_get_lineage": (ct.c_int, [P, I32, P, P, P, P]),
+            "coralai_get_births": (ct.c_int, [P, I32, P, P, P, P, P]),
+            "coralai_merge": (ct.c_int, [P, ct.c_double, U64, S]),
             "coralai_genetic_distance": (ct.c_int, [P, I32, P, I32, P, ct.c_float, P]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
@@ -192,6 +193,10 @@ def coralai_radiate(h, rate: float, sigma: float, step_index: int,
                                  ct.byref(stats) if stats is not None else None))
 
 
+def coralai_merge(h, rate: float, step_index: int, stats: coralai_stats | None = None) -> None:
+    _check(lib().coralai_merge(h, rate, step_index, ct.byref(stats) if stats is not None else None))
+
+
 def coralai_set_daylight(h, period: int, inject_quanta: int, remove_num: int) -> None:
     _check(lib().coralai_set_daylight(h, period, inject_quanta, remove_num))
 
@@ -200,13 +205,16 @@ def coralai_set_physics_variant(h, explore_mode: int, kappa_energy: float) -> No
     _check(lib().coralai_set_physics_variant(h, explore_mode, kappa_energy))
 
 
-def coralai_get_lineage(h, slots: np.ndarray, parents: np.ndarray, births: np.ndarray) -> None:
-    _check(lib().coralai_get_lineage(h, int(slots.size), _host(slots), _host(parents), _host(births)))
+def coralai_get_lineage(h, slots: np.ndarray, parents: np.ndarray, parents2: np.ndarray,
+                        births: np.ndarray) -> None:
+    _check(lib().coralai_get_lineage(h, int(slots.size), _host(slots), _host(parents), _host(parents2),
+                                     _host(births)))
 
 
-def coralai_get_births(h, max_births: int, cells, parents, slots) -> int:
+def coralai_get_births(h, max_births: int, cells, parents, parents2, slots) -> int:
     n = ct.c_int32(0)
-    _check(lib().coralai_get_births(h, max_births, _host(cells), _host(parents), _host(slots), ct.byref(n)))
+    _check(lib().coralai_get_births(h, max_births, _host(cells), _host(parents), _host(parents2),
+                                    _host(slots), ct.byref(n)))
     return int(n.value)
 
 

@@ -91,7 +91,8 @@ struct WorldDev {
     int32_t* gofs;        // [cap + 1] exclusive prefix of network units per genome
     uint8_t* slot_set;    // [cap]
     float* params;        // [cap][56]
-    int32_t* lineage_parent;  // [cap] slot the genome was mutated from (-1: set by the caller)
+    int32_t* lineage_parent;  // [cap] slot the genome was mutated or merged from (-1: set by the caller)
+    int32_t* lineage_parent2; // [cap] a merge's second parent (the partner's genome), else -1
     int64_t* lineage_birth;   // [cap] steps completed when the genome was created
     uint8_t* wfrag;       // [cap][wfrag_stride] weights in MFMA fragment order
     float* bias;          // [cap][bias_stride]
@@ -417,6 +418,10 @@ void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na,
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
                     int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s,
                     int recount = 1);
+// Merging (NEAT crossover through the physics) after step `step`: candidates
+// below T on Philox counter (k, step, 0, 1) that face another genome.
+void launch_merge(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid, int prec,
+                  int n_rad_blocks, uint64_t T, uint64_t step, hipStream_t s, int recount = 1);
 void launch_pack_weights(const WorldDev* wdev, int slot, const float* flat, int unpack, float* out,
                          hipStream_t s);
 void launch_flip(const BatchDev* bdev, hipStream_t s);

@@ -17,6 +17,13 @@
 // free slots (zero count) in ascending order; the new genome is the parent's
 // CPPN plus sigma * N(0,1) from Box-Muller on the Philox blocks
 // (i, step, 1 + b, 0), b = 0..13, and its network is regenerated at once.
+//
+// Merging (NEAT crossover applied through the physics): a candidate cell
+// (counter (k, step, 0, 1), otherwise as the radiation hit test) merges with
+// the neighbour it faces when the two hold different genomes; the merges
+// take free slots in cell order like radiation hits, and the child inherits
+// gene m from the partner when bit m of word 0 of block (i, step, 0, 2) is
+// set, from its own genome otherwise.
 #include <type_traits>
 
 #include <algorithm>
@@ -301,8 +308,9 @@ __device__ __forceinline__ float philox_uniform(uint64_t o) {
 // One block per genome: its 56 parameters are read once into LDS, then the
 // block's threads walk the genome's weight and bias elements.
 // from_radiation = 0: the n_host slots listed by coralai_set_genomes;
-// 1: the slots the last radiation call assigned (count on the device).  A
-// radiation genome is first mutated here: its parameters are the parent's
+// 1: the slots the last radiation call assigned, 2: those the last merging
+// call assigned (counts on the device).  A radiation genome is first
+// mutated here: its parameters are the parent's
 // plus sigma * N(0, 1), four normals per lane 0..13 from Box-Muller on the
 // Philox block (cell, step, 1 + lane, 0); they are stored and go straight
 // to the block's LDS.
@@ -324,7 +332,7 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
     for (int si = blockIdx.x; si < n; si += gridDim.x) {
         const int slot = uniform_i32(slots[si]);
-        const int parent = from_radiation ? uniform_i32(((const int32_t*)w->stage_params)[si]) : -1;
+        const int parent = from_radiation == 1 ? uniform_i32(((const int32_t*)w->stage_params)[si]) : -1;
         if (parent >= 0) {  // radiation: hit list (cell, parent) in the staging buffers
             if (threadIdx.x < 14) {
                 const int lane = threadIdx.x;
@@ -453,6 +461,7 @@ __global__ __launch_bounds__(256) void k_scatter_params(const WorldDev* __restri
             w->slot_set[slot] = 1;
             // a genome the caller sets is a root of the phylogeny
             w->lineage_parent[slot] = -1;
+            w->lineage_parent2[slot] = -1;
             w->lineage_birth[slot] = w->ctl->steps;
         }
     }
@@ -488,10 +497,22 @@ void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na,
 
 // ------------------------------------------------------------------ radiation
 
+// The neighbour cell i faces (direction R[i]) on the torus.
+__device__ __forceinline__ int facing_cell(const WorldDev* __restrict__ w, const uint8_t* __restrict__ R, int i) {
+    const int y = i / w->W, x = i - y * w->W, d = R[i] & 7;
+    return wrap(y + dir_dy(d), w->H) * w->W + wrap(x + dir_dx(d), w->W);
+}
+
+// Hit bits of radiation (MERGE = false, counter word 3 = 0) or of merging
+// (word 3 = 1; a candidate is kept only if the cell it faces holds another
+// genome), 16 cells per thread, and the count per block.
+template <bool MERGE>
 __global__ __launch_bounds__(256) void k_rad_hits(const WorldDev* __restrict__ w, uint64_t T,
                                                   uint64_t step) {
     __shared__ int s_cnt;
     const int N = w->N;
+    const int32_t* __restrict__ G = w->G[w->ctl->cur];
+    const uint8_t* __restrict__ R = w->R[w->ctl->cur];
     for (int blk = blockIdx.x; blk < w->n_rad_blocks; blk += gridDim.x) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
@@ -500,11 +521,18 @@ __global__ __launch_bounds__(256) void k_rad_hits(const WorldDev* __restrict__ w
 #pragma unroll
         for (int q = 0; q < 4; ++q) {  // four independent multiply chains interleave
             const int64_t i0 = base + 4 * q;
-            uint64_t c[4] = {(uint64_t)(i0 >> 2), step, 0ull, 0ull};
+            uint64_t c[4] = {(uint64_t)(i0 >> 2), step, 0ull, MERGE ? 1ull : 0ull};
             philox4x64_10(c, w->seed, 0ull);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (i0 + k < N && c[k] < T) bits |= 1u << (4 * q + k);
+        }
+        if (MERGE) {
+            for (uint32_t m = bits; m; m &= m - 1) {
+                const int j = __builtin_ctz(m);
+                const int i = (int)base + j;
+                if (G[i] == G[facing_cell(w, R, i)]) bits &= ~(1u << j);
+            }
         }
         w->hit_bits[(int64_t)blk * 256 + threadIdx.x] = (uint16_t)bits;
         if (bits) atomicAdd(&s_cnt, __popc(bits));
@@ -595,9 +623,11 @@ __global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__
                 const int slot = w->free_list[rank];
                 hit_cell[rank] = i;
                 hit_parent[rank] = parent;
+                hit_parent[w->cap + rank] = -1;  // one parent
                 G[i] = slot;
                 w->slot_set[slot] = 1;
                 w->lineage_parent[slot] = parent;  // the phylogeny's edge
+                w->lineage_parent2[slot] = -1;
                 w->lineage_birth[slot] = (int64_t)step;
                 // the stripe counts stay current
                 const int cy = i / w->W, cx = i - cy * w->W;
@@ -610,6 +640,76 @@ __global__ __launch_bounds__(256) void k_rad_assign(const WorldDev* __restrict__
     }
 }
 
+
+// ------------------------------------------------------------------ merging
+
+// The k-th merge (cells in ascending order) is listed with its cell and its
+// two parents, read from the genome map before any merge of the call
+// changes it (the commit kernel runs after this one).
+__global__ __launch_bounds__(256) void k_merge_pairs(const WorldDev* __restrict__ w) {
+    __shared__ int s_tmp[4];
+    const Ctl* ctl = w->ctl;
+    const int cur = ctl->cur;
+    const int n_new = ctl->n_new;
+    const int32_t* __restrict__ G = w->G[cur];
+    const uint8_t* __restrict__ R = w->R[cur];
+    int32_t* hit_cell = w->stage_slots;                   // free during merging
+    int32_t* hit_a = (int32_t*)w->stage_params;           // [cap] own genome
+    int32_t* hit_b = hit_a + w->cap;                      // [cap] the partner's
+    for (int blk = blockIdx.x; blk < w->n_rad_blocks; blk += gridDim.x) {
+        if (w->blk_hits[blk] == 0) continue;  // block-uniform
+        const uint32_t bits = w->hit_bits[(int64_t)blk * 256 + threadIdx.x];
+        int tot;
+        int rank = w->blk_ofs[blk] + block_scan_excl<256>(__popc(bits), &tot, s_tmp);
+        for (uint32_t m = bits; m; m &= m - 1, ++rank) {
+            if (rank >= n_new) break;
+            const int i = blk * kRadBlockCells + 16 * threadIdx.x + __builtin_ctz(m);
+            const int a = G[i], b = G[facing_cell(w, R, i)];
+            w->new_slots[rank] = w->free_list[rank];  // every listed slot is valid
+            hit_cell[rank] = i;
+            if (a < 0 || a >= w->cap || b < 0 || b >= w->cap) {  // invalid id: flagged, never dereferenced
+                atomicOr(&w->ctl->err, kErrGenomeRange);
+                hit_a[rank] = -1;
+                hit_b[rank] = -1;
+            } else {
+                hit_a[rank] = a;
+                hit_b[rank] = b;
+            }
+        }
+    }
+}
+
+// One thread per listed merge: the child's parameters (gene m from the
+// partner where bit m of the mask word is set), its cell's genome, the
+// phylogeny (both parents) and the stripe counts.  Children take free slots
+// and parents are live, so no thread reads a slot another one writes.
+__global__ __launch_bounds__(256) void k_merge_commit(const WorldDev* __restrict__ w, uint64_t step) {
+    const int n_new = w->ctl->n_new;
+    int32_t* G = w->G[w->ctl->cur];
+    const int32_t* hit_a = (const int32_t*)w->stage_params;
+    const int32_t* hit_b = hit_a + w->cap;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n_new; k += gridDim.x * 256) {
+        const int a = hit_a[k], b = hit_b[k];
+        if (a < 0) continue;
+        const int i = w->stage_slots[k], slot = w->new_slots[k];
+        uint64_t c[4] = {(uint64_t)i, step, 0ull, 2ull};
+        philox4x64_10(c, w->seed, 0ull);
+        const uint64_t mask = c[0];
+        const float* pa = w->params + (int64_t)a * kNParam;
+        const float* pb = w->params + (int64_t)b * kNParam;
+        float* pc = w->params + (int64_t)slot * kNParam;
+        for (int m = 0; m < kNParam; ++m) pc[m] = ((mask >> m) & 1ull) ? pb[m] : pa[m];
+        G[i] = slot;
+        w->slot_set[slot] = 1;
+        w->lineage_parent[slot] = a;
+        w->lineage_parent2[slot] = b;
+        w->lineage_birth[slot] = (int64_t)step;
+        const int cy = i / w->W, cx = i - cy * w->W;
+        int32_t* sc = w->stripe_counts + (int64_t)cell_stripe(cx, cy, w->btiles_x) * w->cap;
+        atomicAdd(sc + a, -1);
+        atomicAdd(sc + slot, 1);
+    }
+}
 
 template <int NL, int HID, int PREC>
 static void launch_cppn_t(const WorldDev* wdev, int from_radiation, int n_host, uint64_t step, float sigma,
@@ -649,10 +749,22 @@ void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShap
     const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
     // the hit test is a chain of 64-bit multiplies per cell: as many waves as fit
     const int hh = max(1, min(n_rad_blocks, ls.n_cu * 32));
-    hipLaunchKernelGGL(k_rad_hits, dim3(hh), dim3(256), 0, s, wdev, T, step);
+    hipLaunchKernelGGL(k_rad_hits<false>, dim3(hh), dim3(256), 0, s, wdev, T, step);
     hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
     hipLaunchKernelGGL(k_rad_assign, dim3(hb), dim3(256), 0, s, wdev, step);
     launch_cppn(wdev, nl, hid, prec, 1, 0, step, sigma, ls.n_cu, s);  // mutation, then the networks
+}
+
+void launch_merge(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid, int prec,
+                  int n_rad_blocks, uint64_t T, uint64_t step, hipStream_t s, int recount) {
+    launch_hist_only(bdev, ls, s, 1, recount);  // free slots of the current state
+    const int hb = max(1, min(n_rad_blocks, ls.n_cu * 8));
+    const int hh = max(1, min(n_rad_blocks, ls.n_cu * 32));
+    hipLaunchKernelGGL(k_rad_hits<true>, dim3(hh), dim3(256), 0, s, wdev, T, step);
+    hipLaunchKernelGGL(k_rad_scan, dim3(1), dim3(1024), 0, s, wdev);
+    hipLaunchKernelGGL(k_merge_pairs, dim3(hb), dim3(256), 0, s, wdev);
+    hipLaunchKernelGGL(k_merge_commit, dim3(max(1, ls.n_cu)), dim3(256), 0, s, wdev, step);
+    launch_cppn(wdev, nl, hid, prec, 2, 0, step, 0.0f, ls.n_cu, s);  // the children's networks
 }
 
 }  // namespace coralai

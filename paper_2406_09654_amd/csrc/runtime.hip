@@ -52,7 +52,7 @@ struct Layout {
     size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
     size_t eflow;  // 0: not reserved
-    size_t lineage_parent, lineage_birth;
+    size_t lineage_parent, lineage_parent2, lineage_birth;
     size_t scan_part, ctl, wdev, bdev, chunk_prefix, slot_prefix, tile_prefix, group_prefix, tiles_x;
     int n_slot_blocks;
     size_t total;
@@ -99,6 +99,7 @@ Layout make_layout(const coralai_world_desc* d) {
     L.slot_set = take(cap);
     L.params = take(4 * kNParam * cap);
     L.lineage_parent = take(4 * cap);
+    L.lineage_parent2 = take(4 * cap);
     L.lineage_birth = take(8 * cap);
     L.wfrag_stride = (int64_t)net_frags(d->n_weight_layers, d->hidden, d->precision) *
                      net_frag_bytes(d->precision);
@@ -439,6 +440,7 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     h.slot_set = (uint8_t*)(b + L.slot_set);
     h.params = (float*)(b + L.params);
     h.lineage_parent = (int32_t*)(b + L.lineage_parent);
+    h.lineage_parent2 = (int32_t*)(b + L.lineage_parent2);
     h.lineage_birth = (int64_t*)(b + L.lineage_birth);
     h.wfrag = (uint8_t*)(b + L.wfrag);
     h.bias = (float*)(b + L.bias);
@@ -577,6 +579,8 @@ int coralai_set_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids, co
     launch_cppn(w->wdev, w->host.NL, w->host.HID, w->host.prec, 0, n, 0, 0.0f, w->ls.n_cu, w->stream);
     int rc = check_launch();
     if (rc) return rc;
+    // the staging area held the last births: there are none to report now
+    HIP_TRY(hipMemsetAsync(&w->host.ctl->n_new, 0, sizeof(int32_t), w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
     return report_errors(w, nullptr);
 }
@@ -654,6 +658,31 @@ int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_in
     int rc = timed_phase(w, 4, [&] {
         launch_radiate(w->bdev, w->wdev, w->ls, w->host.NL, w->host.HID, w->host.prec, w->L.n_rad_blocks, T, sigma,
                        step_index, w->stream, w->counts_stale ? 1 : 0);
+    });
+    w->counts_stale = false;
+    if (rc) return rc;
+    rc = check_launch();
+    if (rc) return rc;
+    if (out) {
+        uint32_t word = 0;
+        rc = report_errors(w, &word);
+        fill_stats(*w->pinned, out);
+        out->error_word = word;
+        return rc;
+    }
+    return CORALAI_OK;
+}
+
+int coralai_merge(coralai_world* w, double rate, uint64_t step_index, coralai_stats* out) {
+    WORLD_GUARD(w);
+    if (!(rate >= 0.0 && rate <= 1.0)) return fail(CORALAI_E_INVALID, "rate must be in [0, 1]");
+    uint64_t T;
+    if (rate <= 0.0) T = 0;
+    else if (rate >= 1.0) T = UINT64_MAX;
+    else T = (uint64_t)std::floor(rate * 18446744073709551616.0);
+    int rc = timed_phase(w, 4, [&] {
+        launch_merge(w->bdev, w->wdev, w->ls, w->host.NL, w->host.HID, w->host.prec, w->L.n_rad_blocks, T,
+                     step_index, w->stream, w->counts_stale ? 1 : 0);
     });
     w->counts_stale = false;
     if (rc) return rc;
@@ -1182,7 +1211,7 @@ int coralai_get_energy_ledger(coralai_world* w, int64_t* injected_last, int64_t*
 }
 
 int coralai_get_lineage(coralai_world* w, int32_t n, const int32_t* slot_ids, int32_t* parents,
-                        int64_t* birth_steps) {
+                        int32_t* parents2, int64_t* birth_steps) {
     WORLD_GUARD(w);
     if (n < 0 || (n > 0 && !slot_ids)) return fail(CORALAI_E_INVALID, "bad slot list");
     for (int k = 0; k < n; ++k) {
@@ -1190,6 +1219,8 @@ int coralai_get_lineage(coralai_world* w, int32_t n, const int32_t* slot_ids, in
             return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", slot_ids[k], w->host.cap);
         if (parents)
             HIP_TRY(hipMemcpyAsync(parents + k, w->host.lineage_parent + slot_ids[k], 4, hipMemcpyDeviceToHost, w->stream));
+        if (parents2)
+            HIP_TRY(hipMemcpyAsync(parents2 + k, w->host.lineage_parent2 + slot_ids[k], 4, hipMemcpyDeviceToHost, w->stream));
         if (birth_steps)
             HIP_TRY(hipMemcpyAsync(birth_steps + k, w->host.lineage_birth + slot_ids[k], 8, hipMemcpyDeviceToHost, w->stream));
     }
@@ -1197,8 +1228,8 @@ int coralai_get_lineage(coralai_world* w, int32_t n, const int32_t* slot_ids, in
     return CORALAI_OK;
 }
 
-int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int32_t* parents, int32_t* slots,
-                       int32_t* n_births) {
+int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int32_t* parents, int32_t* parents2,
+                       int32_t* slots, int32_t* n_births) {
     WORLD_GUARD(w);
     if (max_births < 0 || !n_births) return fail(CORALAI_E_INVALID, "bad arguments");
     int rc = read_ctl(w);
@@ -1208,6 +1239,9 @@ int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int
     if (n > 0) {
         if (cells) HIP_TRY(hipMemcpyAsync(cells, w->host.stage_slots, 4 * (size_t)n, hipMemcpyDeviceToHost, w->stream));
         if (parents) HIP_TRY(hipMemcpyAsync(parents, w->host.stage_params, 4 * (size_t)n, hipMemcpyDeviceToHost, w->stream));
+        if (parents2)
+            HIP_TRY(hipMemcpyAsync(parents2, (const int32_t*)w->host.stage_params + w->host.cap, 4 * (size_t)n,
+                                   hipMemcpyDeviceToHost, w->stream));
         if (slots) HIP_TRY(hipMemcpyAsync(slots, w->host.new_slots, 4 * (size_t)n, hipMemcpyDeviceToHost, w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));
     }
@@ -1218,8 +1252,8 @@ int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_
                              const int32_t* slots_b, float c3, float* out_device) {
     WORLD_GUARD(w);
     if (na < 0 || nb < 0 || (na > 0 && !slots_a) || (nb > 0 && !slots_b)) return fail(CORALAI_E_INVALID, "bad slot lists");
-    if ((int64_t)na + nb > (int64_t)kNParam * w->host.cap)
-        return fail(CORALAI_E_INVALID, "na + nb must be <= 56 x the genome capacity");
+    if ((int64_t)na + nb > (int64_t)(kNParam - 2) * w->host.cap)
+        return fail(CORALAI_E_INVALID, "na + nb must be <= 54 x the genome capacity");
     if (na == 0 || nb == 0) return CORALAI_OK;
     if (!out_device) return fail(CORALAI_E_INVALID, "out_device is NULL");
     for (int k = 0; k < na + nb; ++k) {
@@ -1227,8 +1261,9 @@ int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_
         if (sl < 0 || sl >= w->host.cap) return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", sl, w->host.cap);
     }
     // the slot lists go through the parameter staging area of set_genomes
-    // (56 x capacity words, free between calls)
-    int32_t* staged = (int32_t*)w->host.stage_params;
+    // (56 x capacity words, free between calls) past its first 2 x capacity
+    // words, which hold the last radiation or merging call's births
+    int32_t* staged = (int32_t*)w->host.stage_params + 2 * (int64_t)w->host.cap;
     HIP_TRY(hipMemcpyAsync(staged, slots_a, 4 * (size_t)na, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(staged + na, slots_b, 4 * (size_t)nb, hipMemcpyHostToDevice, w->stream));
     launch_genetic_distance(w->wdev, staged, na, nb, c3, out_device, w->ls.n_cu, w->stream);

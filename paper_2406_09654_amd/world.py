@@ -129,6 +129,15 @@ class World:
         B.coralai_radiate(self.h, rate, sigma, step_index, None)
         return None
 
+    def merge(self, rate: float, step_index: int, stats: bool = True):
+        """Merging (NEAT crossover of a cell's genome and the one it faces)."""
+        if stats:
+            st = B.coralai_stats()
+            B.coralai_merge(self.h, rate, step_index, st)
+            return st.as_dict()
+        B.coralai_merge(self.h, rate, step_index, None)
+        return None
+
     def set_daylight(self, period: int, inject_quanta: int, remove_num: int) -> None:
         """Day / night cycle: period in steps (0 = off), energy quanta added per
         cell per step at noon, fraction (over 65536) of a cell's energy removed
@@ -142,20 +151,24 @@ class World:
         with flags=WORLD_ENERGY_FLOWS)."""
         B.coralai_set_physics_variant(self.h, explore_mode, kappa_energy)
 
-    def lineage(self, slots) -> tuple[np.ndarray, np.ndarray]:
-        """(parent slot, birth step) of each slot; parent -1 for genomes the caller set."""
+    def lineage(self, slots) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """(parent slot, second parent slot, birth step) of each slot; parent -1
+        for genomes the caller set, second parent -1 unless born by merging."""
         s = np.ascontiguousarray(slots, dtype=np.int32)
         parents = np.empty(s.size, np.int32)
+        parents2 = np.empty(s.size, np.int32)
         births = np.empty(s.size, np.int64)
-        B.coralai_get_lineage(self.h, s, parents, births)
-        return parents, births
+        B.coralai_get_lineage(self.h, s, parents, parents2, births)
+        return parents, parents2, births
 
-    def births(self) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
-        """(cell, parent slot, new slot) of each birth of the last radiation call."""
-        n = B.coralai_get_births(self.h, 0, np.empty(1, np.int32), np.empty(1, np.int32), np.empty(1, np.int32))
-        cells, parents, slots = (np.empty(max(n, 1), np.int32) for _ in range(3))
-        B.coralai_get_births(self.h, n, cells, parents, slots)
-        return cells[:n], parents[:n], slots[:n]
+    def births(self) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        """(cell, parent slot, second parent slot, new slot) of each birth of the
+        last radiation or merging call."""
+        one = lambda: np.empty(1, np.int32)
+        n = B.coralai_get_births(self.h, 0, one(), one(), one(), one())
+        cells, parents, parents2, slots = (np.empty(max(n, 1), np.int32) for _ in range(4))
+        B.coralai_get_births(self.h, n, cells, parents, parents2, slots)
+        return cells[:n], parents[:n], parents2[:n], slots[:n]
 
     def genetic_distance(self, slots_a, slots_b, c3: float = 1.0) -> np.ndarray:
         """NEAT compatibility distance matrix [len(a), len(b)], computed on the GPU."""

@@ -118,7 +118,8 @@ def test_zipf_4096_initial_step_every_row_fp32(stream):
 def test_zipf_4096_bench_state_step_and_radiation(stream, prec):
     """From the state the bench times: one step on every row against the
     oracle (FP32: parity; BF16: error reported, segmentations identical),
-    then radiation after it against the oracle's radiation."""
+    then radiation after it against the oracle's radiation, and merging
+    after that against the oracle's merging."""
     say("4096 bench state prec", prec)
     init = wl.config_zipf_4096(precision=prec)
     cap = init.spec.genome_capacity
@@ -184,6 +185,19 @@ def test_zipf_4096_bench_state_step_and_radiation(stream, prec):
         tol = 1e-5 if prec == 0 else 4e-3
         assert gh.normwise(w.debug_get_weights(int(s), refw.size), refw) <= tol
     say("  radiation: hits", rst["hits"], "dropped", rst["dropped_hits"])
+    # merging after the radiation, at the full size: merge set, slots and the
+    # children's parameters exact
+    live2 = np.unique(after["G"])
+    P = np.zeros((cap, 56))
+    P[live2] = w.get_genomes(live2).astype(np.float64)
+    mst = w.merge(RATE, k + 1)
+    G3, P3, (mc, ms, ma, mb), mdropped = oracle.merge(d, after["G"], after["R"], cap, P, init.spec.seed,
+                                                      k + 1, RATE)
+    np.testing.assert_array_equal(w.get_state()["G"], G3)
+    assert mst["hits"] == len(mc) > 100 and mst["dropped_hits"] == mdropped
+    new = ms[ms >= 0]
+    np.testing.assert_array_equal(w.get_genomes(new).astype(np.float64), P3[new])
+    say("  merging: merges", mst["hits"], "dropped", mst["dropped_hits"])
     w.close()
 
 

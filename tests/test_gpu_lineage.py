@@ -23,8 +23,8 @@ def test_births_and_lineage_match_oracle_radiation(stream):
     ng, cap = 40, 2048
     init = gh.heterogeneous_world(300, 200, n_genomes=ng, capacity=cap, seed=19)
     w = gh.make_world(init, stream)
-    parents, births = w.lineage(np.arange(ng))
-    assert (parents == -1).all() and (births == 0).all()
+    parents, parents2, births = w.lineage(np.arange(ng))
+    assert (parents == -1).all() and (parents2 == -1).all() and (births == 0).all()
     rate, sigma = 2e-3, 0.1
     edges = {}
     for s in range(1, 6):
@@ -36,18 +36,20 @@ def test_births_and_lineage_match_oracle_radiation(stream):
         st = w.radiate(rate, sigma, s)
         G2, P2, hits, dropped = oracle.radiate(before, cap, P, init.spec.seed, s, rate, sigma)
         cells, par, slots = oracle.births(before, hits)
-        gc, gp, gs = w.births()
+        gc, gp, gp2, gs = w.births()
         np.testing.assert_array_equal(gc, cells)
         np.testing.assert_array_equal(gp, par)
         np.testing.assert_array_equal(gs, slots)
+        assert (gp2 == -1).all()                    # a mutation has one parent
         assert st["hits"] - st["dropped_hits"] == len(cells) > 50
-        lp, lb = w.lineage(gs)
+        lp, lp2, lb = w.lineage(gs)
         np.testing.assert_array_equal(lp, par)
+        assert (lp2 == -1).all()
         assert (lb == s).all()
         for c, p, sl in zip(gc, gp, gs):
             edges[int(sl)] = (int(p), s)
     # slots freed by takeovers are reused: the lineage holds their latest genome
-    lp, lb = w.lineage(np.array(sorted(edges), np.int32))
+    lp, _, lb = w.lineage(np.array(sorted(edges), np.int32))
     assert [(int(p), int(b)) for p, b in zip(lp, lb)] == [edges[k] for k in sorted(edges)]
     w.close()
 
