@@ -243,6 +243,13 @@ int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_
 int coralai_get_energy_ledger(coralai_world* w, int64_t* injected_last, int64_t* removed_last,
                               int64_t* injected_total, int64_t* removed_total);
 
+/* Set the count of completed steps (coralai_stats.steps), which sets the
+ * day / night cycle's phase and the birth step of genomes set afterwards:
+ * with coralai_set_state and coralai_set_genomes it resumes a world from a
+ * checkpoint (coralai_get_state, coralai_get_genomes of the live slots and
+ * the stats' step count).  steps >= 0.  Waits for the stream. */
+int coralai_set_step_count(coralai_world* w, int64_t steps);
+
 /* Wait for the world's stream; report (and clear) device error bits. */
 int coralai_sync(coralai_world* w);
 int coralai_get_stats(coralai_world* w, coralai_stats* out);

@@ -38,7 +38,7 @@ EXPORTED = [
     "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
     "coralai_debug_set_weights_noalloc", "coralai_set_daylight", "coralai_get_energy_ledger",
     "coralai_set_physics_variant", "coralai_get_lineage", "coralai_get_births",
-    "coralai_genetic_distance", "coralai_merge",
+    "coralai_genetic_distance", "coralai_merge", "coralai_set_step_count",
 ]
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
@@ -115,6 +115,7 @@ def lib() -> ct.CDLL:
             "coralai_get_lineage": (ct.c_int, [P, I32, P, P, P, P]),
             "coralai_get_births": (ct.c_int, [P, I32, P, P, P, P, P]),
             "coralai_merge": (ct.c_int, [P, ct.c_double, U64, S]),
+            "coralai_set_step_count": (ct.c_int, [P, ct.c_int64]),
             "coralai_genetic_distance": (ct.c_int, [P, I32, P, I32, P, ct.c_float, P]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
@@ -195,6 +196,10 @@ def coralai_radiate(h, rate: float, sigma: float, step_index: int,
 
 def coralai_merge(h, rate: float, step_index: int, stats: coralai_stats | None = None) -> None:
     _check(lib().coralai_merge(h, rate, step_index, ct.byref(stats) if stats is not None else None))
+
+
+def coralai_set_step_count(h, steps: int) -> None:
+    _check(lib().coralai_set_step_count(h, steps))
 
 
 def coralai_set_daylight(h, period: int, inject_quanta: int, remove_num: int) -> None:

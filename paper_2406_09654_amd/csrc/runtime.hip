@@ -698,6 +698,14 @@ int coralai_merge(coralai_world* w, double rate, uint64_t step_index, coralai_st
     return CORALAI_OK;
 }
 
+int coralai_set_step_count(coralai_world* w, int64_t steps) {
+    WORLD_GUARD(w);
+    if (steps < 0) return fail(CORALAI_E_INVALID, "steps must be >= 0");
+    HIP_TRY(hipMemcpyAsync(&w->host.ctl->steps, &steps, sizeof(int64_t), hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
 int coralai_sync(coralai_world* w) {
     WORLD_GUARD(w);
     HIP_TRY(hipStreamSynchronize(w->stream));

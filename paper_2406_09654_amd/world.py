@@ -138,6 +138,10 @@ class World:
         B.coralai_merge(self.h, rate, step_index, None)
         return None
 
+    def set_step_count(self, steps: int) -> None:
+        """Completed-step count (the day / night phase) of a resumed world."""
+        B.coralai_set_step_count(self.h, steps)
+
     def set_daylight(self, period: int, inject_quanta: int, remove_num: int) -> None:
         """Day / night cycle: period in steps (0 = off), energy quanta added per
         cell per step at noon, fraction (over 65536) of a cell's energy removed

@@ -567,3 +567,76 @@ def test_bad_genome_is_reported(stream):
     st = w.stats()            # reported once, then cleared
     assert st["error_word"] == 0
     w.close()
+
+
+def test_nonfinite_cppn_parameters_are_reported(stream):
+    """A genome whose CPPN parameters are not finite: set_genomes reports a
+    numeric error once and stores zero weights, never NaN."""
+    from paper_2406_09654_amd.binding import CoralaiError, CORALAI_E_NUMERIC
+    init = gh.heterogeneous_world(16, 16, n_genomes=3, capacity=4, seed=2)
+    w = gh.make_world(init, stream)
+    bad = init.params[:1].copy()
+    bad[0, :] = np.nan
+    with pytest.raises(CoralaiError) as e:
+        w.set_genomes(np.array([3], np.int32), bad)
+    assert e.value.code == CORALAI_E_NUMERIC
+    assert w.stats()["error_word"] == 0           # reported once, then cleared
+    d = gh.oracle_desc(init.spec)
+    wt = w.debug_get_weights(3, oracle.net_size(d))
+    assert np.isfinite(wt).all() and (wt == 0).all()
+    w.close()
+
+
+def test_ledger_overflow_is_reported_and_mass_still_conserved(stream):
+    """A flow budget of 2^31 quanta or more (I1 above 512 mass units at kappa
+    1/4) sets the ledger error bit rather than wrapping; the clamped plan
+    still conserves mass exactly."""
+    from paper_2406_09654_amd.binding import CoralaiError, CORALAI_E_NUMERIC, ERR_LEDGER
+    init = gh.heterogeneous_world(24, 20, n_genomes=3, seed=3)
+    init.I[5, 7] = 600 << 24
+    w = gh.make_world(init, stream)
+    m0 = int(init.E.sum() + init.I.sum())
+    w.step(1)
+    with pytest.raises(CoralaiError) as e:
+        w.sync()
+    assert e.value.code == CORALAI_E_NUMERIC and "0x%x" % ERR_LEDGER in str(e.value)
+    out = w.get_state()
+    assert int(out["E"].sum() + out["I"].sum()) == m0
+    w.close()
+
+
+def test_resume_from_checkpoint_is_bit_identical(stream):
+    """Checkpoint (state, live genomes, step count) and resume in a new world:
+    steps, radiation and merging continue bit for bit, with the day / night
+    cycle in phase."""
+    ng, cap = 30, 1024
+    init = gh.heterogeneous_world(96, 80, n_genomes=ng, capacity=cap, seed=17)
+    cycle = (10, 1 << 18, 2048)
+    a = gh.make_world(init, stream)
+    a.set_daylight(*cycle)
+    for s in range(1, 8):
+        a.step(1)
+        a.radiate(2e-3, 0.1, s)
+    ck = a.get_state()
+    slots = np.unique(ck["G"]).astype(np.int32)
+    params = a.get_genomes(slots)
+    steps = a.stats()["steps"]
+    assert steps == 7
+    b = gh.make_world(init, stream)
+    b.set_daylight(*cycle)
+    b.set_genomes(slots, params)
+    b.set_state(ck["E"], ck["I"], ck["C"], ck["G"], ck["R"])
+    b.set_step_count(steps)
+    for s in range(8, 14):
+        for w in (a, b):
+            w.step(1)
+            w.radiate(2e-3, 0.1, s)
+            w.merge(2e-3, s)
+    oa, ob = a.get_state(), b.get_state()
+    for ch in ("E", "I", "C", "G", "R"):
+        np.testing.assert_array_equal(oa[ch], ob[ch], err_msg=ch)
+    assert a.stats()["steps"] == b.stats()["steps"] == 13
+    la, lb = a.energy_ledger(), b.energy_ledger()
+    assert (la["injected_last"], la["removed_last"]) == (lb["injected_last"], lb["removed_last"])
+    a.close()
+    b.close()
