@@ -66,6 +66,10 @@ struct Ctl {
 struct WorldDev {
     int32_t W, H, N, cap;
     int32_t NL, HID, prec, n_rad_blocks;
+    // row of a cell: y = (i * w_magic) >> w_shift (64-bit product) for every
+    // i < 2^26, with w_shift = 26 + ceil(log2 W), w_magic = ceil(2^w_shift / W)
+    uint32_t w_magic;
+    int32_t w_shift;
     float rho_i, rho_l, kappa;
     int32_t day_period;   // day / night cycle length in steps (0 = no cycle)
     uint64_t seed;
@@ -277,6 +281,21 @@ __device__ __forceinline__ int find_world(const T* prefix, int n, T u) {
 }
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Row of cell i < 2^26 of a world of width W, by the multiplier of WorldDev:
+// with m = (2^k + e) / W, 0 <= e < W, and i = y W + x, i m / 2^k is
+// y + x / W + i e / (W 2^k), and i e < 2^26 W <= 2^k keeps the last two
+// terms below 1.
+inline void row_magic(int32_t W, uint32_t* magic, int32_t* shift) {
+    int lg = 0;
+    while ((1ll << lg) < W) ++lg;
+    const int k = 26 + lg;
+    *shift = k;
+    *magic = (uint32_t)(((1ull << k) + (uint64_t)W - 1) / (uint64_t)W);
+}
+__device__ __forceinline__ int cell_row(int i, uint32_t magic, int shift) {
+    return (int)(((uint64_t)(uint32_t)i * magic) >> shift);
+}
 
 // Loads and stores through the global address space.  Pointers read from the
 // device-side world table are generic; casting them lets the compiler emit

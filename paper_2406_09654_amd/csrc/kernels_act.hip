@@ -121,6 +121,16 @@ __device__ __forceinline__ void to_directions(const uint32_t (&fs)[8], int r, ui
     for (int d = 0; d < 8; ++d) dst[d] = wd[d];
 }
 
+// floor(max(x, 0)) as a 64-bit integer, for x below 2^63: the high word is
+// floor(x 2^-32) and the low word the exact remainder (both conversions of
+// integral non-negative values)
+__device__ __forceinline__ int64_t floor_nonneg_i64(float x) {
+    const float v = __builtin_floorf(__builtin_fmaxf(x, 0.0f));
+    const float hi = __builtin_floorf(v * 0x1p-32f);
+    const uint32_t h = (uint32_t)hi, l = (uint32_t)__builtin_fmaf(hi, -0x1p32f, v);
+    return (int64_t)(((uint64_t)h << 32) | l);
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -187,7 +197,6 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     int world_lo = 0, world_hi = -1;
     int g = -1, g_lo = 0, g_hi = -1;
     int64_t acc_mass = 0;
-    double acc_f64 = 0.0;
     uint32_t err = 0;
     // the next unit's perm entry (cell index | rotation), loaded while this unit computes
     bool have_pf = false;
@@ -203,6 +212,8 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
 
     // world fields kept in scalar registers
     int Wd = 0, Hd = 0, Nd = 0, cap = 0;
+    uint32_t w_magic = 1u;
+    int w_shift = 0;
     float rho_i = 0.f, rho_l = 0.f, kappa = 0.f;
     // physics variants in one scalar (bit 0: hard-max exploration, bit 1:
     // energy transport), in the kernel compiled with VARIANTS only; their
@@ -218,15 +229,15 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     Ctl* ctl = nullptr;
 
     auto flush = [&]() {
+        // each lane's exact partial, then the FP64 sum over lanes and waves
+        const double mf = wave_sum_f64((double)acc_mass);
         const int64_t m = wave_sum_i64(acc_mass);
-        const double mf = wave_sum_f64(acc_f64);
         if (lane == 0 && ctl != nullptr) {
             atomicAdd((unsigned long long*)&ctl->acc_mass, (unsigned long long)m);
             atomicAdd(&ctl->acc_mass_f64, mf);
         }
         if (err && ctl != nullptr) atomicOr(&ctl->err, err);
         acc_mass = 0;
-        acc_f64 = 0.0;
         err = 0;
     };
 
@@ -267,6 +278,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             world_hi = cld(b->group_prefix + (wi + 1));
             const auto* W = world_at(b, wi);
             Wd = W->W; Hd = W->H; Nd = W->N; cap = W->cap;
+            w_magic = W->w_magic; w_shift = W->w_shift;
             rho_i = W->rho_i; rho_l = W->rho_l; kappa = W->kappa;
             if constexpr (VARIANTS)
                 variant = (W->explore_mode == 1 ? 1 : 0) | (W->eflow != nullptr && W->kappa_e > 0.f ? 2 : 0);
@@ -335,20 +347,30 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             asm volatile("" : "+v"(entry));
         }
         const int i = entry & kPermIndexMask, r = (entry >> kPermRotShift) & 7;
-        // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels
-        const int y = i / Wd, x = i - y * Wd;
-        int nidx[9];
+        // ---- 1. sense: rotation-ordered 3x3 Moore kernel, 6 channels.
+        // The 8 neighbours in direction order from the wrapped columns and
+        // row bases, then rotated by r (one conditional rotation per bit of
+        // r): kernel position p reads direction (r + offset(p)) & 7.
+        const int y = cell_row(i, w_magic, w_shift), x = i - y * Wd;
+        const int xm = (x == 0 ? Wd : x) - 1, xp = x + 1 == Wd ? 0 : x + 1;
+        const int r0 = i - x, rm = (y == 0 ? Nd : r0) - Wd, rp = y + 1 == Hd ? 0 : r0 + Wd;
+        int dn[8] = {r0 + xp, rm + xp, rm + x, rm + xm, r0 + xm, rp + xm, rp + x, rp + xp};
 #pragma unroll
-        for (int p = 0; p < 9; ++p) {
-            nidx[p] = i;
-            if (p > 0) {
-                const int d = kernel_dir(r, p);
-                int nx = x + dir_dx(d), ny = y + dir_dy(d);
-                nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
-                ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
-                nidx[p] = ny * Wd + nx;
-            }
+        for (int sh = 0; sh < 3; ++sh) {
+            // an all-ones or all-zeros lane mask, opaque to the compiler so
+            // that each stage stays one bitfield select per entry
+            int m = -((r >> sh) & 1);
+            asm volatile("" : "+v"(m));
+            int nd[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) nd[k] = (dn[(k + (1 << sh)) & 7] & m) | (dn[k] & ~m);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dn[k] = nd[k];
         }
+        int nidx[9];
+        nidx[0] = i;
+#pragma unroll
+        for (int p = 1; p < 9; ++p) nidx[p] = dn[kernel_offset(p)];
         int64_t gE[9], gI[9];
         float gC[9][4];
 #pragma unroll
@@ -625,8 +647,10 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             if (e_own < 0 || i_own < 0) err |= kErrLedger;
             // invest / liquidate: sigmoid-gated fractions of the pre-step stocks
             const float se = sigmoid_s(a[0]), sl = sigmoid_s(a[1]);
-            int64_t xi = (int64_t)floorf(rho_i * se * i64_to_f32(e_own));
-            int64_t xl = (int64_t)floorf(rho_l * sl * i64_to_f32(i_own));
+            // (negative stocks are flagged above; the transfers then stay
+            // within [0, stock] or are zero, and the ledger still balances)
+            int64_t xi = floor_nonneg_i64(rho_i * se * i64_to_f32(e_own));
+            int64_t xl = floor_nonneg_i64(rho_l * sl * i64_to_f32(i_own));
             xi = xi > e_own ? e_own : xi;
             xl = xl > i_own ? i_own : xl;
             xi = xi < 0 ? 0 : xi;
@@ -650,14 +674,17 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
             const float inv = __builtin_amdgcn_rcpf(ssum);
             // flow budget below 2^31 quanta: each flow word carries the
             // explored flag in its low bit
-            int64_t F = (int64_t)floorf(kappa * i64_to_f32(I1));
-            if (F < 0) F = 0;
-            if (F > 0x7fffffffll) { err |= kErrLedger; F = 0x7fffffffll; }
+            // floor(kappa I1) >= 0, clamped to 2^31 - 1 (the conversion
+            // saturates at 2^32 - 1 beyond 32 bits)
+            const float fF = __builtin_floorf(__builtin_fmaxf(kappa * i64_to_f32(I1), 0.0f));
+            if (fF >= 0x1p31f) err |= kErrLedger;
+            uint32_t Fu = (uint32_t)fF;
+            Fu = Fu < 0x7fffffffu ? Fu : 0x7fffffffu;
             // all amounts are below 2^31: 32-bit integers suffice, and the
             // truncating conversion of a non-negative float is its floor
-            const uint32_t Fu = (uint32_t)F;
             if constexpr (!VARIANTS) {
                 const float per = inv * (float)Fu;  // budget per unit of softmax weight
+                const uint32_t onehot = 1u << best;   // the explored position's flag
                 uint32_t used = 0, fs[8];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
@@ -666,7 +693,7 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                     const uint32_t rem = Fu - used;
                     f = f < rem ? f : rem;
                     used += f;
-                    fs[t] = (f << 1) | (uint32_t)(t == best);
+                    fs[t] = (f << 1) | ((onehot >> t) & 1u);
                 }
                 // kernel position t + 1 points at direction (r + offset) & 7: put
                 // the words in offset order (fixed), then rotate by r, one
@@ -710,7 +737,6 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
                 }
             }
             acc_mass += E1;
-            acc_f64 += (double)E1;
         }
         ++u;
         // the next segment's chunk starts a new run

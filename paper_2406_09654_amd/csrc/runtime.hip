@@ -418,6 +418,7 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     WorldDev& h = w->host;
     memset(&h, 0, sizeof h);
     h.W = desc->width; h.H = desc->height; h.N = desc->width * desc->height; h.cap = desc->genome_capacity;
+    row_magic(h.W, &h.w_magic, &h.w_shift);
     h.NL = desc->n_weight_layers; h.HID = desc->hidden; h.prec = desc->precision;
     h.n_rad_blocks = L.n_rad_blocks;
     h.rho_i = desc->rho_invest; h.rho_l = desc->rho_liquidate; h.kappa = desc->kappa_flow;
