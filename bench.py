@@ -54,6 +54,15 @@ def trans_per_cell(hidden: int, layers: int) -> int:
     return 2 * hidden * (layers - 1) + 2 * 6 + 8 + 1
 
 
+def weight_bytes_per_genome(hidden: int, layers: int) -> int:
+    """Bytes of one genome's BF16 network as the network kernel reads it:
+    fragments of 1 KiB (16-row tiles x 32-wide K-steps; the 54 inputs take
+    2 K-steps) and the FP32 biases."""
+    mt, ks0, ksh = hidden // 16, 2, hidden // 32
+    frags = mt * ks0 + (mt * ksh if layers == 3 else 0) + ksh
+    return 1024 * frags + 4 * (hidden * (layers - 1) + 16)
+
+
 ACT_SOURCES = ["paper_2406_09654_amd/csrc/kernels_act.hip", "paper_2406_09654_amd/csrc/coralai_internal.h"]
 NET_SOURCES = ACT_SOURCES + ["paper_2406_09654_amd/csrc/kernels_genome.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_act_bf16_4096_hbm_traffic.md")
@@ -163,6 +172,7 @@ def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bo
     step_index = 0
     advance(first - 1)
     w.sync()
+    live_start = w.stats()["live_genomes"]
     w.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -185,6 +195,7 @@ def run_form(init, precision: int, steps: int, warmup: int, stream, autotune: bo
                         "timed_steps": [first, first + steps - 1]},
         "phase_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
         "stats": st,
+        "live_genomes_window": [live_start, st["live_genomes"]],
         "tuning": tuning,
     }
 
@@ -530,13 +541,24 @@ def main() -> int:
     act_ms = bf["phase_ms"]["act"]
     trans = trans_per_cell(hidden, layers) * N
     traffic, traffic_note = act_traffic(bf["tuning"])
-    roof = {"kernel": "k_act (sense + grouped MLP + epilogue)", "bound": "alu",
-            "achieved": trans / (act_ms * 1e-3), "peak": PEAK_TRANS,
-            "unit": "transcendental op/s", "frac": trans / (act_ms * 1e-3) / PEAK_TRANS,
+    # the kernel is bound by the vector-memory pipeline (the counter summary
+    # and the design notes give the evidence), so its roofline is memory:
+    # the cells' algorithmic bytes plus each live genome's weights once
+    live = 0.5 * sum(bf["live_genomes_window"])
+    wbytes = weight_bytes_per_genome(hidden, layers)
+    act_bytes = ACT_BYTES_PER_CELL * N + live * wbytes
+    roof = {"kernel": "k_act (sense + grouped MLP + epilogue)", "bound": "hbm",
+            "achieved": act_bytes / (act_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": act_bytes / (act_ms * 1e-3) / PEAK_HBM,
             "traffic": traffic, "traffic_note": traffic_note,
-            "per_unit": "%d transcendental ops per cell (tanh, sigmoid, softmax), %d cells per launch"
-                        % (trans_per_cell(hidden, layers), N),
-            "hbm_frac_algorithmic": ACT_BYTES_PER_CELL * N / (act_ms * 1e-3) / PEAK_HBM,
+            "per_unit": "%d B per cell x %d cells, plus %d B of BF16 weights and biases per live genome "
+                        "x %.0f live genomes (mean over the timed steps), per launch"
+                        % (ACT_BYTES_PER_CELL, N, wbytes, live),
+            "limiter": "vector-memory pipeline (texture data path busy most of the launch, requests "
+                       "waiting on L2); profiles/k_act_4096_memory_pipeline.md",
+            "transcendental": {"achieved": trans / (act_ms * 1e-3), "peak": PEAK_TRANS,
+                               "unit": "op/s", "frac": trans / (act_ms * 1e-3) / PEAK_TRANS,
+                               "per_unit": "%d per cell" % trans_per_cell(hidden, layers)},
             "mfma_frac_bf16": flops_per_cell(hidden, layers) * N / (act_ms * 1e-3) / PEAK_BF16}
     out = {
         "metric": METRIC,
