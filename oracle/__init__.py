@@ -95,6 +95,18 @@ def lib():
         L.orc_merge.restype = ct.c_int64
         L.orc_merge.argtypes = [ct.POINTER(_Desc), P, P, ct.c_int32, P, ct.c_uint64, ct.c_uint64,
                                 ct.c_uint64, P, P, P, P, ct.c_int64, P]
+        L.orc_cppn_to_net_x.restype = None
+        L.orc_cppn_to_net_x.argtypes = [ct.POINTER(_Desc), P, P, P]
+        L.orc_nets_for_x.restype = None
+        L.orc_nets_for_x.argtypes = [ct.POINTER(_Desc), ct.c_int64, P, P, P]
+        L.orc_radiate_x.restype = ct.c_int64
+        L.orc_radiate_x.argtypes = [ct.c_int64, P, ct.c_int32, P, P, ct.c_uint64, ct.c_uint64, ct.c_uint64,
+                                    ct.c_double, ct.c_uint64, ct.c_uint64, P, P, ct.c_int64, P]
+        L.orc_merge_x.restype = ct.c_int64
+        L.orc_merge_x.argtypes = [ct.POINTER(_Desc), P, P, ct.c_int32, P, P, ct.c_uint64, ct.c_uint64,
+                                  ct.c_uint64, P, P, P, P, ct.c_int64, P]
+        L.orc_genetic_distance_x.restype = ct.c_double
+        L.orc_genetic_distance_x.argtypes = [P, P, P, P, ct.c_double, ct.c_double, ct.c_double]
         L.orc_genetic_distance.restype = ct.c_double
         L.orc_genetic_distance.argtypes = [P, P, ct.c_double]
         L.orc_mass.restype = ct.c_int64
@@ -354,6 +366,86 @@ def merge(d: Desc, G: np.ndarray, R: np.ndarray, cap: int, params: np.ndarray, s
     k = min(nh, max_hits)
     return (G2.reshape(shp), P, (hc[:k].copy(), hs[:k].copy(), ha[:k].copy(), hb[:k].copy()),
             int(dropped.value))
+
+
+# Structural genes of a genome (NEAT over the bounded superset of the CPPN;
+# see orc_ext): direct connections input m -> output o at 5 o + m, added
+# nodes splitting hidden j -> output o at 2 j + o.
+EXT_DTYPE = np.dtype([("conn_mask", np.uint32), ("node_mask", np.uint32), ("node_act", np.uint32),
+                      ("pad", np.uint32), ("conn_w", np.float64, (10,)), ("node_in", np.float64, (16,)),
+                      ("node_out", np.float64, (16,))])
+assert EXT_DTYPE.itemsize == 16 + 42 * 8
+
+
+def empty_ext(n: int) -> np.ndarray:
+    return np.zeros(n, EXT_DTYPE)
+
+
+def cppn_to_net_x(d: Desc, p: np.ndarray, e) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    e = np.ascontiguousarray(np.asarray(e, EXT_DTYPE).reshape(1))
+    out = np.zeros(net_size(d))
+    dc = d.c()
+    lib().orc_cppn_to_net_x(ct.byref(dc), _p(p), _p(e), _p(out))
+    return out
+
+
+def nets_for_x(d: Desc, params: np.ndarray, exts: np.ndarray) -> np.ndarray:
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    exts = np.ascontiguousarray(exts, EXT_DTYPE)
+    assert len(exts) == len(params)
+    out = np.zeros((len(params), net_size(d)))
+    dc = d.c()
+    lib().orc_nets_for_x(ct.byref(dc), len(params), _p(params), _p(exts), _p(out))
+    return out
+
+
+def radiate_x(G: np.ndarray, cap: int, params: np.ndarray, ext: np.ndarray, seed: int, step_index: int,
+              rate: float, sigma: float, p_conn: float, p_node: float, max_hits: int = 1 << 20):
+    """Radiation with NEAT's structural mutations: (G', params', ext', hits, dropped)."""
+    shp = G.shape
+    G2 = np.ascontiguousarray(G, dtype=np.int32).ravel().copy()
+    P = np.ascontiguousarray(params, dtype=np.float64).copy()
+    X = np.ascontiguousarray(ext, EXT_DTYPE).copy()
+    assert P.shape == (cap, N_PARAM) and X.shape == (cap,)
+    hc = np.zeros(max_hits, np.int64)
+    hs = np.zeros(max_hits, np.int32)
+    dropped = ct.c_int64(0)
+    nh = lib().orc_radiate_x(G2.size, _p(G2), cap, _p(P), _p(X), int(seed), int(step_index), hit_threshold(rate),
+                             float(sigma), hit_threshold(p_conn), hit_threshold(p_node), _p(hc), _p(hs),
+                             max_hits, ct.byref(dropped))
+    k = min(nh, max_hits)
+    return G2.reshape(shp), P, X, (hc[:k].copy(), hs[:k].copy()), int(dropped.value)
+
+
+def merge_x(d: Desc, G: np.ndarray, R: np.ndarray, cap: int, params: np.ndarray, ext: np.ndarray, seed: int,
+            step_index: int, rate: float, max_hits: int = 1 << 20):
+    """Merging with structural genes: (G', params', ext', (cells, slots, a, b), dropped)."""
+    shp = G.shape
+    G2 = np.ascontiguousarray(G, dtype=np.int32).ravel().copy()
+    R2 = np.ascontiguousarray(R, dtype=np.uint8).ravel()
+    P = np.ascontiguousarray(params, dtype=np.float64).copy()
+    X = np.ascontiguousarray(ext, EXT_DTYPE).copy()
+    hc = np.zeros(max_hits, np.int64)
+    hs = np.zeros(max_hits, np.int32)
+    ha = np.zeros(max_hits, np.int32)
+    hb = np.zeros(max_hits, np.int32)
+    dropped = ct.c_int64(0)
+    dc = d.c()
+    nh = lib().orc_merge_x(ct.byref(dc), _p(G2), _p(R2), cap, _p(P), _p(X), int(seed), int(step_index),
+                           hit_threshold(rate), _p(hc), _p(hs), _p(ha), _p(hb), max_hits, ct.byref(dropped))
+    k = min(nh, max_hits)
+    return (G2.reshape(shp), P, X, (hc[:k].copy(), hs[:k].copy(), ha[:k].copy(), hb[:k].copy()),
+            int(dropped.value))
+
+
+def genetic_distance_x(pa, ea, pb, eb, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4) -> float:
+    """NEAT compatibility distance with structural genes."""
+    pa = np.ascontiguousarray(pa, dtype=np.float64)
+    pb = np.ascontiguousarray(pb, dtype=np.float64)
+    ea = np.ascontiguousarray(np.asarray(ea, EXT_DTYPE).reshape(1))
+    eb = np.ascontiguousarray(np.asarray(eb, EXT_DTYPE).reshape(1))
+    return float(lib().orc_genetic_distance_x(_p(pa), _p(ea), _p(pb), _p(eb), float(c1), float(c2), float(c3)))
 
 
 def mass(E: np.ndarray, I: np.ndarray) -> int:

@@ -176,6 +176,95 @@ void orc_nets_for(const orc_desc* d, int64_t n, const double* params, double* ne
     for (int64_t k = 0; k < n; ++k) orc_cppn_to_net(d, params + k * ORC_NPARAM, nets + k * nsz);
 }
 
+/* NEAT structural genes over a bounded superset of the CPPN (System Design:
+ * NEAT's mutation and crossover operators).  Beyond the 56 base genes (A,
+ * then B) a genome may hold:
+ *   - direct connections input m -> output o (innovation 56 + 5 o + m),
+ *     enabled by bit 5 o + m of conn_mask, weight conn_w[5 o + m];
+ *   - added nodes N_k, k = 2 j + o, that split the connection hidden j ->
+ *     output o (NEAT's add-node mutation): enabled by bit k of node_mask,
+ *     activation node_act bits 2k..2k+1 (sin, gauss, tanh, identity), in
+ *     weight node_in[k] (innovation 66 + 2 k) and out weight node_out[k]
+ *     (innovation 67 + 2 k); while N_k is enabled the base connection
+ *     B[o][j] is disabled.
+ * Output o is then sum over j of (N_{2j+o} enabled ? node_out phi(node_in
+ * h_j) : B[o][j] h_j) plus sum over enabled direct connections of
+ * conn_w z_m.  A genome without structural genes is the base CPPN. */
+typedef struct {
+    uint32_t conn_mask, node_mask, node_act, pad;
+    double conn_w[10];
+    double node_in[16];
+    double node_out[16];
+} orc_ext;
+
+static double node_fn(int f, double s) {
+    switch (f & 3) {
+        case 0: return sin(s);
+        case 1: return exp(-s * s);
+        case 2: return tanh(s);
+        default: return s;
+    }
+}
+
+void orc_cppn_x(const double* p, const orc_ext* e, double x1, double y1, double x2, double y2,
+                double out[2]) {
+    const double z[5] = {x1, y1, x2, y2, 1.0};
+    double h[8];
+    for (int k = 0; k < 8; ++k) {
+        double s = 0.0;
+        for (int m = 0; m < 5; ++m) s += p[k * 5 + m] * z[m];
+        h[k] = node_fn(k, s);
+    }
+    for (int o = 0; o < 2; ++o) {
+        double s = 0.0;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 2 * j + o;
+            if ((e->node_mask >> k) & 1u)
+                s += e->node_out[k] * node_fn((int)(e->node_act >> (2 * k)), e->node_in[k] * h[j]);
+            else
+                s += p[40 + o * 8 + j] * h[j];
+        }
+        for (int m = 0; m < 5; ++m)
+            if ((e->conn_mask >> (5 * o + m)) & 1u) s += e->conn_w[5 * o + m] * z[m];
+        out[o] = s;
+    }
+}
+
+/* orc_cppn_to_net with structural genes (the same substrate queries). */
+void orc_cppn_to_net_x(const orc_desc* d, const double* p, const orc_ext* e, double* net) {
+    int32_t L[8];
+    orc_layer_widths(d, L);
+    int n = d->n_weight_layers;
+    double* w = net;
+    for (int l = 0; l < n; ++l) {
+        double yi = -1.0 + 2.0 * l / n, yo = -1.0 + 2.0 * (l + 1) / n;
+        double scale = 1.0 / sqrt((double)L[l]);
+        for (int o = 0; o < L[l + 1]; ++o) {
+            double xo = -1.0 + 2.0 * o / (L[l + 1] - 1);
+            for (int j = 0; j < L[l]; ++j) {
+                double xi = -1.0 + 2.0 * j / (L[l] - 1);
+                double r[2];
+                orc_cppn_x(p, e, xi, yi, xo, yo, r);
+                w[(int64_t)o * L[l] + j] = r[0] * scale;
+            }
+        }
+        w += (int64_t)L[l + 1] * L[l];
+        for (int o = 0; o < L[l + 1]; ++o) {
+            double xo = -1.0 + 2.0 * o / (L[l + 1] - 1);
+            double r[2];
+            orc_cppn_x(p, e, 0.0, yi, xo, yo, r);
+            w[o] = r[1];
+        }
+        w += L[l + 1];
+    }
+}
+
+void orc_nets_for_x(const orc_desc* d, int64_t n, const double* params, const orc_ext* ext, double* nets) {
+    const int64_t nsz = orc_net_size(d);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < n; ++k) orc_cppn_to_net_x(d, params + k * ORC_NPARAM, ext + k, nets + k * nsz);
+}
+
 /* Sensors over the Kernel (Experiment): u[p*6 + ch] is channel ch of the
  * cell at kernel position p, channels (E, I, C0, C1, C2, C3), E and I as
  * mass values (quanta * 2^-24). */
@@ -735,6 +824,184 @@ int64_t orc_merge(const orc_desc* d, int32_t* G, const uint8_t* R, int32_t cap, 
     free(counts);
     free(freel);
     return merges;
+}
+
+/* Box-Muller normals from Philox blocks (i, s, third0 + b, 0), b = 0, 1, ...:
+ * four normals per block, as in orc_mutation_normals. */
+static void normals_from(uint64_t seed, uint64_t i, uint64_t s, uint64_t third0, int nz, double* z) {
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t key[2] = {seed, 0};
+    for (int b = 0; 4 * b < nz; ++b) {
+        uint64_t ctr[4] = {i, s, third0 + (uint64_t)b, 0}, o[4];
+        orc_philox4x64_10(ctr, key, o);
+        for (int h = 0; h < 2; ++h) {
+            double u1 = orc_uniform(o[2 * h]), u2 = orc_uniform(o[2 * h + 1]);
+            double rr = sqrt(-2.0 * log(u1));
+            if (4 * b + 2 * h < nz) z[4 * b + 2 * h] = rr * cos(two_pi * u2);
+            if (4 * b + 2 * h + 1 < nz) z[4 * b + 2 * h + 1] = rr * sin(two_pi * u2);
+        }
+    }
+}
+
+/* The 42 weights of the structural genes in one array: conn_w, node_in,
+ * node_out. */
+static double* ext_weight(orc_ext* e, int m) {
+    return m < 10 ? &e->conn_w[m] : (m < 26 ? &e->node_in[m - 10] : &e->node_out[m - 26]);
+}
+
+/* Radiation with NEAT's structural mutations (System Design: NEAT's
+ * mutation operator).  The hits, slots and base-gene mutation are those of
+ * orc_radiate.  The child's 42 structural-gene weights (enabled or not) get
+ * sigma * N(0,1) as well, from Philox blocks (i, s, 16 + b, 0), b = 0..10.
+ * Then the block (i, s, 15, 0) decides the structural mutations: word 0
+ * below Tc adds the direct connection (word 2 & 0xffff) mod 10, word 1
+ * below Tn adds the node (word 2 >> 16 & 0xffff) mod 16 with activation
+ * word 3 & 3, in weight 1 and out weight the child's B[o][j], which it
+ * replaces.  Adding a gene that is already there changes nothing.  ext is
+ * cap entries, in/out. */
+int64_t orc_radiate_x(int64_t n, int32_t* G, int32_t cap, double* params, orc_ext* ext, uint64_t seed,
+                      uint64_t s, uint64_t T, double sigma, uint64_t Tc, uint64_t Tn, int64_t* hit_cells,
+                      int32_t* hit_slots, int64_t max_hits, int64_t* dropped) {
+    int32_t* counts = (int32_t*)calloc((size_t)cap, sizeof(int32_t));
+    int32_t* freel = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+    for (int64_t i = 0; i < n; ++i) counts[G[i]]++;
+    int32_t nfree = 0;
+    for (int32_t g = 0; g < cap; ++g)
+        if (counts[g] == 0) freel[nfree++] = g;
+    uint64_t key[2] = {seed, 0};
+    int64_t hits = 0;
+    *dropped = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t ctr[4] = {(uint64_t)(i / 4), s, 0, 0}, o[4];
+        orc_philox4x64_10(ctr, key, o);
+        if (!(o[i % 4] < T)) continue;
+        int32_t slot = -1;
+        if (hits < nfree) {
+            slot = freel[hits];
+            const int32_t parent = G[i];
+            double z[ORC_NPARAM], zx[42];
+            orc_mutation_normals(seed, (uint64_t)i, s, z);
+            double* c = params + (int64_t)slot * ORC_NPARAM;
+            for (int m = 0; m < ORC_NPARAM; ++m) c[m] = params[(int64_t)parent * ORC_NPARAM + m] + sigma * z[m];
+            orc_ext e = ext[parent];
+            normals_from(seed, (uint64_t)i, s, 16, 42, zx);
+            for (int m = 0; m < 42; ++m) *ext_weight(&e, m) += sigma * zx[m];
+            uint64_t sc[4] = {(uint64_t)i, s, 15, 0}, so[4];
+            orc_philox4x64_10(sc, key, so);
+            if (so[0] < Tc) e.conn_mask |= 1u << (int)((so[2] & 0xffff) % 10);
+            if (so[1] < Tn) {
+                const int k = (int)(((so[2] >> 16) & 0xffff) % 16);
+                if (!((e.node_mask >> k) & 1u)) {
+                    const int j = k >> 1, oo = k & 1;
+                    e.node_mask |= 1u << k;
+                    e.node_act = (e.node_act & ~(3u << (2 * k))) | ((uint32_t)(so[3] & 3) << (2 * k));
+                    e.node_in[k] = 1.0;
+                    e.node_out[k] = c[40 + oo * 8 + j];
+                }
+            }
+            ext[slot] = e;
+            G[i] = slot;
+        } else {
+            (*dropped)++;
+        }
+        if (hit_cells && hits < max_hits) {
+            hit_cells[hits] = i;
+            hit_slots[hits] = slot;
+        }
+        hits++;
+    }
+    free(counts);
+    free(freel);
+    return hits;
+}
+
+/* orc_merge with structural genes: the base genes as in orc_merge (word 0
+ * of the block (i, s, 0, 2)); every structural gene position is taken whole
+ * (enabled state, weights, activation) from b where bit c of word 1 (direct
+ * connection c) or bit k of word 2 (added node k) is set, from a otherwise.
+ * A gene both parents hold is so inherited from either with probability
+ * 1/2, and a gene only one holds is kept with probability 1/2: NEAT's
+ * crossover between parents of equal fitness (the ecosystem assigns none). */
+int64_t orc_merge_x(const orc_desc* d, int32_t* G, const uint8_t* R, int32_t cap, double* params, orc_ext* ext,
+                    uint64_t seed, uint64_t s, uint64_t T, int64_t* hit_cells, int32_t* hit_slots,
+                    int32_t* hit_a, int32_t* hit_b, int64_t max_hits, int64_t* dropped) {
+    const int64_t n = (int64_t)d->width * d->height;
+    int32_t* G0 = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    memcpy(G0, G, sizeof(int32_t) * (size_t)n);
+    const int64_t merges = orc_merge(d, G, R, cap, params, seed, s, T, hit_cells, hit_slots, hit_a, hit_b,
+                                     max_hits, dropped);
+    /* orc_merge listed the merges in cell order; replay their structural genes */
+    uint64_t key[2] = {seed, 0};
+    int64_t k = 0;
+    for (int64_t i = 0; i < n && k < merges; ++i) {
+        uint64_t ctr[4] = {(uint64_t)(i / 4), s, 0, 1}, o[4];
+        orc_philox4x64_10(ctr, key, o);
+        if (!(o[i % 4] < T)) continue;
+        const int32_t a = G0[i], b = G0[nbr(d, i, R[i] & 7)];
+        if (a == b) continue;
+        const int32_t slot = G[i] != a ? G[i] : -1;
+        if (slot >= 0) {
+            uint64_t mc[4] = {(uint64_t)i, s, 0, 2}, mo[4];
+            orc_philox4x64_10(mc, key, mo);
+            orc_ext e;
+            memset(&e, 0, sizeof e);
+            for (int c = 0; c < 10; ++c) {
+                const orc_ext* src = ((mo[1] >> c) & 1) ? &ext[b] : &ext[a];
+                e.conn_mask |= src->conn_mask & (1u << c);
+                e.conn_w[c] = src->conn_w[c];
+            }
+            for (int q = 0; q < 16; ++q) {
+                const orc_ext* src = ((mo[2] >> q) & 1) ? &ext[b] : &ext[a];
+                e.node_mask |= src->node_mask & (1u << q);
+                e.node_act |= src->node_act & (3u << (2 * q));
+                e.node_in[q] = src->node_in[q];
+                e.node_out[q] = src->node_out[q];
+            }
+            ext[slot] = e;
+        }
+        ++k;
+    }
+    free(G0);
+    return merges;
+}
+
+/* NEAT's compatibility distance with structural genes: genes are listed by
+ * innovation number (base 0..55, always present; direct connection c at
+ * 56 + c; added node k's in and out connections at 66 + 2k, 67 + 2k, present
+ * while enabled).  Matching genes are those both genomes hold; of the
+ * others, those beyond the smaller of the two genomes' highest innovation
+ * numbers are excess (E), the rest disjoint (D); W is the mean absolute
+ * weight difference of the matching genes and N the larger genome's gene
+ * count: c1 E / N + c2 D / N + c3 W. */
+double orc_genetic_distance_x(const double* pa, const orc_ext* ea, const double* pb, const orc_ext* eb,
+                              double c1, double c2, double c3) {
+    double wa[98], wb[98];
+    int ha[98], hb[98];
+    for (int m = 0; m < 56; ++m) { wa[m] = pa[m]; wb[m] = pb[m]; ha[m] = hb[m] = 1; }
+    for (int c = 0; c < 10; ++c) {
+        wa[56 + c] = ea->conn_w[c]; wb[56 + c] = eb->conn_w[c];
+        ha[56 + c] = (ea->conn_mask >> c) & 1u; hb[56 + c] = (eb->conn_mask >> c) & 1u;
+    }
+    for (int q = 0; q < 16; ++q) {
+        wa[66 + 2 * q] = ea->node_in[q]; wa[67 + 2 * q] = ea->node_out[q];
+        wb[66 + 2 * q] = eb->node_in[q]; wb[67 + 2 * q] = eb->node_out[q];
+        ha[66 + 2 * q] = ha[67 + 2 * q] = (ea->node_mask >> q) & 1u;
+        hb[66 + 2 * q] = hb[67 + 2 * q] = (eb->node_mask >> q) & 1u;
+    }
+    int maxa = 0, maxb = 0, na = 0, nb = 0, match = 0;
+    for (int g = 0; g < 98; ++g) {
+        if (ha[g]) { maxa = g; ++na; }
+        if (hb[g]) { maxb = g; ++nb; }
+    }
+    const int lim = maxa < maxb ? maxa : maxb;
+    double w = 0.0;
+    int E = 0, D = 0;
+    for (int g = 0; g < 98; ++g) {
+        if (ha[g] && hb[g]) { w += fabs(wa[g] - wb[g]); ++match; }
+        else if (ha[g] || hb[g]) { if (g > lim) ++E; else ++D; }
+    }
+    const double N = (double)(na > nb ? na : nb);
+    return c1 * E / N + c2 * D / N + c3 * (w / match);
 }
 
 /* Exact and FP64 total mass sum(E + I). */

@@ -818,3 +818,219 @@ def test_merge_births_record_both_parents(oracle_lib):
         dab = oracle_lib.genetic_distance(P[a], P[b])
         assert oracle_lib.genetic_distance(P2[s_], P[a]) + oracle_lib.genetic_distance(P2[s_], P[b]) \
             == pytest.approx(dab, rel=1e-12)
+
+
+# ---------------------------------------------------------------- structural genes (NEAT)
+
+def _rand_ext(rng, n, p_on=0.5):
+    e = oracle_lib_ext_empty(n)
+    for k in range(n):
+        e[k]["conn_mask"] = int(sum(1 << c for c in range(10) if rng.random() < p_on))
+        e[k]["node_mask"] = int(sum(1 << q for q in range(16) if rng.random() < p_on))
+        e[k]["node_act"] = int(rng.integers(0, 1 << 32, dtype=np.uint64))
+        e[k]["conn_w"] = rng.standard_normal(10)
+        e[k]["node_in"] = rng.standard_normal(16)
+        e[k]["node_out"] = rng.standard_normal(16)
+    return e
+
+
+def oracle_lib_ext_empty(n):
+    import oracle
+    return oracle.empty_ext(n)
+
+
+def _bf_cppn_x(p, e, z):
+    """The structural CPPN from its definition, scalar Python."""
+    fns = [math.sin, lambda s: math.exp(-s * s), math.tanh, lambda s: s]
+    h = [fns[k % 4](sum(p[5 * k + m] * z[m] for m in range(5))) for k in range(8)]
+    out = []
+    for o in range(2):
+        acc = 0.0
+        for j in range(8):
+            k = 2 * j + o
+            if (int(e["node_mask"]) >> k) & 1:
+                act = (int(e["node_act"]) >> (2 * k)) & 3
+                acc += e["node_out"][k] * fns[act](e["node_in"][k] * h[j])
+            else:
+                acc += p[40 + 8 * o + j] * h[j]
+        for m in range(5):
+            if (int(e["conn_mask"]) >> (5 * o + m)) & 1:
+                acc += e["conn_w"][5 * o + m] * z[m]
+        out.append(acc)
+    return out
+
+
+def test_structural_cppn_against_bruteforce(oracle_lib):
+    """Networks of genomes with random structural genes (direct connections,
+    added nodes with every activation) against a scalar evaluation of the
+    definition at every substrate query; empty structure is the base CPPN."""
+    rng = np.random.default_rng(41)
+    d = oracle_lib.Desc(6, 6, 2, 32)
+    for trial in range(4):
+        p = rng.standard_normal(56)
+        e = _rand_ext(rng, 1)[0]
+        net = oracle_lib.cppn_to_net_x(d, p, e)
+        widths = [54, 32, 14]
+        off = 0
+        for l in range(2):
+            Li, Lo = widths[l], widths[l + 1]
+            yi, yo = -1 + 2 * l / 2, -1 + 2 * (l + 1) / 2
+            for o in range(0, Lo, 5):
+                for j in range(0, Li, 7):
+                    z = [-1 + 2 * j / (Li - 1), yi, -1 + 2 * o / (Lo - 1), yo, 1.0]
+                    ref = _bf_cppn_x(p, e, z)[0] / math.sqrt(Li)
+                    assert abs(net[off + o * Li + j] - ref) <= 1e-12 * max(1.0, abs(ref))
+            off += Lo * Li
+            for o in range(Lo):
+                z = [0.0, yi, -1 + 2 * o / (Lo - 1), yo, 1.0]
+                ref = _bf_cppn_x(p, e, z)[1]
+                assert abs(net[off + o] - ref) <= 1e-12 * max(1.0, abs(ref))
+            off += Lo
+        np.testing.assert_array_equal(oracle_lib.cppn_to_net_x(d, p, oracle_lib.empty_ext(1)[0]),
+                                      oracle_lib.cppn_to_net(d, p))
+
+
+def test_structural_radiation_against_bruteforce(oracle_lib):
+    """Radiation with structural mutation: base genes as plain radiation,
+    the 42 structural weights perturbed by Box-Muller normals of the blocks
+    (i, s, 16 + b, 0), and the add-connection / add-node decisions, positions
+    and activations from the block (i, s, 15, 0) (numpy Philox)."""
+    rng = np.random.default_rng(44)
+    W, H, cap = 40, 30, 160
+    G = rng.integers(0, 6, (H, W)).astype(np.int32)
+    P = np.zeros((cap, 56))
+    P[:6] = rng.standard_normal((6, 56))
+    X = oracle_lib.empty_ext(cap)
+    X[:6] = _rand_ext(rng, 6, 0.3)
+    seed, s, rate, sigma, pc, pn = 5, 11, 0.05, 0.1, 0.5, 0.5
+    G2, P2, X2, (hc, hs), dropped = oracle_lib.radiate_x(G, cap, P, X, seed, s, rate, sigma, pc, pn)
+    Gb, Pb, (hcb, hsb), db = oracle_lib.radiate(G, cap, P, seed, s, rate, sigma)
+    np.testing.assert_array_equal(G2, Gb)
+    np.testing.assert_array_equal(P2, Pb)
+    assert hc.tolist() == hcb.tolist() and dropped == db == 0 and len(hc) > 40
+    Tc, Tn = math.floor(pc * 2.0 ** 64), math.floor(pn * 2.0 ** 64)
+    n_conn = n_node = 0
+    for i, slot in zip(hc, hs):
+        par = G.ravel()[i]
+        z = []
+        for b in range(11):
+            o = _numpy_block((int(i), s, 16 + b, 0), (seed, 0))
+            for h in range(2):
+                u1 = (2 * (int(o[2 * h]) >> 41) + 1) * 2.0 ** -24
+                u2 = (2 * (int(o[2 * h + 1]) >> 41) + 1) * 2.0 ** -24
+                rr = math.sqrt(-2 * math.log(u1))
+                z += [rr * math.cos(2 * math.pi * u2), rr * math.sin(2 * math.pi * u2)]
+        w_par = np.concatenate([X[par]["conn_w"], X[par]["node_in"], X[par]["node_out"]])
+        w_exp = w_par + sigma * np.array(z[:42])
+        cm, nm, na = int(X[par]["conn_mask"]), int(X[par]["node_mask"]), int(X[par]["node_act"])
+        o = [int(v) for v in _numpy_block((int(i), s, 15, 0), (seed, 0))]
+        if o[0] < Tc:
+            cm |= 1 << ((o[2] & 0xffff) % 10)
+            n_conn += 1
+        if o[1] < Tn:
+            k = ((o[2] >> 16) & 0xffff) % 16
+            if not (nm >> k) & 1:
+                nm |= 1 << k
+                na = (na & ~(3 << (2 * k))) | ((o[3] & 3) << (2 * k))
+                w_exp[10 + k] = 1.0
+                w_exp[26 + k] = P2[slot, 40 + 8 * (k & 1) + (k >> 1)]
+                n_node += 1
+        c = X2[slot]
+        assert (int(c["conn_mask"]), int(c["node_mask"]), int(c["node_act"])) == (cm, nm, na)
+        got = np.concatenate([c["conn_w"], c["node_in"], c["node_out"]])
+        np.testing.assert_allclose(got, w_exp, rtol=0, atol=1e-14)
+    assert n_conn > 10 and n_node > 10
+
+
+def test_add_node_with_identity_keeps_the_network(oracle_lib):
+    """NEAT's add-node: the split connection's weight moves to the new node's
+    out-connection and its in-weight is 1, so with the identity activation
+    the network is unchanged (sigma 0, every hit adds a node)."""
+    rng = np.random.default_rng(45)
+    W, H, cap = 24, 20, 600
+    G = rng.integers(0, 3, (H, W)).astype(np.int32)
+    P = np.zeros((cap, 56))
+    P[:3] = rng.standard_normal((3, 56))
+    X = oracle_lib.empty_ext(cap)
+    d = oracle_lib.Desc(6, 6, 2, 32)
+    G2, P2, X2, (hc, hs), dropped = oracle_lib.radiate_x(G, cap, P, X, 3, 4, 0.5, 0.0, 0.0, 1.0)
+    n_id = 0
+    for i, slot in zip(hc, hs):
+        e = X2[slot]
+        assert bin(int(e["node_mask"])).count("1") == 1 and int(e["conn_mask"]) == 0
+        k = int(e["node_mask"]).bit_length() - 1
+        if (int(e["node_act"]) >> (2 * k)) & 3 == 3:
+            np.testing.assert_allclose(oracle_lib.cppn_to_net_x(d, P2[slot], e),
+                                       oracle_lib.cppn_to_net(d, P[G.ravel()[i]]), rtol=0, atol=1e-14)
+            n_id += 1
+    assert n_id > 10
+
+
+def test_structural_merge_against_bruteforce(oracle_lib):
+    """Merging with structural genes: base genes as plain merging; each
+    direct-connection and added-node position whole from b where bit c of
+    word 1 (bit k of word 2) of the block (i, s, 0, 2) is set, else from a."""
+    W, H, cap = 40, 30, 300
+    G, R, P = _merge_world(7, W, H, cap=cap)
+    rng = np.random.default_rng(46)
+    X = oracle_lib.empty_ext(cap)
+    X[:6] = _rand_ext(rng, 6, 0.5)
+    d = oracle_lib.Desc(W, H)
+    seed, s = 9, 3
+    G2, P2, X2, (hc, hs, ha, hb), dropped = oracle_lib.merge_x(d, G, R, cap, P, X, seed, s, 0.1)
+    Gm, Pm, (hcm, hsm, ham, hbm), dm = oracle_lib.merge(d, G, R, cap, P, seed, s, 0.1)
+    np.testing.assert_array_equal(G2, Gm)
+    np.testing.assert_array_equal(P2, Pm)
+    assert len(hc) > 50 and dropped == dm
+    for i, slot, a, b in zip(hc, hs, ha, hb):
+        if slot < 0:
+            continue
+        o = [int(v) for v in _numpy_block((int(i), s, 0, 2), (seed, 0))]
+        c = X2[slot]
+        for q in range(10):
+            src = X[b] if (o[1] >> q) & 1 else X[a]
+            assert ((int(c["conn_mask"]) >> q) & 1) == ((int(src["conn_mask"]) >> q) & 1)
+            assert c["conn_w"][q] == src["conn_w"][q]
+        for q in range(16):
+            src = X[b] if (o[2] >> q) & 1 else X[a]
+            assert ((int(c["node_mask"]) >> q) & 1) == ((int(src["node_mask"]) >> q) & 1)
+            assert ((int(c["node_act"]) >> (2 * q)) & 3) == ((int(src["node_act"]) >> (2 * q)) & 3)
+            assert (c["node_in"][q], c["node_out"][q]) == (src["node_in"][q], src["node_out"][q])
+
+
+def _bf_distance(pa, ea, pb, eb, c1, c2, c3):
+    """NEAT compatibility distance from its definition over innovation-numbered genes."""
+    def genes(p, e):
+        g = {m: p[m] for m in range(56)}
+        for c in range(10):
+            if (int(e["conn_mask"]) >> c) & 1:
+                g[56 + c] = e["conn_w"][c]
+        for q in range(16):
+            if (int(e["node_mask"]) >> q) & 1:
+                g[66 + 2 * q] = e["node_in"][q]
+                g[67 + 2 * q] = e["node_out"][q]
+        return g
+    A, B = genes(pa, ea), genes(pb, eb)
+    cut = min(max(A), max(B))
+    match = [k for k in A if k in B]
+    other = [k for k in set(A) ^ set(B)]
+    E = sum(1 for k in other if k > cut)
+    D = len(other) - E
+    N = max(len(A), len(B))
+    Wbar = sum(abs(A[k] - B[k]) for k in match) / len(match)
+    return c1 * E / N + c2 * D / N + c3 * Wbar
+
+
+def test_structural_genetic_distance_against_definition(oracle_lib):
+    rng = np.random.default_rng(47)
+    for _ in range(40):
+        pa, pb = rng.standard_normal(56), rng.standard_normal(56)
+        ea, eb = _rand_ext(rng, 2, rng.random())
+        for c1, c2, c3 in [(1.0, 1.0, 0.4), (2.0, 0.5, 1.0)]:
+            got = oracle_lib.genetic_distance_x(pa, ea, pb, eb, c1, c2, c3)
+            assert abs(got - _bf_distance(pa, ea, pb, eb, c1, c2, c3)) < 1e-12
+            assert got == oracle_lib.genetic_distance_x(pb, eb, pa, ea, c1, c2, c3)
+        assert oracle_lib.genetic_distance_x(pa, ea, pa, ea) == 0.0
+    e0 = oracle_lib.empty_ext(1)[0]
+    assert abs(oracle_lib.genetic_distance_x(pa, e0, pb, e0, 1, 1, 0.7)
+               - oracle_lib.genetic_distance(pa, pb, 0.7)) < 1e-15
