@@ -137,6 +137,43 @@ int coralai_set_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids,
 int coralai_get_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids,
                         float* cppn_params_out);
 
+/* NEAT's structural genes (System Design: Coralai applies NEAT's mutation
+ * and crossover operators), over a bounded superset of the CPPN above.
+ * Innovation numbers are positions: the 56 base genes are 0..55; the
+ * direct connection input m -> output o (m over x1, y1, x2, y2, 1; o = 0
+ * weight, 1 bias) is gene 56 + 5 o + m, enabled by bit 5 o + m of
+ * conn_mask, weight conn_w[5 o + m]; the added node N_k, k = 2 j + o, which
+ * splits the connection hidden j -> output o (NEAT's add-node), has its in
+ * connection (weight node_in[k], gene 66 + 2 k) and out connection (weight
+ * node_out[k], gene 67 + 2 k), is enabled by bit k of node_mask and applies
+ * activation bits 2k..2k+1 of node_act (0 sin, 1 gauss, 2 tanh, 3 identity);
+ * while N_k is enabled it replaces B[o][j].  CPPN output o is then
+ *   sum over j of (N_{2j+o} ? node_out phi(node_in h_j) : B[o][j] h_j)
+ *   + sum over enabled direct connections of conn_w z_m.
+ * coralai_set_genomes gives a slot no structural genes.
+ * coralai_set_genome_ext replaces n slots' structural genes (host records;
+ * 10 and 16 mask bits, finite weights) and regenerates their networks;
+ * coralai_get_genome_ext reads them back.  Both wait for the stream. */
+typedef struct {
+    uint32_t conn_mask, node_mask, node_act, reserved;
+    float conn_w[10];
+    float node_in[16];
+    float node_out[16];
+} coralai_genome_ext;
+int coralai_set_genome_ext(coralai_world* w, int32_t n, const int32_t* slot_ids, const coralai_genome_ext* ext);
+int coralai_get_genome_ext(coralai_world* w, int32_t n, const int32_t* slot_ids, coralai_genome_ext* out);
+
+/* Structural mutation in radiation (NEAT's add-connection and add-node).
+ * Every hit's child also carries its parent's structural genes, whose 42
+ * weights get sigma * N(0,1) like the base genes (Box-Muller on the Philox
+ * blocks (i, step_index, 16 + b, 0), b = 0..10).  Then the block
+ * (i, step_index, 15, 0): word 0 below floor(p_conn 2^64) enables direct
+ * connection (word 2 & 0xffff) mod 10; word 1 below floor(p_node 2^64)
+ * adds node k = ((word 2 >> 16) & 0xffff) mod 16 with activation word 3 & 3,
+ * in weight 1 and out weight the child's B[o][j].  Adding a gene already
+ * present changes nothing.  Both 0 by default.  p in [0, 1]. */
+int coralai_set_structural_mutation(coralai_world* w, double p_conn, double p_node);
+
 /* n_steps updates (System Design; Fig. 1 A and B): bucket cells by genome,
  * sense the rotation-ordered 3x3 Moore kernel, run the genome's network,
  * apply invest / liquidate / communication / exploration, then the
@@ -164,9 +201,13 @@ int coralai_radiate(coralai_world* w, double rate, float sigma, uint64_t step_in
  * b = G[neighbour], both read from the map as it was before the call.  The
  * k-th merge in ascending i takes the k-th free slot (ascending slot ids
  * whose genome count is zero); the new genome is the NEAT crossover of a and
- * b: every CPPN here has the same genes, so all of them match, and gene m
- * (of the 56 parameters) comes from b when bit m of word 0 of the Philox
- * block (i, step_index, 0, 2) is set, from a otherwise.  Its network is
+ * b: base gene m (of the 56 parameters) comes from b when bit m of word 0 of
+ * the Philox block (i, step_index, 0, 2) is set, from a otherwise; each
+ * structural-gene position (see coralai_genome_ext) is taken whole from b
+ * where bit c of word 1 (direct connection c) or bit k of word 2 (added
+ * node k) is set, from a otherwise, so a gene both hold comes from either
+ * parent and a gene one holds is kept with probability 1/2 (NEAT's rule for
+ * parents of equal fitness; the ecosystem assigns none).  Its network is
  * regenerated and G[i] becomes the slot.  Merges beyond the free slots are
  * dropped.  The stats count merges as hits (stats.hits, stats.dropped).
  * rate in [0, 1].  Waits when out != NULL. */
@@ -227,15 +268,18 @@ int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int
                        int32_t* parents2, int32_t* slots, int32_t* n_births);
 
 /* NEAT's measure of genetic similarity (Discussion; Stanley and Miikkulainen's
- * compatibility distance c1 E / N + c2 D / N + c3 W): every CPPN here has the
- * same fixed topology, so all genes match (no excess E or disjoint D genes)
- * and the distance of genomes a and b is c3 times the mean absolute
- * difference of their 56 parameters.  Computes the na x nb matrix
+ * compatibility distance c1 E / N + c2 D / N + c3 W) over the genes above:
+ * matching genes are those both genomes hold; of the others, those beyond
+ * the smaller of the two highest innovation numbers are excess (E), the
+ * rest disjoint (D); W is the mean absolute weight difference of the
+ * matching genes, N the larger genome's gene count.  Without structural
+ * genes all 56 genes match and the distance is c3 times their mean
+ * absolute difference.  Computes the na x nb matrix
  * out_device[i * nb + j] = distance(slots_a[i], slots_b[j]) on the GPU into a
  * caller-owned device buffer of na * nb floats (host slot lists,
  * na + nb <= 54 x genome_capacity).  Waits for the stream. */
 int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_a, int32_t nb,
-                             const int32_t* slots_b, float c3, float* out_device);
+                             const int32_t* slots_b, float c1, float c2, float c3, float* out_device);
 
 /* The cycle's energy ledger in quanta: injected and removed by the last step,
  * and in total since the world was created.  Waits for the stream; any

@@ -38,8 +38,14 @@ EXPORTED = [
     "coralai_batch_set_tuning", "coralai_debug_set_act_segments",
     "coralai_debug_set_weights_noalloc", "coralai_set_daylight", "coralai_get_energy_ledger",
     "coralai_set_physics_variant", "coralai_get_lineage", "coralai_get_births",
-    "coralai_genetic_distance", "coralai_merge", "coralai_set_step_count",
+    "coralai_genetic_distance", "coralai_merge", "coralai_set_step_count", "coralai_set_genome_ext",
+    "coralai_get_genome_ext", "coralai_set_structural_mutation",
 ]
+# coralai_genome_ext (46 words): masks, then direct-connection, added-node in and out weights
+GENOME_EXT_DTYPE = np.dtype([("conn_mask", np.uint32), ("node_mask", np.uint32), ("node_act", np.uint32),
+                             ("reserved", np.uint32), ("conn_w", np.float32, (10,)),
+                             ("node_in", np.float32, (16,)), ("node_out", np.float32, (16,))])
+assert GENOME_EXT_DTYPE.itemsize == 46 * 4
 PHASES = ["bucket", "act", "physics", "finalize", "radiate"]
 
 
@@ -116,7 +122,10 @@ def lib() -> ct.CDLL:
             "coralai_get_births": (ct.c_int, [P, I32, P, P, P, P, P]),
             "coralai_merge": (ct.c_int, [P, ct.c_double, U64, S]),
             "coralai_set_step_count": (ct.c_int, [P, ct.c_int64]),
-            "coralai_genetic_distance": (ct.c_int, [P, I32, P, I32, P, ct.c_float, P]),
+            "coralai_set_genome_ext": (ct.c_int, [P, I32, P, P]),
+            "coralai_get_genome_ext": (ct.c_int, [P, I32, P, P]),
+            "coralai_set_structural_mutation": (ct.c_int, [P, ct.c_double, ct.c_double]),
+            "coralai_genetic_distance": (ct.c_int, [P, I32, P, I32, P, ct.c_float, ct.c_float, ct.c_float, P]),
             "coralai_set_profiling": (ct.c_int, [P, ct.c_int]),
             "coralai_get_profile": (ct.c_int, [P, P, P]),
         }
@@ -198,6 +207,20 @@ def coralai_merge(h, rate: float, step_index: int, stats: coralai_stats | None =
     _check(lib().coralai_merge(h, rate, step_index, ct.byref(stats) if stats is not None else None))
 
 
+def coralai_set_genome_ext(h, slots: np.ndarray, ext: np.ndarray) -> None:
+    assert ext.dtype == GENOME_EXT_DTYPE and ext.size == slots.size
+    _check(lib().coralai_set_genome_ext(h, int(slots.size), _host(slots), _host(ext)))
+
+
+def coralai_get_genome_ext(h, slots: np.ndarray, out: np.ndarray) -> None:
+    assert out.dtype == GENOME_EXT_DTYPE and out.size == slots.size
+    _check(lib().coralai_get_genome_ext(h, int(slots.size), _host(slots), _host(out)))
+
+
+def coralai_set_structural_mutation(h, p_conn: float, p_node: float) -> None:
+    _check(lib().coralai_set_structural_mutation(h, p_conn, p_node))
+
+
 def coralai_set_step_count(h, steps: int) -> None:
     _check(lib().coralai_set_step_count(h, steps))
 
@@ -223,9 +246,10 @@ def coralai_get_births(h, max_births: int, cells, parents, parents2, slots) -> i
     return int(n.value)
 
 
-def coralai_genetic_distance(h, slots_a: np.ndarray, slots_b: np.ndarray, c3: float, out_ptr: int) -> None:
+def coralai_genetic_distance(h, slots_a: np.ndarray, slots_b: np.ndarray, c1: float, c2: float, c3: float,
+                             out_ptr: int) -> None:
     _check(lib().coralai_genetic_distance(h, int(slots_a.size), _host(slots_a), int(slots_b.size),
-                                          _host(slots_b), c3, ct.c_void_p(out_ptr)))
+                                          _host(slots_b), c1, c2, c3, ct.c_void_p(out_ptr)))
 
 
 def coralai_get_energy_ledger(h) -> dict:

@@ -10,6 +10,7 @@
 namespace coralai {
 
 constexpr int kNParam = 56;   // CPPN parameters: A (8x5) then B (2x8)
+constexpr int kNExtW = 42;    // structural-gene weights: 10 direct connections, 16 added nodes x (in, out)
 constexpr int kNIn = 54;      // 9 kernel positions x 6 sensor channels
 constexpr int kNOut = 14;     // invest, liquidate, 4 comm, 8 flow logits
 // perm entries: cell index in bits 0..25 (W*H <= 2^26), rotation in 26..28
@@ -95,6 +96,14 @@ struct WorldDev {
     int32_t* gofs;        // [cap + 1] exclusive prefix of network units per genome
     uint8_t* slot_set;    // [cap]
     float* params;        // [cap][56]
+    // NEAT structural genes per slot (the bounded superset of the CPPN):
+    // ext_w [cap][42] = direct connection weights (10), added nodes' in
+    // weights (16), out weights (16); ext_mask [cap][4] = direct connections
+    // enabled, added nodes enabled, added nodes' activations (2 bits each)
+    float* ext_w;
+    uint32_t* ext_mask;
+    uint64_t t_conn;      // radiation: add-connection threshold (floor(p 2^64))
+    uint64_t t_node;      // radiation: add-node threshold
     int32_t* lineage_parent;  // [cap] slot the genome was mutated or merged from (-1: set by the caller)
     int32_t* lineage_parent2; // [cap] a merge's second parent (the partner's genome), else -1
     int64_t* lineage_birth;   // [cap] steps completed when the genome was created
@@ -432,8 +441,10 @@ void launch_cppn(const WorldDev* wdev, int nl, int hid, int prec, int from_radia
 void launch_scatter_params(const WorldDev* wdev, int n, hipStream_t s);
 // NEAT compatibility distance of genome pairs (slots: device list of the na
 // slots of A, then the nb of B) into out[na][nb] (device).
-void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na, int nb, float c3, float* out,
-                             int n_cu, hipStream_t s);
+void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na, int nb, float c1, float c2,
+                             float c3, float* out, int n_cu, hipStream_t s);
+// structural genes of the slots listed in stage_slots, 46-word records in stage_params
+void launch_scatter_ext(const WorldDev* wdev, int n, hipStream_t s);
 void launch_radiate(const BatchDev* bdev, const WorldDev* wdev, const LaunchShape& ls, int nl, int hid,
                     int prec, int n_rad_blocks, uint64_t T, float sigma, uint64_t step, hipStream_t s,
                     int recount = 1);

@@ -212,6 +212,54 @@ __device__ __forceinline__ T cppn_eval(const float* __restrict__ p, const T* __r
     return s;
 }
 
+// NEAT structural genes (System Design: NEAT's operators), a bounded
+// superset of the CPPN: direct connections input m -> output o (weight
+// xw[5 o + m], bit 5 o + m of conn) and added nodes N_k, k = 2 j + o, that
+// split the connection hidden j -> output o (bit k of node; activation bits
+// 2k..2k+1 of act: sin, gauss, tanh, identity; in weight xw[10 + k], out
+// weight xw[26 + k]); while N_k is enabled it replaces B[o][j].
+template <typename T>
+__device__ __forceinline__ T node_fn(uint32_t f, T s) {
+    switch (f & 3u) {
+        case 0: { T sn, cs; node_sincos(s, &sn, &cs); return sn; }
+        case 1: return node_gauss(s);
+        case 2: return node_tanh(s);
+        default: return s;
+    }
+}
+struct ExtGenes {
+    uint32_t conn, node, act;
+    const float* w;  // 42 weights (LDS)
+};
+// Output `out` of the CPPN with structural genes, at substrate inputs z =
+// (z0, z1, z2, z3, 1) and the same column and row entries: the node values,
+// then the output sum in node order, then the direct connections.
+template <typename T, bool GUARD>
+__device__ __forceinline__ T cppn_eval_x(const float* __restrict__ p, const T* __restrict__ c,
+                                         const T* __restrict__ r, int out, const ExtGenes& x, T z0, T z1, T z2,
+                                         T z3) {
+    T h[8];
+    h[0] = c[kTS0] * r[kTC0] + c[kTC0] * r[kTS0];
+    h[1] = node_gauss(c[kTA1] + r[kTA1]);
+    h[2] = tanh_sum<GUARD>(c[kTE2], r[kTE2], c[kTA2], r[kTA2]);
+    h[3] = c[kTA3] + r[kTA3];
+    h[4] = c[kTS4] * r[kTC4] + c[kTC4] * r[kTS4];
+    h[5] = node_gauss(c[kTA5] + r[kTA5]);
+    h[6] = tanh_sum<GUARD>(c[kTE6], r[kTE6], c[kTA6], r[kTA6]);
+    h[7] = c[kTA7] + r[kTA7];
+    const float* po = p + 40 + 8 * out;
+    T s = T(0);
+    for (int j = 0; j < 8; ++j) {
+        const int k = 2 * j + out;
+        if ((x.node >> k) & 1u) s += T(x.w[26 + k]) * node_fn<T>(x.act >> (2 * k), T(x.w[10 + k]) * h[j]);
+        else s += T(po[j]) * h[j];
+    }
+    const T z[5] = {z0, z1, z2, z3, T(1)};
+    for (int m = 0; m < 5; ++m)
+        if ((x.conn >> (5 * out + m)) & 1u) s += T(x.w[5 * out + m]) * z[m];
+    return s;
+}
+
 // Layer heights y_l = -1 + l * (2 / NL) and the stored scale factors of
 // stored_row_scale / stored_col_scale, in T: for T = float the products are
 // the same as the FP64 ones rounded once (the factors differ by powers of 2).
@@ -242,16 +290,26 @@ __device__ __forceinline__ T row_x(int layer, int row) {
     return T(-1) + T(row) * (layer == NL - 1 ? T(2) / T(kNOut - 1) : T(2) / T(HID - 1));
 }
 
-template <typename T, int NL, int HID, int PREC, bool GUARD>
-__device__ __forceinline__ float cppn_weight(const float* p, const T* ce, const T* re, int layer, int row, int col) {
+template <typename T, int NL, int HID, int PREC, bool GUARD, bool EXT>
+__device__ __forceinline__ float cppn_weight(const float* p, const T* ce, const T* re, int layer, int row, int col,
+                                             const ExtGenes& x) {
     const T rs = layer == 0 ? T(1) / sqrt(T(kNIn)) : T(1) / sqrt(T(HID));  // 1 / sqrt(fan-in)
     const T sc = row_scale<T>(NL, layer, row) * col_scale<T, PREC>(layer, col);
+    if constexpr (EXT)
+        return (float)(cppn_eval_x<T, GUARD>(p, ce, re, 0, x, col_x<T, NL, HID>(layer, col), layer_y<T, NL>(layer),
+                                             row_x<T, NL, HID>(layer, row), layer_y<T, NL>(layer + 1)) *
+                       rs * sc);
     return (float)(cppn_eval<T, GUARD>(p, ce, re, 0) * rs * sc);
 }
 
 // biases: the CPPN at x1 = 0, second output
-template <typename T, int NL, int HID, bool GUARD>
-__device__ __forceinline__ float cppn_bias(const float* p, const T* ce0, const T* re, int layer, int row) {
+template <typename T, int NL, int HID, bool GUARD, bool EXT>
+__device__ __forceinline__ float cppn_bias(const float* p, const T* ce0, const T* re, int layer, int row,
+                                           const ExtGenes& x) {
+    if constexpr (EXT)
+        return (float)(cppn_eval_x<T, GUARD>(p, ce0, re, 1, x, T(0), layer_y<T, NL>(layer), row_x<T, NL, HID>(layer, row),
+                                             layer_y<T, NL>(layer + 1)) *
+                       row_scale<T>(NL, layer, row));
     return (float)(cppn_eval<T, GUARD>(p, ce0, re, 1) * row_scale<T>(NL, layer, row));
 }
 
@@ -327,6 +385,8 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     // 64), row entries of the 64 rows
     __shared__ T stc[NL][65][kTab];
     __shared__ T str[NL][64][kTab];
+    __shared__ float sxw[kNExtW];  // structural genes: weights, then masks
+    __shared__ uint32_t sxm[3];
     static_assert(HID <= 64 && kNIn <= 64, "one table entry per column and row");
     const int n = from_radiation ? w->ctl->n_new : n_host;
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
@@ -355,8 +415,57 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
                     sp[m + 1] = v1;
                 }
             }
-        } else if (threadIdx.x < kNParam) {
-            sp[threadIdx.x] = w->params[(int64_t)slot * kNParam + threadIdx.x];
+            // the structural genes' weights drift with the same sigma (four
+            // normals per lane 14..24 from the Philox blocks (cell, step,
+            // 16 + lane - 14, 0)), enabled or not
+            if (threadIdx.x >= 14 && threadIdx.x < 25) {
+                const int lane = threadIdx.x - 14;
+                const int i = w->stage_slots[si];
+                uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(16 + lane), 0ull};
+                philox4x64_10(c, w->seed, 0ull);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
+                    const float rr = sqrtf(-2.0f * logf(u1));
+                    float sn, cs;
+                    sincospif(2.0f * u2, &sn, &cs);
+                    const int m = 4 * lane + 2 * h;
+                    if (m < kNExtW) sxw[m] = w->ext_w[(int64_t)parent * kNExtW + m] + sigma * (rr * cs);
+                    if (m + 1 < kNExtW) sxw[m + 1] = w->ext_w[(int64_t)parent * kNExtW + m + 1] + sigma * (rr * sn);
+                }
+            }
+            if (threadIdx.x >= 32 && threadIdx.x < 35)
+                sxm[threadIdx.x - 32] = w->ext_mask[(int64_t)parent * 4 + threadIdx.x - 32];
+            __syncthreads();
+            // NEAT's structural mutations from the block (cell, step, 15, 0):
+            // word 0 below t_conn enables the direct connection (word 2 & 0xffff)
+            // mod 10; word 1 below t_node adds the node (word 2 >> 16 & 0xffff)
+            // mod 16 with activation word 3 & 3, in weight 1 and out weight the
+            // child's B[o][j], which it replaces
+            if (threadIdx.x == 0 && (w->t_conn | w->t_node) != 0ull) {
+                const int i = w->stage_slots[si];
+                uint64_t c[4] = {(uint64_t)i, step, 15ull, 0ull};
+                philox4x64_10(c, w->seed, 0ull);
+                if (c[0] < w->t_conn) sxm[0] |= 1u << (int)((c[2] & 0xffffull) % 10ull);
+                if (c[1] < w->t_node) {
+                    const int k = (int)(((c[2] >> 16) & 0xffffull) % 16ull);
+                    if (!((sxm[1] >> k) & 1u)) {
+                        sxm[1] |= 1u << k;
+                        sxm[2] = (sxm[2] & ~(3u << (2 * k))) | ((uint32_t)(c[3] & 3ull) << (2 * k));
+                        sxw[10 + k] = 1.0f;
+                        sxw[26 + k] = sp[40 + 8 * (k & 1) + (k >> 1)];
+                    }
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x < kNExtW) w->ext_w[(int64_t)slot * kNExtW + threadIdx.x] = sxw[threadIdx.x];
+            if (threadIdx.x < 3) w->ext_mask[(int64_t)slot * 4 + threadIdx.x] = sxm[threadIdx.x];
+        } else {
+            if (threadIdx.x < kNParam) sp[threadIdx.x] = w->params[(int64_t)slot * kNParam + threadIdx.x];
+            if (threadIdx.x >= 64 && threadIdx.x < 64 + kNExtW)
+                sxw[threadIdx.x - 64] = w->ext_w[(int64_t)slot * kNExtW + threadIdx.x - 64];
+            if (threadIdx.x >= 128 && threadIdx.x < 131)
+                sxm[threadIdx.x - 128] = w->ext_mask[(int64_t)slot * 4 + threadIdx.x - 128];
         }
         __syncthreads();
         if (threadIdx.x < NL * 8) {
@@ -378,24 +487,28 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
         // block-uniform: only a genome with a part out of range takes the
         // element loop with the direct tanh fallback
         const bool guard = __syncthreads_or(out_of_range);
+        const ExtGenes xg{sxm[0], sxm[1], sxm[2], sxw};
+        const bool ext = (xg.conn | xg.node) != 0u;  // block-uniform
         uint8_t* dst = w->wfrag + (int64_t)slot * w->wfrag_stride;
         float* bdst = w->bias + (int64_t)slot * w->bias_stride;
         uint32_t bad = 0;
-        auto elements = [&](auto guard_c) {
+        auto elements = [&](auto guard_c, auto ext_c) {
             constexpr bool GUARD = decltype(guard_c)::value;
+            constexpr bool EXT = decltype(ext_c)::value;
             for (int e = threadIdx.x; e < ew + eb; e += 256) {
                 float v = 0.0f;
                 if (e < ew) {
                     const FragCoord fc = frag_coord(NL, HID, PREC, e);
                     const int lin = fc.layer == 0 ? kNIn : HID, lout = fc.layer == NL - 1 ? kNOut : HID;
                     if (fc.row < lout && fc.col < lin)
-                        v = cppn_weight<T, NL, HID, PREC, GUARD>(sp, stc[fc.layer][fc.col], str[fc.layer][fc.row],
-                                                                 fc.layer, fc.row, fc.col);
+                        v = cppn_weight<T, NL, HID, PREC, GUARD, EXT>(sp, stc[fc.layer][fc.col],
+                                                                      str[fc.layer][fc.row], fc.layer, fc.row,
+                                                                      fc.col, xg);
                 } else {
                     int layer, row;
                     bias_coord(NL, HID, e - ew, &layer, &row);
                     if (row < (layer == NL - 1 ? kNOut : HID))
-                        v = cppn_bias<T, NL, HID, GUARD>(sp, stc[layer][64], str[layer][row], layer, row);
+                        v = cppn_bias<T, NL, HID, GUARD, EXT>(sp, stc[layer][64], str[layer][row], layer, row, xg);
                 }
                 if (!__builtin_isfinite(v)) { bad = kErrNonFinite; v = 0.0f; }
                 if (e < ew) {
@@ -406,8 +519,15 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
                 }
             }
         };
-        if (guard) elements(std::integral_constant<bool, true>{});
-        else elements(std::integral_constant<bool, false>{});
+        using TrueC = std::integral_constant<bool, true>;
+        using FalseC = std::integral_constant<bool, false>;
+        if (ext) {
+            if (guard) elements(TrueC{}, TrueC{});
+            else elements(FalseC{}, TrueC{});
+        } else {
+            if (guard) elements(TrueC{}, FalseC{});
+            else elements(FalseC{}, FalseC{});
+        }
         if (bad) atomicOr(&w->ctl->err, bad);
         __syncthreads();  // sp is rewritten for the next genome
     }
@@ -464,35 +584,92 @@ __global__ __launch_bounds__(256) void k_scatter_params(const WorldDev* __restri
             w->lineage_parent2[slot] = -1;
             w->lineage_birth[slot] = w->ctl->steps;
         }
+        // and has no structural genes until coralai_set_genome_ext adds some
+        if (m < kNExtW) w->ext_w[(int64_t)slot * kNExtW + m] = 0.0f;
+        if (m < 4) w->ext_mask[(int64_t)slot * 4 + m] = 0u;
+    }
+}
+
+// coralai_set_genome_ext: n records of 46 words (4 mask words, 42 weights)
+// staged in stage_params, for the slots in stage_slots.
+__global__ __launch_bounds__(256) void k_scatter_ext(const WorldDev* __restrict__ w, int n) {
+    const uint32_t* rec = (const uint32_t*)w->stage_params;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < n * 46; e += gridDim.x * 256) {
+        const int k = e / 46, m = e - k * 46;
+        const int slot = w->stage_slots[k];
+        if (m < 4) w->ext_mask[(int64_t)slot * 4 + m] = m < 3 ? rec[e] : 0u;
+        else w->ext_w[(int64_t)slot * kNExtW + (m - 4)] = __builtin_bit_cast(float, rec[e]);
     }
 }
 
 // NEAT's compatibility distance (genetic similarity) of two genomes:
-// c1 E / N + c2 D / N + c3 W, with E / D the excess / disjoint genes and W
-// the mean weight difference of the matching genes.  Every CPPN here has the
-// same fixed topology, so all 56 genes match (E = D = 0) and the distance is
-// c3 times the mean absolute difference of the parameters.
+// c1 E / N + c2 D / N + c3 W.  Genes are numbered by innovation: the 56
+// base genes (always present), direct connection q at 56 + q, added node q's
+// in and out connections at 66 + 2q, 67 + 2q (present while enabled).
+// Matching genes are those both hold; of the others, those beyond the
+// smaller of the two highest innovation numbers are excess (E), the rest
+// disjoint (D); W is the mean absolute weight difference of the matching
+// genes and N the larger genome's gene count.  Without structural genes all
+// 56 genes match and the distance is c3 times their mean difference.
+__device__ __forceinline__ int top_gene(uint32_t conn, uint32_t node) {
+    return node ? 67 + 2 * (31 - __builtin_clz(node)) : (conn ? 56 + (31 - __builtin_clz(conn)) : 55);
+}
 __global__ __launch_bounds__(256) void k_genetic_distance(const WorldDev* __restrict__ w,
                                                           const int32_t* __restrict__ slots, int na, int nb,
-                                                          float c3, float* __restrict__ out) {
+                                                          float c1, float c2, float c3, float* __restrict__ out) {
     const int64_t total = (int64_t)na * nb;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e / nb), j = (int)(e - (int64_t)i * nb);
-        const float* pa = w->params + (int64_t)slots[i] * kNParam;
-        const float* pb = w->params + (int64_t)slots[na + j] * kNParam;
+        const int sa = slots[i], sb = slots[na + j];
+        const float* pa = w->params + (int64_t)sa * kNParam;
+        const float* pb = w->params + (int64_t)sb * kNParam;
         float acc = 0.0f;
 #pragma unroll 8
         for (int m = 0; m < kNParam; ++m) acc += fabsf(pa[m] - pb[m]);
-        out[e] = c3 * (acc * (1.0f / kNParam));
+        const uint32_t ca = w->ext_mask[(int64_t)sa * 4], cb = w->ext_mask[(int64_t)sb * 4];
+        const uint32_t da = w->ext_mask[(int64_t)sa * 4 + 1], db = w->ext_mask[(int64_t)sb * 4 + 1];
+        int match = kNParam;
+        if ((ca | cb | da | db) == 0u) {
+            out[e] = c3 * (acc * (1.0f / kNParam));
+            continue;
+        }
+        const float* xa = w->ext_w + (int64_t)sa * kNExtW;
+        const float* xb = w->ext_w + (int64_t)sb * kNExtW;
+        const int lim = min(top_gene(ca, da), top_gene(cb, db));
+        int E = 0, D = 0;
+        for (int q = 0; q < 10; ++q) {
+            const bool ha = (ca >> q) & 1u, hb = (cb >> q) & 1u;
+            if (ha && hb) { acc += fabsf(xa[q] - xb[q]); ++match; }
+            else if (ha || hb) { if (56 + q > lim) ++E; else ++D; }
+        }
+        for (int q = 0; q < 16; ++q) {
+            const bool ha = (da >> q) & 1u, hb = (db >> q) & 1u;
+            if (ha && hb) {
+                acc += fabsf(xa[10 + q] - xb[10 + q]) + fabsf(xa[26 + q] - xb[26 + q]);
+                match += 2;
+            } else if (ha || hb) {
+                E += (66 + 2 * q > lim) + (67 + 2 * q > lim);
+                D += (66 + 2 * q <= lim) + (67 + 2 * q <= lim);
+            }
+        }
+        const int na_g = kNParam + __builtin_popcount(ca) + 2 * __builtin_popcount(da);
+        const int nb_g = kNParam + __builtin_popcount(cb) + 2 * __builtin_popcount(db);
+        const float N = (float)max(na_g, nb_g);
+        out[e] = c1 * ((float)E / N) + c2 * ((float)D / N) + c3 * (acc / (float)match);
     }
 }
 
-void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na, int nb, float c3, float* out,
-                             int n_cu, hipStream_t s) {
+void launch_genetic_distance(const WorldDev* wdev, const int32_t* slots, int na, int nb, float c1, float c2,
+                             float c3, float* out, int n_cu, hipStream_t s) {
     const int64_t total = (int64_t)na * nb;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, (int64_t)n_cu * 8);
     if (blocks > 0)
-        hipLaunchKernelGGL(k_genetic_distance, dim3(blocks), dim3(256), 0, s, wdev, slots, na, nb, c3, out);
+        hipLaunchKernelGGL(k_genetic_distance, dim3(blocks), dim3(256), 0, s, wdev, slots, na, nb, c1, c2, c3, out);
+}
+
+void launch_scatter_ext(const WorldDev* wdev, int n, hipStream_t s) {
+    const int blocks = max(1, min(1024, (n * 46 + 255) / 256));
+    hipLaunchKernelGGL(k_scatter_ext, dim3(blocks), dim3(256), 0, s, wdev, n);
 }
 
 // ------------------------------------------------------------------ radiation
@@ -699,6 +876,31 @@ __global__ __launch_bounds__(256) void k_merge_commit(const WorldDev* __restrict
         const float* pb = w->params + (int64_t)b * kNParam;
         float* pc = w->params + (int64_t)slot * kNParam;
         for (int m = 0; m < kNParam; ++m) pc[m] = ((mask >> m) & 1ull) ? pb[m] : pa[m];
+        // structural genes: each direct-connection position (bit of word 1)
+        // and added-node position (bit of word 2) whole from b or from a
+        const uint32_t* ma = w->ext_mask + (int64_t)a * 4;
+        const uint32_t* mb = w->ext_mask + (int64_t)b * 4;
+        const float* xa = w->ext_w + (int64_t)a * kNExtW;
+        const float* xb = w->ext_w + (int64_t)b * kNExtW;
+        float* xc = w->ext_w + (int64_t)slot * kNExtW;
+        uint32_t conn = 0u, node = 0u, act = 0u;
+        for (int q = 0; q < 10; ++q) {
+            const bool fb = (c[1] >> q) & 1ull;
+            conn |= (fb ? mb[0] : ma[0]) & (1u << q);
+            xc[q] = fb ? xb[q] : xa[q];
+        }
+        for (int q = 0; q < 16; ++q) {
+            const bool fb = (c[2] >> q) & 1ull;
+            node |= (fb ? mb[1] : ma[1]) & (1u << q);
+            act |= (fb ? mb[2] : ma[2]) & (3u << (2 * q));
+            xc[10 + q] = fb ? xb[10 + q] : xa[10 + q];
+            xc[26 + q] = fb ? xb[26 + q] : xa[26 + q];
+        }
+        uint32_t* mc = w->ext_mask + (int64_t)slot * 4;
+        mc[0] = conn;
+        mc[1] = node;
+        mc[2] = act;
+        mc[3] = 0u;
         G[i] = slot;
         w->slot_set[slot] = 1;
         w->lineage_parent[slot] = a;

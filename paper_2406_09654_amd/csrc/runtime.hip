@@ -49,7 +49,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t EI[2], C[2], G[2], R[2];
     size_t flow, EI1, perm;
-    size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, wfrag, bias;
+    size_t counts, offsets, stripe_counts, cursor, gofs, slot_set, params, ext_w, ext_mask, wfrag, bias;
     size_t hit_bits, blk_hits, blk_ofs, free_list, new_slots, stage_slots, stage_params;
     size_t eflow;  // 0: not reserved
     size_t lineage_parent, lineage_parent2, lineage_birth;
@@ -98,6 +98,8 @@ Layout make_layout(const coralai_world_desc* d) {
     L.gofs = take(4 * (cap + 1));
     L.slot_set = take(cap);
     L.params = take(4 * kNParam * cap);
+    L.ext_w = take(4 * kNExtW * cap);
+    L.ext_mask = take(16 * cap);
     L.lineage_parent = take(4 * cap);
     L.lineage_parent2 = take(4 * cap);
     L.lineage_birth = take(8 * cap);
@@ -440,6 +442,8 @@ int coralai_world_create(const coralai_world_desc* desc, void* dev_arena, size_t
     h.gofs = (int32_t*)(b + L.gofs);
     h.slot_set = (uint8_t*)(b + L.slot_set);
     h.params = (float*)(b + L.params);
+    h.ext_w = (float*)(b + L.ext_w);
+    h.ext_mask = (uint32_t*)(b + L.ext_mask);
     h.lineage_parent = (int32_t*)(b + L.lineage_parent);
     h.lineage_parent2 = (int32_t*)(b + L.lineage_parent2);
     h.lineage_birth = (int64_t*)(b + L.lineage_birth);
@@ -584,6 +588,64 @@ int coralai_set_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids, co
     HIP_TRY(hipMemsetAsync(&w->host.ctl->n_new, 0, sizeof(int32_t), w->stream));
     HIP_TRY(hipStreamSynchronize(w->stream));
     return report_errors(w, nullptr);
+}
+
+int coralai_set_genome_ext(coralai_world* w, int32_t n, const int32_t* slot_ids, const coralai_genome_ext* ext) {
+    WORLD_GUARD(w);
+    static_assert(sizeof(coralai_genome_ext) == 46 * 4, "46-word records");
+    if (n < 0 || n > w->host.cap) return fail(CORALAI_E_INVALID, "n must be in [0, capacity]");
+    if (n == 0) return CORALAI_OK;
+    if (!slot_ids || !ext) return fail(CORALAI_E_INVALID, "slot_ids / ext is NULL");
+    for (int k = 0; k < n; ++k) {
+        if (slot_ids[k] < 0 || slot_ids[k] >= w->host.cap)
+            return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", slot_ids[k], w->host.cap);
+        if ((ext[k].conn_mask >> 10) != 0u || (ext[k].node_mask >> 16) != 0u)
+            return fail(CORALAI_E_INVALID, "conn_mask has 10 bits, node_mask 16");
+        for (int m = 0; m < 10; ++m)
+            if (!std::isfinite(ext[k].conn_w[m])) return fail(CORALAI_E_INVALID, "non-finite weight");
+        for (int m = 0; m < 16; ++m)
+            if (!std::isfinite(ext[k].node_in[m]) || !std::isfinite(ext[k].node_out[m]))
+                return fail(CORALAI_E_INVALID, "non-finite weight");
+    }
+    HIP_TRY(hipMemcpyAsync(w->host.stage_slots, slot_ids, 4 * (size_t)n, hipMemcpyHostToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->host.stage_params, ext, sizeof(coralai_genome_ext) * (size_t)n, hipMemcpyHostToDevice,
+                           w->stream));
+    launch_scatter_ext(w->wdev, n, w->stream);
+    launch_cppn(w->wdev, w->host.NL, w->host.HID, w->host.prec, 0, n, 0, 0.0f, w->ls.n_cu, w->stream);
+    int rc = check_launch();
+    if (rc) return rc;
+    HIP_TRY(hipMemsetAsync(&w->host.ctl->n_new, 0, sizeof(int32_t), w->stream));  // the staging area is reused
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return report_errors(w, nullptr);
+}
+
+int coralai_get_genome_ext(coralai_world* w, int32_t n, const int32_t* slot_ids, coralai_genome_ext* out) {
+    WORLD_GUARD(w);
+    if (n < 0 || (n > 0 && (!slot_ids || !out))) return fail(CORALAI_E_INVALID, "bad arguments");
+    for (int k = 0; k < n; ++k) {
+        if (slot_ids[k] < 0 || slot_ids[k] >= w->host.cap)
+            return fail(CORALAI_E_INVALID, "slot id %d outside [0, %d)", slot_ids[k], w->host.cap);
+        uint32_t* rec = (uint32_t*)(out + k);
+        HIP_TRY(hipMemcpyAsync(rec, w->host.ext_mask + (size_t)slot_ids[k] * 4, 16, hipMemcpyDeviceToHost, w->stream));
+        HIP_TRY(hipMemcpyAsync(rec + 4, w->host.ext_w + (size_t)slot_ids[k] * kNExtW, 4 * kNExtW,
+                               hipMemcpyDeviceToHost, w->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return CORALAI_OK;
+}
+
+int coralai_set_structural_mutation(coralai_world* w, double p_conn, double p_node) {
+    WORLD_GUARD(w);
+    if (!(p_conn >= 0.0 && p_conn <= 1.0 && p_node >= 0.0 && p_node <= 1.0))
+        return fail(CORALAI_E_INVALID, "probabilities must be in [0, 1]");
+    auto thr = [](double p) -> uint64_t {
+        if (p <= 0.0) return 0;
+        if (p >= 1.0) return UINT64_MAX;
+        return (uint64_t)std::floor(p * 18446744073709551616.0);
+    };
+    w->host.t_conn = thr(p_conn);
+    w->host.t_node = thr(p_node);
+    return write_world_tables(w);
 }
 
 int coralai_get_genomes(coralai_world* w, int32_t n, const int32_t* slot_ids, float* out) {
@@ -1258,7 +1320,7 @@ int coralai_get_births(coralai_world* w, int32_t max_births, int32_t* cells, int
 }
 
 int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_a, int32_t nb,
-                             const int32_t* slots_b, float c3, float* out_device) {
+                             const int32_t* slots_b, float c1, float c2, float c3, float* out_device) {
     WORLD_GUARD(w);
     if (na < 0 || nb < 0 || (na > 0 && !slots_a) || (nb > 0 && !slots_b)) return fail(CORALAI_E_INVALID, "bad slot lists");
     if ((int64_t)na + nb > (int64_t)(kNParam - 2) * w->host.cap)
@@ -1275,7 +1337,7 @@ int coralai_genetic_distance(coralai_world* w, int32_t na, const int32_t* slots_
     int32_t* staged = (int32_t*)w->host.stage_params + 2 * (int64_t)w->host.cap;
     HIP_TRY(hipMemcpyAsync(staged, slots_a, 4 * (size_t)na, hipMemcpyHostToDevice, w->stream));
     HIP_TRY(hipMemcpyAsync(staged + na, slots_b, 4 * (size_t)nb, hipMemcpyHostToDevice, w->stream));
-    launch_genetic_distance(w->wdev, staged, na, nb, c3, out_device, w->ls.n_cu, w->stream);
+    launch_genetic_distance(w->wdev, staged, na, nb, c1, c2, c3, out_device, w->ls.n_cu, w->stream);
     int rc = check_launch();
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(w->stream));

@@ -174,7 +174,23 @@ class World:
         B.coralai_get_births(self.h, n, cells, parents, parents2, slots)
         return cells[:n], parents[:n], parents2[:n], slots[:n]
 
-    def genetic_distance(self, slots_a, slots_b, c3: float = 1.0) -> np.ndarray:
+    def set_genome_ext(self, slots, ext) -> None:
+        """NEAT structural genes of the slots (records of B.GENOME_EXT_DTYPE)."""
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        e = np.ascontiguousarray(np.asarray(ext).astype(B.GENOME_EXT_DTYPE))
+        B.coralai_set_genome_ext(self.h, s, e)
+
+    def genome_ext(self, slots) -> np.ndarray:
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        out = np.zeros(s.size, B.GENOME_EXT_DTYPE)
+        B.coralai_get_genome_ext(self.h, s, out)
+        return out
+
+    def set_structural_mutation(self, p_conn: float, p_node: float) -> None:
+        """Probabilities of NEAT's add-connection and add-node at each radiation hit."""
+        B.coralai_set_structural_mutation(self.h, p_conn, p_node)
+
+    def genetic_distance(self, slots_a, slots_b, c3: float = 1.0, c1: float = 1.0, c2: float = 1.0) -> np.ndarray:
         """NEAT compatibility distance matrix [len(a), len(b)], computed on the GPU."""
         a = np.ascontiguousarray(slots_a, dtype=np.int32)
         b = np.ascontiguousarray(slots_b, dtype=np.int32)
@@ -182,7 +198,7 @@ class World:
         ctx = torch.cuda.stream(self.stream) if self.stream is not None else _nullctx()
         with ctx:
             torch.cuda.current_stream().synchronize()
-        B.coralai_genetic_distance(self.h, a, b, c3, out.data_ptr())
+        B.coralai_genetic_distance(self.h, a, b, c1, c2, c3, out.data_ptr())
         return out.cpu().numpy()
 
     def energy_ledger(self) -> dict:
