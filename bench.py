@@ -207,6 +207,8 @@ VARIANTS = [
     ("energy_transport", "energy transport: 1/4 of a cell's energy along the flow directions", dict(variant=(0, 0.25))),
     ("merging", "merging (NEAT crossover with the faced neighbour's genome) at 1e-4 per cell per step, after radiation",
      dict(merge=RATE)),
+    ("structural_mutation", "radiation with NEAT's add-connection and add-node, each with probability 0.5 per hit",
+     dict(structural=(0.5, 0.5))),
 ]
 
 
@@ -229,6 +231,8 @@ def run_variants(init, precision: int, steps: int, warmup: int, tuning, stream):
             w.set_daylight(*opts["daylight"])
         if "variant" in opts:
             w.set_physics_variant(*opts["variant"])
+        if "structural" in opts:
+            w.set_structural_mutation(*opts["structural"])
         k = 0
         for _ in range(warmup):
             w.step(1)

@@ -164,11 +164,13 @@ int coralai_set_genome_ext(coralai_world* w, int32_t n, const int32_t* slot_ids,
 int coralai_get_genome_ext(coralai_world* w, int32_t n, const int32_t* slot_ids, coralai_genome_ext* out);
 
 /* Structural mutation in radiation (NEAT's add-connection and add-node).
- * Every hit's child also carries its parent's structural genes, whose 42
- * weights get sigma * N(0,1) like the base genes (Box-Muller on the Philox
- * blocks (i, step_index, 16 + b, 0), b = 0..10).  Then the block
- * (i, step_index, 15, 0): word 0 below floor(p_conn 2^64) enables direct
- * connection (word 2 & 0xffff) mod 10; word 1 below floor(p_node 2^64)
+ * Every hit's child also carries its parent's structural genes; the
+ * weights of the enabled ones get sigma * N(0,1) like the base genes (weight
+ * m, in the order conn_w, node_in, node_out, from Box-Muller on the Philox
+ * block (i, step_index, 16 + m / 4, 0)), disabled ones keep theirs.  Then
+ * the block (i, step_index, 15, 0): word 0 below floor(p_conn 2^64) adds
+ * direct connection c = (word 2 & 0xffff) mod 10 with weight sigma times
+ * its normal; word 1 below floor(p_node 2^64)
  * adds node k = ((word 2 >> 16) & 0xffff) mod 16 with activation word 3 & 3,
  * in weight 1 and out weight the child's B[o][j].  Adding a gene already
  * present changes nothing.  Both 0 by default.  p in [0, 1]. */

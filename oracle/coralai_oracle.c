@@ -851,10 +851,12 @@ static double* ext_weight(orc_ext* e, int m) {
 
 /* Radiation with NEAT's structural mutations (System Design: NEAT's
  * mutation operator).  The hits, slots and base-gene mutation are those of
- * orc_radiate.  The child's 42 structural-gene weights (enabled or not) get
- * sigma * N(0,1) as well, from Philox blocks (i, s, 16 + b, 0), b = 0..10.
- * Then the block (i, s, 15, 0) decides the structural mutations: word 0
- * below Tc adds the direct connection (word 2 & 0xffff) mod 10, word 1
+ * orc_radiate.  The weights of the child's enabled structural genes get
+ * sigma * N(0,1) as well, normal m (of the 42 weights in ext_weight order)
+ * from the Philox blocks (i, s, 16 + b, 0), b = 0..10; disabled genes keep
+ * their stored weights.  Then the block (i, s, 15, 0) decides the
+ * structural mutations: word 0 below Tc adds the direct connection
+ * c = (word 2 & 0xffff) mod 10 with weight sigma times its normal; word 1
  * below Tn adds the node (word 2 >> 16 & 0xffff) mod 16 with activation
  * word 3 & 3, in weight 1 and out weight the child's B[o][j], which it
  * replaces.  Adding a gene that is already there changes nothing.  ext is
@@ -885,10 +887,20 @@ int64_t orc_radiate_x(int64_t n, int32_t* G, int32_t cap, double* params, orc_ex
             for (int m = 0; m < ORC_NPARAM; ++m) c[m] = params[(int64_t)parent * ORC_NPARAM + m] + sigma * z[m];
             orc_ext e = ext[parent];
             normals_from(seed, (uint64_t)i, s, 16, 42, zx);
-            for (int m = 0; m < 42; ++m) *ext_weight(&e, m) += sigma * zx[m];
+            for (int m = 0; m < 42; ++m) {
+                const int on = m < 10 ? (int)((e.conn_mask >> m) & 1u)
+                                      : (int)((e.node_mask >> (m < 26 ? m - 10 : m - 26)) & 1u);
+                if (on) *ext_weight(&e, m) += sigma * zx[m];
+            }
             uint64_t sc[4] = {(uint64_t)i, s, 15, 0}, so[4];
             orc_philox4x64_10(sc, key, so);
-            if (so[0] < Tc) e.conn_mask |= 1u << (int)((so[2] & 0xffff) % 10);
+            if (so[0] < Tc) {
+                const int cc = (int)((so[2] & 0xffff) % 10);
+                if (!((e.conn_mask >> cc) & 1u)) {
+                    e.conn_mask |= 1u << cc;
+                    e.conn_w[cc] = sigma * zx[cc];
+                }
+            }
             if (so[1] < Tn) {
                 const int k = (int)(((so[2] >> 16) & 0xffff) % 16);
                 if (!((e.node_mask >> k) & 1u)) {

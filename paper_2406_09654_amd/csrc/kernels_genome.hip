@@ -387,6 +387,7 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
     __shared__ T str[NL][64][kTab];
     __shared__ float sxw[kNExtW];  // structural genes: weights, then masks
     __shared__ uint32_t sxm[3];
+    __shared__ float szx[44];      // radiation: normals of the structural weights
     static_assert(HID <= 64 && kNIn <= 64, "one table entry per column and row");
     const int n = from_radiation ? w->ctl->n_new : n_host;
     const int32_t* __restrict__ slots = from_radiation ? w->new_slots : w->stage_slots;
@@ -415,49 +416,67 @@ __global__ __launch_bounds__(256) void k_cppn(const WorldDev* __restrict__ w, in
                     sp[m + 1] = v1;
                 }
             }
-            // the structural genes' weights drift with the same sigma (four
-            // normals per lane 14..24 from the Philox blocks (cell, step,
-            // 16 + lane - 14, 0)), enabled or not
-            if (threadIdx.x >= 14 && threadIdx.x < 25) {
-                const int lane = threadIdx.x - 14;
-                const int i = w->stage_slots[si];
-                uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(16 + lane), 0ull};
-                philox4x64_10(c, w->seed, 0ull);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
-                    const float rr = sqrtf(-2.0f * logf(u1));
-                    float sn, cs;
-                    sincospif(2.0f * u2, &sn, &cs);
-                    const int m = 4 * lane + 2 * h;
-                    if (m < kNExtW) sxw[m] = w->ext_w[(int64_t)parent * kNExtW + m] + sigma * (rr * cs);
-                    if (m + 1 < kNExtW) sxw[m + 1] = w->ext_w[(int64_t)parent * kNExtW + m + 1] + sigma * (rr * sn);
-                }
-            }
-            if (threadIdx.x >= 32 && threadIdx.x < 35)
-                sxm[threadIdx.x - 32] = w->ext_mask[(int64_t)parent * 4 + threadIdx.x - 32];
+            // the structural genes: the parent's; when it has any or structural
+            // mutation is on, the enabled genes' weights drift with the same
+            // sigma (normal m from the Philox blocks (cell, step, 16 + m / 4,
+            // 0), four per lane 14..24) and the block (cell, step, 15, 0)
+            // decides NEAT's structural mutations: word 0 below t_conn adds the
+            // direct connection (word 2 & 0xffff) mod 10 with weight sigma times
+            // its normal; word 1 below t_node adds the node (word 2 >> 16 &
+            // 0xffff) mod 16 with activation word 3 & 3, in weight 1 and out
+            // weight the child's B[o][j], which it replaces
+            if (threadIdx.x >= 64 && threadIdx.x < 64 + kNExtW)
+                sxw[threadIdx.x - 64] = w->ext_w[(int64_t)parent * kNExtW + threadIdx.x - 64];
+            if (threadIdx.x >= 128 && threadIdx.x < 131)
+                sxm[threadIdx.x - 128] = w->ext_mask[(int64_t)parent * 4 + threadIdx.x - 128];
             __syncthreads();
-            // NEAT's structural mutations from the block (cell, step, 15, 0):
-            // word 0 below t_conn enables the direct connection (word 2 & 0xffff)
-            // mod 10; word 1 below t_node adds the node (word 2 >> 16 & 0xffff)
-            // mod 16 with activation word 3 & 3, in weight 1 and out weight the
-            // child's B[o][j], which it replaces
-            if (threadIdx.x == 0 && (w->t_conn | w->t_node) != 0ull) {
-                const int i = w->stage_slots[si];
-                uint64_t c[4] = {(uint64_t)i, step, 15ull, 0ull};
-                philox4x64_10(c, w->seed, 0ull);
-                if (c[0] < w->t_conn) sxm[0] |= 1u << (int)((c[2] & 0xffffull) % 10ull);
-                if (c[1] < w->t_node) {
-                    const int k = (int)(((c[2] >> 16) & 0xffffull) % 16ull);
-                    if (!((sxm[1] >> k) & 1u)) {
-                        sxm[1] |= 1u << k;
-                        sxm[2] = (sxm[2] & ~(3u << (2 * k))) | ((uint32_t)(c[3] & 3ull) << (2 * k));
-                        sxw[10 + k] = 1.0f;
-                        sxw[26 + k] = sp[40 + 8 * (k & 1) + (k >> 1)];
+            const bool grow = (w->t_conn | w->t_node) != 0ull;
+            if ((sxm[0] | sxm[1]) != 0u || grow) {  // block-uniform
+                if (threadIdx.x >= 14 && threadIdx.x < 25) {
+                    const int lane = threadIdx.x - 14;
+                    const int i = w->stage_slots[si];
+                    uint64_t c[4] = {(uint64_t)i, step, (uint64_t)(16 + lane), 0ull};
+                    philox4x64_10(c, w->seed, 0ull);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const float u1 = philox_uniform(c[2 * h]), u2 = philox_uniform(c[2 * h + 1]);
+                        const float rr = sqrtf(-2.0f * logf(u1));
+                        float sn, cs;
+                        sincospif(2.0f * u2, &sn, &cs);
+                        szx[4 * lane + 2 * h] = rr * cs;
+                        szx[4 * lane + 2 * h + 1] = rr * sn;
                     }
                 }
+                __syncthreads();
+                if (threadIdx.x < kNExtW) {
+                    const int m = threadIdx.x;
+                    const uint32_t on = m < 10 ? (sxm[0] >> m) & 1u : (sxm[1] >> (m < 26 ? m - 10 : m - 26)) & 1u;
+                    if (on) sxw[m] = sxw[m] + sigma * szx[m];
+                }
+                __syncthreads();
+                if (threadIdx.x == 0 && grow) {
+                    const int i = w->stage_slots[si];
+                    uint64_t c[4] = {(uint64_t)i, step, 15ull, 0ull};
+                    philox4x64_10(c, w->seed, 0ull);
+                    if (c[0] < w->t_conn) {
+                        const int cc = (int)((c[2] & 0xffffull) % 10ull);
+                        if (!((sxm[0] >> cc) & 1u)) {
+                            sxm[0] |= 1u << cc;
+                            sxw[cc] = sigma * szx[cc];
+                        }
+                    }
+                    if (c[1] < w->t_node) {
+                        const int k = (int)(((c[2] >> 16) & 0xffffull) % 16ull);
+                        if (!((sxm[1] >> k) & 1u)) {
+                            sxm[1] |= 1u << k;
+                            sxm[2] = (sxm[2] & ~(3u << (2 * k))) | ((uint32_t)(c[3] & 3ull) << (2 * k));
+                            sxw[10 + k] = 1.0f;
+                            sxw[26 + k] = sp[40 + 8 * (k & 1) + (k >> 1)];
+                        }
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
             if (threadIdx.x < kNExtW) w->ext_w[(int64_t)slot * kNExtW + threadIdx.x] = sxw[threadIdx.x];
             if (threadIdx.x < 3) w->ext_mask[(int64_t)slot * 4 + threadIdx.x] = sxm[threadIdx.x];
         } else {

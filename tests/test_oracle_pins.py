@@ -892,9 +892,10 @@ def test_structural_cppn_against_bruteforce(oracle_lib):
 
 def test_structural_radiation_against_bruteforce(oracle_lib):
     """Radiation with structural mutation: base genes as plain radiation,
-    the 42 structural weights perturbed by Box-Muller normals of the blocks
-    (i, s, 16 + b, 0), and the add-connection / add-node decisions, positions
-    and activations from the block (i, s, 15, 0) (numpy Philox)."""
+    the enabled structural genes' weights perturbed by Box-Muller normals of
+    the blocks (i, s, 16 + b, 0) (disabled ones kept), and the
+    add-connection / add-node decisions, positions, new weights and
+    activations from the block (i, s, 15, 0) (numpy Philox)."""
     rng = np.random.default_rng(44)
     W, H, cap = 40, 30, 160
     G = rng.integers(0, 6, (H, W)).astype(np.int32)
@@ -921,12 +922,16 @@ def test_structural_radiation_against_bruteforce(oracle_lib):
                 rr = math.sqrt(-2 * math.log(u1))
                 z += [rr * math.cos(2 * math.pi * u2), rr * math.sin(2 * math.pi * u2)]
         w_par = np.concatenate([X[par]["conn_w"], X[par]["node_in"], X[par]["node_out"]])
-        w_exp = w_par + sigma * np.array(z[:42])
         cm, nm, na = int(X[par]["conn_mask"]), int(X[par]["node_mask"]), int(X[par]["node_act"])
+        on = np.array([(cm >> m) & 1 for m in range(10)] + [(nm >> q) & 1 for q in range(16)] * 2, bool)
+        w_exp = np.where(on, w_par + sigma * np.array(z[:42]), w_par)
         o = [int(v) for v in _numpy_block((int(i), s, 15, 0), (seed, 0))]
         if o[0] < Tc:
-            cm |= 1 << ((o[2] & 0xffff) % 10)
-            n_conn += 1
+            cc = (o[2] & 0xffff) % 10
+            if not (cm >> cc) & 1:
+                cm |= 1 << cc
+                w_exp[cc] = sigma * z[cc]
+                n_conn += 1
         if o[1] < Tn:
             k = ((o[2] >> 16) & 0xffff) % 16
             if not (nm >> k) & 1:
