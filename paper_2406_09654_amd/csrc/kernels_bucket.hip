@@ -118,7 +118,9 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
         for (int k = threadIdx.x; k < kHashSlots; k += 256) { s_key[k] = -1; s_cnt[k] = 0; }
         __syncthreads();
         uint32_t bad = 0;
-        // the wavefront's rows of the unit's tiles, loaded up front
+        // the wavefront's rows of the unit's tiles, loaded up front, all
+        // issued before any is used (an invalid lane reads cell 0, and the
+        // slot flags of out-of-range ids are read at slot 0)
         int gv[kBucketGroup][ROWS];
         int tx[kBucketGroup], ty[kBucketGroup];
         bool tile_ok[kBucketGroup];
@@ -133,12 +135,27 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
             for (int it = 0; it < ROWS; ++it) {
                 const int y = ty[tg] * kBucketTile + wv + 4 * it;
                 const bool valid = tile_ok[tg] && x < Wd && y < Hd;
-                int g = valid ? gld(G + (int64_t)y * Wd + x) : 0;
-                if (valid) {
-                    if (g < 0 || g >= capw) { bad |= kErrGenomeRange; g = 0; }
-                    else if (!slot_set[g]) bad |= kErrGenomeUnset;
-                }
-                gv[tg][it] = g;
+                gv[tg][it] = gld(G + (valid ? (int64_t)y * Wd + x : 0));
+            }
+        }
+#pragma unroll
+        for (int tg = 0; tg < kBucketGroup; ++tg) {
+            const int x = tx[tg] * kBucketTile + lane;
+            uint8_t set[ROWS];
+#pragma unroll
+            for (int it = 0; it < ROWS; ++it) {
+                const int g = gv[tg][it];
+                set[it] = gld(slot_set + ((g < 0 || g >= capw) ? 0 : g));
+            }
+#pragma unroll
+            for (int it = 0; it < ROWS; ++it) {
+                const int y = ty[tg] * kBucketTile + wv + 4 * it;
+                const bool valid = tile_ok[tg] && x < Wd && y < Hd;
+                const int g = gv[tg][it];
+                const bool in_range = g >= 0 && g < capw;
+                if (valid && !in_range) bad |= kErrGenomeRange;
+                if (valid && in_range && !set[it]) bad |= kErrGenomeUnset;
+                gv[tg][it] = (valid && in_range) ? g : 0;
             }
         }
         // 1. per-genome counts of the unit (LDS, global on table overflow).
@@ -232,22 +249,26 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
         const int x = tx * kBucketTile + SW * wv + col;  // this wavefront's strip
         uint32_t pk[NIT];
         {
+            // every load is issued before any is used: an invalid lane reads
+            // cell 0 (a conditional load would be a branch, and each branch a
+            // wait for the loads before it)
             int gv[NIT];
             uint32_t rv[NIT];
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int y = ty * kBucketTile + RPI * it + rsub;
                 const bool valid = tile_ok && x < Wd && y < Hd;
-                const int64_t i = (int64_t)y * Wd + x;
-                const int g = valid ? gld(G + i) : 0;
-                rv[it] = valid ? (uint32_t)(gld(Rc + i) & 7) : 0u;
-                gv[it] = (g < 0 || g >= capw) ? 0 : g;  // ids were checked when counted
+                const int64_t i = valid ? (int64_t)y * Wd + x : 0;
+                gv[it] = gld(G + i);
+                rv[it] = gld(Rc + i);
             }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int y = ty * kBucketTile + RPI * it + rsub;
                 const bool valid = tile_ok && x < Wd && y < Hd;
-                const int g = gv[it];
+                const int graw = gv[it];
+                const int g = (!valid || graw < 0 || graw >= capw) ? 0 : graw;  // ids were checked when counted
+                rv[it] = valid ? (rv[it] & 7u) : 0u;
                 const int prev = __shfl_up(g, 1, 64);
                 // runs of equal genomes inside each 16-cell row segment (valid lanes are a
                 // prefix of their segment)
