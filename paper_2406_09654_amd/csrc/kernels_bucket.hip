@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
     __shared__ int s_key[kScatterHash];
     __shared__ int s_cnt[4][kScatterHash];  // per strip: cells so far, then the strip's base
     constexpr uint32_t kAbs = 0x80000000u;  // bits 0..25 hold an absolute position
-    // packed per cell: rotation << 26 | (kAbs | position  or  slot << 12 | rank in the strip)
+    // packed per cell: kAbs | position, or slot << 12 | rank in the strip
     const int n = cld(&b->n_worlds);
     if (n <= 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -253,14 +253,11 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
             // cell 0 (a conditional load would be a branch, and each branch a
             // wait for the loads before it)
             int gv[NIT];
-            uint32_t rv[NIT];
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int y = ty * kBucketTile + RPI * it + rsub;
                 const bool valid = tile_ok && x < Wd && y < Hd;
-                const int64_t i = valid ? (int64_t)y * Wd + x : 0;
-                gv[it] = gld(G + i);
-                rv[it] = gld(Rc + i);
+                gv[it] = gld(G + (valid ? (int64_t)y * Wd + x : 0));
             }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
@@ -268,7 +265,6 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
                 const bool valid = tile_ok && x < Wd && y < Hd;
                 const int graw = gv[it];
                 const int g = (!valid || graw < 0 || graw >= capw) ? 0 : graw;  // ids were checked when counted
-                rv[it] = valid ? (rv[it] & 7u) : 0u;
                 const int prev = __shfl_up(g, 1, 64);
                 // runs of equal genomes inside each 16-cell row segment (valid lanes are a
                 // prefix of their segment)
@@ -286,10 +282,19 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
                 }
                 const uint64_t upto = starts & ((2ull << lane) - 1ull);
                 const int rs = upto ? 63 - __clzll((unsigned long long)upto) : 0;
-                pk[it] = (__shfl(mine, rs, 64) + (uint32_t)(lane - rs)) | (rv[it] << kPermRotShift);
+                pk[it] = __shfl(mine, rs, 64) + (uint32_t)(lane - rs);
             }
         }
         __syncthreads();
+        // the rotations, loaded while the global atomics below are in flight
+        // (not earlier: fewer registers live through the ranking above)
+        uint8_t rv[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int y = ty * kBucketTile + RPI * it + rsub;
+            const bool valid = tile_ok && x < Wd && y < Hd;
+            rv[it] = gld(Rc + (valid ? (int64_t)y * Wd + x : 0));
+        }
         // per genome: one global atomic; the strips' shares laid out in strip
         // order.  A thread's atomics are issued together, then their results
         // used, so their latencies overlap.
@@ -315,16 +320,26 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
             }
         }
         __syncthreads();
+        // Every load and atomic of this tile has returned by now (the bases
+        // above waited for the atomics, issued after the rotation loads).  An
+        // explicit full wait tells the compiler so: otherwise it keeps them
+        // pending along the branches above and waits for all earlier stores
+        // before each store below.
+        __builtin_amdgcn_s_waitcnt(0);
+        int pos[NIT];
+        uint32_t ent[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int y = ty * kBucketTile + RPI * it + rsub;
-            if (tile_ok && x < Wd && y < Hd) {
-                const uint32_t v = pk[it];
-                const int pos = (v & kAbs) ? (int)(v & (uint32_t)kPermIndexMask)
-                                           : s_cnt[wv][(v >> 12) & 0x3ffu] + (int)(v & 0xfffu);
-                const int64_t i = (int64_t)y * Wd + x;
-                gst(permp + pos, (int)i | (int)(v & (7u << kPermRotShift)));
-            }
+            const uint32_t v = pk[it];
+            const int base = s_cnt[wv][(v >> 12) & 0x3ffu];
+            pos[it] = (v & kAbs) ? (int)(v & (uint32_t)kPermIndexMask) : base + (int)(v & 0xfffu);
+            ent[it] = (uint32_t)(y * Wd + x) | ((uint32_t)(rv[it] & 7u) << kPermRotShift);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int y = ty * kBucketTile + RPI * it + rsub;
+            if (tile_ok && x < Wd && y < Hd) gst(permp + pos[it], (int)ent[it]);
         }
         __syncthreads();  // the table is cleared for the next tile
     }
