@@ -173,9 +173,11 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
         const int ty = (int)(lt / tx_n), tx = (int)(lt - (int64_t)ty * tx_n);
         const int x0 = tx * TW, y0 = ty * TH;
 
-        // the thread's own cells (tile cells tid + NT k): their boundary
-        // ledger pairs and rotations are loaded before the halo, so their
-        // latency overlaps the staging
+        // Every load of the tile is issued before any is used: the thread's
+        // own cells (tile cells tid + NT k; a cell outside the world reads
+        // cell 0) and its share of the halo tile, staged through registers.
+        // (Loads under a branch, or a loop that writes each load to LDS
+        // before the next, compile to a wait for every load before it.)
         int cx[CPT], cy[CPT], ct[CPT];
         bool mine[CPT];
         i64x2 ei1[CPT];
@@ -188,16 +190,16 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
             const int gx = x0 + cx[k] - 1, gy = y0 + cy[k] - 1;
             mine[k] = gx < Wd && gy < Hd;
             ct[k] = mine[k] ? gy * Wd + gx : 0;
-            ei1[k] = i64x2{0, 0};
-            r_own[k] = 0;
-            if (mine[k]) {
-                ei1[k] = gld((const i64x2*)EI1p + ct[k]);
-                r_own[k] = gld(Rc + ct[k]);
-            }
+            ei1[k] = gld((const i64x2*)EI1p + ct[k]);
+            r_own[k] = gld(Rc + ct[k]);
         }
-        // stage the halo tile
+        constexpr int HIT = (LN + NT - 1) / NT;  // halo entries per thread
         const bool small = Wd < TW + 2 || Hd < TH + 2;  // tiny worlds wrap more than once
-        for (int idx = tid; idx < LN; idx += NT) {
+        coralai_u32x4 fa[HIT], fb[HIT];
+        int32_t gh[HIT];
+#pragma unroll
+        for (int j = 0; j < HIT; ++j) {
+            const int idx = (tid + NT * j < LN) ? tid + NT * j : 0;
             const int ly = idx / LW, lx = idx - ly * LW;
             int gx = x0 + lx - 1, gy = y0 + ly - 1;
             if (small) {
@@ -208,22 +210,38 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
                 gy = gy < 0 ? gy + Hd : (gy >= Hd ? gy - Hd : gy);
             }
             const int n = gy * Wd + gx;
-            const coralai_u32x4 fa = gld((const coralai_u32x4*)(flow + 8 * (int64_t)n));
-            const coralai_u32x4 fb = gld((const coralai_u32x4*)(flow + 8 * (int64_t)n) + 1);
+            fa[j] = gld((const coralai_u32x4*)(flow + 8 * (int64_t)n));
+            fb[j] = gld((const coralai_u32x4*)(flow + 8 * (int64_t)n) + 1);
+            gh[j] = gld(Gc + n);
+        }
+        // Everything issued so far is needed now (own cells and halo; the
+        // previous tile's stores went out before them).  A full wait here
+        // costs nothing and tells the compiler so: otherwise the halo loads
+        // whose LDS write a thread skips stay pending in its bookkeeping, and
+        // the first reuse of their registers waits for every store after them.
+        __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                s_flow[k][idx] = fa[k];
-                s_flow[4 + k][idx] = fb[k];
+        for (int j = 0; j < HIT; ++j) {
+            const int idx = tid + NT * j;
+            if (idx < LN) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    s_flow[k][idx] = fa[j][k];
+                    s_flow[4 + k][idx] = fb[j][k];
+                }
+                s_g[idx] = gh[j];
             }
-            s_g[idx] = gld(Gc + n);
         }
         __syncthreads();
 
+        bool took[CPT];
+        int32_t g_from[CPT], g_to[CPT];
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int lx = cx[k], ly = cy[k];
-            bool took = false;
-            int32_t g_from = 0, g_to = 0;
+            took[k] = false;
+            g_from[k] = 0;
+            g_to[k] = 0;
             if (mine[k]) {
                 const int t = ct[k];
                 const int own = ly * LW + lx;
@@ -247,12 +265,12 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
                 uint8_t r2 = r_own[k];
                 if (win >= 0 && vbest > i1) {
                     const int so = cell_stripe(x0 + lx - 1, y0 + ly - 1, btx) * capw;
-                    g_from = so + g2;
+                    g_from[k] = so + g2;
                     g2 = s_g[(ly + dir_dy(win)) * LW + (lx + dir_dx(win))];
                     r2 = (uint8_t)((win + 4) & 7);
                     acc_t += 1;
-                    took = true;
-                    g_to = so + g2;
+                    took[k] = true;
+                    g_to[k] = so + g2;
                 }
                 const int64_t em = eflow ? e1 + energy_moved(eflow, x0 + lx - 1, y0 + ly - 1, Wd, Hd) : e1;
                 const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
@@ -263,9 +281,16 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
                 acc_m += i2 + (e2 - e1);
                 acc_f += (double)(i2 + (e2 - e1));
             }
-            // the genome counts follow the takeovers (the next step and radiation use them)
-            wave_count_add(cnt, g_from, -1, took);
-            wave_count_add(cnt, g_to, 1, took);
+        }
+        // the genome counts follow the takeovers (the next step and radiation
+        // use them); after all the tile's stores, and skipped by a wavefront
+        // with no takeover (the common case)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            if (__ballot(took[k])) {
+                wave_count_add(cnt, g_from[k], -1, took[k]);
+                wave_count_add(cnt, g_to[k], 1, took[k]);
+            }
         }
         __syncthreads();  // LDS reused by the next tile
     }
