@@ -417,9 +417,11 @@ struct LaunchShape {
     // 0 = automatic (4 for BF16 networks on large jobs, else 1); k >= 1
     // forces k (a test hook: results do not depend on it)
     int act_segments;
-    // 1: some world of the launch uses a physics variant (hard-max
+    // bit 0: some world of the launch uses a physics variant (hard-max
     // exploration or energy transport), so the network kernel compiled with
-    // the variants' code runs; 0: the kernel without it
+    // the variants' code runs (else the kernel without it); bit 1: some world
+    // uses energy transport, so the physics kernel that loads the energy
+    // records with the rest of the tile runs
     int act_variants;
 };
 

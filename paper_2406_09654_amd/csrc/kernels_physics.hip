@@ -77,7 +77,11 @@ __device__ __forceinline__ void day_night_flush(Ctl* ctl, int64_t inj, int64_t r
     }
 }
 
-template <int TW, int TH>
+// ENERGY: the instantiation launched while energy transport is on in some
+// world of the launch; it loads the energy records with the tile's other
+// loads.  The other one reads them per cell (correct, slower) if it meets a
+// world with energy transport on.
+template <int TW, int TH, bool ENERGY>
 __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b) {
     constexpr int NT = 256, CPT = TW * TH / NT;  // threads, cells per thread
     static_assert(TW * TH % NT == 0, "a tile is a whole number of cells per thread");
@@ -193,6 +197,30 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
             ei1[k] = gld((const i64x2*)EI1p + ct[k]);
             r_own[k] = gld(Rc + ct[k]);
         }
+        // energy transport: each own cell's record and the word its 8
+        // neighbours send toward it
+        int64_t emoved[CPT];
+        coralai_u32x4 ea[CPT], ec[CPT];
+        uint32_t en[CPT][8];
+        if constexpr (ENERGY) {
+            if (eflow) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    const int x = (x0 + cx[k] - 1 < Wd) ? x0 + cx[k] - 1 : 0;
+                    const int y = (y0 + cy[k] - 1 < Hd) ? y0 + cy[k] - 1 : 0;
+                    const int64_t t = (int64_t)y * Wd + x;
+                    ea[k] = gld((const coralai_u32x4*)(eflow + 8 * t));
+                    ec[k] = gld((const coralai_u32x4*)(eflow + 8 * t) + 1);
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        int nx = x + dir_dx(d), ny = y + dir_dy(d);
+                        nx = nx < 0 ? nx + Wd : (nx >= Wd ? nx - Wd : nx);
+                        ny = ny < 0 ? ny + Hd : (ny >= Hd ? ny - Hd : ny);
+                        en[k][d] = gld(eflow + 8 * ((int64_t)ny * Wd + nx) + ((d + 4) & 7));
+                    }
+                }
+            }
+        }
         constexpr int HIT = (LN + NT - 1) / NT;  // halo entries per thread
         const bool small = Wd < TW + 2 || Hd < TH + 2;  // tiny worlds wrap more than once
         coralai_u32x4 fa[HIT], fb[HIT];
@@ -220,6 +248,19 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
         // whose LDS write a thread skips stay pending in its bookkeeping, and
         // the first reuse of their registers waits for every store after them.
         __builtin_amdgcn_s_waitcnt(0);
+        if constexpr (ENERGY) {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                int64_t net = 0;
+                if (eflow) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) net -= (int64_t)(ea[k][q] >> 1) + (int64_t)(ec[k][q] >> 1);
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) net += (int64_t)(en[k][d] >> 1);
+                }
+                emoved[k] = net;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < HIT; ++j) {
             const int idx = tid + NT * j;
@@ -272,7 +313,9 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
                     took[k] = true;
                     g_to[k] = so + g2;
                 }
-                const int64_t em = eflow ? e1 + energy_moved(eflow, x0 + lx - 1, y0 + ly - 1, Wd, Hd) : e1;
+                int64_t em = e1;
+                if constexpr (ENERGY) em += emoved[k];
+                else if (eflow) em += energy_moved(eflow, x0 + lx - 1, y0 + ly - 1, Wd, Hd);
                 const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
                 gst((i64x2*)EIn + t, i64x2{e2, i2});
                 gst(Gn + t, g2);
@@ -528,11 +571,21 @@ int phys_tile_h(int t) { return t == 1 ? 8 : (t == 2 ? 8 : 4); }
 
 void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
                          hipStream_t s) {
+    const bool e = (ls.act_variants & 2) != 0;  // energy transport on in some world
     switch (phys_tile) {
         case 3: hipLaunchKernelGGL(k_physics_stream, dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
-        case 1: hipLaunchKernelGGL((k_physics<32, 8>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
-        case 2: hipLaunchKernelGGL((k_physics<64, 8>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
-        default: hipLaunchKernelGGL((k_physics<64, 4>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev); break;
+        case 1:
+            if (e) hipLaunchKernelGGL((k_physics<32, 8, true>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            else hipLaunchKernelGGL((k_physics<32, 8, false>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            break;
+        case 2:
+            if (e) hipLaunchKernelGGL((k_physics<64, 8, true>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            else hipLaunchKernelGGL((k_physics<64, 8, false>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            break;
+        default:
+            if (e) hipLaunchKernelGGL((k_physics<64, 4, true>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            else hipLaunchKernelGGL((k_physics<64, 4, false>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            break;
     }
 }
 

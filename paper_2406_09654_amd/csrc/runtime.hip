@@ -1263,8 +1263,9 @@ int coralai_set_physics_variant(coralai_world* w, int32_t explore_mode, float ka
     (void)hipStreamSynchronize(w->stream);
     w->host.explore_mode = explore_mode;
     w->host.kappa_e = kappa_energy;
-    // the network kernel with the variants' code runs only while one is on
-    w->ls.act_variants = (explore_mode != 0 || kappa_energy > 0.0f) ? 1 : 0;
+    // the network kernel with the variants' code runs only while one is on,
+    // the physics kernel that loads the energy records only with transport
+    w->ls.act_variants = ((explore_mode != 0 || kappa_energy > 0.0f) ? 1 : 0) | (kappa_energy > 0.0f ? 2 : 0);
     return write_world_tables(w);
 }
 
