@@ -299,15 +299,15 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
         // order.  A thread's atomics are issued together, then their results
         // used, so their latencies overlap.
         {
+            // (the strips' counts are read again from LDS once the bases are
+            // back rather than held in registers meanwhile)
             constexpr int KP = kScatterHash / 256;
-            int gk[KP], base[KP], c[KP][4];
+            int gk[KP], base[KP];
 #pragma unroll
             for (int j = 0; j < KP; ++j) {
                 const int k = threadIdx.x + 256 * j;
                 gk[j] = s_key[k];
-                int tot = 0;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) { c[j][t] = s_cnt[t][k]; tot += c[j][t]; }
+                const int tot = s_cnt[0][k] + s_cnt[1][k] + s_cnt[2][k] + s_cnt[3][k];
                 base[j] = gk[j] >= 0 ? atomicAdd(scur + gk[j], tot) : 0;
             }
 #pragma unroll
@@ -316,7 +316,11 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
                 const int k = threadIdx.x + 256 * j;
                 int bj = base[j];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) { s_cnt[t][k] = bj; bj += c[j][t]; }
+                for (int t = 0; t < 4; ++t) {
+                    const int c = s_cnt[t][k];
+                    s_cnt[t][k] = bj;
+                    bj += c;
+                }
             }
         }
         __syncthreads();
