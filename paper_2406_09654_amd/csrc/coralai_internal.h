@@ -344,15 +344,20 @@ typedef long long i64x2 __attribute__((__vector_size__(16)));
 __device__ __forceinline__ i64x2 buf_ld_i64x2(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(i64x2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
+// Cache-policy operand of buffer memory instructions: the non-temporal
+// (streaming) hint, for data this kernel writes and does not read again.
+constexpr int kCpolNT = 2;
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_st_i64x2(i64x2 v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(coralai_u32x4, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(coralai_u32x4, v), r, off, 0, CPOL);
 }
 typedef float coralai_f32x4 __attribute__((__vector_size__(16)));
 __device__ __forceinline__ coralai_f32x4 buf_ld_f32x4(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(coralai_f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_st_f32x4(coralai_f32x4 v, __amdgpu_buffer_rsrc_t r, int off) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(coralai_u32x4, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(coralai_u32x4, v), r, off, 0, CPOL);
 }
 
 // int64 -> float with at most one extra rounding for values >= 2^32 (exact

@@ -246,12 +246,13 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
     // every lane of every unit, so the wait counts around them are exact.
     auto store_results = [&]() {
         const uint32_t ofs = st_i >= 0 ? 4u * (uint32_t)st_i : 4u * (uint32_t)Nd;
-        buf_st_f32x4(coralai_f32x4{__builtin_bit_cast(float, st_c[0]), __builtin_bit_cast(float, st_c[1]),
+        // the results are read by the physics kernel, not here: streaming stores
+        buf_st_f32x4<kCpolNT>(coralai_f32x4{__builtin_bit_cast(float, st_c[0]), __builtin_bit_cast(float, st_c[1]),
                                    __builtin_bit_cast(float, st_c[2]), __builtin_bit_cast(float, st_c[3])},
                      wC, 4 * ofs);
-        __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[0], st_f[1], st_f[2], st_f[3]}, wFlow, 8 * ofs, 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[4], st_f[5], st_f[6], st_f[7]}, wFlow, 8 * ofs + 16, 0, 0);
-        buf_st_i64x2(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
+        __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[0], st_f[1], st_f[2], st_f[3]}, wFlow, 8 * ofs, 0, kCpolNT);
+        __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_f[4], st_f[5], st_f[6], st_f[7]}, wFlow, 8 * ofs + 16, 0, kCpolNT);
+        buf_st_i64x2<kCpolNT>(i64x2{st_E1, st_I1}, wEI1, 4 * ofs);
         if (VARIANTS && (variant & 2)) {  // world-uniform: energy transport records
             const __amdgpu_buffer_rsrc_t wEflow = buf_rsrc(world_at(b, wi)->eflow, 32u * (uint32_t)Nd);
             __builtin_amdgcn_raw_buffer_store_b128(coralai_u32x4{st_e[0], st_e[1], st_e[2], st_e[3]}, wEflow, 8 * ofs, 0, 0);
@@ -387,23 +388,24 @@ __global__ __launch_bounds__(256, WAVES) void k_act(
         // covers them all and they complete in order, so each wait below
         // leaves what was issued after its operand in flight.
         if (new_run) {
-            // weights of genome g -> registers
+            // weights of genome g -> registers, with the non-temporal hint (each
+            // run reads them once; the gather's lines are the ones worth keeping)
             const uint8_t* wb = wfrag + (int64_t)g * wstride + lane * (NT::FRAG_BYTES / 64);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int s = 0; s < KS0; ++s)
-                    w0[mt][s] = gld((const frag_t*)(wb + (mt * KS0 + s) * NT::FRAG_BYTES));
+                    w0[mt][s] = __builtin_nontemporal_load((const frag_t*)(wb + (mt * KS0 + s) * NT::FRAG_BYTES));
             if constexpr (NL == 3) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                     for (int s = 0; s < KSH; ++s)
-                        w1[mt][s] = gld((const frag_t*)(wb + (NT::F0 + mt * KSH + s) * NT::FRAG_BYTES));
+                        w1[mt][s] = __builtin_nontemporal_load((const frag_t*)(wb + (NT::F0 + mt * KSH + s) * NT::FRAG_BYTES));
             }
 #pragma unroll
             for (int s = 0; s < KSH; ++s)
-                wo[s] = gld((const frag_t*)(wb + (NT::F0 + NT::F1 + s) * NT::FRAG_BYTES));
+                wo[s] = __builtin_nontemporal_load((const frag_t*)(wb + (NT::F0 + NT::F1 + s) * NT::FRAG_BYTES));
             static_assert(net_bias_floats(NL, HID) / 4 <= 64, "one bias load per lane");
             if (lane < net_bias_floats(NL, HID) / 4)
                 bias_ld = gld((const floatx4*)(bias + (int64_t)g * bstride + 4 * lane));

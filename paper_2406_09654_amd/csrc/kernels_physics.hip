@@ -317,9 +317,11 @@ __global__ __launch_bounds__(256) void k_physics(const BatchDev* __restrict__ b)
                 if constexpr (ENERGY) em += emoved[k];
                 else if (eflow) em += energy_moved(eflow, x0 + lx - 1, y0 + ly - 1, Wd, Hd);
                 const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
-                gst((i64x2*)EIn + t, i64x2{e2, i2});
-                gst(Gn + t, g2);
-                gst(Rn + t, r2);
+                // the next state, read by the next step's kernels and not
+                // here: stores with the non-temporal hint
+                __builtin_nontemporal_store(i64x2{e2, i2}, (i64x2*)EIn + t);
+                __builtin_nontemporal_store(g2, Gn + t);
+                __builtin_nontemporal_store(r2, Rn + t);
                 // the network kernel added E1; the energy moved, the cycle's change and I2 complete the sum
                 acc_m += i2 + (e2 - e1);
                 acc_f += (double)(i2 + (e2 - e1));
@@ -499,12 +501,12 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
                     }
                     const int64_t em = eflow ? e1 + energy_moved(eflow, x0 + j, y, Wd, Hd) : e1;
                     const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
-                    gst((i64x2*)EIn + t0 + j, i64x2{e2, i2});
+                    __builtin_nontemporal_store(i64x2{e2, i2}, (i64x2*)EIn + t0 + j);
                     acc_m += i2 + (e2 - e1);
                     acc_f += (double)(i2 + (e2 - e1));
                 }
-                gst((coralai_u32x4*)Gn + t0 / 4, gs);
-                gst((uint32_t*)Rn + t0 / 4, rs);
+                __builtin_nontemporal_store(gs, (coralai_u32x4*)Gn + t0 / 4);
+                __builtin_nontemporal_store(rs, (uint32_t*)Rn + t0 / 4);
             }
             // the genome counts follow the takeovers (the next step and radiation use them)
 #pragma unroll
@@ -553,9 +555,9 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
             }
             const int64_t em = eflow ? e1 + energy_moved(eflow, x, y, Wd, Hd) : e1;
             const int64_t e2 = day_night_energy(em, dn, acc_inj, acc_rem, err);
-            gst((i64x2*)EIn + t, i64x2{e2, i2});
-            gst(Gn + t, g2);
-            gst(Rn + t, r2);
+            __builtin_nontemporal_store(i64x2{e2, i2}, (i64x2*)EIn + t);
+            __builtin_nontemporal_store(g2, Gn + t);
+            __builtin_nontemporal_store(r2, Rn + t);
             acc_m += i2 + (e2 - e1);
             acc_f += (double)(i2 + (e2 - e1));
         }
