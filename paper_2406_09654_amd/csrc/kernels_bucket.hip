@@ -376,8 +376,8 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict_
             if (g < w.cap) {
                 int v = 0;
 #pragma unroll
-                for (int q = 0; q < kStripes; ++q) v += w.stripe_counts[q * w.cap + g];
-                w.counts[g] = v;
+                for (int q = 0; q < kStripes; ++q) v += gld(w.stripe_counts + q * w.cap + g);
+                gst(w.counts + g, v);
                 c += v;
                 gsum += (v + kGroupCells - 1) / kGroupCells;
                 live += v > 0;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict_
         __syncthreads();
         if (threadIdx.x < 4) {
             const int f = threadIdx.x;
-            w.scan_part[sb * 4 + f] = s_red[0][f] + s_red[1][f] + s_red[2][f] + s_red[3][f];
+            gst(w.scan_part + sb * 4 + f, s_red[0][f] + s_red[1][f] + s_red[2][f] + s_red[3][f]);
         }
         __syncthreads();
     }
@@ -416,11 +416,11 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict
     int tot[4];
     for (int f = 0; f < 4; ++f) {
         int sum = 0;
-        for (int k = b0; k < b1; ++k) sum += w.scan_part[k * 4 + f];
+        for (int k = b0; k < b1; ++k) sum += gld(w.scan_part + k * 4 + f);
         int run = block_exclusive_scan<1024>(sum, &tot[f], s_tmp);
         for (int k = b0; k < b1; ++k) {
-            const int v = w.scan_part[k * 4 + f];
-            w.scan_part[k * 4 + f] = run;
+            const int v = gld(w.scan_part + k * 4 + f);
+            gst(w.scan_part + k * 4 + f, run);
             run += v;
         }
     }
@@ -458,32 +458,32 @@ __global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__
         int sc = 0, sg = 0, sf = 0;
         for (int k = 0; k < PER; ++k) {
             const int g = g0 + k;
-            const int v = g < w.cap ? w.counts[g] : 0;
+            const int v = g < w.cap ? gld(w.counts + g) : 0;
             sc += v;
             sg += (v + kGroupCells - 1) / kGroupCells;
             sf += g < w.cap && v == 0;
         }
         int tc, tg, tf;
-        int oc = w.scan_part[sb * 4 + 0] + block_exclusive_scan<256>(sc, &tc, s_tmp);
-        int og = w.scan_part[sb * 4 + 1] + block_exclusive_scan<256>(sg, &tg, s_tmp);
-        int of = w.scan_part[sb * 4 + 3] + block_exclusive_scan<256>(sf, &tf, s_tmp);
+        int oc = gld(w.scan_part + sb * 4 + 0) + block_exclusive_scan<256>(sc, &tc, s_tmp);
+        int og = gld(w.scan_part + sb * 4 + 1) + block_exclusive_scan<256>(sg, &tg, s_tmp);
+        int of = gld(w.scan_part + sb * 4 + 3) + block_exclusive_scan<256>(sf, &tf, s_tmp);
         for (int k = 0; k < PER; ++k) {
             const int g = g0 + k;
             if (g >= w.cap) break;
-            const int v = w.counts[g];
+            const int v = gld(w.counts + g);
             if (free_only) {
-                if (v == 0) w.free_list[of++] = g;
+                if (v == 0) gst(w.free_list + of++, g);
                 continue;
             }
-            w.offsets[g] = oc;
+            gst(w.offsets + g, oc);
             int pos = oc;
 #pragma unroll
             for (int q = 0; q < kStripes; ++q) {
-                w.cursor[q * w.cap + g] = pos;
-                pos += w.stripe_counts[q * w.cap + g];
+                gst(w.cursor + q * w.cap + g, pos);
+                pos += gld(w.stripe_counts + q * w.cap + g);
             }
-            w.gofs[g] = og;
-            if (v == 0) w.free_list[of++] = g;
+            gst(w.gofs + g, og);
+            if (v == 0) gst(w.free_list + of++, g);
             oc += v;
             og += (v + kGroupCells - 1) / kGroupCells;
         }
