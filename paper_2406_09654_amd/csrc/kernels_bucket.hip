@@ -202,14 +202,17 @@ __global__ __launch_bounds__(256) void k_count(const BatchDev* __restrict__ b) {
 // whose neighbourhoods overlap.  Each run of equal genomes in a 16-cell row
 // segment takes its rank inside the strip's share of its genome with one LDS
 // atomic on the wavefront's own counter (after a hash insert); every cell
-// keeps (slot, rank, rotation) in a register.  Then per genome: the strips'
-// shares are laid out one after another behind one global atomic on the
-// unit's stripe cursor, and the cells are written with no second lookup.  A
-// genome that finds the table full takes its run's positions straight from
-// the cursor.  Perm entries carry the cell's rotation in the high bits.
-// (Sixteen dependent steps per wavefront and a small register and LDS
-// footprint keep many tiles in flight.)
-constexpr int kScatterHashLog = 10;
+// keeps (slot, rank) in a register.  Then per genome: the strips' shares are
+// laid out one after another behind one global atomic on the unit's stripe
+// cursor, and the cells are written with no second lookup.  A genome that
+// finds the table full takes its run's positions straight from the cursor.
+// Perm entries carry the cell's rotation in the high bits.  (Sixteen
+// dependent steps per wavefront and a small register and LDS footprint keep
+// many tiles in flight.)
+// 256 slots: a tile holds a few dozen genomes (up to about a hundred late in
+// a long run); a larger table costs its clearing and its scan in every tile
+// (1024 slots: +17 us per 4096^2 step)
+constexpr int kScatterHashLog = 8;
 constexpr int kScatterHash = 1 << kScatterHashLog;
 static_assert(kBucketTile == 64, "four 16-column strips per tile");
 __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b) {
@@ -301,13 +304,13 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchDev* __restrict__ b)
         {
             // (the strips' counts are read again from LDS once the bases are
             // back rather than held in registers meanwhile)
-            constexpr int KP = kScatterHash / 256;
+            constexpr int KP = (kScatterHash + 255) / 256;
             int gk[KP], base[KP];
 #pragma unroll
             for (int j = 0; j < KP; ++j) {
                 const int k = threadIdx.x + 256 * j;
-                gk[j] = s_key[k];
-                const int tot = s_cnt[0][k] + s_cnt[1][k] + s_cnt[2][k] + s_cnt[3][k];
+                gk[j] = k < kScatterHash ? s_key[k] : -1;
+                const int tot = gk[j] >= 0 ? s_cnt[0][k] + s_cnt[1][k] + s_cnt[2][k] + s_cnt[3][k] : 0;
                 base[j] = gk[j] >= 0 ? atomicAdd(scur + gk[j], tot) : 0;
             }
 #pragma unroll

@@ -122,7 +122,10 @@ def test_debug_weights_roundtrip(stream, prec):
 
 
 @pytest.mark.parametrize("W,H,ng,cap", [(1, 1, 1, 1), (37, 23, 5, 9), (64, 64, 16, 16),
-                                        (300, 200, 70, 128)])
+                                        (300, 200, 70, 128),
+                                        # ~1 750 genomes per 64 x 64 tile: the scatter's
+                                        # table fills and most runs take the cursor path
+                                        (256, 130, 2000, 2048)])
 def test_buckets_match_numpy(stream, W, H, ng, cap):
     say("buckets", W, H)
     init = gh.heterogeneous_world(W, H, n_genomes=ng, capacity=cap, seed=W)
