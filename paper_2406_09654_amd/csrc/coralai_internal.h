@@ -21,6 +21,7 @@ constexpr int kBucketTile = 64;   // bucketing tile: 64 x 64 cells
 constexpr int kBucketGroup = 4;   // tiles per bucketing unit (one block)
 constexpr int kStripes = 8;       // genome counts and cursors split by bucketing unit (unit mod 8)
 constexpr int kSlotBlock = 512;   // genome slots per scan block (<= 8192 blocks at 2^22 slots)
+constexpr int kFuseSlotBlocks = 1024;  // up to this many slot blocks the scan takes two passes, not three
 constexpr int kRadBlockCells = 4096;  // cells per radiation hit block (256 x 16)
 constexpr int kPrecFP32 = 0;
 constexpr int kPrecBF16 = 1;
@@ -428,6 +429,10 @@ struct LaunchShape {
     // uses energy transport, so the physics kernel that loads the energy
     // records with the rest of the tile runs
     int act_variants;
+    // 1: every world of the launch has at most kFuseSlotBlocks slot blocks,
+    // so the scan's write pass forms the prefix of the slot blocks' partials
+    // itself (no separate pass over them)
+    int scan_fused;
 };
 
 // Launchers implemented in the kernel translation units.

@@ -441,19 +441,65 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict
     }
 }
 
-// Pass C: per 4096-slot block, the exclusive scans themselves (256 slots per
-// round, block-wide scan, running carry), the partial ranges of each genome
-// laid out one after another, plus the free-slot list.
+// Pass C: per slot block, the exclusive scans themselves (block-wide scan
+// of each thread's serial sums), the partial ranges of each genome laid out
+// one after another, plus the free-slot list.
 // free_only: just the free-slot list (radiation), not the step's ranges.
+// FUSED (every world has at most kFuseSlotBlocks slot blocks): pass B is not
+// run; each block sums the raw partials of the world's earlier blocks itself,
+// and the world's last block publishes the totals.
+template <bool FUSED>
 __global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__ b, int free_only) {
     __shared__ int s_tmp[4];
+    __shared__ int s_red[4][4];
     const int n = cld(&b->n_worlds);
     if (n <= 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t total = cld(b->slot_prefix + (n));
     for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
         const int wi = find_world(b->slot_prefix, n, u);
         const auto& w = *world_at(b, wi);
         const int sb = (int)(u - cld(b->slot_prefix + (wi)));
+        // the exclusive prefix of the block partials (cells, units, live, free)
+        int pre[4];
+        if constexpr (FUSED) {
+            int p[4] = {0, 0, 0, 0};
+            for (int k = threadIdx.x; k < sb; k += 256) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) p[f] += gld(w.scan_part + k * 4 + f);
+            }
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) p[f] += __shfl_xor(p[f], o, 64);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) s_red[wv][f] = p[f];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int f = 0; f < 4; ++f) pre[f] = s_red[0][f] + s_red[1][f] + s_red[2][f] + s_red[3][f];
+            __syncthreads();
+            if (sb == w.n_slot_blocks - 1 && threadIdx.x == 0) {  // the world's totals
+                int tot[4];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) tot[f] = pre[f] + gld(w.scan_part + sb * 4 + f);
+                w.ctl->counts_valid = 1;
+                w.offsets[w.cap] = tot[0];
+                w.gofs[w.cap] = tot[1];
+                w.ctl->total_groups = tot[1];
+                w.ctl->live = tot[2];
+                w.ctl->n_free = tot[3];
+                if (n == 1) {  // the prefix over worlds (k_world_prefix) of a lone world
+                    b->group_prefix[0] = 0;
+                    b->group_prefix[1] = tot[1];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) pre[f] = gld(w.scan_part + sb * 4 + f);
+        }
         // each thread owns kSlotBlock / 256 consecutive slots: serial sums,
         // one block-wide scan per quantity, then serial writes
         constexpr int PER = kSlotBlock / 256;
@@ -467,9 +513,9 @@ __global__ __launch_bounds__(256) void k_scan_write(const BatchDev* __restrict__
             sf += g < w.cap && v == 0;
         }
         int tc, tg, tf;
-        int oc = gld(w.scan_part + sb * 4 + 0) + block_exclusive_scan<256>(sc, &tc, s_tmp);
-        int og = gld(w.scan_part + sb * 4 + 1) + block_exclusive_scan<256>(sg, &tg, s_tmp);
-        int of = gld(w.scan_part + sb * 4 + 3) + block_exclusive_scan<256>(sf, &tf, s_tmp);
+        int oc = pre[0] + block_exclusive_scan<256>(sc, &tc, s_tmp);
+        int og = pre[1] + block_exclusive_scan<256>(sg, &tg, s_tmp);
+        int of = pre[3] + block_exclusive_scan<256>(sf, &tf, s_tmp);
         for (int k = 0; k < PER; ++k) {
             const int g = g0 + k;
             if (g >= w.cap) break;
@@ -539,8 +585,12 @@ __global__ void k_flip(const BatchDev* __restrict__ b) {
 
 static void launch_scan(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(ls.misc_blocks), dim3(256), 0, s, bdev);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1, ls.max_worlds), dim3(1024), 0, s, bdev);
-    hipLaunchKernelGGL(k_scan_write, dim3(ls.misc_blocks), dim3(256), 0, s, bdev, free_only);
+    if (ls.scan_fused) {
+        hipLaunchKernelGGL(k_scan_write<true>, dim3(ls.misc_blocks), dim3(256), 0, s, bdev, free_only);
+    } else {
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1, ls.max_worlds), dim3(1024), 0, s, bdev);
+        hipLaunchKernelGGL(k_scan_write<false>, dim3(ls.misc_blocks), dim3(256), 0, s, bdev, free_only);
+    }
 }
 
 void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int free_only, int recount) {
@@ -554,7 +604,7 @@ void launch_hist_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s
 
 void launch_bucket_only(const BatchDev* bdev, const LaunchShape& ls, hipStream_t s, int recount) {
     launch_hist_only(bdev, ls, s, 0, recount);
-    // a single world's prefix is written by k_scan_blocks
+    // a single world's prefix is written by the scan
     if (ls.max_worlds > 1) hipLaunchKernelGGL(k_world_prefix, dim3(1), dim3(1024), 0, s, bdev);
     hipLaunchKernelGGL(k_scatter, dim3(ls.n_cu * 16), dim3(256), 0, s, bdev);
 }

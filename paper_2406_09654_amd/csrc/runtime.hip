@@ -147,6 +147,7 @@ LaunchShape make_shape(int max_worlds, int max_cap) {
     ls.misc_blocks = ls.n_cu;
     ls.max_worlds = max_worlds;
     ls.max_cap = max_cap;
+    ls.scan_fused = (max_cap + kSlotBlock - 1) / kSlotBlock <= kFuseSlotBlocks ? 1 : 0;
     return ls;
 }
 
@@ -364,8 +365,8 @@ void destroy_graph(hipGraphExec_t* g) {
 }
 
 // Capture the step sequence once; every size it needs is read on the device.
-int tuning_key(int act_cells, int act_waves, int phys_tile, int act_variants) {
-    return act_variants * 1000 + act_cells * 100 + act_waves * 10 + phys_tile;
+int tuning_key(int act_cells, int act_waves, int phys_tile, const LaunchShape& ls) {
+    return (ls.scan_fused ? 0 : 10000) + ls.act_variants * 1000 + act_cells * 100 + act_waves * 10 + phys_tile;
 }
 
 int capture_step(hipStream_t s, const BatchDev* bdev, const LaunchShape& ls, int NL, int HID,
@@ -665,7 +666,7 @@ int coralai_step(coralai_world* w, int32_t n_steps, coralai_stats* out) {
     WORLD_GUARD(w);
     if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
     const bool use_graph = w->stream != nullptr && !w->profiling;
-    const int key = tuning_key(w->act_cells, w->act_waves, w->phys_tile, w->ls.act_variants);
+    const int key = tuning_key(w->act_cells, w->act_waves, w->phys_tile, w->ls);
     const bool stale = w->counts_stale && n_steps > 0;  // the first step recounts
     if (use_graph && (w->graph == nullptr || w->graph_key != key)) {
         destroy_graph(&w->graph);
@@ -1007,11 +1008,12 @@ int batch_upload(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
     std::vector<WorldDev> tab(n);
     std::vector<int64_t> cp(n + 1, 0), tp(n + 1, 0), sp(n + 1, 0);
     std::vector<int32_t> tx(std::max(n, 1), 0);
-    int variants = 0;
+    int variants = 0, max_slot_blocks = 0;
     for (int k = 0; k < n; ++k) {
         coralai_world* w = worlds[k];
         if (!w) return fail(CORALAI_E_INVALID, "world %d is NULL", k);
         variants |= w->ls.act_variants;
+        max_slot_blocks = std::max(max_slot_blocks, w->host.n_slot_blocks);
         if (k == 0) { b->NL = w->host.NL; b->HID = w->host.HID; b->prec = w->host.prec; }
         if (w->host.NL != b->NL || w->host.HID != b->HID || w->host.prec != b->prec)
             return fail(CORALAI_E_INVALID, "world %d: a batch needs one network shape and precision", k);
@@ -1042,6 +1044,7 @@ int batch_upload(coralai_batch* b, coralai_world* const* worlds, int32_t n) {
     b->n = n;
     b->worlds.assign(worlds, worlds + n);
     b->ls.act_variants = variants;  // part of the graph key: the step is recaptured when it changes
+    b->ls.scan_fused = max_slot_blocks <= kFuseSlotBlocks ? 1 : 0;  // likewise
     return CORALAI_OK;
 }
 }  // namespace
@@ -1054,7 +1057,7 @@ int coralai_batch_step(coralai_batch* b, int32_t n_steps) {
     if (n_steps < 0) return fail(CORALAI_E_INVALID, "n_steps < 0");
     if (b->n == 0 || n_steps == 0) return CORALAI_OK;
     const bool use_graph = b->stream != nullptr;
-    const int key = tuning_key(b->act_cells, b->act_waves, b->phys_tile, b->ls.act_variants);
+    const int key = tuning_key(b->act_cells, b->act_waves, b->phys_tile, b->ls);
     bool stale = false;  // some world's counts are stale: the first step recounts
     for (coralai_world* w : b->worlds) stale = stale || w->counts_stale;
     if (use_graph && (b->graph == nullptr || b->graph_key != key)) {

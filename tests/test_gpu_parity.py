@@ -125,7 +125,10 @@ def test_debug_weights_roundtrip(stream, prec):
                                         (300, 200, 70, 128),
                                         # ~1 750 genomes per 64 x 64 tile: the scatter's
                                         # table fills and most runs take the cursor path
-                                        (256, 130, 2000, 2048)])
+                                        (256, 130, 2000, 2048),
+                                        # more than 1024 slot blocks of 512: the scan's
+                                        # three-pass form
+                                        (64, 64, 16, 600_000)])
 def test_buckets_match_numpy(stream, W, H, ng, cap):
     say("buckets", W, H)
     init = gh.heterogeneous_world(W, H, n_genomes=ng, capacity=cap, seed=W)
