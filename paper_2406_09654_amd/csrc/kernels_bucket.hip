@@ -14,9 +14,9 @@
 // a genome owning a sixth of the world costs one atomic per tile instead of
 // one per wavefront.  A genome that finds the table full falls back to
 // direct global atomics (fragmented populations), with identical results.
-// The scan over genome slots is reduce-then-scan over 4096-slot blocks with
-// coalesced loads; it also lists the free (zero-count) slots in ascending
-// order for radiation.
+// The scan over genome slots is reduce-then-scan over 512-slot blocks with
+// coalesced loads, in two passes (three for capacities beyond 1024 blocks);
+// it also lists the free (zero-count) slots in ascending order for radiation.
 #include "coralai_internal.h"
 
 namespace coralai {
@@ -404,8 +404,9 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const BatchDev* __restrict_
     }
 }
 
-// Pass B: per world, exclusive prefix of the block partials (in place) and
-// the world totals.
+// Pass B (only when some world has more than kFuseSlotBlocks slot blocks):
+// per world, exclusive prefix of the block partials (in place) and the
+// world totals.
 __global__ __launch_bounds__(1024) void k_scan_blocks(const BatchDev* __restrict__ b) {
     __shared__ int s_tmp[16];
     const int wi = blockIdx.y;
