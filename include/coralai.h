@@ -325,7 +325,7 @@ int coralai_batch_destroy(coralai_batch* b);
  * network kernel processes together in one pass (1, 2 or 4; a pass holding
  * none of a 64-cell unit's cells is skipped); act_waves: 0 = fewer
  * wavefronts per SIMD with more registers each, 1 = more wavefronts;
- * phys_tile: LDS halo tiles 0 = 64x4, 1 = 32x8, 2 = 64x8, or 3 = streaming
+ * phys_tile: LDS halo tiles 0 = 64x16, 1 = 32x8, 2 = 64x8, or 3 = streaming
  * without LDS (one thread per four cells of a row when the width is a
  * multiple of 4, else per cell).  The batch versions tune the batch's
  * single captured step over its current worlds.  Defaults before any call:

@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256) void k_physics_stream(const BatchDev* __restri
 }
 
 int phys_tile_w(int t) { return t == 1 ? 32 : 64; }
-int phys_tile_h(int t) { return t == 1 ? 8 : (t == 2 ? 8 : 4); }
+int phys_tile_h(int t) { return t == 1 ? 8 : (t == 2 ? 8 : 16); }
 
 void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_tile,
                          hipStream_t s) {
@@ -585,8 +585,8 @@ void launch_physics_only(const BatchDev* bdev, const LaunchShape& ls, int phys_t
             else hipLaunchKernelGGL((k_physics<64, 8, false>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
             break;
         default:
-            if (e) hipLaunchKernelGGL((k_physics<64, 4, true>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
-            else hipLaunchKernelGGL((k_physics<64, 4, false>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            if (e) hipLaunchKernelGGL((k_physics<64, 16, true>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
+            else hipLaunchKernelGGL((k_physics<64, 16, false>), dim3(ls.phys_blocks), dim3(256), 0, s, bdev);
             break;
     }
 }
